@@ -1,0 +1,182 @@
+/*
+ * libmorea -- batched evaluation of MOREA's registration objectives on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * A candidate registration is a dual-dynamic tetrahedral mesh: two point sets
+ * with one shared connectivity, S on the source image I_s and T on the target
+ * image I_t (Sec. 4.2.1; the mesh is duplicated into the target space).  The
+ * pair defines the piecewise-affine map T (source -> target) and its inverse
+ * T' through barycentric coordinates, so every evaluation is symmetric
+ * (Sec. 2.1, Sec. 4.1.2).  For each candidate the library returns
+ *
+ *   obj[0]  f_intensity  Sec. 4.1.2, equations for f_intensity and h
+ *   obj[1]  f_magnitude  Sec. 4.1.1, equation for f_magnitude
+ *   obj[2]  f_guidance   Sec. 4.1.3, equations for f_guidance and g, with the
+ *                        distance-map form of App. A.3
+ *   flags   fold constraint of Sec. 4.1.4 / App. A.4 (sign of every tet's
+ *           signed volume against the sign in the initial mesh)
+ *   severity  sum of |signed volume| of the violating tets (App. A.4)
+ *   counts  |P_s| and |P_t|, the numbers of sample points
+ *
+ * Sample points are the voxel centres inside each tetrahedron (the voxel
+ * association of App. A.2), found by an exact, watertight rasterization:
+ * coordinates are snapped to 2^-10 voxel, and a centre that lies on a face
+ * belongs to the tet that contains it after an infinitesimal move by
+ * (e, e^2, e^3).  Every centre inside a fold-free mesh is therefore sampled
+ * exactly once per direction.
+ *
+ * Coordinates are voxel index units: voxel (i, j, k) has its centre at
+ * (i, j, k).  Images are [nz][ny][nx] with x fastest; both images share the
+ * grid (the pair is cropped to a common box, Sec. 5.1).  Intensity 0 is
+ * background and must be exactly 0; foreground is > 0.
+ *
+ * Conventions for every call:
+ *   - status codes are returned synchronously for argument errors; errors of
+ *     earlier asynchronous device work surface as MOREA_EDEVICE on a later
+ *     call; morea_last_error() returns a message for the calling thread;
+ *   - evaluation calls are asynchronous on the given stream (a hipStream_t,
+ *     NULL for the default stream), perform no host synchronisation and no
+ *     allocation; their pointer arguments are DEVICE pointers that the caller
+ *     owns and keeps alive until the stream has completed the call;
+ *   - a candidate with any coordinate that is not finite or has |x| >= 512
+ *     voxels is invalid: flags bit 2, NaN objectives and severity, zero
+ *     counts;
+ *   - results are deterministic: the same inputs give bitwise-identical
+ *     outputs (fixed reduction order, no floating-point atomics).
+ */
+#ifndef MOREA_H
+#define MOREA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MOREA_OK = 0,
+  MOREA_EINVAL = -1,  /* invalid argument (NULL pointer, bad size, bad index) */
+  MOREA_ENOMEM = -2,  /* device allocation failed */
+  MOREA_EDEVICE = -3, /* HIP runtime / kernel error */
+  MOREA_ERANGE = -4,  /* size beyond what the problem was created for */
+  MOREA_ESTATE = -5   /* call order violated (e.g. partial without groups) */
+} morea_status;
+
+typedef enum {
+  MOREA_STORE_F32 = 0, /* images kept as FP32 */
+  MOREA_STORE_BF16 = 1, /* images rounded (nearest, ties to even) to bfloat16 */
+  MOREA_STORE_F16 = 2  /* images rounded (nearest, ties to even) to IEEE half */
+} morea_store;
+
+typedef struct morea_problem morea_problem; /* opaque; owns all device copies */
+
+/* Problem description.  Every pointer is a HOST pointer; the library copies
+ * what it needs during morea_problem_create and keeps no reference.  */
+typedef struct {
+  int32_t dims[3];              /* nx, ny, nz; each in [1, 1024] */
+  const float *image_src;       /* I_s, [nz][ny][nx], finite, >= 0 */
+  const float *image_tgt;       /* I_t, same shape */
+  int32_t storage;              /* morea_store */
+  int32_t n_points;             /* points per mesh (>= 4) */
+  int32_t n_tets;               /* tetrahedra (>= 1) */
+  const int32_t *tets;          /* [n_tets][4] point indices */
+  const float *ref_points;      /* [n_points][3] initial mesh: reference signs
+                                   of App. A.4; no reference tet may be flat */
+  const float *elasticity;      /* [n_tets] c_delta > 0 (Sec. 4.1.1, App. A.1) */
+  int32_t n_sets;               /* guidance set pairs <C_s, C_t>, 0..8 */
+  const int32_t *set_off_src;   /* CSR offsets [n_sets+1] into set_pts_src */
+  const int32_t *set_off_tgt;   /* CSR offsets [n_sets+1] into set_pts_tgt */
+  const float *set_pts_src;     /* [*][3] points of C_s (on I_s) */
+  const float *set_pts_tgt;     /* [*][3] points of C_t (on I_t) */
+  float radius;                 /* truncation radius r in voxels; <= 0 selects
+                                   2.5% of the image width, 0.025 * nx (App. A.3) */
+  int32_t max_population;       /* largest pop of morea_eval_full (workspace) */
+} morea_problem_desc;
+
+/* Validate the description, copy images (converted to the storage type),
+ * mesh and guidance sets to the current device, and compute the distance
+ * map d(p, C) of every guidance set at every voxel centre (App. A.3).
+ * Blocks until the set-up work is complete.
+ * Errors: MOREA_EINVAL (bad description), MOREA_ENOMEM, MOREA_EDEVICE. */
+morea_status morea_problem_create(const morea_problem_desc *desc, morea_problem **out);
+
+/* Free all device memory of the problem (synchronises the device first).
+ * NULL is accepted. */
+void morea_problem_destroy(morea_problem *p);
+
+/* Bytes of a per-tetrahedron cache for `pop` candidates (App. A.2's partial
+ * objective values per tet, kept so that partial evaluations can reuse
+ * them, Sec. 4.2.1). */
+size_t morea_cache_bytes(const morea_problem *p, int32_t pop);
+
+/* Full evaluation of `pop` candidates (Sec. 4.1).
+ *   pts       [pop][2][3][n_points] FP32, mesh 0 = S, mesh 1 = T,
+ *             coordinate-major (x row, y row, z row) per mesh
+ *   obj       [pop][3]  intensity, magnitude, guidance (FP32)
+ *   flags     [pop]     bit0 fold in S, bit1 fold in T, bit2 invalid
+ *   severity  [pop]     sum of violating |signed volume|, voxel^3 (FP32)
+ *   counts    [pop][2]  |P_s|, |P_t|
+ *   cache     NULL, or morea_cache_bytes(p, pop) bytes of device memory that
+ *             receives the per-tet records for later partial evaluations
+ *   stream    hipStream_t or NULL
+ * 0 <= pop <= max_population.  Errors: MOREA_EINVAL, MOREA_ERANGE,
+ * MOREA_EDEVICE. */
+morea_status morea_eval_full(morea_problem *p, const float *pts, int32_t pop, float *obj,
+                             uint8_t *flags, float *severity, uint32_t *counts, void *cache,
+                             void *stream);
+
+/* Register the family of subsets: n_groups point groups in CSR form (host
+ * pointers).  For every group the library builds the list of dependent
+ * tetrahedra, those with at least one vertex in the group (Sec. 4.2.1), and
+ * the position of each of their vertices in the group.  A group may not repeat
+ * a point.  Synchronous.  Errors: MOREA_EINVAL, MOREA_ENOMEM, MOREA_EDEVICE. */
+morea_status morea_set_groups(morea_problem *p, int32_t n_groups, const int32_t *grp_off,
+                              const int32_t *grp_pts);
+
+/* Maximum number of evaluations and of new-coordinate rows that one
+ * morea_eval_partial call accepts; fixes the partial-evaluation workspace.
+ * Call after morea_set_groups.  Synchronous.  Errors: MOREA_ESTATE,
+ * MOREA_EINVAL, MOREA_ENOMEM. */
+morea_status morea_reserve_partial(morea_problem *p, int32_t max_evals);
+
+/* Partial evaluation (Sec. 3 optimal mixing; Sec. 4.2.1 dependent
+ * tetrahedra): evaluation e is the candidate parent_pts[eval_parent[e]] with
+ * the points of group eval_group[e] moved to new coordinates.  Only the
+ * dependent tets of the group are evaluated; all others come from the
+ * parent's cache (written by morea_eval_full with the same parent_pts).  The
+ * results equal a full evaluation of the child up to FP32 rounding; counts,
+ * flags and invalidity are exact.
+ *   parent_pts    [n_parents][2][3][n_points]
+ *   parent_cache  cache of morea_eval_full for parent_pts
+ *   eval_parent   [n_evals] in [0, n_parents)
+ *   eval_group    [n_evals] in [0, n_groups)
+ *   new_coords    [sum over e of |group e|][2][3]: group points in group order,
+ *                 evaluations in order; [k][m][a] = mesh m, axis a
+ *   obj, flags, severity, counts: [n_evals] as in morea_eval_full
+ * All arrays are device pointers.  The evaluation list is staged through a
+ * library-owned device workspace, so calls on one problem must not overlap
+ * (use one stream per problem).  Errors: MOREA_ESTATE (no groups or no
+ * reservation), MOREA_ERANGE (n_evals or rows beyond the reservation),
+ * MOREA_EINVAL, MOREA_EDEVICE. */
+morea_status morea_eval_partial(morea_problem *p, const float *parent_pts, int32_t n_parents,
+                                const void *parent_cache, int32_t n_evals,
+                                const int32_t *eval_parent, const int32_t *eval_group,
+                                const float *new_coords, float *obj, uint8_t *flags,
+                                float *severity, uint32_t *counts, void *stream);
+
+/* Copy the distance map d(p, C) of guidance set `set` on image `image`
+ * (0 = I_s grid with C_s, 1 = I_t grid with C_t) to host memory `host_out`
+ * ([nz][ny][nx] FP32), and, when `band_out` is not NULL, the per-voxel band
+ * mask (bit s set where map s < r) of that image.  Synchronous; for
+ * verification of the set-up (App. A.3).  Errors: MOREA_EINVAL, MOREA_EDEVICE. */
+morea_status morea_debug_distance_map(morea_problem *p, int32_t image, int32_t set, float *host_out,
+                                      uint8_t *band_out);
+
+/* Message for the last non-OK status returned on the calling thread. */
+const char *morea_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MOREA_H */

@@ -1,0 +1,257 @@
+"""Python binding of libmorea (MOREA objective evaluation on MI355X).
+
+Argument marshalling only: every step of an evaluation runs in the HIP
+kernels of ``libmorea.so``.  The functions carry the names of the C-ABI
+(``include/morea.h``); :class:`Problem` bundles them for device tensors.
+PyTorch provides device memory and streams.  The library must be built
+(``python paper_2303_04873_amd/build.py``); importing the binding without it
+raises, there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmorea.so")
+
+MOREA_OK, MOREA_EINVAL, MOREA_ENOMEM, MOREA_EDEVICE, MOREA_ERANGE, MOREA_ESTATE = 0, -1, -2, -3, -4, -5
+STORE = {"f32": 0, "bf16": 1, "f16": 2}
+
+EXPORTS = ["morea_problem_create", "morea_problem_destroy", "morea_cache_bytes", "morea_eval_full",
+           "morea_set_groups", "morea_reserve_partial", "morea_eval_partial",
+           "morea_debug_distance_map", "morea_last_error"]
+
+
+class MoreaError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"libmorea status {status}: {msg}")
+        self.status = status
+
+
+class morea_problem_desc(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int32 * 3),
+                ("image_src", ctypes.c_void_p), ("image_tgt", ctypes.c_void_p),
+                ("storage", ctypes.c_int32),
+                ("n_points", ctypes.c_int32), ("n_tets", ctypes.c_int32),
+                ("tets", ctypes.c_void_p), ("ref_points", ctypes.c_void_p),
+                ("elasticity", ctypes.c_void_p),
+                ("n_sets", ctypes.c_int32),
+                ("set_off_src", ctypes.c_void_p), ("set_off_tgt", ctypes.c_void_p),
+                ("set_pts_src", ctypes.c_void_p), ("set_pts_tgt", ctypes.c_void_p),
+                ("radius", ctypes.c_float), ("max_population", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load_library():
+    """Load libmorea.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2303_04873_amd/build.py")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I32 = ctypes.c_void_p, ctypes.c_int32
+    L.morea_problem_create.argtypes = [ctypes.POINTER(morea_problem_desc), ctypes.POINTER(P)]
+    L.morea_problem_create.restype = I32
+    L.morea_problem_destroy.argtypes = [P]
+    L.morea_problem_destroy.restype = None
+    L.morea_cache_bytes.argtypes = [P, I32]
+    L.morea_cache_bytes.restype = ctypes.c_size_t
+    L.morea_eval_full.argtypes = [P, P, I32, P, P, P, P, P, P]
+    L.morea_eval_full.restype = I32
+    L.morea_set_groups.argtypes = [P, I32, P, P]
+    L.morea_set_groups.restype = I32
+    L.morea_reserve_partial.argtypes = [P, I32]
+    L.morea_reserve_partial.restype = I32
+    L.morea_eval_partial.argtypes = [P, P, I32, P, I32, P, P, P, P, P, P, P, P]
+    L.morea_eval_partial.restype = I32
+    L.morea_debug_distance_map.argtypes = [P, I32, I32, P, P]
+    L.morea_debug_distance_map.restype = I32
+    L.morea_last_error.argtypes = []
+    L.morea_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def morea_last_error() -> str:
+    return load_library().morea_last_error().decode()
+
+
+def _check(status):
+    if status != MOREA_OK:
+        raise MoreaError(status, morea_last_error())
+
+
+def _host(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _dev_ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream_ptr(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def morea_problem_create(desc: morea_problem_desc) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    _check(load_library().morea_problem_create(ctypes.byref(desc), ctypes.byref(h)))
+    return h
+
+
+def morea_problem_destroy(handle):
+    load_library().morea_problem_destroy(handle)
+
+
+def morea_cache_bytes(handle, pop: int) -> int:
+    return load_library().morea_cache_bytes(handle, pop)
+
+
+def morea_eval_full(handle, pts, pop, obj, flags, severity, counts, cache, stream):
+    _check(load_library().morea_eval_full(handle, _dev_ptr(pts), pop, _dev_ptr(obj), _dev_ptr(flags),
+                                          _dev_ptr(severity), _dev_ptr(counts), _dev_ptr(cache),
+                                          _stream_ptr(stream)))
+
+
+def morea_set_groups(handle, grp_off, grp_pts):
+    off = _host(grp_off, np.int32)
+    pts = _host(grp_pts, np.int32)
+    _check(load_library().morea_set_groups(handle, len(off) - 1, off.ctypes.data_as(ctypes.c_void_p),
+                                           pts.ctypes.data_as(ctypes.c_void_p)))
+
+
+def morea_reserve_partial(handle, max_evals: int):
+    _check(load_library().morea_reserve_partial(handle, max_evals))
+
+
+def morea_eval_partial(handle, parent_pts, n_parents, parent_cache, n_evals, eval_parent, eval_group,
+                       new_coords, obj, flags, severity, counts, stream):
+    _check(load_library().morea_eval_partial(
+        handle, _dev_ptr(parent_pts), n_parents, _dev_ptr(parent_cache), n_evals,
+        _dev_ptr(eval_parent), _dev_ptr(eval_group), _dev_ptr(new_coords), _dev_ptr(obj),
+        _dev_ptr(flags), _dev_ptr(severity), _dev_ptr(counts), _stream_ptr(stream)))
+
+
+def morea_debug_distance_map(handle, image: int, set_index: int, shape):
+    out = np.empty(shape, np.float32)
+    band = np.empty(shape, np.uint8)
+    _check(load_library().morea_debug_distance_map(handle, image, set_index,
+                                                   out.ctypes.data_as(ctypes.c_void_p),
+                                                   band.ctypes.data_as(ctypes.c_void_p)))
+    return out, band
+
+
+class Problem:
+    """A problem on the current GPU; candidates and outputs are torch tensors."""
+
+    def __init__(self, dims, image_src, image_tgt, tets, ref_points, elasticity, sets_src=(),
+                 sets_tgt=(), radius=0.0, storage="f32", max_population=1):
+        nx, ny, nz = (int(d) for d in dims)
+        self.dims = (nx, ny, nz)
+        self._keep = []
+
+        def host(a, dt):
+            h = _host(a, dt)
+            self._keep.append(h)
+            return h.ctypes.data
+
+        sets_src = [np.asarray(s, np.float32).reshape(-1, 3) for s in sets_src]
+        sets_tgt = [np.asarray(s, np.float32).reshape(-1, 3) for s in sets_tgt]
+        n_sets = len(sets_src)
+        off_s = np.cumsum([0] + [len(s) for s in sets_src]).astype(np.int32)
+        off_t = np.cumsum([0] + [len(s) for s in sets_tgt]).astype(np.int32)
+        pts_s = np.concatenate(sets_src) if n_sets else np.zeros((1, 3), np.float32)
+        pts_t = np.concatenate(sets_tgt) if n_sets else np.zeros((1, 3), np.float32)
+        tets = _host(tets, np.int32)
+        ref_points = _host(ref_points, np.float32)
+        d = morea_problem_desc()
+        d.dims[:] = [nx, ny, nz]
+        d.image_src = host(image_src, np.float32)
+        d.image_tgt = host(image_tgt, np.float32)
+        d.storage = STORE[storage]
+        d.n_points = ref_points.shape[0]
+        d.n_tets = tets.shape[0]
+        d.tets = host(tets, np.int32)
+        d.ref_points = host(ref_points, np.float32)
+        d.elasticity = host(elasticity, np.float32)
+        d.n_sets = n_sets
+        d.set_off_src = host(off_s, np.int32)
+        d.set_off_tgt = host(off_t, np.int32)
+        d.set_pts_src = host(pts_s, np.float32)
+        d.set_pts_tgt = host(pts_t, np.float32)
+        d.radius = float(radius)
+        d.max_population = int(max_population)
+        self.n_points = d.n_points
+        self.n_tets = d.n_tets
+        self.n_sets = n_sets
+        self.max_population = int(max_population)
+        self.handle = morea_problem_create(d)
+        self._keep = []
+
+    @classmethod
+    def from_synth(cls, p, storage="f32", max_population=1, image_src=None, image_tgt=None):
+        return cls(p.dims, p.image_src if image_src is None else image_src,
+                   p.image_tgt if image_tgt is None else image_tgt, p.tets, p.ref_points,
+                   p.elasticity, p.sets_src, p.sets_tgt, p.radius, storage, max_population)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            morea_problem_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def cache_bytes(self, pop):
+        return morea_cache_bytes(self.handle, pop)
+
+    def new_cache(self, pop):
+        import torch
+        return torch.empty(self.cache_bytes(pop), dtype=torch.uint8, device="cuda")
+
+    def outputs(self, n):
+        import torch
+        dev = "cuda"
+        return dict(obj=torch.empty((n, 3), dtype=torch.float32, device=dev),
+                    flags=torch.empty(n, dtype=torch.uint8, device=dev),
+                    severity=torch.empty(n, dtype=torch.float32, device=dev),
+                    counts=torch.empty((n, 2), dtype=torch.int32, device=dev))
+
+    def eval_full(self, pts, cache=None, out=None, stream=None):
+        """pts: float32 CUDA tensor [pop][2][3][n_points]."""
+        assert pts.is_cuda and pts.dtype.is_floating_point and pts.is_contiguous()
+        pop = pts.shape[0]
+        assert tuple(pts.shape[1:]) == (2, 3, self.n_points)
+        out = self.outputs(pop) if out is None else out
+        morea_eval_full(self.handle, pts, pop, out["obj"], out["flags"], out["severity"],
+                        out["counts"], cache, stream)
+        return out
+
+    def set_groups(self, grp_off, grp_pts):
+        morea_set_groups(self.handle, grp_off, grp_pts)
+
+    def reserve_partial(self, max_evals):
+        morea_reserve_partial(self.handle, max_evals)
+
+    def eval_partial(self, parent_pts, parent_cache, eval_parent, eval_group, new_coords, out=None,
+                     stream=None):
+        n = eval_parent.shape[0]
+        out = self.outputs(n) if out is None else out
+        morea_eval_partial(self.handle, parent_pts, parent_pts.shape[0], parent_cache, n,
+                           eval_parent, eval_group, new_coords, out["obj"], out["flags"],
+                           out["severity"], out["counts"], stream)
+        return out
+
+    def distance_map(self, image, set_index):
+        return morea_debug_distance_map(self.handle, image, set_index, self.dims[::-1])

@@ -1,0 +1,315 @@
+// Host side of libmorea: the C-ABI entry points declared in include/morea.h.
+// Argument validation, conversion of the images to their storage type,
+// device uploads, set-up kernels and kernel launches.  No entry point that
+// evaluates candidates allocates memory or synchronises the host.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "morea_internal.h"
+
+using namespace morea;
+
+namespace {
+
+thread_local std::string g_error;
+
+morea_status fail(morea_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_error = buf;
+  return s;
+}
+
+morea_status hip_fail(hipError_t e, const char* what) {
+  return fail(MOREA_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Round-to-nearest-even conversions of the stored images.
+uint16_t to_bf16(float f) {
+  uint32_t u;
+  memcpy(&u, &f, 4);
+  u = u + 0x7FFFu + ((u >> 16) & 1u);
+  return static_cast<uint16_t>(u >> 16);
+}
+
+uint16_t to_f16(float f) {
+  _Float16 h = static_cast<_Float16>(f);
+  uint16_t u;
+  memcpy(&u, &h, 2);
+  return u;
+}
+
+int64_t snap_host(float x) { return static_cast<int64_t>(rint(static_cast<double>(x) * 1024.0)); }
+
+bool coord_ok(float x) { return fabsf(x) < kCoordLimit; }
+
+template <typename T>
+morea_status upload(morea_problem* p, T** dst, const void* src, size_t bytes) {
+  void* d = nullptr;
+  hipError_t e = hipMalloc(&d, bytes ? bytes : 4);
+  if (e != hipSuccess) return fail(MOREA_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+  p->allocations.push_back(d);
+  if (src && bytes) {
+    e = hipMemcpy(d, src, bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+  }
+  *dst = static_cast<T*>(d);
+  return MOREA_OK;
+}
+
+morea_status check_pending() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "earlier device work failed");
+  return MOREA_OK;
+}
+
+void free_all(morea_problem* p) {
+  for (void* a : p->allocations) (void)hipFree(a);
+  p->allocations.clear();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* morea_last_error(void) { return g_error.c_str(); }
+
+morea_status morea_problem_create(const morea_problem_desc* d, morea_problem** out) {
+  if (!out) return fail(MOREA_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!d) return fail(MOREA_EINVAL, "desc is NULL");
+  for (int k = 0; k < 3; k++)
+    if (d->dims[k] < 1 || d->dims[k] > 1024) return fail(MOREA_EINVAL, "dims[%d]=%d outside [1,1024]", k, d->dims[k]);
+  if (!d->image_src || !d->image_tgt) return fail(MOREA_EINVAL, "image pointer is NULL");
+  if (d->storage < 0 || d->storage > 2) return fail(MOREA_EINVAL, "storage %d unknown", d->storage);
+  if (d->n_points < 4 || d->n_tets < 1) return fail(MOREA_EINVAL, "need >= 4 points and >= 1 tet");
+  if (!d->tets || !d->ref_points || !d->elasticity) return fail(MOREA_EINVAL, "mesh pointer is NULL");
+  if (d->n_sets < 0 || d->n_sets > kMaxSets) return fail(MOREA_EINVAL, "n_sets %d outside [0,%d]", d->n_sets, kMaxSets);
+  if (d->max_population < 1) return fail(MOREA_EINVAL, "max_population must be >= 1");
+  const int nx = d->dims[0], ny = d->dims[1], nz = d->dims[2];
+  const size_t V = static_cast<size_t>(nx) * ny * nz;
+  for (size_t i = 0; i < V; i++) {
+    float a = d->image_src[i], b = d->image_tgt[i];
+    if (!(a >= 0.f && a < INFINITY) || !(b >= 0.f && b < INFINITY))
+      return fail(MOREA_EINVAL, "image value at %zu is negative or not finite", i);
+  }
+  for (int i = 0; i < 3 * d->n_points; i++)
+    if (!coord_ok(d->ref_points[i])) return fail(MOREA_EINVAL, "ref_points[%d] out of range", i);
+  std::vector<int8_t> ref_sign(d->n_tets);
+  for (int t = 0; t < d->n_tets; t++) {
+    int64_t v[4][3];
+    for (int i = 0; i < 4; i++) {
+      int idx = d->tets[4 * t + i];
+      if (idx < 0 || idx >= d->n_points) return fail(MOREA_EINVAL, "tet %d has vertex index %d", t, idx);
+      for (int k = 0; k < 3; k++) v[i][k] = snap_host(d->ref_points[3 * idx + k]);
+    }
+    int64_t a[3], b[3], c[3];
+    for (int k = 0; k < 3; k++) {
+      a[k] = v[1][k] - v[0][k];
+      b[k] = v[2][k] - v[0][k];
+      c[k] = v[3][k] - v[0][k];
+    }
+    int64_t det = a[0] * (b[1] * c[2] - b[2] * c[1]) - a[1] * (b[0] * c[2] - b[2] * c[0]) +
+                  a[2] * (b[0] * c[1] - b[1] * c[0]);
+    if (det == 0) return fail(MOREA_EINVAL, "reference tet %d is flat", t);
+    ref_sign[t] = det > 0 ? 1 : -1;
+    float c_d = d->elasticity[t];
+    if (!(c_d > 0.f && c_d < INFINITY)) return fail(MOREA_EINVAL, "elasticity[%d] not positive", t);
+  }
+  std::vector<int> set_off[2];
+  std::vector<int> set_fix[2];
+  float set_w[2][kMaxSets] = {};
+  if (d->n_sets > 0) {
+    const int32_t* offs[2] = {d->set_off_src, d->set_off_tgt};
+    const float* pts[2] = {d->set_pts_src, d->set_pts_tgt};
+    for (int m = 0; m < 2; m++) {
+      if (!offs[m] || !pts[m]) return fail(MOREA_EINVAL, "guidance set pointer is NULL");
+      if (offs[m][0] != 0) return fail(MOREA_EINVAL, "set offsets must start at 0");
+      for (int s = 0; s < d->n_sets; s++)
+        if (offs[m][s + 1] <= offs[m][s]) return fail(MOREA_EINVAL, "guidance set %d of image %d is empty", s, m);
+      const int total = offs[m][d->n_sets];
+      set_off[m].assign(offs[m], offs[m] + d->n_sets + 1);
+      set_fix[m].resize(3 * static_cast<size_t>(total));
+      for (int i = 0; i < 3 * total; i++) {
+        if (!coord_ok(pts[m][i])) return fail(MOREA_EINVAL, "guidance point coordinate %d out of range", i);
+        set_fix[m][i] = static_cast<int>(snap_host(pts[m][i]));
+      }
+      for (int s = 0; s < d->n_sets; s++)
+        set_w[m][s] = static_cast<float>(static_cast<double>(offs[m][s + 1] - offs[m][s]) / total);
+    }
+  }
+  float radius = d->radius > 0.f ? d->radius : 0.025f * static_cast<float>(nx);
+  if (!(radius < INFINITY)) return fail(MOREA_EINVAL, "radius not finite");
+
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  morea_problem* p = new morea_problem();
+  p->device = dev;
+  p->storage = d->storage;
+  p->max_population = d->max_population;
+  p->voxels = V;
+  ProblemView& P = p->view;
+  P.nx = nx;
+  P.ny = ny;
+  P.nz = nz;
+  P.n_points = d->n_points;
+  P.n_tets = d->n_tets;
+  P.n_sets = d->n_sets;
+  P.radius = radius;
+  P.inv_radius = 1.0f / radius;
+  memcpy(P.set_w, set_w, sizeof(set_w));
+
+  morea_status st = MOREA_OK;
+  auto guard = [&](morea_status s) {
+    if (s != MOREA_OK && st == MOREA_OK) st = s;
+    return s == MOREA_OK;
+  };
+  // images in their storage type
+  for (int m = 0; m < 2 && st == MOREA_OK; m++) {
+    const float* img = m == 0 ? d->image_src : d->image_tgt;
+    void* dst = nullptr;
+    if (d->storage == kF32) {
+      guard(upload(p, &dst, img, V * sizeof(float)));
+    } else {
+      std::vector<uint16_t> q(V);
+      for (size_t i = 0; i < V; i++) q[i] = d->storage == kBF16 ? to_bf16(img[i]) : to_f16(img[i]);
+      guard(upload(p, &dst, q.data(), V * sizeof(uint16_t)));
+    }
+    P.img[m] = dst;
+  }
+  int4* tets = nullptr;
+  int8_t* rs = nullptr;
+  float* el = nullptr;
+  if (st == MOREA_OK) guard(upload(p, &tets, d->tets, sizeof(int4) * d->n_tets));
+  if (st == MOREA_OK) guard(upload(p, &rs, ref_sign.data(), d->n_tets));
+  if (st == MOREA_OK) guard(upload(p, &el, d->elasticity, sizeof(float) * d->n_tets));
+  P.tets = tets;
+  P.ref_sign = rs;
+  P.elasticity = el;
+  for (int m = 0; m < 2 && st == MOREA_OK; m++) {
+    float* dm = nullptr;
+    uint8_t* band = nullptr;
+    guard(upload(p, &dm, nullptr, sizeof(float) * V * std::max(d->n_sets, 1)));
+    if (st == MOREA_OK) guard(upload(p, &band, nullptr, V));
+    if (st != MOREA_OK) break;
+    if (d->n_sets > 0) {
+      int* doff = nullptr;
+      int* dpts = nullptr;
+      guard(upload(p, &doff, set_off[m].data(), sizeof(int) * set_off[m].size()));
+      if (st == MOREA_OK) guard(upload(p, &dpts, set_fix[m].data(), sizeof(int) * set_fix[m].size()));
+      if (st != MOREA_OK) break;
+      e = launch_distance_maps(nx, ny, nz, d->n_sets, doff, dpts, radius, dm, band, nullptr);
+      if (e != hipSuccess) guard(hip_fail(e, "distance map kernel"));
+    } else {
+      e = hipMemset(band, 0, V);
+      if (e != hipSuccess) guard(hip_fail(e, "hipMemset"));
+    }
+    P.dmap[m] = dm;
+    P.band[m] = band;
+  }
+  if (st == MOREA_OK) {
+    const size_t nrec = static_cast<size_t>(d->max_population) * d->n_tets * 2;
+    guard(upload(p, &p->work_records, nullptr, nrec * sizeof(Record)));
+    if (st == MOREA_OK) guard(upload(p, &p->work_totals, nullptr, sizeof(Totals) * d->max_population));
+  }
+  if (st == MOREA_OK) {
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) guard(hip_fail(e, "set-up"));
+  }
+  if (st != MOREA_OK) {
+    std::string msg = g_error;
+    free_all(p);
+    delete p;
+    g_error = msg;
+    return st;
+  }
+  *out = p;
+  return MOREA_OK;
+}
+
+void morea_problem_destroy(morea_problem* p) {
+  if (!p) return;
+  (void)hipDeviceSynchronize();
+  free_all(p);
+  delete p;
+}
+
+size_t morea_cache_bytes(const morea_problem* p, int32_t pop) {
+  if (!p || pop < 0) return 0;
+  return static_cast<size_t>(pop) * p->view.n_tets * 2 * sizeof(Record) +
+         static_cast<size_t>(pop) * sizeof(Totals);
+}
+
+morea_status morea_eval_full(morea_problem* p, const float* pts, int32_t pop, float* obj,
+                             uint8_t* flags, float* severity, uint32_t* counts, void* cache,
+                             void* stream) {
+  if (!p) return fail(MOREA_EINVAL, "problem is NULL");
+  if (pop < 0) return fail(MOREA_EINVAL, "pop %d < 0", pop);
+  if (pop > p->max_population) return fail(MOREA_ERANGE, "pop %d > max_population %d", pop, p->max_population);
+  if (pop == 0) return MOREA_OK;
+  if (!pts || !obj || !flags || !severity || !counts) return fail(MOREA_EINVAL, "NULL argument");
+  morea_status st = check_pending();
+  if (st != MOREA_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Record* rec = p->work_records;
+  Totals* tot = nullptr;
+  if (cache) {
+    rec = static_cast<Record*>(cache);
+    tot = reinterpret_cast<Totals*>(static_cast<char*>(cache) +
+                                    static_cast<size_t>(pop) * p->view.n_tets * 2 * sizeof(Record));
+  }
+  hipError_t e = launch_eval_full(p->view, p->storage, pts, pop, rec, s);
+  if (e != hipSuccess) return hip_fail(e, "eval kernel launch");
+  e = launch_finalize(p->view, pts, pop, rec, obj, flags, severity, counts, tot, s);
+  if (e != hipSuccess) return hip_fail(e, "finalize kernel launch");
+  return MOREA_OK;
+}
+
+morea_status morea_debug_distance_map(morea_problem* p, int32_t image, int32_t set, float* host_out,
+                                      uint8_t* band_out) {
+  if (!p || !host_out || image < 0 || image > 1 || set < 0 || set >= p->view.n_sets)
+    return fail(MOREA_EINVAL, "bad argument");
+  hipError_t e = hipMemcpy(host_out, p->view.dmap[image] + static_cast<size_t>(set) * p->voxels,
+                           p->voxels * sizeof(float), hipMemcpyDeviceToHost);
+  if (e == hipSuccess && band_out)
+    e = hipMemcpy(band_out, p->view.band[image], p->voxels, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+  return MOREA_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+morea_status morea_set_groups(morea_problem* p, int32_t n_groups, const int32_t* grp_off,
+                              const int32_t* grp_pts) {
+  (void)p; (void)n_groups; (void)grp_off; (void)grp_pts;
+  return fail(MOREA_ESTATE, "partial evaluation is not available in this build");
+}
+
+morea_status morea_reserve_partial(morea_problem* p, int32_t max_evals) {
+  (void)p; (void)max_evals;
+  return fail(MOREA_ESTATE, "partial evaluation is not available in this build");
+}
+
+morea_status morea_eval_partial(morea_problem* p, const float* parent_pts, int32_t n_parents,
+                                const void* parent_cache, int32_t n_evals,
+                                const int32_t* eval_parent, const int32_t* eval_group,
+                                const float* new_coords, float* obj, uint8_t* flags,
+                                float* severity, uint32_t* counts, void* stream) {
+  (void)p; (void)parent_pts; (void)n_parents; (void)parent_cache; (void)n_evals; (void)eval_parent;
+  (void)eval_group; (void)new_coords; (void)obj; (void)flags; (void)severity; (void)counts; (void)stream;
+  return fail(MOREA_ESTATE, "partial evaluation is not available in this build");
+}
+
+}  // extern "C"

@@ -1,0 +1,117 @@
+// Internal types shared by the libmorea HIP sources.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/morea.h"
+
+namespace morea {
+
+constexpr int kFracBits = 10;                 // fixed-point snap: 2^-10 voxel
+constexpr float kFixOne = 1024.0f;
+constexpr float kCoordLimit = 512.0f;         // |x| < 512 voxels keeps every extent < 2^20
+constexpr int kFastExtent = 1 << 16;          // tets up to 64 voxels: exact plane tests in FP64
+constexpr int kMaxSets = 8;
+constexpr int kWave = 64;
+
+// Per-(candidate, tet, direction) partial objective record.  Direction 0
+// rasterizes the source tet on I_s and samples I_t; direction 1 rasterizes
+// the target tet on I_t and samples I_s.
+struct Record {
+  float h;        // sum of h over this tet's samples
+  float g;        // set-weighted guidance sum
+  uint32_t n;     // samples
+  float mag;      // magnitude term of the tet (direction 0 only, else 0)
+  float vol;      // |signed volume| (voxel^3) when the tet violates, else 0
+  uint32_t bits;  // bit0: violation of this direction's mesh; bit2: invalid vertex
+};
+static_assert(sizeof(Record) == 24, "record layout");
+
+// Per-candidate totals kept after the records in a cache (compensated
+// double-float sums: value = hi + lo).
+struct Totals {
+  float h_hi, h_lo, g_hi, g_lo, m_hi, m_lo, v_hi, v_lo;
+  uint32_t n[2];
+  uint32_t viol[2];   // violating tets per mesh
+  uint32_t bad;       // invalid coordinates of the candidate
+  uint32_t pad[3];
+};
+static_assert(sizeof(Totals) == 64, "totals layout");
+
+enum Store { kF32 = 0, kBF16 = 1, kF16 = 2 };
+
+// Device view of a problem, passed by value to kernels.
+struct ProblemView {
+  int nx, ny, nz;
+  int n_points, n_tets, n_sets;
+  float radius, inv_radius;
+  const void* img[2];            // [0] = I_s, [1] = I_t, storage type
+  const float* dmap[2];          // [n_sets][V] distance maps on each image grid
+  const uint8_t* band[2];        // [V] bit s set where dmap[s] < radius
+  float set_w[2][kMaxSets];      // |C_i| / |G| per direction
+  const int4* tets;
+  const int8_t* ref_sign;
+  const float* elasticity;
+};
+
+// Work item of one wave: candidate geometry source.
+struct FullItems {
+  const float* pts;   // [pop][2][3][n_points]
+  int pop;
+};
+
+struct PartialItems {
+  const float* parent_pts;     // [n_parents][2][3][n_points]
+  const int* eval_parent;      // [n_evals]
+  const int* eval_group;       // [n_evals]
+  const float* new_coords;     // [rows][2][3]
+  const int* row_off;          // [n_evals] first new-coordinate row of each evaluation
+  const int* item_off;         // [n_evals + 1] prefix of dependent tets per evaluation
+  const int* dep_off;          // [n_groups + 1] CSR into dep_tet / dep_local
+  const int* dep_tet;          // dependent tets per group
+  const int8_t* dep_local;     // [.][4] position of each tet vertex in the group, -1 if none
+  int n_evals;
+  int total_items;             // item_off[n_evals] (device value mirrored by kernels)
+};
+
+}  // namespace morea
+
+struct morea_problem {
+  int device = 0;
+  morea::ProblemView view{};
+  int storage = 0;
+  int max_population = 0;
+  size_t voxels = 0;
+  std::vector<void*> allocations;
+  morea::Record* work_records = nullptr;   // [max_population][n_tets][2]
+  morea::Totals* work_totals = nullptr;    // [max_population]
+  // family of subsets
+  int n_groups = 0;
+  std::vector<int> grp_size;               // host copy of group sizes
+  int* d_grp_size = nullptr;
+  int* d_dep_off = nullptr;
+  int* d_dep_tet = nullptr;
+  int8_t* d_dep_local = nullptr;
+  int max_dep = 0;
+  // partial workspace
+  int max_evals = 0;
+  int* d_row_off = nullptr;
+  int* d_item_off = nullptr;
+  morea::Record* d_partial_records = nullptr;  // [max_evals * max_dep][2]
+  int* d_queue = nullptr;
+};
+
+namespace morea {
+// Kernel launchers (defined with the kernels).
+hipError_t launch_distance_maps(int nx, int ny, int nz, int n_sets, const int* set_off,
+                                const int* pts_fix, float radius, float* dmap, uint8_t* band,
+                                hipStream_t s);
+hipError_t launch_eval_full(const ProblemView& P, int storage, const float* pts, int pop,
+                            Record* rec, hipStream_t s);
+hipError_t launch_finalize(const ProblemView& P, const float* pts, int pop, const Record* rec,
+                           float* obj, uint8_t* flags, float* severity, uint32_t* counts,
+                           Totals* totals, hipStream_t s);
+}  // namespace morea

@@ -1,0 +1,110 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry point
+declared in include/morea.h, and rejects bad problem descriptions before any
+device work."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2303_04873_amd as morea
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "morea.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(morea_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ["morea_problem_create", "morea_problem_destroy", "morea_eval_full",
+                     "morea_eval_partial", "morea_set_groups", "morea_last_error"]:
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(morea.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert sorted(morea.EXPORTS) == declared_functions()
+
+
+def _desc(p, **over):
+    keep = []
+
+    def h(a, dt):
+        a = np.ascontiguousarray(a, dtype=dt)
+        keep.append(a)
+        return a.ctypes.data
+
+    d = morea.morea_problem_desc()
+    d.dims[:] = list(p.dims)
+    d.image_src = h(over.get("image_src", p.image_src), np.float32)
+    d.image_tgt = h(p.image_tgt, np.float32)
+    d.storage = over.get("storage", 0)
+    pts = over.get("ref_points", p.ref_points)
+    tets = over.get("tets", p.tets)
+    d.n_points = len(pts)
+    d.n_tets = len(tets)
+    d.tets = h(tets, np.int32)
+    d.ref_points = h(pts, np.float32)
+    d.elasticity = h(over.get("elasticity", p.elasticity), np.float32)
+    d.n_sets = over.get("n_sets", 0)
+    d.radius = 0.0
+    d.max_population = over.get("max_population", 1)
+    if "dims" in over:
+        d.dims[:] = list(over["dims"])
+    return d, keep
+
+
+@pytest.mark.parametrize("case", ["dims", "negative_image", "flat_tet", "bad_index", "elasticity",
+                                  "storage", "n_sets", "max_population"])
+def test_create_rejects_bad_descriptions(case, c1):
+    p = c1
+    over = {}
+    if case == "dims":
+        over["dims"] = (0, 32, 32)
+    elif case == "negative_image":
+        img = p.image_src.copy()
+        img[3, 4, 5] = -0.1
+        over["image_src"] = img
+    elif case == "flat_tet":
+        pts = p.ref_points.copy()
+        t = p.tets[0]
+        pts[t[3]] = pts[t[0]]
+        over["ref_points"] = pts
+    elif case == "bad_index":
+        tets = p.tets.copy()
+        tets[2, 1] = 10 ** 6
+        over["tets"] = tets
+    elif case == "elasticity":
+        e = p.elasticity.copy()
+        e[0] = 0.0
+        over["elasticity"] = e
+    elif case == "storage":
+        over["storage"] = 7
+    elif case == "n_sets":
+        over["n_sets"] = 99
+    elif case == "max_population":
+        over["max_population"] = 0
+    d, keep = _desc(p, **over)
+    h = ctypes.c_void_p()
+    st = morea.load_library().morea_problem_create(ctypes.byref(d), ctypes.byref(h))
+    assert st == morea.MOREA_EINVAL
+    assert h.value is None
+    assert len(morea.morea_last_error()) > 0
+
+
+def test_null_arguments_rejected():
+    L = morea.load_library()
+    assert L.morea_problem_create(None, None) == morea.MOREA_EINVAL
+    h = ctypes.c_void_p()
+    assert L.morea_problem_create(None, ctypes.byref(h)) == morea.MOREA_EINVAL
+    assert L.morea_eval_full(None, None, 1, None, None, None, None, None, None) == morea.MOREA_EINVAL
+    L.morea_problem_destroy(None)   # accepted
