@@ -36,6 +36,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="CPU time budget of the oracle baseline sample (0 = skip)")
     ap.add_argument("--parity-samples", type=int, default=3)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one plain device copy of this size first (counter calibration)")
     return ap.parse_args()
 
 
@@ -62,6 +64,13 @@ def main():
     out = prob.outputs(pop)
     stream = torch.cuda.current_stream()
 
+    if args.calib_copy_mib > 0:
+        n = args.calib_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         prob.eval_full(pts, out=out)
     torch.cuda.synchronize()

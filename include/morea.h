@@ -134,10 +134,11 @@ morea_status morea_eval_full(morea_problem *p, const float *pts, int32_t pop, fl
 morea_status morea_set_groups(morea_problem *p, int32_t n_groups, const int32_t *grp_off,
                               const int32_t *grp_pts);
 
-/* Maximum number of evaluations and of new-coordinate rows that one
- * morea_eval_partial call accepts; fixes the partial-evaluation workspace.
- * Call after morea_set_groups.  Synchronous.  Errors: MOREA_ESTATE,
- * MOREA_EINVAL, MOREA_ENOMEM. */
+/* Maximum number of evaluations that one morea_eval_partial call accepts;
+ * allocates the partial-evaluation workspace (per-item records for
+ * max_evals times the largest dependent-tet list).  Call after every
+ * morea_set_groups.  Synchronous.  Errors: MOREA_ESTATE, MOREA_EINVAL,
+ * MOREA_ENOMEM, MOREA_EDEVICE. */
 morea_status morea_reserve_partial(morea_problem *p, int32_t max_evals);
 
 /* Partial evaluation (Sec. 3 optimal mixing; Sec. 4.2.1 dependent
@@ -152,11 +153,18 @@ morea_status morea_reserve_partial(morea_problem *p, int32_t max_evals);
  *   eval_parent   [n_evals] in [0, n_parents)
  *   eval_group    [n_evals] in [0, n_groups)
  *   new_coords    [sum over e of |group e|][2][3]: group points in group order,
- *                 evaluations in order; [k][m][a] = mesh m, axis a
+ *                 evaluations in order; [k][m][a] = mesh m, axis a (an
+ *                 evaluation whose group index is out of range owns no rows)
  *   obj, flags, severity, counts: [n_evals] as in morea_eval_full
- * All arrays are device pointers.  The evaluation list is staged through a
- * library-owned device workspace, so calls on one problem must not overlap
- * (use one stream per problem).  Errors: MOREA_ESTATE (no groups or no
+ * All arrays are device pointers.  The three kernels of a call (list prefix
+ * sums, one persistent launch that takes (evaluation, dependent tet,
+ * direction) items from a device work queue, and the per-evaluation
+ * reduction) are captured once into a HIP graph and replayed while the
+ * pointer arguments and sizes stay the same; a call with new buffers
+ * captures a new graph.  Out-of-range eval_parent / eval_group entries give
+ * that evaluation flags bit 2 and NaN objectives.  The evaluation list is
+ * staged through a library-owned device workspace, so calls on one problem
+ * must not overlap (use one stream per problem).  Errors: MOREA_ESTATE (no groups or no
  * reservation), MOREA_ERANGE (n_evals or rows beyond the reservation),
  * MOREA_EINVAL, MOREA_EDEVICE. */
 morea_status morea_eval_partial(morea_problem *p, const float *parent_pts, int32_t n_parents,
@@ -172,6 +180,23 @@ morea_status morea_eval_partial(morea_problem *p, const float *parent_pts, int32
  * verification of the set-up (App. A.3).  Errors: MOREA_EINVAL, MOREA_EDEVICE. */
 morea_status morea_debug_distance_map(morea_problem *p, int32_t image, int32_t set, float *host_out,
                                       uint8_t *band_out);
+
+/* Autotuner of the persistent partial-evaluation launch: with the same
+ * arguments as morea_eval_partial, times every launch shape (persistent
+ * blocks per compute unit up to the occupancy limit x work items taken per
+ * queue pop in {1, 2, 4}) on the given inputs with HIP events and keeps the
+ * fastest for later morea_eval_partial calls.  Synchronous; overwrites the
+ * output arrays.  *best_ms (may be NULL) receives the best time.  Errors as
+ * morea_eval_partial. */
+morea_status morea_tune_partial(morea_problem *p, const float *parent_pts, int32_t n_parents,
+                                const void *parent_cache, int32_t n_evals,
+                                const int32_t *eval_parent, const int32_t *eval_group,
+                                const float *new_coords, float *obj, uint8_t *flags,
+                                float *severity, uint32_t *counts, void *stream, float *best_ms);
+
+/* Current persistent launch shape of partial evaluation (blocks of 256
+ * threads, items per queue pop).  Errors: MOREA_EINVAL. */
+morea_status morea_partial_shape(const morea_problem *p, int32_t *blocks, int32_t *chunk);
 
 /* Message for the last non-OK status returned on the calling thread. */
 const char *morea_last_error(void);

@@ -22,7 +22,8 @@ STORE = {"f32": 0, "bf16": 1, "f16": 2}
 
 EXPORTS = ["morea_problem_create", "morea_problem_destroy", "morea_cache_bytes", "morea_eval_full",
            "morea_set_groups", "morea_reserve_partial", "morea_eval_partial",
-           "morea_debug_distance_map", "morea_last_error"]
+           "morea_debug_distance_map", "morea_tune_partial", "morea_partial_shape",
+           "morea_last_error"]
 
 
 class MoreaError(RuntimeError):
@@ -70,6 +71,10 @@ def load_library():
     L.morea_reserve_partial.restype = I32
     L.morea_eval_partial.argtypes = [P, P, I32, P, I32, P, P, P, P, P, P, P, P]
     L.morea_eval_partial.restype = I32
+    L.morea_tune_partial.argtypes = [P, P, I32, P, I32, P, P, P, P, P, P, P, P, P]
+    L.morea_tune_partial.restype = I32
+    L.morea_partial_shape.argtypes = [P, P, P]
+    L.morea_partial_shape.restype = I32
     L.morea_debug_distance_map.argtypes = [P, I32, I32, P, P]
     L.morea_debug_distance_map.restype = I32
     L.morea_last_error.argtypes = []
@@ -138,6 +143,23 @@ def morea_eval_partial(handle, parent_pts, n_parents, parent_cache, n_evals, eva
         handle, _dev_ptr(parent_pts), n_parents, _dev_ptr(parent_cache), n_evals,
         _dev_ptr(eval_parent), _dev_ptr(eval_group), _dev_ptr(new_coords), _dev_ptr(obj),
         _dev_ptr(flags), _dev_ptr(severity), _dev_ptr(counts), _stream_ptr(stream)))
+
+
+def morea_tune_partial(handle, parent_pts, n_parents, parent_cache, n_evals, eval_parent, eval_group,
+                       new_coords, obj, flags, severity, counts, stream) -> float:
+    best = ctypes.c_float()
+    _check(load_library().morea_tune_partial(
+        handle, _dev_ptr(parent_pts), n_parents, _dev_ptr(parent_cache), n_evals,
+        _dev_ptr(eval_parent), _dev_ptr(eval_group), _dev_ptr(new_coords), _dev_ptr(obj),
+        _dev_ptr(flags), _dev_ptr(severity), _dev_ptr(counts), _stream_ptr(stream),
+        ctypes.byref(best)))
+    return best.value
+
+
+def morea_partial_shape(handle):
+    b, c = ctypes.c_int32(), ctypes.c_int32()
+    _check(load_library().morea_partial_shape(handle, ctypes.byref(b), ctypes.byref(c)))
+    return b.value, c.value
 
 
 def morea_debug_distance_map(handle, image: int, set_index: int, shape):
@@ -252,6 +274,15 @@ class Problem:
                            eval_parent, eval_group, new_coords, out["obj"], out["flags"],
                            out["severity"], out["counts"], stream)
         return out
+
+    def tune_partial(self, parent_pts, parent_cache, eval_parent, eval_group, new_coords, out=None,
+                     stream=None):
+        n = eval_parent.shape[0]
+        out = self.outputs(n) if out is None else out
+        ms = morea_tune_partial(self.handle, parent_pts, parent_pts.shape[0], parent_cache, n,
+                                eval_parent, eval_group, new_coords, out["obj"], out["flags"],
+                                out["severity"], out["counts"], stream)
+        return ms, morea_partial_shape(self.handle)
 
     def distance_map(self, image, set_index):
         return morea_debug_distance_map(self.handle, image, set_index, self.dims[::-1])

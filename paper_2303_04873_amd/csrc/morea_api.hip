@@ -158,6 +158,7 @@ morea_status morea_problem_create(const morea_problem_desc* d, morea_problem** o
   p->storage = d->storage;
   p->max_population = d->max_population;
   p->voxels = V;
+  p->tets_host.assign(d->tets, d->tets + 4 * static_cast<size_t>(d->n_tets));
   ProblemView& P = p->view;
   P.nx = nx;
   P.ny = ny;
@@ -178,12 +179,19 @@ morea_status morea_problem_create(const morea_problem_desc* d, morea_problem** o
   for (int m = 0; m < 2 && st == MOREA_OK; m++) {
     const float* img = m == 0 ? d->image_src : d->image_tgt;
     void* dst = nullptr;
+    // kImagePad zero elements before and after the voxels: the paired corner
+    // loads of the evaluator read one element past either end of a row
     if (d->storage == kF32) {
-      guard(upload(p, &dst, img, V * sizeof(float)));
+      std::vector<float> q(V + 2 * kImagePad, 0.f);
+      memcpy(q.data() + kImagePad, img, V * sizeof(float));
+      guard(upload(p, &dst, q.data(), q.size() * sizeof(float)));
+      if (dst) dst = static_cast<float*>(dst) + kImagePad;
     } else {
-      std::vector<uint16_t> q(V);
-      for (size_t i = 0; i < V; i++) q[i] = d->storage == kBF16 ? to_bf16(img[i]) : to_f16(img[i]);
-      guard(upload(p, &dst, q.data(), V * sizeof(uint16_t)));
+      std::vector<uint16_t> q(V + 2 * kImagePad, 0);
+      for (size_t i = 0; i < V; i++)
+        q[kImagePad + i] = d->storage == kBF16 ? to_bf16(img[i]) : to_f16(img[i]);
+      guard(upload(p, &dst, q.data(), q.size() * sizeof(uint16_t)));
+      if (dst) dst = static_cast<uint16_t*>(dst) + kImagePad;
     }
     P.img[m] = dst;
   }
@@ -240,6 +248,10 @@ morea_status morea_problem_create(const morea_problem_desc* d, morea_problem** o
 void morea_problem_destroy(morea_problem* p) {
   if (!p) return;
   (void)hipDeviceSynchronize();
+  if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+  if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
+  for (void* a : p->partial_allocs) (void)hipFree(a);
+  for (void* a : p->group_allocs) (void)hipFree(a);
   free_all(p);
   delete p;
 }
@@ -289,17 +301,185 @@ morea_status morea_debug_distance_map(morea_problem* p, int32_t image, int32_t s
 
 }  // extern "C"
 
+namespace {
+
+void free_list(std::vector<void*>& v) {
+  for (void* a : v) (void)hipFree(a);
+  v.clear();
+}
+
+template <typename T>
+morea_status upload_to(std::vector<void*>& list, T** dst, const void* src, size_t bytes) {
+  void* d = nullptr;
+  hipError_t e = hipMalloc(&d, bytes ? bytes : 4);
+  if (e != hipSuccess) return fail(MOREA_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+  list.push_back(d);
+  if (src && bytes) {
+    e = hipMemcpy(d, src, bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+  }
+  *dst = static_cast<T*>(d);
+  return MOREA_OK;
+}
+
+void drop_graph(morea_problem* p) {
+  if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+  p->graph_exec = nullptr;
+}
+
+void drop_partial(morea_problem* p) {
+  drop_graph(p);
+  (void)hipDeviceSynchronize();
+  free_list(p->partial_allocs);
+  p->max_evals = 0;
+  p->d_row_off = p->d_item_off = p->d_queue = nullptr;
+  p->d_partial_records = nullptr;
+}
+
+}  // namespace
+
 extern "C" {
 
 morea_status morea_set_groups(morea_problem* p, int32_t n_groups, const int32_t* grp_off,
                               const int32_t* grp_pts) {
-  (void)p; (void)n_groups; (void)grp_off; (void)grp_pts;
-  return fail(MOREA_ESTATE, "partial evaluation is not available in this build");
+  if (!p) return fail(MOREA_EINVAL, "problem is NULL");
+  if (n_groups < 1 || !grp_off || !grp_pts) return fail(MOREA_EINVAL, "need n_groups >= 1 and CSR arrays");
+  const int NP = p->view.n_points, NT = p->view.n_tets;
+  if (grp_off[0] != 0) return fail(MOREA_EINVAL, "grp_off[0] must be 0");
+  for (int g = 0; g < n_groups; g++)
+    if (grp_off[g + 1] <= grp_off[g]) return fail(MOREA_EINVAL, "group %d is empty", g);
+  // point -> incident tets
+  std::vector<int> inc_off(NP + 1, 0), inc;
+  for (int t = 0; t < NT; t++)
+    for (int i = 0; i < 4; i++) inc_off[p->tets_host[4 * t + i] + 1]++;
+  for (int v = 0; v < NP; v++) inc_off[v + 1] += inc_off[v];
+  inc.resize(inc_off[NP]);
+  {
+    std::vector<int> fill(inc_off.begin(), inc_off.end() - 1);
+    for (int t = 0; t < NT; t++)
+      for (int i = 0; i < 4; i++) {
+        const int v = p->tets_host[4 * t + i];
+        inc[fill[v]++] = t;
+      }
+  }
+  std::vector<int> pos(NP, -1), tet_mark(NT, -1), dep_off(1, 0), dep_tet;
+  std::vector<int8_t> dep_local;
+  int max_dep = 0, max_group = 0;
+  for (int g = 0; g < n_groups; g++) {
+    const int b = grp_off[g], e = grp_off[g + 1];
+    if (e - b > 127) return fail(MOREA_EINVAL, "group %d has %d points (at most 127)", g, e - b);
+    max_group = std::max(max_group, e - b);
+    std::vector<int> tl;
+    for (int k = b; k < e; k++) {
+      const int v = grp_pts[k];
+      if (v < 0 || v >= NP) return fail(MOREA_EINVAL, "group %d point %d out of range", g, v);
+      if (pos[v] >= 0) return fail(MOREA_EINVAL, "group %d repeats point %d", g, v);
+      pos[v] = k - b;
+      for (int q = inc_off[v]; q < inc_off[v + 1]; q++)
+        if (tet_mark[inc[q]] != g) {
+          tet_mark[inc[q]] = g;
+          tl.push_back(inc[q]);
+        }
+    }
+    std::sort(tl.begin(), tl.end());
+    for (int t : tl) {
+      dep_tet.push_back(t);
+      for (int i = 0; i < 4; i++) dep_local.push_back(static_cast<int8_t>(pos[p->tets_host[4 * t + i]]));
+    }
+    for (int k = b; k < e; k++) pos[grp_pts[k]] = -1;
+    dep_off.push_back(static_cast<int>(dep_tet.size()));
+    max_dep = std::max(max_dep, static_cast<int>(tl.size()));
+  }
+  drop_partial(p);
+  free_list(p->group_allocs);
+  morea_status st = upload_to(p->group_allocs, &p->d_grp_off, grp_off, sizeof(int) * (n_groups + 1));
+  if (st == MOREA_OK)
+    st = upload_to(p->group_allocs, &p->d_grp_pts, grp_pts, sizeof(int) * grp_off[n_groups]);
+  if (st == MOREA_OK) st = upload_to(p->group_allocs, &p->d_dep_off, dep_off.data(), sizeof(int) * dep_off.size());
+  if (st == MOREA_OK) st = upload_to(p->group_allocs, &p->d_dep_tet, dep_tet.data(), sizeof(int) * dep_tet.size());
+  if (st == MOREA_OK) st = upload_to(p->group_allocs, &p->d_dep_local, dep_local.data(), dep_local.size());
+  if (st != MOREA_OK) {
+    free_list(p->group_allocs);
+    p->n_groups = 0;
+    return st;
+  }
+  p->n_groups = n_groups;
+  p->max_dep = max_dep;
+  p->max_group = max_group;
+  return MOREA_OK;
 }
 
 morea_status morea_reserve_partial(morea_problem* p, int32_t max_evals) {
-  (void)p; (void)max_evals;
-  return fail(MOREA_ESTATE, "partial evaluation is not available in this build");
+  if (!p) return fail(MOREA_EINVAL, "problem is NULL");
+  if (p->n_groups == 0) return fail(MOREA_ESTATE, "call morea_set_groups first");
+  if (max_evals < 1) return fail(MOREA_EINVAL, "max_evals must be >= 1");
+  drop_partial(p);
+  morea_status st = upload_to(p->partial_allocs, &p->d_row_off, nullptr, sizeof(int) * max_evals);
+  if (st == MOREA_OK) st = upload_to(p->partial_allocs, &p->d_item_off, nullptr, sizeof(int) * (max_evals + 1));
+  if (st == MOREA_OK) st = upload_to(p->partial_allocs, &p->d_queue, nullptr, sizeof(int) * 64);
+  if (st == MOREA_OK)
+    st = upload_to(p->partial_allocs, &p->d_partial_records, nullptr,
+                   sizeof(Record) * 2 * static_cast<size_t>(max_evals) * p->max_dep);
+  if (st != MOREA_OK) {
+    free_list(p->partial_allocs);
+    return st;
+  }
+  if (!p->capture_stream) {
+    hipError_t e = hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+  }
+  if (p->partial_blocks == 0) {
+    int cus = 0, per_cu = 0;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
+    per_cu = partial_blocks_per_cu(p->storage);
+    p->partial_blocks = std::max(1, cus) * std::max(1, per_cu);
+    p->partial_chunk = 1;
+  }
+  p->max_evals = max_evals;
+  return MOREA_OK;
+}
+
+static morea_status partial_args(morea_problem* p, const float* parent_pts, int32_t n_parents,
+                                 const void* parent_cache, int32_t n_evals,
+                                 const int32_t* eval_parent, const int32_t* eval_group,
+                                 const float* new_coords, float* obj, uint8_t* flags,
+                                 float* severity, uint32_t* counts) {
+  if (!p) return fail(MOREA_EINVAL, "problem is NULL");
+  if (p->n_groups == 0) return fail(MOREA_ESTATE, "call morea_set_groups first");
+  if (p->max_evals == 0) return fail(MOREA_ESTATE, "call morea_reserve_partial first");
+  if (n_evals < 0 || n_parents < 1) return fail(MOREA_EINVAL, "bad n_evals / n_parents");
+  if (n_evals > p->max_evals) return fail(MOREA_ERANGE, "n_evals %d > reserved %d", n_evals, p->max_evals);
+  if (n_evals > 0 && (!parent_pts || !parent_cache || !eval_parent || !eval_group || !new_coords ||
+                      !obj || !flags || !severity || !counts))
+    return fail(MOREA_EINVAL, "NULL argument");
+  return MOREA_OK;
+}
+
+static hipError_t partial_launch(morea_problem* p, const float* parent_pts, int32_t n_parents,
+                                 const void* parent_cache, int32_t n_evals,
+                                 const int32_t* eval_parent, const int32_t* eval_group,
+                                 const float* new_coords, float* obj, uint8_t* flags,
+                                 float* severity, uint32_t* counts, int blocks, int chunk,
+                                 hipStream_t s) {
+  PartialItems I;
+  I.parent_pts = parent_pts;
+  I.eval_parent = eval_parent;
+  I.eval_group = eval_group;
+  I.new_coords = new_coords;
+  I.row_off = p->d_row_off;
+  I.item_off = p->d_item_off;
+  I.grp_off = p->d_grp_off;
+  I.grp_pts = p->d_grp_pts;
+  I.dep_off = p->d_dep_off;
+  I.dep_tet = p->d_dep_tet;
+  I.dep_local = p->d_dep_local;
+  I.n_evals = n_evals;
+  const Record* prec = static_cast<const Record*>(parent_cache);
+  const Totals* ptot = reinterpret_cast<const Totals*>(
+      static_cast<const char*>(parent_cache) + static_cast<size_t>(n_parents) * p->view.n_tets * 2 * sizeof(Record));
+  return launch_partial(p->view, p->storage, I, n_parents, p->n_groups, prec, ptot,
+                        p->d_partial_records, p->d_queue, blocks, chunk, obj, flags, severity,
+                        counts, s);
 }
 
 morea_status morea_eval_partial(morea_problem* p, const float* parent_pts, int32_t n_parents,
@@ -307,9 +487,109 @@ morea_status morea_eval_partial(morea_problem* p, const float* parent_pts, int32
                                 const int32_t* eval_parent, const int32_t* eval_group,
                                 const float* new_coords, float* obj, uint8_t* flags,
                                 float* severity, uint32_t* counts, void* stream) {
-  (void)p; (void)parent_pts; (void)n_parents; (void)parent_cache; (void)n_evals; (void)eval_parent;
-  (void)eval_group; (void)new_coords; (void)obj; (void)flags; (void)severity; (void)counts; (void)stream;
-  return fail(MOREA_ESTATE, "partial evaluation is not available in this build");
+  morea_status st = partial_args(p, parent_pts, n_parents, parent_cache, n_evals, eval_parent,
+                                 eval_group, new_coords, obj, flags, severity, counts);
+  if (st != MOREA_OK) return st;
+  if (n_evals == 0) return MOREA_OK;
+  st = check_pending();
+  if (st != MOREA_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const void* key[9] = {parent_pts, parent_cache, eval_parent, eval_group, new_coords, obj, flags,
+                        severity, counts};
+  const int key_n[4] = {n_parents, n_evals, p->partial_blocks, p->partial_chunk};
+  const bool same = p->graph_exec && memcmp(key, p->graph_key, sizeof(key)) == 0 &&
+                    memcmp(key_n, p->graph_key_n, sizeof(key_n)) == 0;
+  if (!same) {
+    drop_graph(p);
+    hipError_t e = hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    hipError_t le = partial_launch(p, parent_pts, n_parents, parent_cache, n_evals, eval_parent,
+                                   eval_group, new_coords, obj, flags, severity, counts,
+                                   p->partial_blocks, p->partial_chunk, p->capture_stream);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(p->capture_stream, &g);
+    if (le != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return hip_fail(le, "partial kernels");
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&p->graph_exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      p->graph_exec = nullptr;
+      return hip_fail(e, "hipGraphInstantiate");
+    }
+    memcpy(p->graph_key, key, sizeof(key));
+    memcpy(p->graph_key_n, key_n, sizeof(key_n));
+  }
+  hipError_t e = hipGraphLaunch(p->graph_exec, s);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  return MOREA_OK;
+}
+
+morea_status morea_tune_partial(morea_problem* p, const float* parent_pts, int32_t n_parents,
+                                const void* parent_cache, int32_t n_evals,
+                                const int32_t* eval_parent, const int32_t* eval_group,
+                                const float* new_coords, float* obj, uint8_t* flags,
+                                float* severity, uint32_t* counts, void* stream,
+                                float* best_ms) {
+  morea_status st = partial_args(p, parent_pts, n_parents, parent_cache, n_evals, eval_parent,
+                                 eval_group, new_coords, obj, flags, severity, counts);
+  if (st != MOREA_OK) return st;
+  if (n_evals == 0) return MOREA_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int cus = 0, per_cu = 0;
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
+  per_cu = partial_blocks_per_cu(p->storage);
+  cus = std::max(cus, 1);
+  per_cu = std::max(per_cu, 1);
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+    return fail(MOREA_EDEVICE, "hipEventCreate");
+  float best = 1e30f;
+  int best_blocks = p->partial_blocks, best_chunk = p->partial_chunk;
+  const int chunks[3] = {1, 2, 4};
+  for (int bpc = 1; bpc <= per_cu; bpc++)
+    for (int c = 0; c < 3; c++) {
+      const int blocks = bpc * cus, chunk = chunks[c];
+      float total = 0.f;
+      hipError_t e = hipSuccess;
+      for (int rep = 0; rep < 3 && e == hipSuccess; rep++) {
+        e = hipEventRecord(a, s);
+        if (e == hipSuccess)
+          e = partial_launch(p, parent_pts, n_parents, parent_cache, n_evals, eval_parent, eval_group,
+                             new_coords, obj, flags, severity, counts, blocks, chunk, s);
+        if (e == hipSuccess) e = hipEventRecord(b, s);
+        if (e == hipSuccess) e = hipEventSynchronize(b);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+        if (rep > 0) total += ms;   // first repetition is a warm-up
+      }
+      if (e != hipSuccess) {
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        return hip_fail(e, "tuning run");
+      }
+      if (total < best) {
+        best = total;
+        best_blocks = blocks;
+        best_chunk = chunk;
+      }
+    }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  p->partial_blocks = best_blocks;
+  p->partial_chunk = best_chunk;
+  drop_graph(p);
+  if (best_ms) *best_ms = best / 2.0f;
+  return MOREA_OK;
+}
+
+morea_status morea_partial_shape(const morea_problem* p, int32_t* blocks, int32_t* chunk) {
+  if (!p || !blocks || !chunk) return fail(MOREA_EINVAL, "NULL argument");
+  *blocks = p->partial_blocks;
+  *chunk = p->partial_chunk;
+  return MOREA_OK;
 }
 
 }  // extern "C"

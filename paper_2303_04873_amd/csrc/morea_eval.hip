@@ -81,6 +81,11 @@ __device__ __forceinline__ int64_t floor_div_pos(int64_t a, int64_t b) {  // b >
   return (q * b > a) ? q - 1 : q;
 }
 
+// Two consecutive floats read by one 8-byte load at 4-byte alignment.
+struct __attribute__((aligned(4))) F2 {
+  float a, b;
+};
+
 // Compensated (double-float) accumulation: value = hi + lo.
 __device__ __forceinline__ void df_add(float& hi, float& lo, float x) {
   float s = hi + x;
@@ -98,8 +103,23 @@ __device__ __forceinline__ int64_t det_i64(const int v[4][3]) {
   return a0 * (b1 * c2 - b2 * c1) - a1 * (b0 * c2 - b2 * c0) + a2 * (b0 * c1 - b1 * c0);
 }
 
+// Per-item constants, written once per work item into the wave's LDS and
+// read back (broadcast) by the row and sample loops.  Face plane i evaluated
+// at voxel (lo0 + j, lo1 + yr, lo2 + zr), plus its tie-break bit lex_i, is
+//   s_i + lex_i = A_i j + PY_i yr + PZ_i zr + B0_i      (exact integers)
+// and the mapped point is q = qlo + M (p - lo).
+struct ItemConst {
+  double A[4], invA[4], PY[4], PZ[4], B0[4];   // exact in FP64 when the extent is <= 2^16
+  long long Ai[4], PYi[4], PZi[4], B0i[4];     // int64 copies for wider tets
+  int kind[4];                                 // sign of A_i
+  double M[3][3];
+  double qlo[3];
+  double guard[3];                             // FP64 error bound of q per axis (x1000 margin)
+};
+
 // LDS scratch of one wave.
 struct WaveLds {
+  ItemConst c;
   int row_x0[kWave];
   int row_yz[kWave];
   int row_off[kWave];
@@ -108,7 +128,7 @@ struct WaveLds {
 };
 
 // Exact support test of the trilinear stencil (rare path, taken only when
-// the FP32 mapped coordinate is within its error bound of an integer on some
+// the mapped coordinate is within its error bound of an integer on some
 // axis).  Recomputes D * lambda_i(p) exactly, forms the mapped coordinate as
 // the rational N / (|D| 2^10) in 128-bit integers and finds its exact floor
 // k: if N / (|D| 2^10) == k only corner k carries weight on that axis,
@@ -117,7 +137,7 @@ struct WaveLds {
 template <int ST>
 __device__ __noinline__ bool exact_foreground(const void* img, int nx, int ny, int nz,
                                               const int* vert, int sigma, int64_t absD, int x,
-                                              int y, int z, float q0, float q1, float q2,
+                                              int y, int z, double q0, double q1, double q2,
                                               int amb) {
   int own[4][3], oth[4][3];
   for (int i = 0; i < 4; i++)
@@ -134,16 +154,16 @@ __device__ __noinline__ bool exact_foreground(const void* img, int nx, int ny, i
     s[i] = sigma * det_i64(w);
   }
   const __int128 den = static_cast<__int128>(absD) * 1024;
-  const float q[3] = {q0, q1, q2};
+  const double q[3] = {q0, q1, q2};
   int lo[3], hi[3];
   for (int a = 0; a < 3; a++) {
     if (amb & (1 << a)) {
       __int128 num = 0;
       for (int i = 0; i < 4; i++) num += static_cast<__int128>(s[i]) * oth[i][a];
-      // exact floor k of num / den, starting from the FP32 estimate; the
+      // exact floor k of num / den, starting from the FP64 estimate; the
       // mapped point is a convex combination of valid vertices, so
       // |k| <= 513 and the corrections terminate.
-      int k = static_cast<int>(floorf(q[a]));
+      int k = static_cast<int>(floor(q[a]));
       k = min(max(k, -600), 600);
       while (static_cast<__int128>(k) * den > num) k--;
       while (static_cast<__int128>(k + 1) * den <= num) k++;
@@ -151,7 +171,7 @@ __device__ __noinline__ bool exact_foreground(const void* img, int nx, int ny, i
       lo[a] = k;
       hi[a] = on_grid ? k : k + 1;
     } else {
-      lo[a] = static_cast<int>(floorf(q[a]));
+      lo[a] = static_cast<int>(floor(q[a]));
       hi[a] = lo[a] + 1;
     }
   }
@@ -164,45 +184,49 @@ __device__ __noinline__ bool exact_foreground(const void* img, int nx, int ny, i
   return fg;
 }
 
-// Exact x-interval [js, je] (relative to the row start x0, clipped to
-// [0, W]) of one row for one face: the set of j with a*j + b + lex > 0.
-// T is double (exact for extents <= 2^16) or int64_t.
+// x-interval [js, je] (relative to the bounding-box start, clipped to
+// [0, W]) of one row: the j with A_i j + b_i > 0 for every face.  The FP64
+// quotient estimate is corrected by one exact evaluation on each side; T is
+// double (exact for extents <= 2^16) or int64.
 template <typename T>
-__device__ __forceinline__ void clip_face(T a, T bl, int W, int& js, int& je) {
-  if (a > 0) {
-    double t = -static_cast<double>(bl) / static_cast<double>(a);
-    t = fmin(fmax(t, -2.0), W + 1.0);
+__device__ __forceinline__ void clip_face(int kind, T A, double invA, T b, int W, int& js, int& je) {
+  if (kind > 0) {
+    const double t = fmin(fmax(-static_cast<double>(b) * invA, -2.0), W + 1.0);
     int j = static_cast<int>(floor(t)) + 1;
-    if (a * static_cast<T>(j - 1) + bl > 0) j -= 1;
-    if (a * static_cast<T>(j) + bl <= 0) j += 1;
+    if (A * static_cast<T>(j) + b <= 0) j += 1;
+    else if (A * static_cast<T>(j - 1) + b > 0) j -= 1;
     js = max(js, j);
-  } else if (a < 0) {
-    double t = static_cast<double>(bl) / -static_cast<double>(a);
-    t = fmin(fmax(t, -2.0), W + 1.0);
+  } else if (kind < 0) {
+    const double t = fmin(fmax(-static_cast<double>(b) * invA, -2.0), W + 1.0);
     int j = static_cast<int>(ceil(t)) - 1;
-    if (a * static_cast<T>(j + 1) + bl > 0) j += 1;
-    if (a * static_cast<T>(j) + bl <= 0) j -= 1;
+    if (A * static_cast<T>(j) + b <= 0) j -= 1;
+    else if (A * static_cast<T>(j + 1) + b > 0) j += 1;
     je = min(je, j);
-  } else if (!(bl > 0)) {
+  } else if (!(b > 0)) {
     je = -1;
   }
 }
 
-struct Planes {
-  // s_i(x0 + j, y, z) = A[i] * j + Cx[i] + NY[i] * (1024 y - RY[i]) + NZ[i] * (1024 z - RZ[i])
-  int64_t A[4], Cx[4], NY[4], NZ[4], RY[4], RZ[4];
-  int lex[4];
-};
+__device__ __forceinline__ void span_fast(const ItemConst& c, int yr, int zr, int W, int& js, int& je) {
+  js = 0;
+  je = W;
+  const double y = yr, z = zr;
+#pragma unroll
+  for (int i = 0; i < 4; i++) {
+    const int kind = __builtin_amdgcn_readfirstlane(c.kind[i]);
+    const double b = fma(c.PY[i], y, fma(c.PZ[i], z, c.B0[i]));
+    clip_face<double>(kind, c.A[i], c.invA[i], b, W, js, je);
+  }
+}
 
-template <typename T>
-__device__ __forceinline__ void row_span(const Planes& pl, int y, int z, int W, int& js, int& je) {
+__device__ __forceinline__ void span_wide(const ItemConst& c, int yr, int zr, int W, int& js, int& je) {
   js = 0;
   je = W;
 #pragma unroll
   for (int i = 0; i < 4; i++) {
-    T b = static_cast<T>(pl.Cx[i]) + static_cast<T>(pl.NY[i]) * static_cast<T>(1024 * (int64_t)y - pl.RY[i]) +
-          static_cast<T>(pl.NZ[i]) * static_cast<T>(1024 * (int64_t)z - pl.RZ[i]) + static_cast<T>(pl.lex[i]);
-    clip_face<T>(static_cast<T>(pl.A[i]), b, W, js, je);
+    const int kind = __builtin_amdgcn_readfirstlane(c.kind[i]);
+    const long long b = c.PYi[i] * yr + c.PZi[i] * zr + c.B0i[i];
+    clip_face<long long>(kind, c.Ai[i], c.invA[i], b, W, js, je);
   }
 }
 
@@ -222,14 +246,12 @@ __device__ void eval_tet_dir(const ProblemView& P, int tet, int dir, float coord
     return;
   }
   if (lane < 24) L->vert[lane] = fix;
-  int own[4][3], oth[4][3];
+  int own[4][3];
 #pragma unroll
   for (int i = 0; i < 4; i++)
 #pragma unroll
-    for (int k = 0; k < 3; k++) {
-      own[i][k] = __builtin_amdgcn_readlane(fix, 3 * i + k);
-      oth[i][k] = __builtin_amdgcn_readlane(fix, 12 + 3 * i + k);
-    }
+    for (int k = 0; k < 3; k++) own[i][k] = __builtin_amdgcn_readlane(fix, 3 * i + k);
+  wave_sync();
 
   // ---- fold check (App. A.4): exact signed volume vs the reference sign
   const int64_t D = det_i64(own);
@@ -240,41 +262,47 @@ __device__ void eval_tet_dir(const ProblemView& P, int tet, int dir, float coord
   Record rec{0.f, 0.f, 0u, 0.f, 0.f, viol ? 1u : 0u};
   if (viol) rec.vol = static_cast<float>(static_cast<double>(absD) * (1.0 / (6.0 * 1073741824.0)));
 
-  // ---- deformation magnitude (Sec. 4.1.1), computed once, by direction 0:
-  // |e_s| - |e_t| = (|e_s|^2 - |e_t|^2) / (|e_s| + |e_t|) with the squared
-  // lengths exact in int64, so small differences do not cancel.
+  // ---- deformation magnitude (Sec. 4.1.1), by direction 0, one edge per
+  // lane: |e_s| - |e_t| = (|e_s|^2 - |e_t|^2) / (|e_s| + |e_t|) with the
+  // squared lengths exact in int64, so small differences do not cancel.
   if (dir == 0) {
-    float acc = 0.f;
-#pragma unroll
-    for (int i = 0; i < 4; i++)
-#pragma unroll
-      for (int j = i + 1; j < 4; j++) {
-        int64_t ls = 0, lt = 0;
+    float term = 0.f;
+    if (lane < 10) {
+      int64_t ls = 0, lt = 0;
+      float scale;
+      if (lane < 6) {
+        const int i = lane < 3 ? 0 : (lane < 5 ? 1 : 2);
+        const int j = lane < 3 ? lane + 1 : (lane < 5 ? lane - 1 : 3);
 #pragma unroll
         for (int k = 0; k < 3; k++) {
-          int64_t ds = own[i][k] - own[j][k], dt = oth[i][k] - oth[j][k];
+          const int64_t ds = L->vert[3 * i + k] - L->vert[3 * j + k];
+          const int64_t dt = L->vert[12 + 3 * i + k] - L->vert[12 + 3 * j + k];
           ls += ds * ds;
           lt += dt * dt;
         }
-        float den = sqrtf(static_cast<float>(ls)) + sqrtf(static_cast<float>(lt));
-        float d = den > 0.f ? static_cast<float>(ls - lt) / den * (1.0f / kFixOne) : 0.f;
-        acc += d * d;
-      }
+        scale = 1.0f / kFixOne;
+      } else {
+        const int v = lane - 6;
 #pragma unroll
-    for (int i = 0; i < 4; i++) {
-      int64_t ls = 0, lt = 0;
+        for (int k = 0; k < 3; k++) {
+          int64_t ss = 0, st = 0;
 #pragma unroll
-      for (int k = 0; k < 3; k++) {
-        int64_t ds = 4 * (int64_t)own[i][k] - (own[0][k] + own[1][k] + own[2][k] + own[3][k]);
-        int64_t dt = 4 * (int64_t)oth[i][k] - (oth[0][k] + oth[1][k] + oth[2][k] + oth[3][k]);
-        ls += ds * ds;
-        lt += dt * dt;
+          for (int w = 0; w < 4; w++) {
+            ss += L->vert[3 * w + k];
+            st += L->vert[12 + 3 * w + k];
+          }
+          const int64_t ds = 4 * static_cast<int64_t>(L->vert[3 * v + k]) - ss;
+          const int64_t dt = 4 * static_cast<int64_t>(L->vert[12 + 3 * v + k]) - st;
+          ls += ds * ds;
+          lt += dt * dt;
+        }
+        scale = 1.0f / (4.0f * kFixOne);
       }
-      float den = sqrtf(static_cast<float>(ls)) + sqrtf(static_cast<float>(lt));
-      float d = den > 0.f ? static_cast<float>(ls - lt) / den * (1.0f / (4.0f * kFixOne)) : 0.f;
-      acc += d * d;
+      const float den = sqrtf(static_cast<float>(ls)) + sqrtf(static_cast<float>(lt));
+      const float d = den > 0.f ? static_cast<float>(ls - lt) / den * scale : 0.f;
+      term = d * d;
     }
-    rec.mag = P.elasticity[tet] * acc;
+    rec.mag = P.elasticity[tet] * wave_sum(term);
   }
 
   // ---- bounding box on this direction's grid
@@ -282,8 +310,8 @@ __device__ void eval_tet_dir(const ProblemView& P, int tet, int dir, float coord
   const int dims[3] = {P.nx, P.ny, P.nz};
 #pragma unroll
   for (int k = 0; k < 3; k++) {
-    int mn = min(min(own[0][k], own[1][k]), min(own[2][k], own[3][k]));
-    int mx = max(max(own[0][k], own[1][k]), max(own[2][k], own[3][k]));
+    const int mn = min(min(own[0][k], own[1][k]), min(own[2][k], own[3][k]));
+    const int mx = max(max(own[0][k], own[1][k]), max(own[2][k], own[3][k]));
     ext = max(ext, mx - mn);
     lo[k] = max(0, -static_cast<int>(floor_div_pos(-static_cast<int64_t>(mn), 1024)));
     hi[k] = min(dims[k] - 1, static_cast<int>(floor_div_pos(mx, 1024)));
@@ -295,114 +323,114 @@ __device__ void eval_tet_dir(const ProblemView& P, int tet, int dir, float coord
   }
   const int sigma = D > 0 ? 1 : -1;
 
-  // ---- face planes: gradient n_i of D * lambda_i (inward after sigma) and a
-  // reference vertex r_i on the face.
-  Planes pl;
-  {
+  // ---- per-item constants, spread over lanes: lanes 0..3 build face plane
+  // i (the gradient of D * lambda_i, oriented inwards, and its value at the
+  // box corner), lanes 8..10 build row a of the map and its error bound.
+  ItemConst& C = L->c;
+  if (lane < 4) {
+    const int i = lane;
+    const int b0 = i == 0 ? 1 : 0;                            // base vertex on the face
+    const int u0 = i == 0 ? 2 : (i == 1 ? 2 : (i == 2 ? 3 : 1));
+    const int w0 = i == 0 ? 3 : (i == 1 ? 3 : (i == 2 ? 1 : 2));
+    int64_t u[3], w[3], r[3];
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+      r[k] = L->vert[3 * b0 + k];
+      u[k] = L->vert[3 * u0 + k] - r[k];
+      w[k] = L->vert[3 * w0 + k] - r[k];
+    }
+    const int64_t sg = (i == 0 ? -sigma : sigma);
+    const int64_t nx_ = sg * (u[1] * w[2] - u[2] * w[1]);
+    const int64_t ny_ = sg * (u[2] * w[0] - u[0] * w[2]);
+    const int64_t nz_ = sg * (u[0] * w[1] - u[1] * w[0]);
+    const int lex = (nx_ > 0 || (nx_ == 0 && (ny_ > 0 || (ny_ == 0 && nz_ > 0)))) ? 1 : 0;
+    const int64_t B0 = nx_ * (1024 * static_cast<int64_t>(lo[0]) - r[0]) +
+                       ny_ * (1024 * static_cast<int64_t>(lo[1]) - r[1]) +
+                       nz_ * (1024 * static_cast<int64_t>(lo[2]) - r[2]) + lex;
+    C.Ai[i] = nx_ * 1024;
+    C.PYi[i] = ny_ * 1024;
+    C.PZi[i] = nz_ * 1024;
+    C.B0i[i] = B0;
+    C.A[i] = static_cast<double>(nx_ * 1024);
+    C.PY[i] = static_cast<double>(ny_ * 1024);
+    C.PZ[i] = static_cast<double>(nz_ * 1024);
+    C.B0[i] = static_cast<double>(B0);
+    C.invA[i] = nx_ != 0 ? 1.0 / static_cast<double>(nx_ * 1024) : 0.0;
+    C.kind[i] = (nx_ > 0) - (nx_ < 0);
+  } else if (lane >= 8 && lane < 11) {
+    const int a = lane - 8;
     int64_t e[3][3];
 #pragma unroll
     for (int i = 0; i < 3; i++)
 #pragma unroll
       for (int k = 0; k < 3; k++) e[i][k] = own[i + 1][k] - own[0][k];
-    int64_t n[4][3];
-    auto cross = [](const int64_t* u, const int64_t* v, int64_t* r) {
-      r[0] = u[1] * v[2] - u[2] * v[1];
-      r[1] = u[2] * v[0] - u[0] * v[2];
-      r[2] = u[0] * v[1] - u[1] * v[0];
-    };
-    cross(e[1], e[2], n[1]);
-    cross(e[2], e[0], n[2]);
-    cross(e[0], e[1], n[3]);
+    int64_t adj[3][3];
+    adj[0][0] = e[1][1] * e[2][2] - e[1][2] * e[2][1];
+    adj[0][1] = e[1][2] * e[2][0] - e[1][0] * e[2][2];
+    adj[0][2] = e[1][0] * e[2][1] - e[1][1] * e[2][0];
+    adj[1][0] = e[2][1] * e[0][2] - e[2][2] * e[0][1];
+    adj[1][1] = e[2][2] * e[0][0] - e[2][0] * e[0][2];
+    adj[1][2] = e[2][0] * e[0][1] - e[2][1] * e[0][0];
+    adj[2][0] = e[0][1] * e[1][2] - e[0][2] * e[1][1];
+    adj[2][1] = e[0][2] * e[1][0] - e[0][0] * e[1][2];
+    adj[2][2] = e[0][0] * e[1][1] - e[0][1] * e[1][0];
+    const double inv = 1.0 / static_cast<double>(D);
+    const double ainv = fabs(inv);
+    const double oth0 = L->vert[12 + a];
+    double q = oth0 * (1.0 / 1024.0);
+    double bound = fabs(q) + 1.0;
 #pragma unroll
-    for (int k = 0; k < 3; k++) n[0][k] = -(n[1][k] + n[2][k] + n[3][k]);
+    for (int cc = 0; cc < 3; cc++) {
+      double num = 0.0, mag = 0.0;
 #pragma unroll
-    for (int i = 0; i < 4; i++) {
-      const int rv = (i == 0) ? 1 : 0;
-      int64_t nx_ = sigma * n[i][0], ny_ = sigma * n[i][1], nz_ = sigma * n[i][2];
-      pl.A[i] = nx_ * 1024;
-      pl.Cx[i] = nx_ * (1024 * (int64_t)lo[0] - own[rv][0]);
-      pl.NY[i] = ny_;
-      pl.NZ[i] = nz_;
-      pl.RY[i] = own[rv][1];
-      pl.RZ[i] = own[rv][2];
-      pl.lex[i] = (nx_ > 0 || (nx_ == 0 && (ny_ > 0 || (ny_ == 0 && nz_ > 0)))) ? 1 : 0;
-    }
-  }
-
-  // ---- affine map of this direction: q = M (p - p_lo) + q_lo (FP32), with
-  // M = B adj(A) / D from the exact edge matrices, and a per-axis bound
-  // `guard` on the FP32 error of q.
-  float M[3][3], qlo[3], guard[3];
-  {
-    double inv = 1.0 / static_cast<double>(D);
-    // rows of adj(A) are n_1, n_2, n_3 (before sigma): recompute them here
-    int64_t e[3][3], b[3][3];
-#pragma unroll
-    for (int i = 0; i < 3; i++)
-#pragma unroll
-      for (int k = 0; k < 3; k++) {
-        e[i][k] = own[i + 1][k] - own[0][k];
-        b[i][k] = oth[i + 1][k] - oth[0][k];
+      for (int i = 0; i < 3; i++) {
+        const double bi = static_cast<double>(L->vert[12 + 3 * (i + 1) + a]) - oth0;
+        const double t = bi * static_cast<double>(adj[i][cc]);
+        num += t;
+        mag += fabs(t);
       }
-    double adj[3][3];
-    adj[0][0] = (double)(e[1][1] * e[2][2] - e[1][2] * e[2][1]);
-    adj[0][1] = (double)(e[1][2] * e[2][0] - e[1][0] * e[2][2]);
-    adj[0][2] = (double)(e[1][0] * e[2][1] - e[1][1] * e[2][0]);
-    adj[1][0] = (double)(e[2][1] * e[0][2] - e[2][2] * e[0][1]);
-    adj[1][1] = (double)(e[2][2] * e[0][0] - e[2][0] * e[0][2]);
-    adj[1][2] = (double)(e[2][0] * e[0][1] - e[2][1] * e[0][0]);
-    adj[2][0] = (double)(e[0][1] * e[1][2] - e[0][2] * e[1][1]);
-    adj[2][1] = (double)(e[0][2] * e[1][0] - e[0][0] * e[1][2]);
-    adj[2][2] = (double)(e[0][0] * e[1][1] - e[0][1] * e[1][0]);
-    double Md[3][3];
-#pragma unroll
-    for (int a = 0; a < 3; a++)
-#pragma unroll
-      for (int c = 0; c < 3; c++)
-        Md[a][c] = ((double)b[0][a] * adj[0][c] + (double)b[1][a] * adj[1][c] + (double)b[2][a] * adj[2][c]) * inv;
-    const double pl0[3] = {lo[0] - own[0][0] / 1024.0, lo[1] - own[0][1] / 1024.0, lo[2] - own[0][2] / 1024.0};
-#pragma unroll
-    for (int a = 0; a < 3; a++) {
-      double q = oth[0][a] / 1024.0 + Md[a][0] * pl0[0] + Md[a][1] * pl0[1] + Md[a][2] * pl0[2];
-      qlo[a] = static_cast<float>(q);
-      double bound = fabs(q) + 1.0;
-#pragma unroll
-      for (int c = 0; c < 3; c++) {
-        M[a][c] = static_cast<float>(Md[a][c]);
-        bound += fabs(Md[a][c]) * (hi[c] - lo[c]);
-      }
-      guard[a] = static_cast<float>(bound * (1.0 / 1048576.0));   // 2^-20 * bound >= 4x the error
+      const double m = num * inv;
+      const double off = lo[cc] - own[0][cc] * (1.0 / 1024.0);
+      C.M[a][cc] = m;
+      q += m * off;
+      bound += mag * ainv * (fabs(off) + (hi[cc] - lo[cc]));
     }
+    C.qlo[a] = q;
+    C.guard[a] = bound * 0x1p-40;
   }
+  wave_sync();
 
   const int W = hi[0] - lo[0];
   const int NYb = hi[1] - lo[1] + 1;
   const int R = NYb * (hi[2] - lo[2] + 1);
+  const float invNYb = 1.0f / static_cast<float>(NYb);
   const bool fast = ext <= kFastExtent;
   const void* img_own = P.img[dir];
   const void* img_oth = P.img[1 - dir];
   const uint8_t* band_own = P.band[dir];
   const float* map_own = P.dmap[dir];
   const float* map_oth = P.dmap[1 - dir];
-  const int V = P.nx * P.ny * P.nz;
+  const unsigned V = static_cast<unsigned>(P.nx * P.ny * P.nz);
   const float r = P.radius, inv_r = P.inv_radius;
   const bool guided = P.n_sets > 0;
+  const int nx = P.nx, ny = P.ny, nz = P.nz;
+  const unsigned sy = static_cast<unsigned>(nx), sz = static_cast<unsigned>(nx * ny);
 
   float h_acc = 0.f, g_acc = 0.f;
   int n_acc = 0;
-  wave_sync();   // vertex table visible to the exact path
 
   for (int rb = 0; rb < R; rb += kWave) {
     const int rr = rb + lane;
-    int js = 1, je = 0, y = 0, z = 0;
+    int js = 1, je = 0, yr = 0, zr = 0;
     if (rr < R) {
-      const int zr = rr / NYb;
-      z = lo[2] + zr;
-      y = lo[1] + (rr - zr * NYb);
+      zr = static_cast<int>(static_cast<float>(rr) * invNYb);
+      if (zr * NYb > rr) zr -= 1;
+      else if ((zr + 1) * NYb <= rr) zr += 1;
+      yr = rr - zr * NYb;
       if (fast)
-        row_span<double>(pl, y, z, W, js, je);
+        span_fast(L->c, yr, zr, W, js, je);
       else
-        row_span<int64_t>(pl, y, z, W, js, je);
+        span_wide(L->c, yr, zr, W, js, je);
     }
     const int len = max(0, je - js + 1);
     const uint64_t rows_mask = __ballot(len > 0);
@@ -413,7 +441,7 @@ __device__ void eval_tet_dir(const ProblemView& P, int tet, int dir, float coord
     if (len > 0) {
       const int ci = bits_below(rows_mask);
       L->row_x0[ci] = lo[0] + js;
-      L->row_yz[ci] = y | (z << 16);
+      L->row_yz[ci] = (lo[1] + yr) | ((lo[2] + zr) << 16);
       L->row_off[ci] = off;
     }
     wave_sync();
@@ -435,72 +463,85 @@ __device__ void eval_tet_dir(const ProblemView& P, int tet, int dir, float coord
         const int x = L->row_x0[ri] + (s - L->row_off[ri]);
         const int yz = L->row_yz[ri];
         const int yy = yz & 0xffff, zz = yz >> 16;
-        const int vi = (zz * P.ny + yy) * P.nx + x;
+        const unsigned vi = static_cast<unsigned>((zz * ny + yy) * nx + x);
         const float a = ld_img<ST>(img_own, vi);
-        const float dx = static_cast<float>(x - lo[0]);
-        const float dy = static_cast<float>(yy - lo[1]);
-        const float dz = static_cast<float>(zz - lo[2]);
-        float q[3], f[3];
+        const double dx = x - lo[0], dy = yy - lo[1], dz = zz - lo[2];
+        double qd[3];
+        float f[3];
         int c[3];
         int amb = 0;
 #pragma unroll
         for (int k = 0; k < 3; k++) {
-          q[k] = fmaf(M[k][0], dx, fmaf(M[k][1], dy, fmaf(M[k][2], dz, qlo[k])));
-          const float fl = floorf(q[k]);
-          f[k] = q[k] - fl;
+          qd[k] = fma(L->c.M[k][0], dx, fma(L->c.M[k][1], dy, fma(L->c.M[k][2], dz, L->c.qlo[k])));
+          const double fl = floor(qd[k]);
+          const double fr = qd[k] - fl;
+          f[k] = static_cast<float>(fr);
           c[k] = static_cast<int>(fl);
-          if (f[k] <= guard[k] || f[k] >= 1.0f - guard[k]) amb |= 1 << k;
+          const double g = L->c.guard[k];
+          if (fr <= g || fr >= 1.0 - g) amb |= 1 << k;
         }
-        const bool x0ok = c[0] >= 0 && c[0] < P.nx, x1ok = c[0] + 1 >= 0 && c[0] + 1 < P.nx;
-        const bool y0ok = c[1] >= 0 && c[1] < P.ny, y1ok = c[1] + 1 >= 0 && c[1] + 1 < P.ny;
-        const bool z0ok = c[2] >= 0 && c[2] < P.nz, z1ok = c[2] + 1 >= 0 && c[2] + 1 < P.nz;
-        const int base = (c[2] * P.ny + c[1]) * P.nx + c[0];
-        const int sy = P.nx, sz = P.nx * P.ny;
-        const float v000 = (z0ok && y0ok && x0ok) ? ld_img<ST>(img_oth, base) : 0.f;
-        const float v001 = (z0ok && y0ok && x1ok) ? ld_img<ST>(img_oth, base + 1) : 0.f;
-        const float v010 = (z0ok && y1ok && x0ok) ? ld_img<ST>(img_oth, base + sy) : 0.f;
-        const float v011 = (z0ok && y1ok && x1ok) ? ld_img<ST>(img_oth, base + sy + 1) : 0.f;
-        const float v100 = (z1ok && y0ok && x0ok) ? ld_img<ST>(img_oth, base + sz) : 0.f;
-        const float v101 = (z1ok && y0ok && x1ok) ? ld_img<ST>(img_oth, base + sz + 1) : 0.f;
-        const float v110 = (z1ok && y1ok && x0ok) ? ld_img<ST>(img_oth, base + sz + sy) : 0.f;
-        const float v111 = (z1ok && y1ok && x1ok) ? ld_img<ST>(img_oth, base + sz + sy + 1) : 0.f;
+        const bool vx0 = c[0] >= 0 && c[0] < nx, vx1 = c[0] >= -1 && c[0] < nx - 1;
+        const bool vy0 = c[1] >= 0 && c[1] < ny, vy1 = c[1] >= -1 && c[1] < ny - 1;
+        const bool vz0 = c[2] >= 0 && c[2] < nz, vz1 = c[2] >= -1 && c[2] < nz - 1;
+        const unsigned cy0 = min(max(c[1], 0), ny - 1), cy1 = min(max(c[1] + 1, 0), ny - 1);
+        const unsigned cz0 = min(max(c[2], 0), nz - 1), cz1 = min(max(c[2] + 1, 0), nz - 1);
+        const unsigned r00 = cz0 * sz + cy0 * sy, r01 = cz0 * sz + cy1 * sy;
+        const unsigned r10 = cz1 * sz + cy0 * sy, r11 = cz1 * sz + cy1 * sy;
+        float v000, v001, v010, v011, v100, v101, v110, v111;
+        if constexpr (ST == kF32) {
+          // one 8-byte load per corner pair (x, x+1); the image allocation is
+          // padded so that x = -1 and x = nx - 1 stay inside it
+          const int xs = min(max(c[0], -1), nx - 1);
+          const float* base = static_cast<const float*>(img_oth) + xs;
+          const F2 p00 = *reinterpret_cast<const F2*>(base + r00);
+          const F2 p01 = *reinterpret_cast<const F2*>(base + r01);
+          const F2 p10 = *reinterpret_cast<const F2*>(base + r10);
+          const F2 p11 = *reinterpret_cast<const F2*>(base + r11);
+          v000 = p00.a; v001 = p00.b; v010 = p01.a; v011 = p01.b;
+          v100 = p10.a; v101 = p10.b; v110 = p11.a; v111 = p11.b;
+        } else {
+          const unsigned cx0 = min(max(c[0], 0), nx - 1), cx1 = min(max(c[0] + 1, 0), nx - 1);
+          v000 = ld_img<ST>(img_oth, r00 + cx0); v001 = ld_img<ST>(img_oth, r00 + cx1);
+          v010 = ld_img<ST>(img_oth, r01 + cx0); v011 = ld_img<ST>(img_oth, r01 + cx1);
+          v100 = ld_img<ST>(img_oth, r10 + cx0); v101 = ld_img<ST>(img_oth, r10 + cx1);
+          v110 = ld_img<ST>(img_oth, r11 + cx0); v111 = ld_img<ST>(img_oth, r11 + cx1);
+        }
+        v000 = (vz0 && vy0 && vx0) ? v000 : 0.f;
+        v001 = (vz0 && vy0 && vx1) ? v001 : 0.f;
+        v010 = (vz0 && vy1 && vx0) ? v010 : 0.f;
+        v011 = (vz0 && vy1 && vx1) ? v011 : 0.f;
+        v100 = (vz1 && vy0 && vx0) ? v100 : 0.f;
+        v101 = (vz1 && vy0 && vx1) ? v101 : 0.f;
+        v110 = (vz1 && vy1 && vx0) ? v110 : 0.f;
+        v111 = (vz1 && vy1 && vx1) ? v111 : 0.f;
         const float e00 = fmaf(f[0], v001 - v000, v000), e01 = fmaf(f[0], v011 - v010, v010);
         const float e10 = fmaf(f[0], v101 - v100, v100), e11 = fmaf(f[0], v111 - v110, v110);
         const float e0 = fmaf(f[1], e01 - e00, e00), e1 = fmaf(f[1], e11 - e10, e10);
-        float b = fmaf(f[2], e1 - e0, e0);
-        bool fg_b = (v000 > 0.f) | (v001 > 0.f) | (v010 > 0.f) | (v011 > 0.f) | (v100 > 0.f) |
-                    (v101 > 0.f) | (v110 > 0.f) | (v111 > 0.f);
+        const float b = fmaf(f[2], e1 - e0, e0);
+        bool fg_b = (fmaxf(fmaxf(fmaxf(v000, v001), fmaxf(v010, v011)),
+                           fmaxf(fmaxf(v100, v101), fmaxf(v110, v111))) > 0.f);
         if (amb)
-          fg_b = exact_foreground<ST>(img_oth, P.nx, P.ny, P.nz, L->vert, sigma, absD, x, yy, zz,
-                                      q[0], q[1], q[2], amb);
+          fg_b = exact_foreground<ST>(img_oth, nx, ny, nz, L->vert, sigma, absD, x, yy, zz, qd[0],
+                                      qd[1], qd[2], amb);
         const bool fg_a = a > 0.f;
-        float h;
-        if (fg_a && fg_b) {
-          const float dd = a - b;
-          h = dd * dd;
-        } else {
-          h = (fg_a != fg_b) ? 1.f : 0.f;
-        }
+        const float dd = a - b;
+        const float h = (fg_a && fg_b) ? dd * dd : ((fg_a != fg_b) ? 1.f : 0.f);
         h_acc += h;
         n_acc += 1;
 
         if (guided) {
           unsigned bandbits = band_own[vi];
           if (bandbits) {
-            const int cx0 = min(max(c[0], 0), P.nx - 1), cx1 = min(max(c[0] + 1, 0), P.nx - 1);
-            const int cy0 = min(max(c[1], 0), P.ny - 1), cy1 = min(max(c[1] + 1, 0), P.ny - 1);
-            const int cz0 = min(max(c[2], 0), P.nz - 1), cz1 = min(max(c[2] + 1, 0), P.nz - 1);
-            const int i00 = (cz0 * P.ny + cy0) * P.nx, i01 = (cz0 * P.ny + cy1) * P.nx;
-            const int i10 = (cz1 * P.ny + cy0) * P.nx, i11 = (cz1 * P.ny + cy1) * P.nx;
+            const unsigned cx0 = min(max(c[0], 0), nx - 1), cx1 = min(max(c[0] + 1, 0), nx - 1);
             while (bandbits) {
               const int sidx = __builtin_ctz(bandbits);
               bandbits &= bandbits - 1;
               const float* mo = map_oth + static_cast<size_t>(sidx) * V;
               const float d = map_own[static_cast<size_t>(sidx) * V + vi];
-              const float u00 = fmaf(f[0], mo[i00 + cx1] - mo[i00 + cx0], mo[i00 + cx0]);
-              const float u01 = fmaf(f[0], mo[i01 + cx1] - mo[i01 + cx0], mo[i01 + cx0]);
-              const float u10 = fmaf(f[0], mo[i10 + cx1] - mo[i10 + cx0], mo[i10 + cx0]);
-              const float u11 = fmaf(f[0], mo[i11 + cx1] - mo[i11 + cx0], mo[i11 + cx0]);
+              const float u00 = fmaf(f[0], mo[r00 + cx1] - mo[r00 + cx0], mo[r00 + cx0]);
+              const float u01 = fmaf(f[0], mo[r01 + cx1] - mo[r01 + cx0], mo[r01 + cx0]);
+              const float u10 = fmaf(f[0], mo[r10 + cx1] - mo[r10 + cx0], mo[r10 + cx0]);
+              const float u11 = fmaf(f[0], mo[r11 + cx1] - mo[r11 + cx0], mo[r11 + cx0]);
               const float u0 = fmaf(f[1], u01 - u00, u00), u1 = fmaf(f[1], u11 - u10, u10);
               const float d2 = fmaf(f[2], u1 - u0, u0);
               const float diff = d - d2;
@@ -710,4 +751,248 @@ hipError_t launch_finalize(const ProblemView& P, const float* pts, int pop, cons
   return hipGetLastError();
 }
 
+}  // namespace morea
+
+// ------------------------------------------------------- partial evaluation
+namespace morea {
+
+// Prefix sums of the evaluation list (one block, fixed order): first
+// new-coordinate row of each evaluation and first work item (dependent tet).
+// An evaluation with an out-of-range group owns no new-coordinate rows; one
+// with an out-of-range parent or group gets no work items and is reported
+// invalid by the finalize kernel.  Also resets the work queue.
+__global__ __launch_bounds__(1024) void k_partial_prep(const int* eval_parent, const int* eval_group,
+                                                        int n_evals, int n_parents, int n_groups,
+                                                        const int* grp_off, const int* dep_off,
+                                                        int* row_off, int* item_off, int* queue) {
+  __shared__ int s_rows[1024], s_items[1024];
+  const int tid = threadIdx.x;
+  const int per = (n_evals + 1023) / 1024;
+  const int b = tid * per, e_end = min(n_evals, b + per);
+  int rows = 0, items = 0;
+  for (int e = b; e < e_end; e++) {
+    const int g = eval_group[e], par = eval_parent[e];
+    if (g >= 0 && g < n_groups) {
+      rows += grp_off[g + 1] - grp_off[g];
+      if (par >= 0 && par < n_parents) items += dep_off[g + 1] - dep_off[g];
+    }
+  }
+  s_rows[tid] = rows;
+  s_items[tid] = items;
+  __syncthreads();
+  for (int d = 1; d < 1024; d <<= 1) {
+    int r = tid >= d ? s_rows[tid - d] : 0, it = tid >= d ? s_items[tid - d] : 0;
+    __syncthreads();
+    s_rows[tid] += r;
+    s_items[tid] += it;
+    __syncthreads();
+  }
+  rows = s_rows[tid] - rows;
+  items = s_items[tid] - items;
+  for (int e = b; e < e_end; e++) {
+    row_off[e] = rows;
+    item_off[e] = items;
+    const int g = eval_group[e], par = eval_parent[e];
+    if (g >= 0 && g < n_groups) {
+      rows += grp_off[g + 1] - grp_off[g];
+      if (par >= 0 && par < n_parents) items += dep_off[g + 1] - dep_off[g];
+    }
+  }
+  if (tid == 1023) item_off[n_evals] = s_items[1023];
+  if (tid == 0) *queue = 0;
+}
+
+__device__ __forceinline__ int find_eval(const int* item_off, int n_evals, int idx) {
+  int lo = 0, hi = n_evals;   // largest e with item_off[e] <= idx
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (item_off[mid] <= idx) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Persistent evaluation of all (evaluation, dependent tet, direction) items:
+// each wave takes `chunk` consecutive items from a device work queue until
+// the list is exhausted.  Every wave leaves the loop once the queue passes
+// the end of the list.
+template <int ST>
+__global__ __launch_bounds__(256) void k_eval_partial(ProblemView P, PartialItems I, Record* out,
+                                                       int* queue, int chunk) {
+  __shared__ WaveLds lds[4];
+  const int wave = threadIdx.x >> 6;
+  const int lane = lane_id();
+  const int total = I.item_off[I.n_evals] * 2;
+  while (true) {
+    int base = 0;
+    if (lane == 0) base = atomicAdd(queue, chunk);
+    base = __shfl(base, 0, 64);
+    if (base >= total) break;
+    const int end = min(total, base + chunk);
+    for (int item = base; item < end; item++) {
+      const int dir = item & 1;
+      const int idx = item >> 1;
+      const int e = find_eval(I.item_off, I.n_evals, idx);
+      const int j = idx - I.item_off[e];
+      const int g = I.eval_group[e], par = I.eval_parent[e];
+      const int slot = I.dep_off[g] + j;
+      const int tet = I.dep_tet[slot];
+      float coord = 0.f;
+      if (lane < 24) {
+        const int i = (lane % 12) / 3, k = lane % 3;
+        const int mesh = lane < 12 ? dir : 1 - dir;
+        const int loc = I.dep_local[4 * slot + i];
+        if (loc >= 0) {
+          coord = I.new_coords[((static_cast<size_t>(I.row_off[e]) + loc) * 2 + mesh) * 3 + k];
+        } else {
+          const int4 tv = P.tets[tet];
+          const int v = i == 0 ? tv.x : (i == 1 ? tv.y : (i == 2 ? tv.z : tv.w));
+          coord = I.parent_pts[((static_cast<size_t>(par) * 2 + mesh) * 3 + k) * P.n_points + v];
+        }
+      }
+      eval_tet_dir<ST>(P, tet, dir, coord, &lds[wave], &out[static_cast<size_t>(idx) * 2 + dir]);
+    }
+  }
+}
+
+template __global__ void k_eval_partial<kF32>(ProblemView, PartialItems, Record*, int*, int);
+template __global__ void k_eval_partial<kBF16>(ProblemView, PartialItems, Record*, int*, int);
+template __global__ void k_eval_partial<kF16>(ProblemView, PartialItems, Record*, int*, int);
+
+__device__ __forceinline__ void df_wave_sum(float& hi, float& lo) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    const float h2 = __shfl_xor(hi, d, 64), l2 = __shfl_xor(lo, d, 64);
+    df_add(hi, lo, h2);
+    lo += l2;
+  }
+}
+
+// Child totals = parent totals - parent records of the dependent tets + new
+// records, in compensated arithmetic; counts, violations and invalid
+// coordinates are exact integer deltas.  One wave per evaluation.
+__global__ __launch_bounds__(256) void k_finalize_partial(ProblemView P, PartialItems I,
+                                                           const Record* parent_rec,
+                                                           const Totals* parent_tot, int n_parents,
+                                                           int n_groups, const Record* new_rec,
+                                                           float* obj, uint8_t* flags,
+                                                           float* severity, uint32_t* counts) {
+  const int e = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (e >= I.n_evals) return;
+  const int lane = lane_id();
+  const int g = I.eval_group[e], par = I.eval_parent[e];
+  if (g < 0 || g >= n_groups || par < 0 || par >= n_parents) {
+    if (lane == 0) {
+      const float nan = __builtin_nanf("");
+      obj[3 * e] = obj[3 * e + 1] = obj[3 * e + 2] = nan;
+      flags[e] = 4;
+      severity[e] = nan;
+      counts[2 * e] = counts[2 * e + 1] = 0;
+    }
+    return;
+  }
+  const Totals T = parent_tot[par];
+  float hh = lane == 0 ? T.h_hi : 0.f, hl = lane == 0 ? T.h_lo : 0.f;
+  float gh = lane == 0 ? T.g_hi : 0.f, gl = lane == 0 ? T.g_lo : 0.f;
+  float mh = lane == 0 ? T.m_hi : 0.f, ml = lane == 0 ? T.m_lo : 0.f;
+  float vh = lane == 0 ? T.v_hi : 0.f, vl = lane == 0 ? T.v_lo : 0.f;
+  int dns = 0, dnt = 0, dvs = 0, dvt = 0, dbad = 0;
+  const int n_dep = I.item_off[e + 1] - I.item_off[e];
+  const Record* pr = parent_rec + static_cast<size_t>(par) * P.n_tets * 2;
+  const Record* nr = new_rec + static_cast<size_t>(I.item_off[e]) * 2;
+  for (int j = lane; j < n_dep; j += 64) {
+    const int tet = I.dep_tet[I.dep_off[g] + j];
+    const Record o0 = pr[2 * tet], o1 = pr[2 * tet + 1];
+    const Record n0 = nr[2 * j], n1 = nr[2 * j + 1];
+    df_add(hh, hl, -o0.h); df_add(hh, hl, -o1.h); df_add(hh, hl, n0.h); df_add(hh, hl, n1.h);
+    df_add(gh, gl, -o0.g); df_add(gh, gl, -o1.g); df_add(gh, gl, n0.g); df_add(gh, gl, n1.g);
+    df_add(mh, ml, -o0.mag); df_add(mh, ml, n0.mag);
+    df_add(vh, vl, -o0.vol); df_add(vh, vl, -o1.vol); df_add(vh, vl, n0.vol); df_add(vh, vl, n1.vol);
+    dns += static_cast<int>(n0.n) - static_cast<int>(o0.n);
+    dnt += static_cast<int>(n1.n) - static_cast<int>(o1.n);
+    dvs += static_cast<int>(n0.bits & 1u) - static_cast<int>(o0.bits & 1u);
+    dvt += static_cast<int>(n1.bits & 1u) - static_cast<int>(o1.bits & 1u);
+  }
+  // invalid coordinates: the group's old coordinates leave, the new ones enter
+  const int g0 = I.grp_off[g], size = I.grp_off[g + 1] - g0;
+  const float* pp = I.parent_pts + static_cast<size_t>(par) * 6 * P.n_points;
+  for (int k = lane; k < size * 6; k += 64) {
+    const float nv = I.new_coords[static_cast<size_t>(I.row_off[e]) * 6 + k];
+    const int pt = I.grp_pts[g0 + k / 6], ma = k % 6;   // ma = mesh * 3 + axis
+    const float ov = pp[static_cast<size_t>(ma) * P.n_points + pt];
+    dbad += static_cast<int>(!(fabsf(nv) < kCoordLimit)) - static_cast<int>(!(fabsf(ov) < kCoordLimit));
+  }
+  df_wave_sum(hh, hl);
+  df_wave_sum(gh, gl);
+  df_wave_sum(mh, ml);
+  df_wave_sum(vh, vl);
+  dns = wave_sum_i(dns);
+  dnt = wave_sum_i(dnt);
+  dvs = wave_sum_i(dvs);
+  dvt = wave_sum_i(dvt);
+  dbad = wave_sum_i(dbad);
+  if (lane == 0) {
+    const uint32_t Ns = T.n[0] + dns, Nt = T.n[1] + dnt;
+    const int bad = static_cast<int>(T.bad) + dbad;
+    if (bad > 0) {
+      const float nan = __builtin_nanf("");
+      obj[3 * e] = obj[3 * e + 1] = obj[3 * e + 2] = nan;
+      flags[e] = 4;
+      severity[e] = nan;
+      counts[2 * e] = counts[2 * e + 1] = 0;
+    } else {
+      const float N = static_cast<float>(Ns) + static_cast<float>(Nt);
+      obj[3 * e + 0] = (hh + hl) / N;
+      obj[3 * e + 1] = (mh + ml) / (10.0f * static_cast<float>(P.n_tets));
+      obj[3 * e + 2] = (gh + gl) / N;
+      flags[e] = static_cast<uint8_t>((T.viol[0] + dvs ? 1 : 0) | (T.viol[1] + dvt ? 2 : 0));
+      severity[e] = vh + vl;
+      counts[2 * e] = Ns;
+      counts[2 * e + 1] = Nt;
+    }
+  }
+}
+
+}  // namespace morea
+
+namespace morea {
+
+hipError_t launch_partial(const ProblemView& P, int storage, const PartialItems& I, int n_parents,
+                          int n_groups, const Record* parent_rec, const Totals* parent_tot,
+                          Record* new_rec, int* queue, int blocks, int chunk, float* obj,
+                          uint8_t* flags, float* severity, uint32_t* counts, hipStream_t s) {
+  if (I.n_evals == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_partial_prep, dim3(1), dim3(1024), 0, s, I.eval_parent, I.eval_group,
+                     I.n_evals, n_parents, n_groups, I.grp_off, I.dep_off,
+                     const_cast<int*>(I.row_off), const_cast<int*>(I.item_off), queue);
+  switch (storage) {
+    case kF32:
+      hipLaunchKernelGGL(k_eval_partial<kF32>, dim3(blocks), dim3(256), 0, s, P, I, new_rec, queue, chunk);
+      break;
+    case kBF16:
+      hipLaunchKernelGGL(k_eval_partial<kBF16>, dim3(blocks), dim3(256), 0, s, P, I, new_rec, queue, chunk);
+      break;
+    default:
+      hipLaunchKernelGGL(k_eval_partial<kF16>, dim3(blocks), dim3(256), 0, s, P, I, new_rec, queue, chunk);
+      break;
+  }
+  hipLaunchKernelGGL(k_finalize_partial, dim3((I.n_evals + 3) / 4), dim3(256), 0, s, P, I,
+                     parent_rec, parent_tot, n_parents, n_groups, new_rec, obj, flags, severity,
+                     counts);
+  return hipGetLastError();
+}
+
+}  // namespace morea
+
+namespace morea {
+int partial_blocks_per_cu(int storage) {
+  int n = 0;
+  hipError_t e;
+  if (storage == kF32)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(&k_eval_partial<kF32>), 256, 0);
+  else if (storage == kBF16)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(&k_eval_partial<kBF16>), 256, 0);
+  else
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(&k_eval_partial<kF16>), 256, 0);
+  return e == hipSuccess ? n : 1;
+}
 }  // namespace morea

@@ -16,6 +16,7 @@ constexpr float kCoordLimit = 512.0f;         // |x| < 512 voxels keeps every ex
 constexpr int kFastExtent = 1 << 16;          // tets up to 64 voxels: exact plane tests in FP64
 constexpr int kMaxSets = 8;
 constexpr int kWave = 64;
+constexpr int kImagePad = 16;                // zero elements around each stored image
 
 // Per-(candidate, tet, direction) partial objective record.  Direction 0
 // rasterizes the source tet on I_s and samples I_t; direction 1 rasterizes
@@ -70,11 +71,12 @@ struct PartialItems {
   const float* new_coords;     // [rows][2][3]
   const int* row_off;          // [n_evals] first new-coordinate row of each evaluation
   const int* item_off;         // [n_evals + 1] prefix of dependent tets per evaluation
+  const int* grp_off;          // [n_groups + 1] CSR into grp_pts
+  const int* grp_pts;          // group points
   const int* dep_off;          // [n_groups + 1] CSR into dep_tet / dep_local
   const int* dep_tet;          // dependent tets per group
   const int8_t* dep_local;     // [.][4] position of each tet vertex in the group, -1 if none
   int n_evals;
-  int total_items;             // item_off[n_evals] (device value mirrored by kernels)
 };
 
 }  // namespace morea
@@ -86,12 +88,16 @@ struct morea_problem {
   int max_population = 0;
   size_t voxels = 0;
   std::vector<void*> allocations;
+  std::vector<void*> group_allocs;
+  std::vector<void*> partial_allocs;
+  std::vector<int> tets_host;
   morea::Record* work_records = nullptr;   // [max_population][n_tets][2]
   morea::Totals* work_totals = nullptr;    // [max_population]
   // family of subsets
   int n_groups = 0;
-  std::vector<int> grp_size;               // host copy of group sizes
-  int* d_grp_size = nullptr;
+  int max_group = 0;
+  int* d_grp_off = nullptr;
+  int* d_grp_pts = nullptr;
   int* d_dep_off = nullptr;
   int* d_dep_tet = nullptr;
   int8_t* d_dep_local = nullptr;
@@ -102,6 +108,14 @@ struct morea_problem {
   int* d_item_off = nullptr;
   morea::Record* d_partial_records = nullptr;  // [max_evals * max_dep][2]
   int* d_queue = nullptr;
+  hipStream_t capture_stream = nullptr;
+  // autotuned persistent launch shape
+  int partial_blocks = 0;
+  int partial_chunk = 1;
+  // the last captured partial-evaluation graph and the arguments it bakes in
+  hipGraphExec_t graph_exec = nullptr;
+  const void* graph_key[9] = {};
+  int graph_key_n[4] = {};
 };
 
 namespace morea {
@@ -114,4 +128,9 @@ hipError_t launch_eval_full(const ProblemView& P, int storage, const float* pts,
 hipError_t launch_finalize(const ProblemView& P, const float* pts, int pop, const Record* rec,
                            float* obj, uint8_t* flags, float* severity, uint32_t* counts,
                            Totals* totals, hipStream_t s);
+int partial_blocks_per_cu(int storage);
+hipError_t launch_partial(const ProblemView& P, int storage, const PartialItems& I, int n_parents,
+                          int n_groups, const Record* parent_rec, const Totals* parent_tot,
+                          Record* new_rec, int* queue, int blocks, int chunk, float* obj,
+                          uint8_t* flags, float* severity, uint32_t* counts, hipStream_t s);
 }  // namespace morea
