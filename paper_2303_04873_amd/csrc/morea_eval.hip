@@ -117,12 +117,19 @@ struct ItemConst {
   double guard[3];                             // FP64 error bound of q per axis (x1000 margin)
 };
 
+// 6 x signed volume in FP64: exact when every coordinate difference is
+// <= 2^16 (the result is below 6 * 2^48).
+__device__ __forceinline__ double det_f64(const int v[4][3]) {
+  const double a0 = v[1][0] - v[0][0], a1 = v[1][1] - v[0][1], a2 = v[1][2] - v[0][2];
+  const double b0 = v[2][0] - v[0][0], b1 = v[2][1] - v[0][1], b2 = v[2][2] - v[0][2];
+  const double c0 = v[3][0] - v[0][0], c1 = v[3][1] - v[0][1], c2 = v[3][2] - v[0][2];
+  return a0 * (b1 * c2 - b2 * c1) - a1 * (b0 * c2 - b2 * c0) + a2 * (b0 * c1 - b1 * c0);
+}
+
 // LDS scratch of one wave.
 struct WaveLds {
   ItemConst c;
-  int row_x0[kWave];
-  int row_yz[kWave];
-  int row_off[kWave];
+  int4 row[kWave];   // x start, y | z << 16, first sample, unused
   int mark[kWave];
   int vert[24];   // snapped own tet (12), then other tet (12)
 };
@@ -253,8 +260,22 @@ __device__ void eval_tet_dir(const ProblemView& P, int tet, int dir, float coord
     for (int k = 0; k < 3; k++) own[i][k] = __builtin_amdgcn_readlane(fix, 3 * i + k);
   wave_sync();
 
+  // ---- bounding box on this direction's grid
+  int lo[3], hi[3], ext = 0;
+  const int dims[3] = {P.nx, P.ny, P.nz};
+#pragma unroll
+  for (int k = 0; k < 3; k++) {
+    const int mn = min(min(own[0][k], own[1][k]), min(own[2][k], own[3][k]));
+    const int mx = max(max(own[0][k], own[1][k]), max(own[2][k], own[3][k]));
+    ext = max(ext, mx - mn);
+    lo[k] = max(0, -static_cast<int>(floor_div_pos(-static_cast<int64_t>(mn), 1024)));
+    hi[k] = min(dims[k] - 1, static_cast<int>(floor_div_pos(mx, 1024)));
+  }
+  const bool fast = ext <= kFastExtent;
+
   // ---- fold check (App. A.4): exact signed volume vs the reference sign
-  const int64_t D = det_i64(own);
+  // (FP64 is exact for extents <= 2^16: |6V| <= 6 E^3 < 2^53)
+  const int64_t D = fast ? static_cast<int64_t>(det_f64(own)) : det_i64(own);
   const int ref = P.ref_sign[tet];
   const int sgnD = (D > 0) - (D < 0);
   const bool viol = (sgnD == 0) || (sgnD != ref);
@@ -268,54 +289,40 @@ __device__ void eval_tet_dir(const ProblemView& P, int tet, int dir, float coord
   if (dir == 0) {
     float term = 0.f;
     if (lane < 10) {
-      int64_t ls = 0, lt = 0;
+      // squared lengths are exact in FP64: components < 2^22, sums < 2^46
+      double ls = 0.0, lt = 0.0;
       float scale;
       if (lane < 6) {
         const int i = lane < 3 ? 0 : (lane < 5 ? 1 : 2);
         const int j = lane < 3 ? lane + 1 : (lane < 5 ? lane - 1 : 3);
 #pragma unroll
         for (int k = 0; k < 3; k++) {
-          const int64_t ds = L->vert[3 * i + k] - L->vert[3 * j + k];
-          const int64_t dt = L->vert[12 + 3 * i + k] - L->vert[12 + 3 * j + k];
-          ls += ds * ds;
-          lt += dt * dt;
+          const double ds = L->vert[3 * i + k] - L->vert[3 * j + k];
+          const double dt = L->vert[12 + 3 * i + k] - L->vert[12 + 3 * j + k];
+          ls = fma(ds, ds, ls);
+          lt = fma(dt, dt, lt);
         }
         scale = 1.0f / kFixOne;
       } else {
         const int v = lane - 6;
 #pragma unroll
         for (int k = 0; k < 3; k++) {
-          int64_t ss = 0, st = 0;
-#pragma unroll
-          for (int w = 0; w < 4; w++) {
-            ss += L->vert[3 * w + k];
-            st += L->vert[12 + 3 * w + k];
-          }
-          const int64_t ds = 4 * static_cast<int64_t>(L->vert[3 * v + k]) - ss;
-          const int64_t dt = 4 * static_cast<int64_t>(L->vert[12 + 3 * v + k]) - st;
-          ls += ds * ds;
-          lt += dt * dt;
+          const int ss = L->vert[k] + L->vert[3 + k] + L->vert[6 + k] + L->vert[9 + k];
+          const int st = L->vert[12 + k] + L->vert[15 + k] + L->vert[18 + k] + L->vert[21 + k];
+          const double ds = 4 * L->vert[3 * v + k] - ss;
+          const double dt = 4 * L->vert[12 + 3 * v + k] - st;
+          ls = fma(ds, ds, ls);
+          lt = fma(dt, dt, lt);
         }
         scale = 1.0f / (4.0f * kFixOne);
       }
-      const float den = sqrtf(static_cast<float>(ls)) + sqrtf(static_cast<float>(lt));
+      const float den = static_cast<float>(sqrt(ls)) + static_cast<float>(sqrt(lt));
       const float d = den > 0.f ? static_cast<float>(ls - lt) / den * scale : 0.f;
       term = d * d;
     }
     rec.mag = P.elasticity[tet] * wave_sum(term);
   }
 
-  // ---- bounding box on this direction's grid
-  int lo[3], hi[3], ext = 0;
-  const int dims[3] = {P.nx, P.ny, P.nz};
-#pragma unroll
-  for (int k = 0; k < 3; k++) {
-    const int mn = min(min(own[0][k], own[1][k]), min(own[2][k], own[3][k]));
-    const int mx = max(max(own[0][k], own[1][k]), max(own[2][k], own[3][k]));
-    ext = max(ext, mx - mn);
-    lo[k] = max(0, -static_cast<int>(floor_div_pos(-static_cast<int64_t>(mn), 1024)));
-    hi[k] = min(dims[k] - 1, static_cast<int>(floor_div_pos(mx, 1024)));
-  }
   const bool empty = D == 0 || lo[0] > hi[0] || lo[1] > hi[1] || lo[2] > hi[2];
   if (empty) {
     if (lane == 0) *out = rec;
@@ -332,39 +339,47 @@ __device__ void eval_tet_dir(const ProblemView& P, int tet, int dir, float coord
     const int b0 = i == 0 ? 1 : 0;                            // base vertex on the face
     const int u0 = i == 0 ? 2 : (i == 1 ? 2 : (i == 2 ? 3 : 1));
     const int w0 = i == 0 ? 3 : (i == 1 ? 3 : (i == 2 ? 1 : 2));
-    int64_t u[3], w[3], r[3];
+    double u[3], w[3], r[3];
 #pragma unroll
     for (int k = 0; k < 3; k++) {
-      r[k] = L->vert[3 * b0 + k];
-      u[k] = L->vert[3 * u0 + k] - r[k];
-      w[k] = L->vert[3 * w0 + k] - r[k];
+      const int rk = L->vert[3 * b0 + k];
+      r[k] = rk;
+      u[k] = L->vert[3 * u0 + k] - rk;
+      w[k] = L->vert[3 * w0 + k] - rk;
     }
-    const int64_t sg = (i == 0 ? -sigma : sigma);
-    const int64_t nx_ = sg * (u[1] * w[2] - u[2] * w[1]);
-    const int64_t ny_ = sg * (u[2] * w[0] - u[0] * w[2]);
-    const int64_t nz_ = sg * (u[0] * w[1] - u[1] * w[0]);
+    // cross product: |components| < 2^41, exact in FP64
+    const double sg = (i == 0 ? -sigma : sigma);
+    const double nx_ = sg * (u[1] * w[2] - u[2] * w[1]);
+    const double ny_ = sg * (u[2] * w[0] - u[0] * w[2]);
+    const double nz_ = sg * (u[0] * w[1] - u[1] * w[0]);
     const int lex = (nx_ > 0 || (nx_ == 0 && (ny_ > 0 || (ny_ == 0 && nz_ > 0)))) ? 1 : 0;
-    const int64_t B0 = nx_ * (1024 * static_cast<int64_t>(lo[0]) - r[0]) +
-                       ny_ * (1024 * static_cast<int64_t>(lo[1]) - r[1]) +
-                       nz_ * (1024 * static_cast<int64_t>(lo[2]) - r[2]) + lex;
-    C.Ai[i] = nx_ * 1024;
-    C.PYi[i] = ny_ * 1024;
-    C.PZi[i] = nz_ * 1024;
-    C.B0i[i] = B0;
-    C.A[i] = static_cast<double>(nx_ * 1024);
-    C.PY[i] = static_cast<double>(ny_ * 1024);
-    C.PZ[i] = static_cast<double>(nz_ * 1024);
-    C.B0[i] = static_cast<double>(B0);
-    C.invA[i] = nx_ != 0 ? 1.0 / static_cast<double>(nx_ * 1024) : 0.0;
+    const double ox = 1024.0 * lo[0] - r[0], oy = 1024.0 * lo[1] - r[1], oz = 1024.0 * lo[2] - r[2];
+    C.A[i] = nx_ * 1024.0;
+    C.PY[i] = ny_ * 1024.0;
+    C.PZ[i] = nz_ * 1024.0;
+    C.invA[i] = nx_ != 0 ? 1.0 / (nx_ * 1024.0) : 0.0;
     C.kind[i] = (nx_ > 0) - (nx_ < 0);
+    if (fast) {
+      // |terms| <= 2 E^3 <= 2^49: exact
+      C.B0[i] = fma(nx_, ox, fma(ny_, oy, nz_ * oz)) + lex;
+    } else {
+      const long long nxi = static_cast<long long>(nx_), nyi = static_cast<long long>(ny_),
+                      nzi = static_cast<long long>(nz_);
+      C.Ai[i] = nxi * 1024;
+      C.PYi[i] = nyi * 1024;
+      C.PZi[i] = nzi * 1024;
+      C.B0i[i] = nxi * static_cast<long long>(ox) + nyi * static_cast<long long>(oy) +
+                 nzi * static_cast<long long>(oz) + lex;
+    }
   } else if (lane >= 8 && lane < 11) {
     const int a = lane - 8;
-    int64_t e[3][3];
+    double e[3][3];
 #pragma unroll
     for (int i = 0; i < 3; i++)
 #pragma unroll
       for (int k = 0; k < 3; k++) e[i][k] = own[i + 1][k] - own[0][k];
-    int64_t adj[3][3];
+    // adjugate rows (exact: |entries| < 2^41)
+    double adj[3][3];
     adj[0][0] = e[1][1] * e[2][2] - e[1][2] * e[2][1];
     adj[0][1] = e[1][2] * e[2][0] - e[1][0] * e[2][2];
     adj[0][2] = e[1][0] * e[2][1] - e[1][1] * e[2][0];
@@ -385,7 +400,7 @@ __device__ void eval_tet_dir(const ProblemView& P, int tet, int dir, float coord
 #pragma unroll
       for (int i = 0; i < 3; i++) {
         const double bi = static_cast<double>(L->vert[12 + 3 * (i + 1) + a]) - oth0;
-        const double t = bi * static_cast<double>(adj[i][cc]);
+        const double t = bi * adj[i][cc];
         num += t;
         mag += fabs(t);
       }
@@ -404,7 +419,6 @@ __device__ void eval_tet_dir(const ProblemView& P, int tet, int dir, float coord
   const int NYb = hi[1] - lo[1] + 1;
   const int R = NYb * (hi[2] - lo[2] + 1);
   const float invNYb = 1.0f / static_cast<float>(NYb);
-  const bool fast = ext <= kFastExtent;
   const void* img_own = P.img[dir];
   const void* img_oth = P.img[1 - dir];
   const uint8_t* band_own = P.band[dir];
@@ -440,12 +454,10 @@ __device__ void eval_tet_dir(const ProblemView& P, int tet, int dir, float coord
     const int total = __shfl(off + len, 63, 64);
     if (len > 0) {
       const int ci = bits_below(rows_mask);
-      L->row_x0[ci] = lo[0] + js;
-      L->row_yz[ci] = (lo[1] + yr) | ((lo[2] + zr) << 16);
-      L->row_off[ci] = off;
+      L->row[ci] = make_int4(lo[0] + js, (lo[1] + yr) | ((lo[2] + zr) << 16), off, 0);
     }
     wave_sync();
-    const int my_off = lane < nrows ? L->row_off[lane] : 0x7fffffff;
+    const int my_off = lane < nrows ? L->row[lane].z : 0x7fffffff;
 
     for (int sb = 0; sb < total; sb += kWave) {
       // row of each lane's sample: rows starting at or before sb, plus rows
@@ -460,10 +472,10 @@ __device__ void eval_tet_dir(const ProblemView& P, int tet, int dir, float coord
       const int ri = first + bits_below(starts) + static_cast<int>((starts >> lane) & 1ull);
       const int s = sb + lane;
       if (s < total) {
-        const int x = L->row_x0[ri] + (s - L->row_off[ri]);
-        const int yz = L->row_yz[ri];
-        const int yy = yz & 0xffff, zz = yz >> 16;
-        const unsigned vi = static_cast<unsigned>((zz * ny + yy) * nx + x);
+        const int4 rw = L->row[ri];
+        const int x = rw.x + (s - rw.z);
+        const int yy = rw.y & 0xffff, zz = rw.y >> 16;
+        const unsigned vi = __umul24(__umul24(zz, ny) + yy, nx) + x;
         const float a = ld_img<ST>(img_own, vi);
         const double dx = x - lo[0], dy = yy - lo[1], dz = zz - lo[2];
         double qd[3];
@@ -485,8 +497,8 @@ __device__ void eval_tet_dir(const ProblemView& P, int tet, int dir, float coord
         const bool vz0 = c[2] >= 0 && c[2] < nz, vz1 = c[2] >= -1 && c[2] < nz - 1;
         const unsigned cy0 = min(max(c[1], 0), ny - 1), cy1 = min(max(c[1] + 1, 0), ny - 1);
         const unsigned cz0 = min(max(c[2], 0), nz - 1), cz1 = min(max(c[2] + 1, 0), nz - 1);
-        const unsigned r00 = cz0 * sz + cy0 * sy, r01 = cz0 * sz + cy1 * sy;
-        const unsigned r10 = cz1 * sz + cy0 * sy, r11 = cz1 * sz + cy1 * sy;
+        const unsigned r00 = __umul24(cz0, sz) + __umul24(cy0, sy), r01 = __umul24(cz0, sz) + __umul24(cy1, sy);
+        const unsigned r10 = __umul24(cz1, sz) + __umul24(cy0, sy), r11 = __umul24(cz1, sz) + __umul24(cy1, sy);
         float v000, v001, v010, v011, v100, v101, v110, v111;
         if constexpr (ST == kF32) {
           // one 8-byte load per corner pair (x, x+1); the image allocation is
