@@ -112,7 +112,13 @@ struct ItemConst {
   double A[4], invA[4], PY[4], PZ[4], B0[4];   // exact in FP64 when the extent is <= 2^16
   long long Ai[4], PYi[4], PZi[4], B0i[4];     // int64 copies for wider tets
   int kind[4];                                 // sign of A_i
+  int lex[4];                                  // tie-break bit of face i
+  // x position of face i's plane on row (yr, zr): t_i = TA yr + TB zr + TG
+  // (= -(PY yr + PZ zr + B0) / A), with TE an error bound of that estimate
+  double TA[4], TB[4], TG[4], TE[4];
+  double n[4][3];                              // oriented face normals (set-up only)
   double M[3][3];
+  double Mabs[3][3];
   double qlo[3];
   double guard[3];                             // FP64 error bound of q per axis (x1000 margin)
 };
@@ -127,60 +133,56 @@ __device__ __forceinline__ double det_f64(const int v[4][3]) {
 }
 
 // LDS scratch of one wave.
+constexpr int kDeferCap = 128;
+
 struct WaveLds {
   ItemConst c;
   int4 row[kWave];   // x start, y | z << 16, first sample, unused
   int mark[kWave];
+  int4 defer[kDeferCap];   // near-grid samples: (j | yr << 10 | zr << 20, a, b, amb | fg_a << 3)
   int vert[24];   // snapped own tet (12), then other tet (12)
 };
 
 // Exact support test of the trilinear stencil (rare path, taken only when
 // the mapped coordinate is within its error bound of an integer on some
-// axis).  Recomputes D * lambda_i(p) exactly, forms the mapped coordinate as
-// the rational N / (|D| 2^10) in 128-bit integers and finds its exact floor
-// k: if N / (|D| 2^10) == k only corner k carries weight on that axis,
-// otherwise corners k and k + 1 do.  Returns whether any supported in-grid
-// corner is > 0.
+// axis).  The face values s_i(p) = D * lambda_i(p) come exactly from the
+// stored plane constants; the mapped coordinate is the rational
+// N / (|D| 2^10), N = sum_i s_i * other_i, in 128-bit integers, and its exact
+// floor k decides: if N / (|D| 2^10) == k only corner k carries weight on that
+// axis, otherwise corners k and k + 1 do.  Returns whether any supported
+// in-grid corner is > 0.
 template <int ST>
-__device__ __noinline__ bool exact_foreground(const void* img, int nx, int ny, int nz,
-                                              const int* vert, int sigma, int64_t absD, int x,
-                                              int y, int z, double q0, double q1, double q2,
-                                              int amb) {
-  int own[4][3], oth[4][3];
-  for (int i = 0; i < 4; i++)
-    for (int k = 0; k < 3; k++) {
-      own[i][k] = vert[3 * i + k];
-      oth[i][k] = vert[12 + 3 * i + k];
-    }
-  const int p[3] = {x * 1024, y * 1024, z * 1024};
+__device__ __forceinline__ bool exact_foreground(const void* img, int nx, int ny, int nz,
+                                                 const WaveLds* L, bool fast, int64_t absD,
+                                                 int jx, int jy, int jz, const double q[3], int amb) {
   int64_t s[4];
+#pragma unroll
   for (int i = 0; i < 4; i++) {
-    int w[4][3];
-    for (int j = 0; j < 4; j++)
-      for (int k = 0; k < 3; k++) w[j][k] = (j == i) ? p[k] : own[j][k];
-    s[i] = sigma * det_i64(w);
+    if (fast)
+      s[i] = static_cast<int64_t>(fma(L->c.A[i], jx, fma(L->c.PY[i], jy, fma(L->c.PZ[i], jz, L->c.B0[i]))));
+    else
+      s[i] = L->c.Ai[i] * jx + L->c.PYi[i] * jy + L->c.PZi[i] * jz + L->c.B0i[i];
+    s[i] -= L->c.lex[i];
   }
   const __int128 den = static_cast<__int128>(absD) * 1024;
-  const double q[3] = {q0, q1, q2};
   int lo[3], hi[3];
+#pragma unroll
   for (int a = 0; a < 3; a++) {
+    int k = static_cast<int>(floor(q[a]));
+    bool on_grid = false;
     if (amb & (1 << a)) {
       __int128 num = 0;
-      for (int i = 0; i < 4; i++) num += static_cast<__int128>(s[i]) * oth[i][a];
-      // exact floor k of num / den, starting from the FP64 estimate; the
-      // mapped point is a convex combination of valid vertices, so
-      // |k| <= 513 and the corrections terminate.
-      int k = static_cast<int>(floor(q[a]));
+#pragma unroll
+      for (int i = 0; i < 4; i++) num += static_cast<__int128>(s[i]) * L->vert[12 + 3 * i + a];
+      // exact floor of num / den from the FP64 estimate; the mapped point is
+      // a convex combination of valid vertices, so |k| <= 513
       k = min(max(k, -600), 600);
       while (static_cast<__int128>(k) * den > num) k--;
       while (static_cast<__int128>(k + 1) * den <= num) k++;
-      const bool on_grid = static_cast<__int128>(k) * den == num;
-      lo[a] = k;
-      hi[a] = on_grid ? k : k + 1;
-    } else {
-      lo[a] = static_cast<int>(floor(q[a]));
-      hi[a] = lo[a] + 1;
+      on_grid = static_cast<__int128>(k) * den == num;
     }
+    lo[a] = k;
+    hi[a] = on_grid ? k : k + 1;
   }
   bool fg = false;
   for (int cz = lo[2]; cz <= hi[2]; cz++)
@@ -221,8 +223,27 @@ __device__ __forceinline__ void span_fast(const ItemConst& c, int yr, int zr, in
 #pragma unroll
   for (int i = 0; i < 4; i++) {
     const int kind = __builtin_amdgcn_readfirstlane(c.kind[i]);
-    const double b = fma(c.PY[i], y, fma(c.PZ[i], z, c.B0[i]));
-    clip_face<double>(kind, c.A[i], c.invA[i], b, W, js, je);
+    if (kind == 0) {
+      const double b = fma(c.PY[i], y, fma(c.PZ[i], z, c.B0[i]));
+      if (!(b > 0.0)) je = -1;
+      continue;
+    }
+    // boundary position t: row samples j with j > t (kind > 0) or j < t
+    // (kind < 0) are inside this face.  Away from integers the FP64
+    // estimate decides; near one (within its error bound) the exact
+    // integer test does.
+    const double t = fma(c.TA[i], y, fma(c.TB[i], z, c.TG[i]));
+    const double tr = rint(t);
+    if (fabs(t - tr) <= c.TE[i] && t > -3.0 && t < W + 3.0) {
+      const double b = fma(c.PY[i], y, fma(c.PZ[i], z, c.B0[i]));
+      clip_face<double>(kind, c.A[i], c.invA[i], b, W, js, je);
+    } else {
+      const int fl = static_cast<int>(floor(fmin(fmax(t, -2.0), W + 1.0)));
+      if (kind > 0)
+        js = max(js, fl + 1);
+      else
+        je = min(je, fl);
+    }
   }
 }
 
@@ -235,6 +256,149 @@ __device__ __forceinline__ void span_wide(const ItemConst& c, int yr, int zr, in
     const long long b = c.PYi[i] * yr + c.PZi[i] * zr + c.B0i[i];
     clip_face<long long>(kind, c.Ai[i], c.invA[i], b, W, js, je);
   }
+}
+
+// One voxel sample p = (x, y, z) of a work item: map it into the other tet
+// (q = qlo + M (p - lo) in FP64), sample the other image trilinearly with
+// zero padding, decide foreground exactly, add h (Sec. 4.1.2) and, inside
+// the guidance band, the set-weighted guidance term (Sec. 4.1.3, App. A.3).
+// INTERIOR: every corner of every mapped point lies inside the grid (the
+// other tet is at least 2^-10 voxel inside it), so no clamping is needed.
+// Returns the axes on which the mapped point is within its error bound of a
+// grid plane; such a sample's h is left to the caller (deferred queue).
+template <int ST, bool INTERIOR>
+__device__ __forceinline__ int sample_one(const ProblemView& P, WaveLds* L, int dir, int x, int yy,
+                                          int zz, const int lo[3], float& h_acc, float& g_acc,
+                                          float& a_out, float& b_out) {
+  const int nx = P.nx, ny = P.ny, nz = P.nz;
+  const unsigned sy = static_cast<unsigned>(nx), sz = static_cast<unsigned>(nx * ny);
+  const void* img_oth = P.img[1 - dir];
+  const unsigned vi = __umul24(__umul24(zz, ny) + yy, nx) + x;
+  const float a = ld_img<ST>(P.img[dir], vi);
+  const double dx = x - lo[0], dy = yy - lo[1], dz = zz - lo[2];
+  double qd[3];
+  float f[3];
+  int c[3];
+  int amb = 0;
+#pragma unroll
+  for (int k = 0; k < 3; k++) {
+    qd[k] = fma(L->c.M[k][0], dx, fma(L->c.M[k][1], dy, fma(L->c.M[k][2], dz, L->c.qlo[k])));
+    const double fl = floor(qd[k]);
+    const double fr = qd[k] - fl;
+    f[k] = static_cast<float>(fr);
+    c[k] = static_cast<int>(fl);
+    const double g = L->c.guard[k];
+    if (fr <= g || fr >= 1.0 - g) amb |= 1 << k;
+  }
+  unsigned cx0, cx1, cy0, cy1, cz0, cz1;
+  if constexpr (INTERIOR) {
+    cx0 = c[0]; cx1 = c[0] + 1; cy0 = c[1]; cy1 = c[1] + 1; cz0 = c[2]; cz1 = c[2] + 1;
+  } else {
+    cx0 = min(max(c[0], 0), nx - 1); cx1 = min(max(c[0] + 1, 0), nx - 1);
+    cy0 = min(max(c[1], 0), ny - 1); cy1 = min(max(c[1] + 1, 0), ny - 1);
+    cz0 = min(max(c[2], 0), nz - 1); cz1 = min(max(c[2] + 1, 0), nz - 1);
+  }
+  const unsigned z0 = __umul24(cz0, sz), z1 = __umul24(cz1, sz);
+  const unsigned r00 = z0 + __umul24(cy0, sy), r01 = z0 + __umul24(cy1, sy);
+  const unsigned r10 = z1 + __umul24(cy0, sy), r11 = z1 + __umul24(cy1, sy);
+  float v000, v001, v010, v011, v100, v101, v110, v111;
+  if constexpr (ST == kF32) {
+    // one 8-byte load per corner pair (x, x+1); the image allocation is
+    // padded so that x = -1 and x = nx - 1 stay inside it
+    const int xs = INTERIOR ? c[0] : min(max(c[0], -1), nx - 1);
+    const float* base = static_cast<const float*>(img_oth) + xs;
+    const F2 p00 = *reinterpret_cast<const F2*>(base + r00);
+    const F2 p01 = *reinterpret_cast<const F2*>(base + r01);
+    const F2 p10 = *reinterpret_cast<const F2*>(base + r10);
+    const F2 p11 = *reinterpret_cast<const F2*>(base + r11);
+    v000 = p00.a; v001 = p00.b; v010 = p01.a; v011 = p01.b;
+    v100 = p10.a; v101 = p10.b; v110 = p11.a; v111 = p11.b;
+  } else {
+    v000 = ld_img<ST>(img_oth, r00 + cx0); v001 = ld_img<ST>(img_oth, r00 + cx1);
+    v010 = ld_img<ST>(img_oth, r01 + cx0); v011 = ld_img<ST>(img_oth, r01 + cx1);
+    v100 = ld_img<ST>(img_oth, r10 + cx0); v101 = ld_img<ST>(img_oth, r10 + cx1);
+    v110 = ld_img<ST>(img_oth, r11 + cx0); v111 = ld_img<ST>(img_oth, r11 + cx1);
+  }
+  if constexpr (!INTERIOR) {
+    const bool vx0 = c[0] >= 0 && c[0] < nx, vx1 = c[0] >= -1 && c[0] < nx - 1;
+    const bool vy0 = c[1] >= 0 && c[1] < ny, vy1 = c[1] >= -1 && c[1] < ny - 1;
+    const bool vz0 = c[2] >= 0 && c[2] < nz, vz1 = c[2] >= -1 && c[2] < nz - 1;
+    v000 = (vz0 && vy0 && vx0) ? v000 : 0.f;
+    v001 = (vz0 && vy0 && vx1) ? v001 : 0.f;
+    v010 = (vz0 && vy1 && vx0) ? v010 : 0.f;
+    v011 = (vz0 && vy1 && vx1) ? v011 : 0.f;
+    v100 = (vz1 && vy0 && vx0) ? v100 : 0.f;
+    v101 = (vz1 && vy0 && vx1) ? v101 : 0.f;
+    v110 = (vz1 && vy1 && vx0) ? v110 : 0.f;
+    v111 = (vz1 && vy1 && vx1) ? v111 : 0.f;
+  }
+  const float e00 = fmaf(f[0], v001 - v000, v000), e01 = fmaf(f[0], v011 - v010, v010);
+  const float e10 = fmaf(f[0], v101 - v100, v100), e11 = fmaf(f[0], v111 - v110, v110);
+  const float e0 = fmaf(f[1], e01 - e00, e00), e1 = fmaf(f[1], e11 - e10, e10);
+  const float b = fmaf(f[2], e1 - e0, e0);
+  const bool fg8 = (fmaxf(fmaxf(fmaxf(v000, v001), fmaxf(v010, v011)),
+                         fmaxf(fmaxf(v100, v101), fmaxf(v110, v111))) > 0.f);
+
+  if (P.n_sets > 0) {
+    unsigned bandbits = P.band[dir][vi];
+    if (bandbits) {
+      // the other distance map is edge-clamped: the clamped corners above
+      // are exactly that (and interior corners need no clamping)
+      const unsigned V = static_cast<unsigned>(nx * ny * nz);
+      const float r = P.radius, inv_r = P.inv_radius;
+      while (bandbits) {
+        const int sidx = __builtin_ctz(bandbits);
+        bandbits &= bandbits - 1;
+        const float* mo = P.dmap[1 - dir] + static_cast<size_t>(sidx) * V;
+        const float d = P.dmap[dir][static_cast<size_t>(sidx) * V + vi];
+        const float u00 = fmaf(f[0], mo[r00 + cx1] - mo[r00 + cx0], mo[r00 + cx0]);
+        const float u01 = fmaf(f[0], mo[r01 + cx1] - mo[r01 + cx0], mo[r01 + cx0]);
+        const float u10 = fmaf(f[0], mo[r10 + cx1] - mo[r10 + cx0], mo[r10 + cx0]);
+        const float u11 = fmaf(f[0], mo[r11 + cx1] - mo[r11 + cx0], mo[r11 + cx0]);
+        const float u0 = fmaf(f[1], u01 - u00, u00), u1 = fmaf(f[1], u11 - u10, u10);
+        const float d2 = fmaf(f[2], u1 - u0, u0);
+        const float diff = d - d2;
+        g_acc += P.set_w[dir][sidx] * ((r - d) * inv_r) * diff * diff;
+      }
+    }
+  }
+  // foreground of the interpolated sample: any of the 8 corners, unless the
+  // mapped point is within its error bound of a grid plane (rare): then the
+  // exact support decides, later, from the deferred queue
+  a_out = a;
+  b_out = b;
+  if (amb) return amb;
+  const bool fg_a = a > 0.f;
+  const float dd = a - b;
+  h_acc += (fg_a && fg8) ? dd * dd : ((fg_a != fg8) ? 1.f : 0.f);
+  return 0;
+}
+
+// Resolve the deferred near-grid samples of a wave: one sample per lane,
+// the mapped point recomputed from the item constants, foreground decided
+// on the exact support, h returned for accumulation.
+template <int ST>
+__device__ __forceinline__ float flush_deferred(const ProblemView& P, const WaveLds* L, int dir,
+                                             const int lo[3], bool fast, int64_t absD, int count) {
+  const int lane = lane_id();
+  float h = 0.f;
+  for (int base = 0; base < count; base += kWave) {
+    const int e = base + lane;
+    if (e >= count) continue;
+    const int4 d = L->defer[e];
+    const int jx = d.x & 1023, jy = (d.x >> 10) & 1023, jz = (d.x >> 20) & 1023;
+    const float a = __int_as_float(d.y), b = __int_as_float(d.z);
+    double q[3];
+#pragma unroll
+    for (int k = 0; k < 3; k++)
+      q[k] = fma(L->c.M[k][0], static_cast<double>(jx),
+                 fma(L->c.M[k][1], static_cast<double>(jy), fma(L->c.M[k][2], static_cast<double>(jz), L->c.qlo[k])));
+    const bool fg_b = exact_foreground<ST>(P.img[1 - dir], P.nx, P.ny, P.nz, L, fast, absD, jx, jy, jz, q, d.w);
+    const bool fg_a = a > 0.f;
+    const float dd = a - (fg_b ? b : 0.f);
+    h += (fg_a && fg_b) ? dd * dd : ((fg_a != fg_b) ? 1.f : 0.f);
+  }
+  return h;
 }
 
 // Evaluate one (tet, direction) for the candidate whose vertex coordinates
@@ -316,7 +480,7 @@ __device__ void eval_tet_dir(const ProblemView& P, int tet, int dir, float coord
         }
         scale = 1.0f / (4.0f * kFixOne);
       }
-      const float den = static_cast<float>(sqrt(ls)) + static_cast<float>(sqrt(lt));
+      const float den = sqrtf(static_cast<float>(ls)) + sqrtf(static_cast<float>(lt));
       const float d = den > 0.f ? static_cast<float>(ls - lt) / den * scale : 0.f;
       term = d * d;
     }
@@ -334,6 +498,9 @@ __device__ void eval_tet_dir(const ProblemView& P, int tet, int dir, float coord
   // i (the gradient of D * lambda_i, oriented inwards, and its value at the
   // box corner), lanes 8..10 build row a of the map and its error bound.
   ItemConst& C = L->c;
+  const int NYb0 = hi[1] - lo[1] + 1, NZb0 = hi[2] - lo[2] + 1;
+  // phase 1, lanes 0..3: face plane i (gradient of D * lambda_i, oriented
+  // inwards, its value at the box corner, and its row-boundary estimate)
   if (lane < 4) {
     const int i = lane;
     const int b0 = i == 0 ? 1 : 0;                            // base vertex on the face
@@ -352,16 +519,28 @@ __device__ void eval_tet_dir(const ProblemView& P, int tet, int dir, float coord
     const double nx_ = sg * (u[1] * w[2] - u[2] * w[1]);
     const double ny_ = sg * (u[2] * w[0] - u[0] * w[2]);
     const double nz_ = sg * (u[0] * w[1] - u[1] * w[0]);
+    C.n[i][0] = nx_;
+    C.n[i][1] = ny_;
+    C.n[i][2] = nz_;
     const int lex = (nx_ > 0 || (nx_ == 0 && (ny_ > 0 || (ny_ == 0 && nz_ > 0)))) ? 1 : 0;
     const double ox = 1024.0 * lo[0] - r[0], oy = 1024.0 * lo[1] - r[1], oz = 1024.0 * lo[2] - r[2];
-    C.A[i] = nx_ * 1024.0;
-    C.PY[i] = ny_ * 1024.0;
-    C.PZ[i] = nz_ * 1024.0;
-    C.invA[i] = nx_ != 0 ? 1.0 / (nx_ * 1024.0) : 0.0;
+    const double A = nx_ * 1024.0, PY = ny_ * 1024.0, PZ = nz_ * 1024.0;
+    C.A[i] = A;
+    C.PY[i] = PY;
+    C.PZ[i] = PZ;
+    const double invA = nx_ != 0 ? 1.0 / A : 0.0;
+    C.invA[i] = invA;
     C.kind[i] = (nx_ > 0) - (nx_ < 0);
+    C.lex[i] = lex;
     if (fast) {
       // |terms| <= 2 E^3 <= 2^49: exact
-      C.B0[i] = fma(nx_, ox, fma(ny_, oy, nz_ * oz)) + lex;
+      const double B0 = fma(nx_, ox, fma(ny_, oy, nz_ * oz)) + lex;
+      C.B0[i] = B0;
+      const double ta = -PY * invA, tb = -PZ * invA, tg = -B0 * invA;
+      C.TA[i] = ta;
+      C.TB[i] = tb;
+      C.TG[i] = tg;
+      C.TE[i] = (fabs(ta) * NYb0 + fabs(tb) * NZb0 + fabs(tg) + 128.0) * 0x1p-48;
     } else {
       const long long nxi = static_cast<long long>(nx_), nyi = static_cast<long long>(ny_),
                       nzi = static_cast<long long>(nz_);
@@ -371,67 +550,61 @@ __device__ void eval_tet_dir(const ProblemView& P, int tet, int dir, float coord
       C.B0i[i] = nxi * static_cast<long long>(ox) + nyi * static_cast<long long>(oy) +
                  nzi * static_cast<long long>(oz) + lex;
     }
-  } else if (lane >= 8 && lane < 11) {
-    const int a = lane - 8;
-    double e[3][3];
-#pragma unroll
-    for (int i = 0; i < 3; i++)
-#pragma unroll
-      for (int k = 0; k < 3; k++) e[i][k] = own[i + 1][k] - own[0][k];
-    // adjugate rows (exact: |entries| < 2^41)
-    double adj[3][3];
-    adj[0][0] = e[1][1] * e[2][2] - e[1][2] * e[2][1];
-    adj[0][1] = e[1][2] * e[2][0] - e[1][0] * e[2][2];
-    adj[0][2] = e[1][0] * e[2][1] - e[1][1] * e[2][0];
-    adj[1][0] = e[2][1] * e[0][2] - e[2][2] * e[0][1];
-    adj[1][1] = e[2][2] * e[0][0] - e[2][0] * e[0][2];
-    adj[1][2] = e[2][0] * e[0][1] - e[2][1] * e[0][0];
-    adj[2][0] = e[0][1] * e[1][2] - e[0][2] * e[1][1];
-    adj[2][1] = e[0][2] * e[1][0] - e[0][0] * e[1][2];
-    adj[2][2] = e[0][0] * e[1][1] - e[0][1] * e[1][0];
-    const double inv = 1.0 / static_cast<double>(D);
-    const double ainv = fabs(inv);
+  }
+  wave_sync();
+  // phase 2, lanes 0..8: map entry M[a][c] = sum_i b_i[a] adj_i[c] / D with
+  // b_i = oth_i - oth_0 and adj_i = sigma n_i (i = 1..3) the rows of adj(E)
+  const double invD = 1.0 / static_cast<double>(D);
+  if (lane < 9) {
+    const int a = lane / 3, cc = lane % 3;
     const double oth0 = L->vert[12 + a];
-    double q = oth0 * (1.0 / 1024.0);
+    double num = 0.0, mag = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+      const double bi = static_cast<double>(L->vert[12 + 3 * (i + 1) + a]) - oth0;
+      const double t = bi * (sigma * C.n[i + 1][cc]);
+      num += t;
+      mag += fabs(t);
+    }
+    C.M[a][cc] = num * invD;
+    C.Mabs[a][cc] = mag * fabs(invD);
+  }
+  wave_sync();
+  // phase 3, lanes 0..2: q at the box corner and the FP64 error bound of q
+  if (lane < 3) {
+    const int a = lane;
+    double q = L->vert[12 + a] * (1.0 / 1024.0);
     double bound = fabs(q) + 1.0;
 #pragma unroll
     for (int cc = 0; cc < 3; cc++) {
-      double num = 0.0, mag = 0.0;
-#pragma unroll
-      for (int i = 0; i < 3; i++) {
-        const double bi = static_cast<double>(L->vert[12 + 3 * (i + 1) + a]) - oth0;
-        const double t = bi * adj[i][cc];
-        num += t;
-        mag += fabs(t);
-      }
-      const double m = num * inv;
       const double off = lo[cc] - own[0][cc] * (1.0 / 1024.0);
-      C.M[a][cc] = m;
-      q += m * off;
-      bound += mag * ainv * (fabs(off) + (hi[cc] - lo[cc]));
+      q += C.M[a][cc] * off;
+      bound += C.Mabs[a][cc] * (fabs(off) + (hi[cc] - lo[cc]));
     }
     C.qlo[a] = q;
     C.guard[a] = bound * 0x1p-40;
   }
-  wave_sync();
-
   const int W = hi[0] - lo[0];
   const int NYb = hi[1] - lo[1] + 1;
   const int R = NYb * (hi[2] - lo[2] + 1);
   const float invNYb = 1.0f / static_cast<float>(NYb);
-  const void* img_own = P.img[dir];
-  const void* img_oth = P.img[1 - dir];
-  const uint8_t* band_own = P.band[dir];
-  const float* map_own = P.dmap[dir];
-  const float* map_oth = P.dmap[1 - dir];
-  const unsigned V = static_cast<unsigned>(P.nx * P.ny * P.nz);
-  const float r = P.radius, inv_r = P.inv_radius;
-  const bool guided = P.n_sets > 0;
-  const int nx = P.nx, ny = P.ny, nz = P.nz;
-  const unsigned sy = static_cast<unsigned>(nx), sz = static_cast<unsigned>(nx * ny);
+  // the other tet lies at least 2^-10 voxel inside the grid on every axis:
+  // all trilinear corners of all mapped points are valid voxels
+  bool interior = true;
+#pragma unroll
+  for (int k = 0; k < 3; k++) {
+    int mn = __builtin_amdgcn_readlane(fix, 12 + k), mx = mn;
+#pragma unroll
+    for (int i = 1; i < 4; i++) {
+      const int v = __builtin_amdgcn_readlane(fix, 12 + 3 * i + k);
+      mn = min(mn, v);
+      mx = max(mx, v);
+    }
+    interior = interior && mn >= 1 && mx <= 1024 * (dims[k] - 1) - 1;
+  }
 
   float h_acc = 0.f, g_acc = 0.f;
-  int n_acc = 0;
+  int n_acc = 0, n_defer = 0;
 
   for (int rb = 0; rb < R; rb += kWave) {
     const int rr = rb + lane;
@@ -471,99 +644,39 @@ __device__ void eval_tet_dir(const ProblemView& P, int tet, int dir, float coord
       const uint64_t starts = __ballot(L->mark[lane] != 0);
       const int ri = first + bits_below(starts) + static_cast<int>((starts >> lane) & 1ull);
       const int s = sb + lane;
+      int amb = 0, x = 0, yy = 0, zz = 0;
+      float a = 0.f, b = 0.f;
       if (s < total) {
         const int4 rw = L->row[ri];
-        const int x = rw.x + (s - rw.z);
-        const int yy = rw.y & 0xffff, zz = rw.y >> 16;
-        const unsigned vi = __umul24(__umul24(zz, ny) + yy, nx) + x;
-        const float a = ld_img<ST>(img_own, vi);
-        const double dx = x - lo[0], dy = yy - lo[1], dz = zz - lo[2];
-        double qd[3];
-        float f[3];
-        int c[3];
-        int amb = 0;
-#pragma unroll
-        for (int k = 0; k < 3; k++) {
-          qd[k] = fma(L->c.M[k][0], dx, fma(L->c.M[k][1], dy, fma(L->c.M[k][2], dz, L->c.qlo[k])));
-          const double fl = floor(qd[k]);
-          const double fr = qd[k] - fl;
-          f[k] = static_cast<float>(fr);
-          c[k] = static_cast<int>(fl);
-          const double g = L->c.guard[k];
-          if (fr <= g || fr >= 1.0 - g) amb |= 1 << k;
-        }
-        const bool vx0 = c[0] >= 0 && c[0] < nx, vx1 = c[0] >= -1 && c[0] < nx - 1;
-        const bool vy0 = c[1] >= 0 && c[1] < ny, vy1 = c[1] >= -1 && c[1] < ny - 1;
-        const bool vz0 = c[2] >= 0 && c[2] < nz, vz1 = c[2] >= -1 && c[2] < nz - 1;
-        const unsigned cy0 = min(max(c[1], 0), ny - 1), cy1 = min(max(c[1] + 1, 0), ny - 1);
-        const unsigned cz0 = min(max(c[2], 0), nz - 1), cz1 = min(max(c[2] + 1, 0), nz - 1);
-        const unsigned r00 = __umul24(cz0, sz) + __umul24(cy0, sy), r01 = __umul24(cz0, sz) + __umul24(cy1, sy);
-        const unsigned r10 = __umul24(cz1, sz) + __umul24(cy0, sy), r11 = __umul24(cz1, sz) + __umul24(cy1, sy);
-        float v000, v001, v010, v011, v100, v101, v110, v111;
-        if constexpr (ST == kF32) {
-          // one 8-byte load per corner pair (x, x+1); the image allocation is
-          // padded so that x = -1 and x = nx - 1 stay inside it
-          const int xs = min(max(c[0], -1), nx - 1);
-          const float* base = static_cast<const float*>(img_oth) + xs;
-          const F2 p00 = *reinterpret_cast<const F2*>(base + r00);
-          const F2 p01 = *reinterpret_cast<const F2*>(base + r01);
-          const F2 p10 = *reinterpret_cast<const F2*>(base + r10);
-          const F2 p11 = *reinterpret_cast<const F2*>(base + r11);
-          v000 = p00.a; v001 = p00.b; v010 = p01.a; v011 = p01.b;
-          v100 = p10.a; v101 = p10.b; v110 = p11.a; v111 = p11.b;
-        } else {
-          const unsigned cx0 = min(max(c[0], 0), nx - 1), cx1 = min(max(c[0] + 1, 0), nx - 1);
-          v000 = ld_img<ST>(img_oth, r00 + cx0); v001 = ld_img<ST>(img_oth, r00 + cx1);
-          v010 = ld_img<ST>(img_oth, r01 + cx0); v011 = ld_img<ST>(img_oth, r01 + cx1);
-          v100 = ld_img<ST>(img_oth, r10 + cx0); v101 = ld_img<ST>(img_oth, r10 + cx1);
-          v110 = ld_img<ST>(img_oth, r11 + cx0); v111 = ld_img<ST>(img_oth, r11 + cx1);
-        }
-        v000 = (vz0 && vy0 && vx0) ? v000 : 0.f;
-        v001 = (vz0 && vy0 && vx1) ? v001 : 0.f;
-        v010 = (vz0 && vy1 && vx0) ? v010 : 0.f;
-        v011 = (vz0 && vy1 && vx1) ? v011 : 0.f;
-        v100 = (vz1 && vy0 && vx0) ? v100 : 0.f;
-        v101 = (vz1 && vy0 && vx1) ? v101 : 0.f;
-        v110 = (vz1 && vy1 && vx0) ? v110 : 0.f;
-        v111 = (vz1 && vy1 && vx1) ? v111 : 0.f;
-        const float e00 = fmaf(f[0], v001 - v000, v000), e01 = fmaf(f[0], v011 - v010, v010);
-        const float e10 = fmaf(f[0], v101 - v100, v100), e11 = fmaf(f[0], v111 - v110, v110);
-        const float e0 = fmaf(f[1], e01 - e00, e00), e1 = fmaf(f[1], e11 - e10, e10);
-        const float b = fmaf(f[2], e1 - e0, e0);
-        bool fg_b = (fmaxf(fmaxf(fmaxf(v000, v001), fmaxf(v010, v011)),
-                           fmaxf(fmaxf(v100, v101), fmaxf(v110, v111))) > 0.f);
-        if (amb)
-          fg_b = exact_foreground<ST>(img_oth, nx, ny, nz, L->vert, sigma, absD, x, yy, zz, qd[0],
-                                      qd[1], qd[2], amb);
-        const bool fg_a = a > 0.f;
-        const float dd = a - b;
-        const float h = (fg_a && fg_b) ? dd * dd : ((fg_a != fg_b) ? 1.f : 0.f);
-        h_acc += h;
+        x = rw.x + (s - rw.z);
+        yy = rw.y & 0xffff;
+        zz = rw.y >> 16;
+        if (interior)
+          amb = sample_one<ST, true>(P, L, dir, x, yy, zz, lo, h_acc, g_acc, a, b);
+        else
+          amb = sample_one<ST, false>(P, L, dir, x, yy, zz, lo, h_acc, g_acc, a, b);
         n_acc += 1;
-
-        if (guided) {
-          unsigned bandbits = band_own[vi];
-          if (bandbits) {
-            const unsigned cx0 = min(max(c[0], 0), nx - 1), cx1 = min(max(c[0] + 1, 0), nx - 1);
-            while (bandbits) {
-              const int sidx = __builtin_ctz(bandbits);
-              bandbits &= bandbits - 1;
-              const float* mo = map_oth + static_cast<size_t>(sidx) * V;
-              const float d = map_own[static_cast<size_t>(sidx) * V + vi];
-              const float u00 = fmaf(f[0], mo[r00 + cx1] - mo[r00 + cx0], mo[r00 + cx0]);
-              const float u01 = fmaf(f[0], mo[r01 + cx1] - mo[r01 + cx0], mo[r01 + cx0]);
-              const float u10 = fmaf(f[0], mo[r10 + cx1] - mo[r10 + cx0], mo[r10 + cx0]);
-              const float u11 = fmaf(f[0], mo[r11 + cx1] - mo[r11 + cx0], mo[r11 + cx0]);
-              const float u0 = fmaf(f[1], u01 - u00, u00), u1 = fmaf(f[1], u11 - u10, u10);
-              const float d2 = fmaf(f[2], u1 - u0, u0);
-              const float diff = d - d2;
-              g_acc += P.set_w[dir][sidx] * ((r - d) * inv_r) * diff * diff;
-            }
-          }
+      }
+      const uint64_t amb_mask = __ballot(amb != 0);
+      if (amb_mask) {
+        if (amb) {
+          const int slot = n_defer + bits_below(amb_mask);
+          L->defer[slot] = make_int4((x - lo[0]) | ((yy - lo[1]) << 10) | ((zz - lo[2]) << 20),
+                                     __float_as_int(a), __float_as_int(b), amb);
         }
+        n_defer += __popcll(amb_mask);
+      }
+      if (n_defer > kDeferCap - kWave) {
+        wave_sync();
+        h_acc += flush_deferred<ST>(P, L, dir, lo, fast, absD, n_defer);
+        n_defer = 0;
       }
       wave_sync();
     }
+  }
+  if (n_defer > 0) {
+    wave_sync();
+    h_acc += flush_deferred<ST>(P, L, dir, lo, fast, absD, n_defer);
   }
   rec.h = wave_sum(h_acc);
   rec.g = wave_sum(g_acc);
@@ -584,7 +697,7 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 
 // Full evaluation: item = (tet * pop + candidate) * 2 + direction.
 template <int ST>
-__global__ __launch_bounds__(256) void k_eval_full(ProblemView P, FullItems F, Record* rec,
+__global__ __launch_bounds__(256, 5) void k_eval_full(ProblemView P, FullItems F, Record* rec,
                                                     int n_items) {
   __shared__ WaveLds lds[4];
   const int wave = threadIdx.x >> 6;
