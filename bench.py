@@ -38,7 +38,160 @@ def parse():
     ap.add_argument("--parity-samples", type=int, default=3)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this size first (counter calibration)")
+    ap.add_argument("--forms", default="partial,reduced,surrogate",
+                    help="comma list of the other forms to measure after the main timing "
+                         "(partial, reduced, surrogate) or 'none'")
     return ap.parse_args()
+
+
+def timed(fn, steps, warmup):
+    """Average milliseconds of fn() on the current stream (HIP events)."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def form_partial(p, pop_np, prob_full_ms, steps):
+    """Config 3: 512 parents x 64 FOS groups of 4-48 points in one
+    persistent launch, replayed from a HIP graph, autotuned launch shape."""
+    import torch
+
+    import oracle
+    import paper_2303_04873_amd as morea
+    import synth
+    off, pts = synth.make_groups(p)
+    ep, eg, new = synth.make_children(p, pop_np, off, pts)
+    prob = morea.Problem.from_synth(p, max_population=pop_np.shape[0])
+    prob.set_groups(off, pts)
+    prob.reserve_partial(len(ep))
+    par = torch.from_numpy(pop_np).cuda()
+    cache = prob.new_cache(pop_np.shape[0])
+    prob.eval_full(par, cache=cache)
+    dep, deg, dnew = (torch.from_numpy(a).cuda() for a in (ep, eg, new))
+    out = prob.outputs(len(ep))
+    tune_ms, shape = prob.tune_partial(par, cache, dep, deg, dnew, out=out)
+    ms = timed(lambda: prob.eval_partial(par, cache, dep, deg, dnew, out=out), steps, 2)
+    g = {k: v.cpu().numpy() for k, v in out.items()}
+    idx = [0, 12345, len(ep) - 1]
+    kids = np.stack([synth.apply_child(pop_np, off, pts, ep, eg, new, e) for e in idx])
+    o = oracle.Problem.from_synth(p).evaluate(kids)
+    rel = np.abs(g["obj"][idx] - o["obj"]) / np.maximum(np.abs(o["obj"]), 1e-30)
+    exact = bool((g["counts"][idx] == o["counts"]).all() and (g["flags"][idx] == o["flags"]).all())
+    evals_s = len(ep) / (ms * 1e-3)
+    return {"workload": f"{pop_np.shape[0]} parents x {len(off) - 1} groups of 4-48 points "
+                        f"({len(ep)} partial evaluations) per launch",
+            "ms_per_launch": ms, "partial_evals_per_s": evals_s,
+            "vs_plain_full_evals_per_s": evals_s / (pop_np.shape[0] / (prob_full_ms * 1e-3)),
+            "launch_shape": {"blocks": shape[0], "items_per_pop": shape[1], "tuned_ms": tune_ms},
+            "parity": {"evals": idx, "counts_flags_exact": exact,
+                       "max_rel_err": [float(x) for x in rel.max(axis=0)]}}
+
+
+def form_reduced(steps):
+    """Config 4: 192x192x128 images stored BF16 / FP16 (and FP32 for
+    reference), 9,126 tets, population 256, full evaluation."""
+    import torch
+
+    import oracle
+    import paper_2303_04873_amd as morea
+    import synth
+    p = synth.make_problem(4)
+    pop_np = synth.make_population(p)
+    pts = torch.from_numpy(pop_np).cuda()
+    res = {"workload": f"{p.dims[0]}x{p.dims[1]}x{p.dims[2]}, {p.n_tets} tets, population "
+                       f"{pop_np.shape[0]}, full evaluation"}
+    o32 = oracle.Problem.from_synth(p).evaluate(pop_np[:2])
+    for storage in ("f32", "bf16", "f16"):
+        prob = morea.Problem.from_synth(p, storage=storage, max_population=pop_np.shape[0])
+        out = prob.outputs(pop_np.shape[0])
+        ms = timed(lambda: prob.eval_full(pts, out=out), steps, 2)
+        g = {k: v.cpu().numpy() for k, v in out.items()}
+        oq = oracle.Problem.from_synth(p, image_src=oracle.quantize(p.image_src, storage),
+                                       image_tgt=oracle.quantize(p.image_tgt, storage)).evaluate(pop_np[:2])
+        rel = np.abs(g["obj"][:2] - oq["obj"]) / np.maximum(np.abs(oq["obj"]), 1e-30)
+        eff = np.abs(g["obj"][:2] - o32["obj"]) / np.maximum(np.abs(o32["obj"]), 1e-30)
+        res[storage] = {"ms_per_step": ms, "evals_per_s": pop_np.shape[0] / (ms * 1e-3),
+                        "samples_per_s": float(g["counts"].astype(np.int64).sum()) / (ms * 1e-3),
+                        "max_rel_err_vs_oracle_same_storage": [float(x) for x in rel.max(axis=0)],
+                        "storage_effect_vs_fp32_oracle": [float(x) for x in eff.max(axis=0)],
+                        "counts_flags_exact": bool((g["counts"][:2] == oq["counts"]).all()
+                                                   and (g["flags"][:2] == oq["flags"]).all())}
+        prob.close()
+    return res
+
+
+def form_surrogate(full_evals_per_s, steps):
+    """Config 5: 4,096 offspring of 512 parents (source fixed) pre-screened by
+    the per-tet MLP, the best 512 evaluated exactly; trained first on ~1 M
+    exact per-tet targets of 296 other candidates."""
+    import torch
+
+    import paper_2303_04873_amd as morea
+    import synth
+    p = synth.make_problem(5)
+    prob = morea.Problem.from_synth(p, max_population=4096)
+    sur = morea.Surrogate(prob, max_rows=8192, seed=11)
+    _, train = synth.make_offspring(p, n_parents=37, per_parent=8, seed=105)
+    tr = torch.from_numpy(train).cuda()
+    cache = prob.new_cache(len(train))
+    prob.eval_full(tr, cache=cache)
+    X = sur.features(tr).reshape(-1, 20).contiguous()
+    t = sur.targets(cache, len(train)).reshape(-1).contiguous()
+    n = t.numel()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gen = torch.Generator(device="cpu").manual_seed(0)
+    loss = torch.empty(1, device="cuda")
+    for epoch in range(6):
+        perm = torch.randperm(n, generator=gen).cuda()
+        for b in range(0, n - 8191, 8192):
+            sel = perm[b:b + 8192]
+            sur.train_step(X[sel].contiguous(), t[sel].contiguous(), 2e-3 if epoch < 4 else 5e-4,
+                           loss_out=loss)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    _, off = synth.make_offspring(p)
+    offs = torch.from_numpy(off).cuda()
+    exact_all = prob.eval_full(offs)
+    f = exact_all["obj"][:, 0].cpu().numpy().astype(np.float64)
+    score = torch.empty(len(off), device="cuda")
+    prob512 = morea.Problem.from_synth(p, max_population=512)
+    out512 = prob512.outputs(512)
+
+    def screened():
+        sur.prescreen(offs, score=score)
+        _, chosen = morea.morea_surrogate_select(score, 512, offs)
+        prob512.eval_full(chosen, out=out512)
+
+    ms_pre = timed(lambda: sur.prescreen(offs, score=score), steps, 2)
+    ms_all = timed(screened, steps, 2)
+    idx, _ = morea.morea_surrogate_select(score, 512, offs)
+    idx = idx.cpu().numpy()
+    rnd = np.random.default_rng(0).choice(len(f), 512, replace=False)
+    best = np.argsort(f)[:512]
+    sc = score.cpu().numpy()
+    rs, rf = np.argsort(np.argsort(sc)), np.argsort(np.argsort(f))
+    per_tet = (sur.predict_rows(X[:200000]).cpu().numpy() - t[:200000].cpu().numpy())
+    return {"workload": f"{len(off)} offspring of 512 parents, top 512 evaluated exactly",
+            "train_rows": n, "train_seconds": train_s, "final_train_loss": loss.item(),
+            "prescreen_ms": ms_pre, "offspring_screened_per_s": len(off) / (ms_pre * 1e-3),
+            "screen_select_exact512_ms": ms_all,
+            "offspring_per_s_with_exact_top512": len(off) / (ms_all * 1e-3),
+            "vs_plain_full_evals_per_s": len(off) / (ms_all * 1e-3) / full_evals_per_s,
+            "mean_exact_f_int": {"surrogate_top512": float(f[idx].mean()),
+                                 "random_512": float(f[rnd].mean()),
+                                 "true_top512": float(f[best].mean())},
+            "overlap_with_true_top512": len(set(idx.tolist()) & set(best.tolist())) / 512,
+            "spearman_score_vs_exact": float(np.corrcoef(rs, rf)[0, 1]),
+            "per_tet_rmse_train_rows": float(np.sqrt(np.mean(per_tet ** 2)))}
 
 
 def main():
@@ -119,6 +272,18 @@ def main():
                    "sample": f"first {n_done} of {pop} candidates of the same population "
                              f"(FP64 C oracle, OpenMP), {t_cpu:.1f}s"}
 
+    forms = {}
+    wanted = [] if args.forms == "none" else args.forms.split(",")
+    for name in wanted:
+        t_form = time.time()
+        if name == "partial":
+            forms["partial_config3"] = form_partial(p, pop_np, ms_per_step, max(3, args.steps // 4))
+        elif name == "reduced":
+            forms["reduced_precision_config4"] = form_reduced(max(3, args.steps // 4))
+        elif name == "surrogate":
+            forms["surrogate_config5"] = form_surrogate(evals_per_s, max(3, args.steps // 4))
+        print(f"# form {name} done in {time.time() - t_form:.1f}s", file=sys.stderr, flush=True)
+
     achieved_ops = samples * SAMPLE_OPS / (launch_ms * 1e-3)
     line = {
         "metric": "candidate objective evals/s + voxel samples/s vs plain GPU at <=1e-5 rel err",
@@ -142,6 +307,7 @@ def main():
                      "hbm_algorithmic_frac": samples * SAMPLE_BYTES / (launch_ms * 1e-3) / HBM_PEAK},
         "parity": parity,
         "cpu_baseline": cpu,
+        "forms": forms,
     }
     print(json.dumps(line), flush=True)
 

@@ -74,7 +74,7 @@ typedef struct morea_problem morea_problem; /* opaque; owns all device copies */
 /* Problem description.  Every pointer is a HOST pointer; the library copies
  * what it needs during morea_problem_create and keeps no reference.  */
 typedef struct {
-  int32_t dims[3];              /* nx, ny, nz; each in [1, 1024] */
+  int32_t dims[3];              /* nx, ny, nz; each in [1, 1024], nx*ny*nz <= 2^29 */
   const float *image_src;       /* I_s, [nz][ny][nx], finite, >= 0 */
   const float *image_tgt;       /* I_t, same shape */
   int32_t storage;              /* morea_store */
@@ -197,6 +197,82 @@ morea_status morea_tune_partial(morea_problem *p, const float *parent_pts, int32
 /* Current persistent launch shape of partial evaluation (blocks of 256
  * threads, items per queue pop).  Errors: MOREA_EINVAL. */
 morea_status morea_partial_shape(const morea_problem *p, int32_t *blocks, int32_t *chunk);
+
+/* ------------------------------------------------------------------------
+ * Learned pre-screen of offspring.  A per-tetrahedron multilayer perceptron
+ * 20 -> 128 -> 128 -> 1 (ReLU) predicts each tet's mean intensity term, the
+ * sum of h (Sec. 4.1.2) over the tet's samples in both directions divided by
+ * their number.  Inputs per (candidate, tet): the 12 target-mesh vertex
+ * coordinates of the tet scaled to [-1, 1] by the image extent, and 8
+ * statistics of the tet's region in the reference mesh (mean, std and
+ * foreground fraction of I_s and of I_t over its voxels, their mean squared
+ * difference, its voxel count over the mean count).  A candidate's score is
+ * the voxel-count-weighted mean of its tets' predictions (a predicted
+ * f_intensity); the best-scoring offspring are then evaluated exactly.  Dense
+ * layers run on the matrix cores with BF16 operands and FP32 accumulation;
+ * master weights, gradients and Adam state are FP32.  The surrogate is an
+ * addition of this library; the paper has no counterpart.  Parameters are
+ * one FP32 vector: W1 [128][20], b1 [128], W2 [128][128], b2 [128],
+ * w3 [128], b3 [1] (19,329 values).
+ * All array arguments are device pointers unless named host_*; calls with a
+ * stream are asynchronous on it. */
+typedef struct morea_surrogate morea_surrogate;
+
+int32_t morea_surrogate_num_params(void);
+
+/* Create a surrogate for problem p (which must outlive it): He-normal
+ * weights from `seed`, zero Adam state, the per-tet statistics of the
+ * reference mesh, and a training workspace for batches of up to max_rows
+ * rows.  Synchronous.  Errors: MOREA_EINVAL, MOREA_ENOMEM, MOREA_EDEVICE. */
+morea_status morea_surrogate_create(morea_problem *p, int32_t max_rows, uint64_t seed,
+                                    morea_surrogate **out);
+void morea_surrogate_destroy(morea_surrogate *s);
+
+/* Input rows of every (candidate, tet): feats [pop][n_tets][20] FP32. */
+morea_status morea_surrogate_features(morea_surrogate *s, const float *pts, int32_t pop,
+                                      float *feats, void *stream);
+
+/* Training targets from a cache written by morea_eval_full for `pop`
+ * candidates: targets [pop][n_tets] FP32 (0 for a tet without samples). */
+morea_status morea_surrogate_targets(morea_surrogate *s, const void *cache, int32_t pop,
+                                     float *targets, void *stream);
+
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8) on the mean squared error of
+ * n_rows <= max_rows rows; *loss_out (device, may be NULL) receives the loss
+ * before the step.  Errors: MOREA_EINVAL, MOREA_ERANGE, MOREA_EDEVICE. */
+morea_status morea_surrogate_train_step(morea_surrogate *s, const float *feats,
+                                        const float *targets, int32_t n_rows, float lr,
+                                        float *loss_out, void *stream);
+
+/* Gradient of that loss without an update: grads [19,329] FP32 (device). */
+morea_status morea_surrogate_gradients(morea_surrogate *s, const float *feats,
+                                       const float *targets, int32_t n_rows, float *grads,
+                                       float *loss_out, void *stream);
+
+/* Predictions pred [n_rows] for explicit input rows. */
+morea_status morea_surrogate_predict_rows(morea_surrogate *s, const float *feats, int32_t n_rows,
+                                          float *pred, void *stream);
+
+/* Pre-screen: score [pop] of candidates pts [pop][2][3][n_points]
+ * (features built on the fly; one launch). */
+morea_status morea_surrogate_prescreen(morea_surrogate *s, const float *pts, int32_t pop,
+                                       float *score, void *stream);
+
+/* Indices of the k lowest scores (ties: lower index first) into idx_out [k],
+ * 1 <= k <= n <= 8192; when pts and selected_pts are not NULL the selected
+ * candidates are copied to selected_pts [k][2][3][n_points] in that order. */
+morea_status morea_surrogate_select(const float *score, int32_t n, int32_t k, const float *pts,
+                                    int32_t n_points, int32_t *idx_out, float *selected_pts,
+                                    void *stream);
+
+/* Copy the FP32 parameter vector out / in (host arrays of 19,329 floats;
+ * checkpoints).  Synchronous. */
+morea_status morea_surrogate_get_params(morea_surrogate *s, float *host_params);
+morea_status morea_surrogate_set_params(morea_surrogate *s, const float *host_params);
+
+/* The per-tet statistics host_stats [n_tets][8] and reference voxel counts
+ * host_counts [n_tets] (may be NULL).  Synchronous. */
+morea_status morea_surrogate_stats(morea_surrogate *s, float *host_stats, int32_t *host_counts);
 
 /* Message for the last non-OK status returned on the calling thread. */
 const char *morea_last_error(void);

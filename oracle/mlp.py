@@ -1,0 +1,77 @@
+"""FP64 reference of the surrogate MLP (test infrastructure).
+
+The surrogate that pre-screens offspring is a per-tetrahedron multilayer
+perceptron 20 -> 128 -> 128 -> 1 with ReLU activations and mean squared
+error loss.  This module evaluates it and its exact gradient with plain NumPy
+in FP64 so that the GPU kernels' forward pass and backward pass can be
+checked against it.  The surrogate is this build's own addition (no
+counterpart in the paper), so there is no passage of the paper to cite; the
+mathematics is the textbook chain rule for a dense network.
+
+Parameter order (a flat vector of 19,329 values), shared with the library's
+parameter buffer:
+    W1 [128][20], b1 [128], W2 [128][128], b2 [128], w3 [128], b3 [1]
+where layer k computes h_k = relu(W_k h_{k-1} + b_k) and the output is
+y = w3 . h_2 + b3.
+"""
+import numpy as np
+
+N_IN, N_HID = 20, 128
+SHAPES = [("W1", (N_HID, N_IN)), ("b1", (N_HID,)), ("W2", (N_HID, N_HID)), ("b2", (N_HID,)),
+          ("w3", (N_HID,)), ("b3", (1,))]
+N_PARAMS = sum(int(np.prod(s)) for _, s in SHAPES)
+
+
+def unpack(theta):
+    theta = np.asarray(theta, dtype=np.float64)
+    out, o = {}, 0
+    for name, shape in SHAPES:
+        n = int(np.prod(shape))
+        out[name] = theta[o:o + n].reshape(shape)
+        o += n
+    return out
+
+
+def pack(p):
+    return np.concatenate([np.asarray(p[name], np.float64).ravel() for name, _ in SHAPES])
+
+
+def forward(theta, X):
+    """Predictions y [n] for inputs X [n][20], and the activations."""
+    p = unpack(theta)
+    X = np.asarray(X, np.float64)
+    z1 = X @ p["W1"].T + p["b1"]
+    h1 = np.maximum(z1, 0.0)
+    z2 = h1 @ p["W2"].T + p["b2"]
+    h2 = np.maximum(z2, 0.0)
+    y = h2 @ p["w3"] + p["b3"][0]
+    return y, (X, z1, h1, z2, h2)
+
+
+def loss(theta, X, t):
+    y, _ = forward(theta, X)
+    return float(np.mean((y - np.asarray(t, np.float64)) ** 2))
+
+
+def gradient(theta, X, t):
+    """Exact gradient of the mean squared error with respect to theta."""
+    p = unpack(theta)
+    y, (X, z1, h1, z2, h2) = forward(theta, X)
+    n = X.shape[0]
+    dy = 2.0 * (y - np.asarray(t, np.float64)) / n
+    g = {"w3": h2.T @ dy, "b3": np.array([dy.sum()])}
+    dz2 = np.outer(dy, p["w3"]) * (z2 > 0)
+    g["W2"] = dz2.T @ h1
+    g["b2"] = dz2.sum(axis=0)
+    dz1 = (dz2 @ p["W2"]) * (z1 > 0)
+    g["W1"] = dz1.T @ X
+    g["b1"] = dz1.sum(axis=0)
+    return pack(g)
+
+
+def bf16(a):
+    """Round to bfloat16 (nearest, ties to even) and return as FP64."""
+    a32 = np.ascontiguousarray(a, dtype=np.float32)
+    u = a32.view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint32) << 16
+    return r.view(np.float32).astype(np.float64)

@@ -23,7 +23,11 @@ STORE = {"f32": 0, "bf16": 1, "f16": 2}
 EXPORTS = ["morea_problem_create", "morea_problem_destroy", "morea_cache_bytes", "morea_eval_full",
            "morea_set_groups", "morea_reserve_partial", "morea_eval_partial",
            "morea_debug_distance_map", "morea_tune_partial", "morea_partial_shape",
-           "morea_last_error"]
+           "morea_surrogate_num_params", "morea_surrogate_create", "morea_surrogate_destroy",
+           "morea_surrogate_features", "morea_surrogate_targets", "morea_surrogate_train_step",
+           "morea_surrogate_gradients", "morea_surrogate_predict_rows", "morea_surrogate_prescreen",
+           "morea_surrogate_select", "morea_surrogate_get_params", "morea_surrogate_set_params",
+           "morea_surrogate_stats", "morea_last_error"]
 
 
 class MoreaError(RuntimeError):
@@ -77,6 +81,28 @@ def load_library():
     L.morea_partial_shape.restype = I32
     L.morea_debug_distance_map.argtypes = [P, I32, I32, P, P]
     L.morea_debug_distance_map.restype = I32
+    L.morea_surrogate_num_params.argtypes = []
+    L.morea_surrogate_num_params.restype = I32
+    L.morea_surrogate_create.argtypes = [P, I32, ctypes.c_uint64, ctypes.POINTER(P)]
+    L.morea_surrogate_create.restype = I32
+    L.morea_surrogate_destroy.argtypes = [P]
+    L.morea_surrogate_destroy.restype = None
+    for name, n in [("features", 5), ("targets", 5), ("predict_rows", 5), ("prescreen", 5)]:
+        f = getattr(L, "morea_surrogate_" + name)
+        f.argtypes = [P, P, I32, P, P]
+        f.restype = I32
+    L.morea_surrogate_train_step.argtypes = [P, P, P, I32, ctypes.c_float, P, P]
+    L.morea_surrogate_train_step.restype = I32
+    L.morea_surrogate_gradients.argtypes = [P, P, P, I32, P, P, P]
+    L.morea_surrogate_gradients.restype = I32
+    L.morea_surrogate_select.argtypes = [P, I32, I32, P, I32, P, P, P]
+    L.morea_surrogate_select.restype = I32
+    for name in ["get_params", "set_params"]:
+        f = getattr(L, "morea_surrogate_" + name)
+        f.argtypes = [P, P]
+        f.restype = I32
+    L.morea_surrogate_stats.argtypes = [P, P, P]
+    L.morea_surrogate_stats.restype = I32
     L.morea_last_error.argtypes = []
     L.morea_last_error.restype = ctypes.c_char_p
     _lib = L
@@ -286,3 +312,102 @@ class Problem:
 
     def distance_map(self, image, set_index):
         return morea_debug_distance_map(self.handle, image, set_index, self.dims[::-1])
+
+
+class Surrogate:
+    """The learned pre-screen (see include/morea.h); tensors are CUDA tensors."""
+
+    def __init__(self, problem: "Problem", max_rows: int = 1 << 16, seed: int = 0):
+        self.problem = problem
+        self.n_params = load_library().morea_surrogate_num_params()
+        h = ctypes.c_void_p()
+        _check(load_library().morea_surrogate_create(problem.handle, int(max_rows), int(seed),
+                                                     ctypes.byref(h)))
+        self.handle = h
+        self.max_rows = int(max_rows)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load_library().morea_surrogate_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def features(self, pts, stream=None):
+        import torch
+        out = torch.empty((pts.shape[0], self.problem.n_tets, 20), dtype=torch.float32, device="cuda")
+        _check(load_library().morea_surrogate_features(self.handle, _dev_ptr(pts), pts.shape[0],
+                                                       _dev_ptr(out), _stream_ptr(stream)))
+        return out
+
+    def targets(self, cache, pop, stream=None):
+        import torch
+        out = torch.empty((pop, self.problem.n_tets), dtype=torch.float32, device="cuda")
+        _check(load_library().morea_surrogate_targets(self.handle, _dev_ptr(cache), pop, _dev_ptr(out),
+                                                      _stream_ptr(stream)))
+        return out
+
+    def train_step(self, feats, targets, lr, loss_out=None, stream=None):
+        n = targets.numel()
+        _check(load_library().morea_surrogate_train_step(self.handle, _dev_ptr(feats), _dev_ptr(targets),
+                                                         n, float(lr), _dev_ptr(loss_out),
+                                                         _stream_ptr(stream)))
+
+    def gradients(self, feats, targets, stream=None):
+        import torch
+        g = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        _check(load_library().morea_surrogate_gradients(self.handle, _dev_ptr(feats), _dev_ptr(targets),
+                                                        targets.numel(), _dev_ptr(g), _dev_ptr(loss),
+                                                        _stream_ptr(stream)))
+        return g, loss
+
+    def predict_rows(self, feats, stream=None):
+        import torch
+        n = feats.numel() // 20
+        y = torch.empty(n, dtype=torch.float32, device="cuda")
+        _check(load_library().morea_surrogate_predict_rows(self.handle, _dev_ptr(feats), n, _dev_ptr(y),
+                                                           _stream_ptr(stream)))
+        return y
+
+    def prescreen(self, pts, score=None, stream=None):
+        import torch
+        score = torch.empty(pts.shape[0], dtype=torch.float32, device="cuda") if score is None else score
+        _check(load_library().morea_surrogate_prescreen(self.handle, _dev_ptr(pts), pts.shape[0],
+                                                        _dev_ptr(score), _stream_ptr(stream)))
+        return score
+
+    def get_params(self):
+        out = np.empty(self.n_params, np.float32)
+        _check(load_library().morea_surrogate_get_params(self.handle, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def set_params(self, params):
+        a = _host(params, np.float32)
+        assert a.size == self.n_params
+        _check(load_library().morea_surrogate_set_params(self.handle, a.ctypes.data_as(ctypes.c_void_p)))
+
+    def stats(self):
+        st = np.empty((self.problem.n_tets, 8), np.float32)
+        cnt = np.empty(self.problem.n_tets, np.int32)
+        _check(load_library().morea_surrogate_stats(self.handle, st.ctypes.data_as(ctypes.c_void_p),
+                                                    cnt.ctypes.data_as(ctypes.c_void_p)))
+        return st, cnt
+
+
+def morea_surrogate_select(score, k, pts=None, n_points=0, stream=None):
+    """Indices of the k lowest scores and (optionally) the selected candidates."""
+    import torch
+    idx = torch.empty(k, dtype=torch.int32, device="cuda")
+    sel = None
+    if pts is not None:
+        sel = torch.empty((k,) + tuple(pts.shape[1:]), dtype=torch.float32, device="cuda")
+        n_points = pts.shape[-1]
+    _check(load_library().morea_surrogate_select(_dev_ptr(score), score.numel(), k, _dev_ptr(pts),
+                                                 n_points, _dev_ptr(idx), _dev_ptr(sel),
+                                                 _stream_ptr(stream)))
+    return idx, sel

@@ -79,6 +79,10 @@ void free_all(morea_problem* p) {
 
 }  // namespace
 
+namespace morea {
+void set_error(const char* msg) { g_error = msg; }
+}  // namespace morea
+
 extern "C" {
 
 const char* morea_last_error(void) { return g_error.c_str(); }
@@ -97,6 +101,8 @@ morea_status morea_problem_create(const morea_problem_desc* d, morea_problem** o
   if (d->max_population < 1) return fail(MOREA_EINVAL, "max_population must be >= 1");
   const int nx = d->dims[0], ny = d->dims[1], nz = d->dims[2];
   const size_t V = static_cast<size_t>(nx) * ny * nz;
+  if (V > (static_cast<size_t>(1) << 29))
+    return fail(MOREA_EINVAL, "%zu voxels per image exceed the limit 2^29", V);
   for (size_t i = 0; i < V; i++) {
     float a = d->image_src[i], b = d->image_tgt[i];
     if (!(a >= 0.f && a < INFINITY) || !(b >= 0.f && b < INFINITY))
@@ -159,6 +165,7 @@ morea_status morea_problem_create(const morea_problem_desc* d, morea_problem** o
   p->max_population = d->max_population;
   p->voxels = V;
   p->tets_host.assign(d->tets, d->tets + 4 * static_cast<size_t>(d->n_tets));
+  p->ref_host.assign(d->ref_points, d->ref_points + 3 * static_cast<size_t>(d->n_points));
   ProblemView& P = p->view;
   P.nx = nx;
   P.ny = ny;

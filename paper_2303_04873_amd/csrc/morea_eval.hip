@@ -103,24 +103,33 @@ __device__ __forceinline__ int64_t det_i64(const int v[4][3]) {
   return a0 * (b1 * c2 - b2 * c1) - a1 * (b0 * c2 - b2 * c0) + a2 * (b0 * c1 - b1 * c0);
 }
 
-// Per-item constants, written once per work item into the wave's LDS and
-// read back (broadcast) by the row and sample loops.  Face plane i evaluated
-// at voxel (lo0 + j, lo1 + yr, lo2 + zr), plus its tie-break bit lex_i, is
+// Per-direction constants of a work item, written once into the wave's LDS
+// and read back by the row and sample loops.  Direction 0 rasterizes the
+// source tet S on I_s and samples I_t; direction 1 the target tet T on I_t
+// and samples I_s.  Face plane i of the rasterized tet evaluated at voxel
+// (lo0 + j, lo1 + yr, lo2 + zr), plus its tie-break bit lex_i, is
 //   s_i + lex_i = A_i j + PY_i yr + PZ_i zr + B0_i      (exact integers)
 // and the mapped point is q = qlo + M (p - lo).
-struct ItemConst {
-  double A[4], invA[4], PY[4], PZ[4], B0[4];   // exact in FP64 when the extent is <= 2^16
+struct DirConst {
+  double A[4], PY[4], PZ[4], B0[4];            // exact in FP64 when the extent is <= 2^16
+  double invA[4];
   long long Ai[4], PYi[4], PZi[4], B0i[4];     // int64 copies for wider tets
+  // x position of face i's plane on row (yr, zr): t_i = TA yr + TB zr + TG
+  // (= -(PY yr + PZ zr + B0) / A); for a face with A = 0 the same three
+  // numbers hold PY, PZ, B0 (so "t" is the face value itself).  TE bounds the
+  // FP64 error of t.
+  double TA[4], TB[4], TG[4], TE[4];
   int kind[4];                                 // sign of A_i
   int lex[4];                                  // tie-break bit of face i
-  // x position of face i's plane on row (yr, zr): t_i = TA yr + TB zr + TG
-  // (= -(PY yr + PZ zr + B0) / A), with TE an error bound of that estimate
-  double TA[4], TB[4], TG[4], TE[4];
   double n[4][3];                              // oriented face normals (set-up only)
   double M[3][3];
   double Mabs[3][3];
   double qlo[3];
   double guard[3];                             // FP64 error bound of q per axis (x1000 margin)
+  double gthr[3];                              // 0.5 - guard: near-grid iff |frac(q) - 0.5| >= gthr
+  int64_t absD;
+  int fast;                                    // extent <= 2^16: FP64 plane arithmetic
+  int pad;
 };
 
 // 6 x signed volume in FP64: exact when every coordinate difference is
@@ -132,15 +141,16 @@ __device__ __forceinline__ double det_f64(const int v[4][3]) {
   return a0 * (b1 * c2 - b2 * c1) - a1 * (b0 * c2 - b2 * c0) + a2 * (b0 * c1 - b1 * c0);
 }
 
-// LDS scratch of one wave.
 constexpr int kDeferCap = 128;
 
+// LDS scratch of one wave.
 struct WaveLds {
-  ItemConst c;
-  int4 row[kWave];   // x start, y | z << 16, first sample, unused
+  DirConst c[2];
+  int4 row[kWave];         // x, y | z << 16, first sample, jx | jy << 10 | jz << 20
+  double rowq[kWave][4];   // mapped point of each row's first sample (x, y, z, unused)
   int mark[kWave];
-  int4 defer[kDeferCap];   // near-grid samples: (j | yr << 10 | zr << 20, a, b, amb | fg_a << 3)
-  int vert[24];   // snapped own tet (12), then other tet (12)
+  int4 defer[kDeferCap];   // near-grid samples: (jx | jy << 10 | jz << 20 | dir << 30, a, b, axes)
+  int vert[24];            // snapped S (12), then T (12)
 };
 
 // Exact support test of the trilinear stencil (rare path, taken only when
@@ -153,18 +163,20 @@ struct WaveLds {
 // in-grid corner is > 0.
 template <int ST>
 __device__ __forceinline__ bool exact_foreground(const void* img, int nx, int ny, int nz,
-                                                 const WaveLds* L, bool fast, int64_t absD,
-                                                 int jx, int jy, int jz, const double q[3], int amb) {
+                                                 const WaveLds* L, int d, int jx, int jy, int jz,
+                                                 const double q[3], int amb) {
+  const DirConst& c = L->c[d];
+  const int* oth = L->vert + (d == 0 ? 12 : 0);
   int64_t s[4];
 #pragma unroll
   for (int i = 0; i < 4; i++) {
-    if (fast)
-      s[i] = static_cast<int64_t>(fma(L->c.A[i], jx, fma(L->c.PY[i], jy, fma(L->c.PZ[i], jz, L->c.B0[i]))));
+    if (c.fast)
+      s[i] = static_cast<int64_t>(fma(c.A[i], jx, fma(c.PY[i], jy, fma(c.PZ[i], jz, c.B0[i]))));
     else
-      s[i] = L->c.Ai[i] * jx + L->c.PYi[i] * jy + L->c.PZi[i] * jz + L->c.B0i[i];
-    s[i] -= L->c.lex[i];
+      s[i] = c.Ai[i] * jx + c.PYi[i] * jy + c.PZi[i] * jz + c.B0i[i];
+    s[i] -= c.lex[i];
   }
-  const __int128 den = static_cast<__int128>(absD) * 1024;
+  const __int128 den = static_cast<__int128>(c.absD) * 1024;
   int lo[3], hi[3];
 #pragma unroll
   for (int a = 0; a < 3; a++) {
@@ -173,7 +185,7 @@ __device__ __forceinline__ bool exact_foreground(const void* img, int nx, int ny
     if (amb & (1 << a)) {
       __int128 num = 0;
 #pragma unroll
-      for (int i = 0; i < 4; i++) num += static_cast<__int128>(s[i]) * L->vert[12 + 3 * i + a];
+      for (int i = 0; i < 4; i++) num += static_cast<__int128>(s[i]) * oth[3 * i + a];
       // exact floor of num / den from the FP64 estimate; the mapped point is
       // a convex combination of valid vertices, so |k| <= 513
       k = min(max(k, -600), 600);
@@ -193,8 +205,7 @@ __device__ __forceinline__ bool exact_foreground(const void* img, int nx, int ny
   return fg;
 }
 
-// x-interval [js, je] (relative to the bounding-box start, clipped to
-// [0, W]) of one row: the j with A_i j + b_i > 0 for every face.  The FP64
+// Exact x-interval update for one face: the j with A j + b > 0.  The FP64
 // quotient estimate is corrected by one exact evaluation on each side; T is
 // double (exact for extents <= 2^16) or int64.
 template <typename T>
@@ -216,81 +227,99 @@ __device__ __forceinline__ void clip_face(int kind, T A, double invA, T b, int W
   }
 }
 
-__device__ __forceinline__ void span_fast(const ItemConst& c, int yr, int zr, int W, int& js, int& je) {
+// x-interval [js, je] (relative to the box start, within [0, W]) of row
+// (yr, zr) of one direction.  Extents <= 2^16: the FP64 boundary estimate
+// decides away from integers, the exact test near them.  Wider tets: int64.
+__device__ __forceinline__ void row_span(const DirConst& c, int yr, int zr, int W, int& js, int& je) {
   js = 0;
   je = W;
-  const double y = yr, z = zr;
+  if (c.fast) {
+    const double y = yr, z = zr;
 #pragma unroll
-  for (int i = 0; i < 4; i++) {
-    const int kind = __builtin_amdgcn_readfirstlane(c.kind[i]);
-    if (kind == 0) {
-      const double b = fma(c.PY[i], y, fma(c.PZ[i], z, c.B0[i]));
-      if (!(b > 0.0)) je = -1;
-      continue;
+    for (int i = 0; i < 4; i++) {
+      const int kind = c.kind[i];
+      const double t = fma(c.TA[i], y, fma(c.TB[i], z, c.TG[i]));
+      if (kind != 0 && fabs(t - rint(t)) <= c.TE[i] && t > -3.0 && t < W + 3.0) {
+        const double b = fma(c.PY[i], y, fma(c.PZ[i], z, c.B0[i]));
+        clip_face<double>(kind, c.A[i], c.invA[i], b, W, js, je);
+      } else {
+        const int fl = static_cast<int>(floor(fmin(fmax(t, -2.0), W + 1.0)));
+        js = kind > 0 ? max(js, fl + 1) : js;
+        je = kind < 0 ? min(je, fl) : ((kind == 0 && !(t > 0.0)) ? -1 : je);
+      }
     }
-    // boundary position t: row samples j with j > t (kind > 0) or j < t
-    // (kind < 0) are inside this face.  Away from integers the FP64
-    // estimate decides; near one (within its error bound) the exact
-    // integer test does.
-    const double t = fma(c.TA[i], y, fma(c.TB[i], z, c.TG[i]));
-    const double tr = rint(t);
-    if (fabs(t - tr) <= c.TE[i] && t > -3.0 && t < W + 3.0) {
-      const double b = fma(c.PY[i], y, fma(c.PZ[i], z, c.B0[i]));
-      clip_face<double>(kind, c.A[i], c.invA[i], b, W, js, je);
-    } else {
-      const int fl = static_cast<int>(floor(fmin(fmax(t, -2.0), W + 1.0)));
-      if (kind > 0)
-        js = max(js, fl + 1);
-      else
-        je = min(je, fl);
+  } else {
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      const long long b = c.PYi[i] * yr + c.PZi[i] * zr + c.B0i[i];
+      clip_face<long long>(c.kind[i], c.Ai[i], c.invA[i], b, W, js, je);
     }
   }
 }
 
-__device__ __forceinline__ void span_wide(const ItemConst& c, int yr, int zr, int W, int& js, int& je) {
-  js = 0;
-  je = W;
-#pragma unroll
-  for (int i = 0; i < 4; i++) {
-    const int kind = __builtin_amdgcn_readfirstlane(c.kind[i]);
-    const long long b = c.PYi[i] * yr + c.PZi[i] * zr + c.B0i[i];
-    clip_face<long long>(kind, c.Ai[i], c.invA[i], b, W, js, je);
+// Buffer resource over a stored image including its padding, so that
+// element index i (from -kImagePad) is byte offset (i + kImagePad) * size.
+template <int ST>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t image_rsrc(const void* img, unsigned voxels) {
+  constexpr int esize = ST == kF32 ? 4 : 2;
+  char* base = const_cast<char*>(static_cast<const char*>(img)) - kImagePad * esize;
+  return __builtin_amdgcn_make_buffer_rsrc(base, static_cast<short>(0),
+                                           static_cast<int>((voxels + 2 * kImagePad) * esize), 0x00020000);
+}
+
+template <int ST>
+__device__ __forceinline__ float ld_buf(__amdgpu_buffer_rsrc_t r, int idx) {
+  if constexpr (ST == kF32) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (idx + kImagePad) * 4, 0, 0));
+  } else {
+    const unsigned short u = __builtin_amdgcn_raw_buffer_load_b16(r, (idx + kImagePad) * 2, 0, 0);
+    if constexpr (ST == kBF16)
+      return __uint_as_float(static_cast<uint32_t>(u) << 16);
+    else
+      return static_cast<float>(__builtin_bit_cast(_Float16, u));
   }
 }
 
-// One voxel sample p = (x, y, z) of a work item: map it into the other tet
-// (q = qlo + M (p - lo) in FP64), sample the other image trilinearly with
-// zero padding, decide foreground exactly, add h (Sec. 4.1.2) and, inside
-// the guidance band, the set-weighted guidance term (Sec. 4.1.3, App. A.3).
-// INTERIOR: every corner of every mapped point lies inside the grid (the
-// other tet is at least 2^-10 voxel inside it), so no clamping is needed.
-// Returns the axes on which the mapped point is within its error bound of a
-// grid plane; such a sample's h is left to the caller (deferred queue).
+// Two consecutive FP32 voxels (idx, idx + 1) in one 8-byte buffer load.
+__device__ __forceinline__ F2 ld_pair(__amdgpu_buffer_rsrc_t r, int idx) {
+  typedef float f2v __attribute__((ext_vector_type(2)));
+  const f2v v = __builtin_bit_cast(f2v, __builtin_amdgcn_raw_buffer_load_b64(r, (idx + kImagePad) * 4, 0, 0));
+  return F2{v.x, v.y};
+}
+
+// One voxel sample: the centre p = (x, y, z) of direction d whose mapped
+// point is q = q_row + k * M[:, 0] (q_row of the sample's row, k its offset
+// in the row).  Samples the other image trilinearly with zero padding, adds
+// h (Sec. 4.1.2) and, inside the guidance band, the set-weighted guidance
+// term (Sec. 4.1.3, App. A.3).
+// INTERIOR: every corner of every mapped point lies inside the grid, so no
+// clamping is needed.  Returns the axes on which the mapped point is within
+// its error bound of a grid plane; such a sample's h is left to the caller
+// (a_out, b_out carry what it needs).
 template <int ST, bool INTERIOR>
-__device__ __forceinline__ int sample_one(const ProblemView& P, WaveLds* L, int dir, int x, int yy,
-                                          int zz, const int lo[3], float& h_acc, float& g_acc,
-                                          float& a_out, float& b_out) {
+__device__ __forceinline__ int sample_one(const ProblemView& P, const DirConst& C,
+                                          __amdgpu_buffer_rsrc_t r_own, __amdgpu_buffer_rsrc_t r_oth,
+                                          int d, int x, int yy, int zz, const double qr[3], int k,
+                                          float& h_acc, float& g_acc, float& a_out, float& b_out) {
   const int nx = P.nx, ny = P.ny, nz = P.nz;
-  const unsigned sy = static_cast<unsigned>(nx), sz = static_cast<unsigned>(nx * ny);
-  const void* img_oth = P.img[1 - dir];
-  const unsigned vi = __umul24(__umul24(zz, ny) + yy, nx) + x;
-  const float a = ld_img<ST>(P.img[dir], vi);
-  const double dx = x - lo[0], dy = yy - lo[1], dz = zz - lo[2];
+  const int sy = nx, sz = nx * ny;
+  const int vi = __umul24(__umul24(zz, ny) + yy, nx) + x;
+  const float a = ld_buf<ST>(r_own, vi);
+  const double kd = k;
   double qd[3];
   float f[3];
   int c[3];
   int amb = 0;
 #pragma unroll
-  for (int k = 0; k < 3; k++) {
-    qd[k] = fma(L->c.M[k][0], dx, fma(L->c.M[k][1], dy, fma(L->c.M[k][2], dz, L->c.qlo[k])));
-    const double fl = floor(qd[k]);
-    const double fr = qd[k] - fl;
-    f[k] = static_cast<float>(fr);
-    c[k] = static_cast<int>(fl);
-    const double g = L->c.guard[k];
-    if (fr <= g || fr >= 1.0 - g) amb |= 1 << k;
+  for (int t = 0; t < 3; t++) {
+    qd[t] = fma(C.M[t][0], kd, qr[t]);
+    const double fl = floor(qd[t]);
+    const double fr = qd[t] - fl;
+    f[t] = static_cast<float>(fr);
+    c[t] = static_cast<int>(fl);
+    if (fabs(fr - 0.5) >= C.gthr[t]) amb |= 1 << t;
   }
-  unsigned cx0, cx1, cy0, cy1, cz0, cz1;
+  int cx0, cx1, cy0, cy1, cz0, cz1;
   if constexpr (INTERIOR) {
     cx0 = c[0]; cx1 = c[0] + 1; cy0 = c[1]; cy1 = c[1] + 1; cz0 = c[2]; cz1 = c[2] + 1;
   } else {
@@ -298,26 +327,23 @@ __device__ __forceinline__ int sample_one(const ProblemView& P, WaveLds* L, int 
     cy0 = min(max(c[1], 0), ny - 1); cy1 = min(max(c[1] + 1, 0), ny - 1);
     cz0 = min(max(c[2], 0), nz - 1); cz1 = min(max(c[2] + 1, 0), nz - 1);
   }
-  const unsigned z0 = __umul24(cz0, sz), z1 = __umul24(cz1, sz);
-  const unsigned r00 = z0 + __umul24(cy0, sy), r01 = z0 + __umul24(cy1, sy);
-  const unsigned r10 = z1 + __umul24(cy0, sy), r11 = z1 + __umul24(cy1, sy);
+  const int z0 = __umul24(cz0, sz), z1 = __umul24(cz1, sz);
+  const int r00 = z0 + __umul24(cy0, sy), r01 = z0 + __umul24(cy1, sy);
+  const int r10 = z1 + __umul24(cy0, sy), r11 = z1 + __umul24(cy1, sy);
   float v000, v001, v010, v011, v100, v101, v110, v111;
   if constexpr (ST == kF32) {
-    // one 8-byte load per corner pair (x, x+1); the image allocation is
-    // padded so that x = -1 and x = nx - 1 stay inside it
+    // one 8-byte load per corner pair (x, x+1); the padding keeps x = -1
+    // and x = nx - 1 inside the buffer
     const int xs = INTERIOR ? c[0] : min(max(c[0], -1), nx - 1);
-    const float* base = static_cast<const float*>(img_oth) + xs;
-    const F2 p00 = *reinterpret_cast<const F2*>(base + r00);
-    const F2 p01 = *reinterpret_cast<const F2*>(base + r01);
-    const F2 p10 = *reinterpret_cast<const F2*>(base + r10);
-    const F2 p11 = *reinterpret_cast<const F2*>(base + r11);
+    const F2 p00 = ld_pair(r_oth, r00 + xs), p01 = ld_pair(r_oth, r01 + xs);
+    const F2 p10 = ld_pair(r_oth, r10 + xs), p11 = ld_pair(r_oth, r11 + xs);
     v000 = p00.a; v001 = p00.b; v010 = p01.a; v011 = p01.b;
     v100 = p10.a; v101 = p10.b; v110 = p11.a; v111 = p11.b;
   } else {
-    v000 = ld_img<ST>(img_oth, r00 + cx0); v001 = ld_img<ST>(img_oth, r00 + cx1);
-    v010 = ld_img<ST>(img_oth, r01 + cx0); v011 = ld_img<ST>(img_oth, r01 + cx1);
-    v100 = ld_img<ST>(img_oth, r10 + cx0); v101 = ld_img<ST>(img_oth, r10 + cx1);
-    v110 = ld_img<ST>(img_oth, r11 + cx0); v111 = ld_img<ST>(img_oth, r11 + cx1);
+    v000 = ld_buf<ST>(r_oth, r00 + cx0); v001 = ld_buf<ST>(r_oth, r00 + cx1);
+    v010 = ld_buf<ST>(r_oth, r01 + cx0); v011 = ld_buf<ST>(r_oth, r01 + cx1);
+    v100 = ld_buf<ST>(r_oth, r10 + cx0); v101 = ld_buf<ST>(r_oth, r10 + cx1);
+    v110 = ld_buf<ST>(r_oth, r11 + cx0); v111 = ld_buf<ST>(r_oth, r11 + cx1);
   }
   if constexpr (!INTERIOR) {
     const bool vx0 = c[0] >= 0 && c[0] < nx, vx1 = c[0] >= -1 && c[0] < nx - 1;
@@ -340,25 +366,27 @@ __device__ __forceinline__ int sample_one(const ProblemView& P, WaveLds* L, int 
                          fmaxf(fmaxf(v100, v101), fmaxf(v110, v111))) > 0.f);
 
   if (P.n_sets > 0) {
-    unsigned bandbits = P.band[dir][vi];
+    unsigned bandbits = (d ? P.band[1] : P.band[0])[vi];
     if (bandbits) {
       // the other distance map is edge-clamped: the clamped corners above
       // are exactly that (and interior corners need no clamping)
       const unsigned V = static_cast<unsigned>(nx * ny * nz);
       const float r = P.radius, inv_r = P.inv_radius;
+      const float* map_own = d ? P.dmap[1] : P.dmap[0];
+      const float* map_oth = d ? P.dmap[0] : P.dmap[1];
       while (bandbits) {
         const int sidx = __builtin_ctz(bandbits);
         bandbits &= bandbits - 1;
-        const float* mo = P.dmap[1 - dir] + static_cast<size_t>(sidx) * V;
-        const float d = P.dmap[dir][static_cast<size_t>(sidx) * V + vi];
+        const float* mo = map_oth + static_cast<size_t>(sidx) * V;
+        const float dist = map_own[static_cast<size_t>(sidx) * V + vi];
         const float u00 = fmaf(f[0], mo[r00 + cx1] - mo[r00 + cx0], mo[r00 + cx0]);
         const float u01 = fmaf(f[0], mo[r01 + cx1] - mo[r01 + cx0], mo[r01 + cx0]);
         const float u10 = fmaf(f[0], mo[r10 + cx1] - mo[r10 + cx0], mo[r10 + cx0]);
         const float u11 = fmaf(f[0], mo[r11 + cx1] - mo[r11 + cx0], mo[r11 + cx0]);
         const float u0 = fmaf(f[1], u01 - u00, u00), u1 = fmaf(f[1], u11 - u10, u10);
         const float d2 = fmaf(f[2], u1 - u0, u0);
-        const float diff = d - d2;
-        g_acc += P.set_w[dir][sidx] * ((r - d) * inv_r) * diff * diff;
+        const float diff = dist - d2;
+        g_acc += P.set_w[d][sidx] * ((r - dist) * inv_r) * diff * diff;
       }
     }
   }
@@ -376,84 +404,98 @@ __device__ __forceinline__ int sample_one(const ProblemView& P, WaveLds* L, int 
 
 // Resolve the deferred near-grid samples of a wave: one sample per lane,
 // the mapped point recomputed from the item constants, foreground decided
-// on the exact support, h returned for accumulation.
+// on the exact support; h is added to the accumulator of its direction.
 template <int ST>
-__device__ __forceinline__ float flush_deferred(const ProblemView& P, const WaveLds* L, int dir,
-                                             const int lo[3], bool fast, int64_t absD, int count) {
+__device__ __forceinline__ void flush_deferred(const ProblemView& P, const WaveLds* L, int count,
+                                               float& h0, float& h1) {
   const int lane = lane_id();
-  float h = 0.f;
   for (int base = 0; base < count; base += kWave) {
     const int e = base + lane;
     if (e >= count) continue;
-    const int4 d = L->defer[e];
-    const int jx = d.x & 1023, jy = (d.x >> 10) & 1023, jz = (d.x >> 20) & 1023;
-    const float a = __int_as_float(d.y), b = __int_as_float(d.z);
+    const int4 q4 = L->defer[e];
+    const int jx = q4.x & 1023, jy = (q4.x >> 10) & 1023, jz = (q4.x >> 20) & 1023, d = (q4.x >> 30) & 1;
+    const float a = __int_as_float(q4.y), b = __int_as_float(q4.z);
+    const DirConst& C = L->c[d];
     double q[3];
 #pragma unroll
     for (int k = 0; k < 3; k++)
-      q[k] = fma(L->c.M[k][0], static_cast<double>(jx),
-                 fma(L->c.M[k][1], static_cast<double>(jy), fma(L->c.M[k][2], static_cast<double>(jz), L->c.qlo[k])));
-    const bool fg_b = exact_foreground<ST>(P.img[1 - dir], P.nx, P.ny, P.nz, L, fast, absD, jx, jy, jz, q, d.w);
+      q[k] = fma(C.M[k][0], static_cast<double>(jx),
+                 fma(C.M[k][1], static_cast<double>(jy), fma(C.M[k][2], static_cast<double>(jz), C.qlo[k])));
+    const bool fg_b = exact_foreground<ST>(d ? P.img[0] : P.img[1], P.nx, P.ny, P.nz, L, d, jx, jy,
+                                           jz, q, q4.w);
     const bool fg_a = a > 0.f;
     const float dd = a - (fg_b ? b : 0.f);
-    h += (fg_a && fg_b) ? dd * dd : ((fg_a != fg_b) ? 1.f : 0.f);
+    const float h = (fg_a && fg_b) ? dd * dd : ((fg_a != fg_b) ? 1.f : 0.f);
+    if (d) h1 += h; else h0 += h;
   }
-  return h;
 }
 
-// Evaluate one (tet, direction) for the candidate whose vertex coordinates
-// are held by lanes 0..23 (`coord`: lanes 0..11 own tet v0x v0y v0z v1x ...,
-// lanes 12..23 the other tet).  The wave writes one Record.
+// Evaluate one tet of one candidate in both directions.  Lanes 0..11 hold
+// the source tet's coordinates (v0x v0y v0z v1x ...), lanes 12..23 the
+// target tet's (`coord`).  The wave writes out[0] (direction 0) and out[1].
 template <int ST>
-__device__ void eval_tet_dir(const ProblemView& P, int tet, int dir, float coord, WaveLds* L,
-                             Record* out) {
+__device__ void eval_tet(const ProblemView& P, int tet, float coord, WaveLds* L, Record* out) {
   const int lane = lane_id();
   // ---- snap and validate (the loading lane snaps its own coordinate)
   const bool in_range = lane >= 24 || fabsf(coord) < kCoordLimit;
   const bool all_ok = __ballot(in_range) == ~0ull;
   const int fix = (lane < 24 && in_range) ? static_cast<int>(rintf(coord * kFixOne)) : 0;
   if (!all_ok) {
-    if (lane == 0) *out = Record{0.f, 0.f, 0u, 0.f, 0.f, 4u};
+    if (lane < 2) out[lane] = Record{0.f, 0.f, 0u, 0.f, 0.f, 4u};
     return;
   }
   if (lane < 24) L->vert[lane] = fix;
-  int own[4][3];
+  int V[2][4][3];
 #pragma unroll
-  for (int i = 0; i < 4; i++)
+  for (int m = 0; m < 2; m++)
 #pragma unroll
-    for (int k = 0; k < 3; k++) own[i][k] = __builtin_amdgcn_readlane(fix, 3 * i + k);
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+      for (int k = 0; k < 3; k++) V[m][i][k] = __builtin_amdgcn_readlane(fix, 12 * m + 3 * i + k);
   wave_sync();
 
-  // ---- bounding box on this direction's grid
-  int lo[3], hi[3], ext = 0;
+  // ---- per direction: box on its grid, fold check (App. A.4), interior flag
   const int dims[3] = {P.nx, P.ny, P.nz};
-#pragma unroll
-  for (int k = 0; k < 3; k++) {
-    const int mn = min(min(own[0][k], own[1][k]), min(own[2][k], own[3][k]));
-    const int mx = max(max(own[0][k], own[1][k]), max(own[2][k], own[3][k]));
-    ext = max(ext, mx - mn);
-    lo[k] = max(0, -static_cast<int>(floor_div_pos(-static_cast<int64_t>(mn), 1024)));
-    hi[k] = min(dims[k] - 1, static_cast<int>(floor_div_pos(mx, 1024)));
-  }
-  const bool fast = ext <= kFastExtent;
-
-  // ---- fold check (App. A.4): exact signed volume vs the reference sign
-  // (FP64 is exact for extents <= 2^16: |6V| <= 6 E^3 < 2^53)
-  const int64_t D = fast ? static_cast<int64_t>(det_f64(own)) : det_i64(own);
   const int ref = P.ref_sign[tet];
-  const int sgnD = (D > 0) - (D < 0);
-  const bool viol = (sgnD == 0) || (sgnD != ref);
-  const int64_t absD = D < 0 ? -D : D;
-  Record rec{0.f, 0.f, 0u, 0.f, 0.f, viol ? 1u : 0u};
-  if (viol) rec.vol = static_cast<float>(static_cast<double>(absD) * (1.0 / (6.0 * 1073741824.0)));
+  int lo[2][3], hi[2][3], R[2], NYb[2], W[2];
+  bool fast[2], interior[2], active[2];
+  int64_t D[2];
+  Record rec[2];
+#pragma unroll
+  for (int m = 0; m < 2; m++) {
+    int ext = 0;
+    interior[m] = true;
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+      const int mn = min(min(V[m][0][k], V[m][1][k]), min(V[m][2][k], V[m][3][k]));
+      const int mx = max(max(V[m][0][k], V[m][1][k]), max(V[m][2][k], V[m][3][k]));
+      ext = max(ext, mx - mn);
+      lo[m][k] = max(0, -static_cast<int>(floor_div_pos(-static_cast<int64_t>(mn), 1024)));
+      hi[m][k] = min(dims[k] - 1, static_cast<int>(floor_div_pos(mx, 1024)));
+      // the tet of mesh m is sampled by direction 1 - m: all trilinear
+      // corners are valid voxels when it is >= 2^-10 voxel inside the grid
+      interior[m] = interior[m] && mn >= 1 && mx <= 1024 * (dims[k] - 1) - 1;
+    }
+    fast[m] = ext <= kFastExtent;
+    // FP64 is exact for extents <= 2^16: |6V| <= 6 E^3 < 2^53
+    D[m] = fast[m] ? static_cast<int64_t>(det_f64(V[m])) : det_i64(V[m]);
+    const int sg = (D[m] > 0) - (D[m] < 0);
+    const bool viol = (sg == 0) || (sg != ref);
+    const int64_t absD = D[m] < 0 ? -D[m] : D[m];
+    rec[m] = Record{0.f, 0.f, 0u, 0.f, 0.f, viol ? 1u : 0u};
+    if (viol) rec[m].vol = static_cast<float>(static_cast<double>(absD) * (1.0 / (6.0 * 1073741824.0)));
+    active[m] = D[m] != 0 && lo[m][0] <= hi[m][0] && lo[m][1] <= hi[m][1] && lo[m][2] <= hi[m][2];
+    W[m] = hi[m][0] - lo[m][0];
+    NYb[m] = hi[m][1] - lo[m][1] + 1;
+    R[m] = active[m] ? NYb[m] * (hi[m][2] - lo[m][2] + 1) : 0;
+  }
 
-  // ---- deformation magnitude (Sec. 4.1.1), by direction 0, one edge per
-  // lane: |e_s| - |e_t| = (|e_s|^2 - |e_t|^2) / (|e_s| + |e_t|) with the
-  // squared lengths exact in int64, so small differences do not cancel.
-  if (dir == 0) {
+  // ---- deformation magnitude (Sec. 4.1.1), one edge per lane:
+  // |e_s| - |e_t| = (|e_s|^2 - |e_t|^2) / (|e_s| + |e_t|) with the squared
+  // lengths exact in FP64 (components < 2^22, sums < 2^46).
+  {
     float term = 0.f;
     if (lane < 10) {
-      // squared lengths are exact in FP64: components < 2^22, sums < 2^46
       double ls = 0.0, lt = 0.0;
       float scale;
       if (lane < 6) {
@@ -481,38 +523,34 @@ __device__ void eval_tet_dir(const ProblemView& P, int tet, int dir, float coord
         scale = 1.0f / (4.0f * kFixOne);
       }
       const float den = sqrtf(static_cast<float>(ls)) + sqrtf(static_cast<float>(lt));
-      const float d = den > 0.f ? static_cast<float>(ls - lt) / den * scale : 0.f;
-      term = d * d;
+      const float dd = den > 0.f ? static_cast<float>(ls - lt) / den * scale : 0.f;
+      term = dd * dd;
     }
-    rec.mag = P.elasticity[tet] * wave_sum(term);
+    rec[0].mag = P.elasticity[tet] * wave_sum(term);
   }
-
-  const bool empty = D == 0 || lo[0] > hi[0] || lo[1] > hi[1] || lo[2] > hi[2];
-  if (empty) {
-    if (lane == 0) *out = rec;
+  if (!active[0] && !active[1]) {
+    if (lane < 2) out[lane] = rec[lane];
     return;
   }
-  const int sigma = D > 0 ? 1 : -1;
 
-  // ---- per-item constants, spread over lanes: lanes 0..3 build face plane
-  // i (the gradient of D * lambda_i, oriented inwards, and its value at the
-  // box corner), lanes 8..10 build row a of the map and its error bound.
-  ItemConst& C = L->c;
-  const int NYb0 = hi[1] - lo[1] + 1, NZb0 = hi[2] - lo[2] + 1;
-  // phase 1, lanes 0..3: face plane i (gradient of D * lambda_i, oriented
-  // inwards, its value at the box corner, and its row-boundary estimate)
-  if (lane < 4) {
-    const int i = lane;
+  // ---- set-up phase 1, lanes 0..7 (direction d = lane / 4, face i): face
+  // plane (gradient of D * lambda_i oriented inwards, its value at the box
+  // corner, the row-boundary estimate)
+  if (lane < 8) {
+    const int d = lane >> 2, i = lane & 3;
+    DirConst& C = L->c[d];
+    const int* own = L->vert + 12 * d;
+    const int sigma = D[d] > 0 ? 1 : -1;
     const int b0 = i == 0 ? 1 : 0;                            // base vertex on the face
     const int u0 = i == 0 ? 2 : (i == 1 ? 2 : (i == 2 ? 3 : 1));
     const int w0 = i == 0 ? 3 : (i == 1 ? 3 : (i == 2 ? 1 : 2));
     double u[3], w[3], r[3];
 #pragma unroll
     for (int k = 0; k < 3; k++) {
-      const int rk = L->vert[3 * b0 + k];
+      const int rk = own[3 * b0 + k];
       r[k] = rk;
-      u[k] = L->vert[3 * u0 + k] - rk;
-      w[k] = L->vert[3 * w0 + k] - rk;
+      u[k] = own[3 * u0 + k] - rk;
+      w[k] = own[3 * w0 + k] - rk;
     }
     // cross product: |components| < 2^41, exact in FP64
     const double sg = (i == 0 ? -sigma : sigma);
@@ -523,24 +561,33 @@ __device__ void eval_tet_dir(const ProblemView& P, int tet, int dir, float coord
     C.n[i][1] = ny_;
     C.n[i][2] = nz_;
     const int lex = (nx_ > 0 || (nx_ == 0 && (ny_ > 0 || (ny_ == 0 && nz_ > 0)))) ? 1 : 0;
-    const double ox = 1024.0 * lo[0] - r[0], oy = 1024.0 * lo[1] - r[1], oz = 1024.0 * lo[2] - r[2];
+    const int* lod = lo[d];
+    const double ox = 1024.0 * lod[0] - r[0], oy = 1024.0 * lod[1] - r[1], oz = 1024.0 * lod[2] - r[2];
     const double A = nx_ * 1024.0, PY = ny_ * 1024.0, PZ = nz_ * 1024.0;
     C.A[i] = A;
     C.PY[i] = PY;
     C.PZ[i] = PZ;
     const double invA = nx_ != 0 ? 1.0 / A : 0.0;
     C.invA[i] = invA;
-    C.kind[i] = (nx_ > 0) - (nx_ < 0);
+    const int kind = (nx_ > 0) - (nx_ < 0);
+    C.kind[i] = kind;
     C.lex[i] = lex;
-    if (fast) {
+    if (fast[d]) {
       // |terms| <= 2 E^3 <= 2^49: exact
       const double B0 = fma(nx_, ox, fma(ny_, oy, nz_ * oz)) + lex;
       C.B0[i] = B0;
-      const double ta = -PY * invA, tb = -PZ * invA, tg = -B0 * invA;
-      C.TA[i] = ta;
-      C.TB[i] = tb;
-      C.TG[i] = tg;
-      C.TE[i] = (fabs(ta) * NYb0 + fabs(tb) * NZb0 + fabs(tg) + 128.0) * 0x1p-48;
+      if (kind != 0) {
+        const double ta = -PY * invA, tb = -PZ * invA, tg = -B0 * invA;
+        C.TA[i] = ta;
+        C.TB[i] = tb;
+        C.TG[i] = tg;
+        C.TE[i] = (fabs(ta) * NYb[d] + fabs(tb) * (hi[d][2] - lo[d][2] + 1) + fabs(tg) + 128.0) * 0x1p-48;
+      } else {
+        C.TA[i] = PY;
+        C.TB[i] = PZ;
+        C.TG[i] = B0;
+        C.TE[i] = 0.0;
+      }
     } else {
       const long long nxi = static_cast<long long>(nx_), nyi = static_cast<long long>(ny_),
                       nzi = static_cast<long long>(nz_);
@@ -550,18 +597,26 @@ __device__ void eval_tet_dir(const ProblemView& P, int tet, int dir, float coord
       C.B0i[i] = nxi * static_cast<long long>(ox) + nyi * static_cast<long long>(oy) +
                  nzi * static_cast<long long>(oz) + lex;
     }
+    if (i == 0) {
+      C.absD = D[d] < 0 ? -D[d] : D[d];
+      C.fast = fast[d] ? 1 : 0;
+    }
   }
   wave_sync();
-  // phase 2, lanes 0..8: map entry M[a][c] = sum_i b_i[a] adj_i[c] / D with
-  // b_i = oth_i - oth_0 and adj_i = sigma n_i (i = 1..3) the rows of adj(E)
-  const double invD = 1.0 / static_cast<double>(D);
-  if (lane < 9) {
-    const int a = lane / 3, cc = lane % 3;
-    const double oth0 = L->vert[12 + a];
+  // phase 2, lanes 0..17: map entry M[a][c] of direction d = lane / 9:
+  // sum_i b_i[a] adj_i[c] / D with b_i = oth_i - oth_0 and adj_i = sigma n_i
+  // (i = 1..3), the rows of adj(E)
+  if (lane < 18) {
+    const int d = lane / 9, a = (lane % 9) / 3, cc = lane % 3;
+    DirConst& C = L->c[d];
+    const int* oth = L->vert + 12 * (1 - d);
+    const double sigma = D[d] > 0 ? 1.0 : -1.0;
+    const double invD = 1.0 / static_cast<double>(D[d] != 0 ? D[d] : 1);
+    const double oth0 = oth[a];
     double num = 0.0, mag = 0.0;
 #pragma unroll
     for (int i = 0; i < 3; i++) {
-      const double bi = static_cast<double>(L->vert[12 + 3 * (i + 1) + a]) - oth0;
+      const double bi = static_cast<double>(oth[3 * (i + 1) + a]) - oth0;
       const double t = bi * (sigma * C.n[i + 1][cc]);
       num += t;
       mag += fabs(t);
@@ -570,118 +625,117 @@ __device__ void eval_tet_dir(const ProblemView& P, int tet, int dir, float coord
     C.Mabs[a][cc] = mag * fabs(invD);
   }
   wave_sync();
-  // phase 3, lanes 0..2: q at the box corner and the FP64 error bound of q
-  if (lane < 3) {
-    const int a = lane;
-    double q = L->vert[12 + a] * (1.0 / 1024.0);
+  // phase 3, lanes 0..5: q at the box corner and the FP64 error bound of q
+  if (lane < 6) {
+    const int d = lane / 3, a = lane % 3;
+    DirConst& C = L->c[d];
+    const int* own = L->vert + 12 * d;
+    const int* oth = L->vert + 12 * (1 - d);
+    double q = oth[a] * (1.0 / 1024.0);
     double bound = fabs(q) + 1.0;
 #pragma unroll
     for (int cc = 0; cc < 3; cc++) {
-      const double off = lo[cc] - own[0][cc] * (1.0 / 1024.0);
+      const double off = lo[d][cc] - own[cc] * (1.0 / 1024.0);
       q += C.M[a][cc] * off;
-      bound += C.Mabs[a][cc] * (fabs(off) + (hi[cc] - lo[cc]));
+      bound += C.Mabs[a][cc] * (fabs(off) + (hi[d][cc] - lo[d][cc]));
     }
     C.qlo[a] = q;
     C.guard[a] = bound * 0x1p-40;
+    C.gthr[a] = 0.5 - bound * 0x1p-40;
   }
-  const int W = hi[0] - lo[0];
-  const int NYb = hi[1] - lo[1] + 1;
-  const int R = NYb * (hi[2] - lo[2] + 1);
-  const float invNYb = 1.0f / static_cast<float>(NYb);
-  // the other tet lies at least 2^-10 voxel inside the grid on every axis:
-  // all trilinear corners of all mapped points are valid voxels
-  bool interior = true;
-#pragma unroll
-  for (int k = 0; k < 3; k++) {
-    int mn = __builtin_amdgcn_readlane(fix, 12 + k), mx = mn;
-#pragma unroll
-    for (int i = 1; i < 4; i++) {
-      const int v = __builtin_amdgcn_readlane(fix, 12 + 3 * i + k);
-      mn = min(mn, v);
-      mx = max(mx, v);
-    }
-    interior = interior && mn >= 1 && mx <= 1024 * (dims[k] - 1) - 1;
-  }
+  wave_sync();
 
-  float h_acc = 0.f, g_acc = 0.f;
-  int n_acc = 0, n_defer = 0;
-
-  for (int rb = 0; rb < R; rb += kWave) {
-    const int rr = rb + lane;
-    int js = 1, je = 0, yr = 0, zr = 0;
-    if (rr < R) {
-      zr = static_cast<int>(static_cast<float>(rr) * invNYb);
-      if (zr * NYb > rr) zr -= 1;
-      else if ((zr + 1) * NYb <= rr) zr += 1;
-      yr = rr - zr * NYb;
-      if (fast)
-        span_fast(L->c, yr, zr, W, js, je);
-      else
-        span_wide(L->c, yr, zr, W, js, je);
-    }
-    const int len = max(0, je - js + 1);
-    const uint64_t rows_mask = __ballot(len > 0);
-    if (rows_mask == 0) continue;
-    const int nrows = __popcll(rows_mask);
-    const int off = wave_excl_scan(len);
-    const int total = __shfl(off + len, 63, 64);
-    if (len > 0) {
-      const int ci = bits_below(rows_mask);
-      L->row[ci] = make_int4(lo[0] + js, (lo[1] + yr) | ((lo[2] + zr) << 16), off, 0);
-    }
-    wave_sync();
-    const int my_off = lane < nrows ? L->row[lane].z : 0x7fffffff;
-
-    for (int sb = 0; sb < total; sb += kWave) {
-      // row of each lane's sample: rows starting at or before sb, plus rows
-      // starting inside (sb, sb + lane]
-      const int first = __popcll(__ballot(my_off <= sb)) - 1;
-      L->mark[lane] = 0;
-      wave_sync();
-      const int rel = my_off - sb;
-      if (rel > 0 && rel < kWave) L->mark[rel] = 1;
-      wave_sync();
-      const uint64_t starts = __ballot(L->mark[lane] != 0);
-      const int ri = first + bits_below(starts) + static_cast<int>((starts >> lane) & 1ull);
-      const int s = sb + lane;
-      int amb = 0, x = 0, yy = 0, zz = 0;
-      float a = 0.f, b = 0.f;
-      if (s < total) {
-        const int4 rw = L->row[ri];
-        x = rw.x + (s - rw.z);
-        yy = rw.y & 0xffff;
-        zz = rw.y >> 16;
-        if (interior)
-          amb = sample_one<ST, true>(P, L, dir, x, yy, zz, lo, h_acc, g_acc, a, b);
-        else
-          amb = sample_one<ST, false>(P, L, dir, x, yy, zz, lo, h_acc, g_acc, a, b);
-        n_acc += 1;
+  // ---- rows and samples, one direction at a time (wave-uniform d)
+  for (int d = 0; d < 2; d++) {
+    if (!active[d]) continue;
+    const int Rd = R[d], nyb = NYb[d], Wd = W[d];
+    const int lox = lo[d][0], loy = lo[d][1], loz = lo[d][2];
+    const float inv_nyb = 1.0f / static_cast<float>(nyb);
+    const DirConst& Cd = L->c[d];
+    const unsigned nvox = static_cast<unsigned>(P.nx * P.ny * P.nz);
+    const __amdgpu_buffer_rsrc_t r_own = image_rsrc<ST>(P.img[d], nvox);
+    const __amdgpu_buffer_rsrc_t r_oth = image_rsrc<ST>(P.img[1 - d], nvox);
+    float h = 0.f, g = 0.f;
+    int n = 0, n_defer = 0;
+    for (int rb = 0; rb < Rd; rb += kWave) {
+      const int rr = rb + lane;
+      int js = 1, je = 0, yr = 0, zr = 0;
+      if (rr < Rd) {
+        zr = static_cast<int>(static_cast<float>(rr) * inv_nyb);
+        if (zr * nyb > rr) zr -= 1;
+        else if ((zr + 1) * nyb <= rr) zr += 1;
+        yr = rr - zr * nyb;
+        row_span(Cd, yr, zr, Wd, js, je);
       }
-      const uint64_t amb_mask = __ballot(amb != 0);
-      if (amb_mask) {
-        if (amb) {
-          const int slot = n_defer + bits_below(amb_mask);
-          L->defer[slot] = make_int4((x - lo[0]) | ((yy - lo[1]) << 10) | ((zz - lo[2]) << 20),
-                                     __float_as_int(a), __float_as_int(b), amb);
-        }
-        n_defer += __popcll(amb_mask);
+      const int len = max(0, je - js + 1);
+      const uint64_t rows_mask = __ballot(len > 0);
+      if (rows_mask == 0) continue;
+      const int nrows = __popcll(rows_mask);
+      const int off = wave_excl_scan(len);
+      const int total = __shfl(off + len, 63, 64);
+      if (len > 0) {
+        const int ci = bits_below(rows_mask);
+        L->row[ci] = make_int4(lox + js, (loy + yr) | ((loz + zr) << 16), off,
+                               js | (yr << 10) | (zr << 20));
+        const double jx = js, jy = yr, jz = zr;
+#pragma unroll
+        for (int t = 0; t < 3; t++)
+          L->rowq[ci][t] = fma(Cd.M[t][0], jx, fma(Cd.M[t][1], jy, fma(Cd.M[t][2], jz, Cd.qlo[t])));
       }
-      if (n_defer > kDeferCap - kWave) {
+      wave_sync();
+      const int my_off = lane < nrows ? L->row[lane].z : 0x7fffffff;
+
+      for (int sb = 0; sb < total; sb += kWave) {
+        // row of each lane's sample: rows starting at or before sb, plus rows
+        // starting inside (sb, sb + lane]
+        const int first = __popcll(__ballot(my_off <= sb)) - 1;
+        L->mark[lane] = 0;
         wave_sync();
-        h_acc += flush_deferred<ST>(P, L, dir, lo, fast, absD, n_defer);
-        n_defer = 0;
+        const int rel = my_off - sb;
+        if (rel > 0 && rel < kWave) L->mark[rel] = 1;
+        wave_sync();
+        const uint64_t starts = __ballot(L->mark[lane] != 0);
+        const int ri = first + bits_below(starts) + static_cast<int>((starts >> lane) & 1ull);
+        const int s = sb + lane;
+        int amb = 0, jpack = 0;
+        float a = 0.f, b = 0.f;
+        if (s < total) {
+          const int4 rw = L->row[ri];
+          const int k = s - rw.z;
+          const int x = rw.x + k, yy = rw.y & 0xffff, zz = rw.y >> 16;
+          const double qr[3] = {L->rowq[ri][0], L->rowq[ri][1], L->rowq[ri][2]};
+          if (interior[1 - d])
+            amb = sample_one<ST, true>(P, Cd, r_own, r_oth, d, x, yy, zz, qr, k, h, g, a, b);
+          else
+            amb = sample_one<ST, false>(P, Cd, r_own, r_oth, d, x, yy, zz, qr, k, h, g, a, b);
+          n += 1;
+          jpack = (rw.w + k) | (d << 30);
+        }
+        const uint64_t amb_mask = __ballot(amb != 0);
+        if (amb_mask) {
+          if (amb) {
+            const int slot = n_defer + bits_below(amb_mask);
+            L->defer[slot] = make_int4(jpack, __float_as_int(a), __float_as_int(b), amb);
+          }
+          n_defer += __popcll(amb_mask);
+        }
+        if (n_defer > kDeferCap - kWave) {
+          wave_sync();
+          flush_deferred<ST>(P, L, n_defer, h, h);
+          n_defer = 0;
+        }
+        wave_sync();
       }
-      wave_sync();
     }
+    if (n_defer > 0) {
+      wave_sync();
+      flush_deferred<ST>(P, L, n_defer, h, h);
+    }
+    rec[d].h = wave_sum(h);
+    rec[d].g = wave_sum(g);
+    rec[d].n = static_cast<uint32_t>(wave_sum_i(n));
   }
-  if (n_defer > 0) {
-    wave_sync();
-    h_acc += flush_deferred<ST>(P, L, dir, lo, fast, absD, n_defer);
-  }
-  rec.h = wave_sum(h_acc);
-  rec.g = wave_sum(g_acc);
-  rec.n = static_cast<uint32_t>(wave_sum_i(n_acc));
-  if (lane == 0) *out = rec;
+  if (lane < 2) out[lane] = rec[lane];
 }
 
 // Block index remap so that each of the 8 XCDs (which receive blocks
@@ -695,7 +749,8 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 
 // ------------------------------------------------------------------ kernels
 
-// Full evaluation: item = (tet * pop + candidate) * 2 + direction.
+// Full evaluation: one wave per (candidate, tet), item = tet * pop + candidate,
+// so the 4 waves of a block are 4 candidates of one tet.
 template <int ST>
 __global__ __launch_bounds__(256, 5) void k_eval_full(ProblemView P, FullItems F, Record* rec,
                                                     int n_items) {
@@ -703,20 +758,18 @@ __global__ __launch_bounds__(256, 5) void k_eval_full(ProblemView P, FullItems F
   const int wave = threadIdx.x >> 6;
   const int item = xcd_block(blockIdx.x, gridDim.x) * 4 + wave;
   if (item >= n_items) return;
-  const int dir = item & 1;
-  const int rest = item >> 1;
-  const int cand = rest % F.pop;
-  const int tet = rest / F.pop;
+  const int cand = item % F.pop;
+  const int tet = item / F.pop;
   const int lane = lane_id();
   float coord = 0.f;
   if (lane < 24) {
     const int4 tv = P.tets[tet];
     const int i = (lane % 12) / 3, k = lane % 3;
     const int v = i == 0 ? tv.x : (i == 1 ? tv.y : (i == 2 ? tv.z : tv.w));
-    const int mesh = lane < 12 ? dir : 1 - dir;
+    const int mesh = lane < 12 ? 0 : 1;
     coord = F.pts[((static_cast<size_t>(cand) * 2 + mesh) * 3 + k) * P.n_points + v];
   }
-  eval_tet_dir<ST>(P, tet, dir, coord, &lds[wave], &rec[(static_cast<size_t>(cand) * P.n_tets + tet) * 2 + dir]);
+  eval_tet<ST>(P, tet, coord, &lds[wave], &rec[(static_cast<size_t>(cand) * P.n_tets + tet) * 2]);
 }
 
 template __global__ void k_eval_full<kF32>(ProblemView, FullItems, Record*, int);
@@ -849,7 +902,7 @@ hipError_t launch_distance_maps(int nx, int ny, int nz, int n_sets, const int* s
 
 hipError_t launch_eval_full(const ProblemView& P, int storage, const float* pts, int pop,
                             Record* rec, hipStream_t s) {
-  const size_t n_items = static_cast<size_t>(pop) * P.n_tets * 2;
+  const size_t n_items = static_cast<size_t>(pop) * P.n_tets;
   if (n_items == 0) return hipSuccess;
   const int blocks = static_cast<int>((n_items + 3) / 4);
   FullItems F{pts, pop};
@@ -936,26 +989,24 @@ __device__ __forceinline__ int find_eval(const int* item_off, int n_evals, int i
   return lo;
 }
 
-// Persistent evaluation of all (evaluation, dependent tet, direction) items:
-// each wave takes `chunk` consecutive items from a device work queue until
-// the list is exhausted.  Every wave leaves the loop once the queue passes
-// the end of the list.
+// Persistent evaluation of all (evaluation, dependent tet) items, both
+// directions per item: each wave takes `chunk` consecutive items from a
+// device work queue until the list is exhausted.  Every wave leaves the loop
+// once the queue passes the end of the list.
 template <int ST>
 __global__ __launch_bounds__(256) void k_eval_partial(ProblemView P, PartialItems I, Record* out,
                                                        int* queue, int chunk) {
   __shared__ WaveLds lds[4];
   const int wave = threadIdx.x >> 6;
   const int lane = lane_id();
-  const int total = I.item_off[I.n_evals] * 2;
+  const int total = I.item_off[I.n_evals];
   while (true) {
     int base = 0;
     if (lane == 0) base = atomicAdd(queue, chunk);
     base = __shfl(base, 0, 64);
     if (base >= total) break;
     const int end = min(total, base + chunk);
-    for (int item = base; item < end; item++) {
-      const int dir = item & 1;
-      const int idx = item >> 1;
+    for (int idx = base; idx < end; idx++) {
       const int e = find_eval(I.item_off, I.n_evals, idx);
       const int j = idx - I.item_off[e];
       const int g = I.eval_group[e], par = I.eval_parent[e];
@@ -964,7 +1015,7 @@ __global__ __launch_bounds__(256) void k_eval_partial(ProblemView P, PartialItem
       float coord = 0.f;
       if (lane < 24) {
         const int i = (lane % 12) / 3, k = lane % 3;
-        const int mesh = lane < 12 ? dir : 1 - dir;
+        const int mesh = lane < 12 ? 0 : 1;
         const int loc = I.dep_local[4 * slot + i];
         if (loc >= 0) {
           coord = I.new_coords[((static_cast<size_t>(I.row_off[e]) + loc) * 2 + mesh) * 3 + k];
@@ -974,7 +1025,7 @@ __global__ __launch_bounds__(256) void k_eval_partial(ProblemView P, PartialItem
           coord = I.parent_pts[((static_cast<size_t>(par) * 2 + mesh) * 3 + k) * P.n_points + v];
         }
       }
-      eval_tet_dir<ST>(P, tet, dir, coord, &lds[wave], &out[static_cast<size_t>(idx) * 2 + dir]);
+      eval_tet<ST>(P, tet, coord, &lds[wave], &out[static_cast<size_t>(idx) * 2]);
     }
   }
 }

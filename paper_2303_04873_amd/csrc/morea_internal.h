@@ -91,6 +91,7 @@ struct morea_problem {
   std::vector<void*> group_allocs;
   std::vector<void*> partial_allocs;
   std::vector<int> tets_host;
+  std::vector<float> ref_host;
   morea::Record* work_records = nullptr;   // [max_population][n_tets][2]
   morea::Totals* work_totals = nullptr;    // [max_population]
   // family of subsets
@@ -129,6 +130,7 @@ hipError_t launch_finalize(const ProblemView& P, const float* pts, int pop, cons
                            float* obj, uint8_t* flags, float* severity, uint32_t* counts,
                            Totals* totals, hipStream_t s);
 int partial_blocks_per_cu(int storage);
+void set_error(const char* msg);   // message returned by morea_last_error() on this thread
 hipError_t launch_partial(const ProblemView& P, int storage, const PartialItems& I, int n_parents,
                           int n_groups, const Record* parent_rec, const Totals* parent_tot,
                           Record* new_rec, int* queue, int blocks, int chunk, float* obj,

@@ -1,0 +1,843 @@
+// Learned pre-screen of offspring: a per-tetrahedron multilayer perceptron
+// 20 -> 128 -> 128 -> 1 (ReLU) that predicts each tet's mean intensity term
+// (the sum of h over the tet's samples in both directions divided by their
+// number, Sec. 4.1.2), trained on records produced by the exact evaluator and
+// used to rank a batch of offspring before only the best are evaluated
+// exactly.  The surrogate has no counterpart in the paper; it sits in front of
+// the exact evaluation, which stays the judge of every selected candidate.
+//
+// Dense layers run on the matrix cores: v_mfma_f32_32x32x8_bf16 with BF16
+// operands and FP32 accumulation, one 64-lane wave per tile of 32 rows.
+// Lane l holds row (A) / column (B) l % 32 and the k-quad 4 * (l / 32);
+// accumulator element r of lane l is row 8 (r / 4) + 4 (l / 32) + r % 4,
+// column l % 32.  Master weights, gradients and the Adam state are FP32.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <random>
+#include <string>
+#include <vector>
+
+#include "morea_internal.h"
+
+namespace morea {
+namespace surr {
+
+constexpr int kIn = 20, kInPad = 24, kHid = 128;
+constexpr int oW1 = 0, oB1 = oW1 + kHid * kIn, oW2 = oB1 + kHid, oB2 = oW2 + kHid * kHid,
+              oW3 = oB2 + kHid, oB3 = oW3 + kHid, kParams = oB3 + 1;   // 19,329
+constexpr int kRowTile = 32;
+constexpr int kWavePart = 3 * kHid + 2;   // per-wave partials: dw3, db2, db1, db3, loss
+constexpr int kSplitK = 16;
+constexpr int kGradTiles = 20;            // 16 tiles of W2, 4 of W1
+
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef float f16v __attribute__((ext_vector_type(16)));
+typedef unsigned short bf16;
+
+__device__ __forceinline__ bf16 f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return static_cast<bf16>(u >> 16);
+}
+__device__ __forceinline__ float bf2f(bf16 b) { return __uint_as_float(static_cast<uint32_t>(b) << 16); }
+__device__ __forceinline__ s4 ld4(const bf16* p) { return *reinterpret_cast<const s4*>(p); }
+__device__ __forceinline__ f16v mma(s4 a, s4 b, f16v c) {
+  return __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ int acc_row(int r, int kh) { return 8 * (r >> 2) + 4 * kh + (r & 3); }
+__device__ __forceinline__ int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Weights staged in LDS by every block that runs the network.
+struct alignas(16) NetLds {
+  bf16 w1[kHid][kInPad];   // W1[j][k], k padded with zeros
+  bf16 w2[kHid][kHid];     // W2[j][k]
+  float b1[kHid], b2[kHid], w3[kHid];
+  float b3;
+};
+
+// Per-wave tile buffers.  For inference the output reduction reuses the
+// layer-1 activations' space (dead once layer 2 has consumed them).
+typedef float RedTile[kRowTile][kRowTile + 1];
+struct alignas(16) TileLds {
+  bf16 x[kRowTile][kInPad];
+  union {
+    bf16 h1[kRowTile][kHid];
+    RedTile red;
+  };
+  float y[kRowTile];
+};
+
+__device__ void load_net(NetLds* N, const bf16* w1b, const bf16* w2b, const float* params) {
+  for (int i = threadIdx.x; i < kHid * kInPad; i += blockDim.x) (&N->w1[0][0])[i] = w1b[i];
+  for (int i = threadIdx.x; i < kHid * kHid / 4; i += blockDim.x)
+    reinterpret_cast<s4*>(&N->w2[0][0])[i] = reinterpret_cast<const s4*>(w2b)[i];
+  for (int i = threadIdx.x; i < kHid; i += blockDim.x) {
+    N->b1[i] = params[oB1 + i];
+    N->b2[i] = params[oB2 + i];
+    N->w3[i] = params[oW3 + i];
+  }
+  if (threadIdx.x == 0) N->b3 = params[oB3];
+}
+
+// Forward pass of one tile of 32 rows (T->x filled).  Leaves relu(z1) in
+// T->h1 (BF16) unless `red` overlays it, returns the layer-2
+// pre-activations (4 column tiles) in z2 and writes y to T->y.
+__device__ void tile_forward(const NetLds* N, TileLds* T, RedTile& red, f16v z2[4]) {
+  const int lane = lane_id(), i = lane & 31, kh = lane >> 5;
+#pragma unroll
+  for (int n = 0; n < 4; n++) {
+    f16v acc = {};
+#pragma unroll
+    for (int s = 0; s < kInPad / 8; s++)
+      acc = mma(ld4(&T->x[i][8 * s + 4 * kh]), ld4(&N->w1[32 * n + i][8 * s + 4 * kh]), acc);
+    const float bias = N->b1[32 * n + i];
+#pragma unroll
+    for (int r = 0; r < 16; r++) T->h1[acc_row(r, kh)][32 * n + i] = f2bf(fmaxf(acc[r] + bias, 0.f));
+  }
+  wave_sync();
+  float part[16];
+#pragma unroll
+  for (int r = 0; r < 16; r++) part[r] = 0.f;
+#pragma unroll
+  for (int n = 0; n < 4; n++) {
+    f16v acc = {};
+#pragma unroll
+    for (int s = 0; s < kHid / 8; s++)
+      acc = mma(ld4(&T->h1[i][8 * s + 4 * kh]), ld4(&N->w2[32 * n + i][8 * s + 4 * kh]), acc);
+    const float bias = N->b2[32 * n + i], w = N->w3[32 * n + i];
+#pragma unroll
+    for (int r = 0; r < 16; r++) {
+      acc[r] += bias;
+      part[r] = fmaf(fmaxf(acc[r], 0.f), w, part[r]);
+    }
+    z2[n] = acc;
+  }
+  // y[row] = sum over the 128 columns: this lane holds column i of 16 rows
+  wave_sync();
+#pragma unroll
+  for (int r = 0; r < 16; r++) red[acc_row(r, kh)][i] = part[r];
+  wave_sync();
+  if (lane < kRowTile) {
+    float y = N->b3;
+    for (int c = 0; c < kRowTile; c++) y += red[lane][c];
+    T->y[lane] = y;
+  }
+  wave_sync();
+}
+
+// ------------------------------------------------------------- features
+
+// Features of (candidate, tet): the 12 target-mesh vertex coordinates of the
+// tet scaled to [-1, 1] by the image extent, then the tet's 8 source-region
+// statistics.  Lane half kh = 0 writes the coordinates, kh = 1 the
+// statistics and the zero padding.
+__device__ __forceinline__ void row_features(const ProblemView& P, const float* cand, int tet,
+                                             const float* stats, int kh, float* out) {
+  if (kh == 0) {
+    const int4 tv = P.tets[tet];
+    const int vs[4] = {tv.x, tv.y, tv.z, tv.w};
+    const float sc[3] = {2.f / (P.nx - 1 > 0 ? P.nx - 1 : 1), 2.f / (P.ny - 1 > 0 ? P.ny - 1 : 1),
+                         2.f / (P.nz - 1 > 0 ? P.nz - 1 : 1)};
+#pragma unroll
+    for (int v = 0; v < 4; v++)
+#pragma unroll
+      for (int a = 0; a < 3; a++)
+        out[3 * v + a] = cand[(3 + a) * P.n_points + vs[v]] * sc[a] - 1.f;
+  } else {
+#pragma unroll
+    for (int f = 0; f < 8; f++) out[f] = stats[8 * tet + f];
+  }
+}
+
+// Source-region statistics of each tet of the reference mesh: voxel count,
+// mean / std / foreground fraction of I_s and of I_t over the voxel centres
+// inside the tet, and the mean squared difference.  (Features only: the
+// containment test is a plain FP64 barycentric one.)  One wave per tet.
+template <int ST>
+__global__ void k_tet_stats(ProblemView P, const float* ref, float* stats, int* counts, float inv_mean) {
+  const int tet = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int4 tv = P.tets[tet];
+  const int vs[4] = {tv.x, tv.y, tv.z, tv.w};
+  double v[4][3];
+  for (int i = 0; i < 4; i++)
+    for (int a = 0; a < 3; a++) v[i][a] = ref[3 * vs[i] + a];
+  double e[3][3];
+  for (int i = 0; i < 3; i++)
+    for (int a = 0; a < 3; a++) e[i][a] = v[i + 1][a] - v[0][a];
+  const double det = e[0][0] * (e[1][1] * e[2][2] - e[1][2] * e[2][1]) -
+                     e[0][1] * (e[1][0] * e[2][2] - e[1][2] * e[2][0]) +
+                     e[0][2] * (e[1][0] * e[2][1] - e[1][1] * e[2][0]);
+  int lo[3], hi[3];
+  const int dims[3] = {P.nx, P.ny, P.nz};
+  for (int a = 0; a < 3; a++) {
+    double mn = v[0][a], mx = v[0][a];
+    for (int i = 1; i < 4; i++) {
+      mn = fmin(mn, v[i][a]);
+      mx = fmax(mx, v[i][a]);
+    }
+    lo[a] = max(0, static_cast<int>(ceil(mn)));
+    hi[a] = min(dims[a] - 1, static_cast<int>(floor(mx)));
+  }
+  // inverse of the edge matrix (rows: barycentric 1..3)
+  double inv[3][3];
+  inv[0][0] = (e[1][1] * e[2][2] - e[1][2] * e[2][1]) / det;
+  inv[0][1] = (e[1][2] * e[2][0] - e[1][0] * e[2][2]) / det;
+  inv[0][2] = (e[1][0] * e[2][1] - e[1][1] * e[2][0]) / det;
+  inv[1][0] = (e[2][1] * e[0][2] - e[2][2] * e[0][1]) / det;
+  inv[1][1] = (e[2][2] * e[0][0] - e[2][0] * e[0][2]) / det;
+  inv[1][2] = (e[2][0] * e[0][1] - e[2][1] * e[0][0]) / det;
+  inv[2][0] = (e[0][1] * e[1][2] - e[0][2] * e[1][1]) / det;
+  inv[2][1] = (e[0][2] * e[1][0] - e[0][0] * e[1][2]) / det;
+  inv[2][2] = (e[0][0] * e[1][1] - e[0][1] * e[1][0]) / det;
+  const int wx = max(0, hi[0] - lo[0] + 1), wy = max(0, hi[1] - lo[1] + 1), wz = max(0, hi[2] - lo[2] + 1);
+  const long long nbox = static_cast<long long>(wx) * wy * wz;
+  float s[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // n, Is, Is^2, fg_s, It, It^2, fg_t, (Is-It)^2
+  for (long long q = lane; q < nbox; q += 64) {
+    const int x = lo[0] + static_cast<int>(q % wx), y = lo[1] + static_cast<int>((q / wx) % wy),
+              z = lo[2] + static_cast<int>(q / (static_cast<long long>(wx) * wy));
+    const double d[3] = {x - v[0][0], y - v[0][1], z - v[0][2]};
+    double l1 = inv[0][0] * d[0] + inv[0][1] * d[1] + inv[0][2] * d[2];
+    double l2 = inv[1][0] * d[0] + inv[1][1] * d[1] + inv[1][2] * d[2];
+    double l3 = inv[2][0] * d[0] + inv[2][1] * d[1] + inv[2][2] * d[2];
+    if (!(det != 0.0 && l1 >= 0 && l2 >= 0 && l3 >= 0 && l1 + l2 + l3 <= 1)) continue;
+    const int vi = (z * P.ny + y) * P.nx + x;
+    float is, it;
+    if constexpr (ST == kF32) {
+      is = static_cast<const float*>(P.img[0])[vi];
+      it = static_cast<const float*>(P.img[1])[vi];
+    } else if constexpr (ST == kBF16) {
+      is = bf2f(static_cast<const bf16*>(P.img[0])[vi]);
+      it = bf2f(static_cast<const bf16*>(P.img[1])[vi]);
+    } else {
+      is = static_cast<float>(static_cast<const _Float16*>(P.img[0])[vi]);
+      it = static_cast<float>(static_cast<const _Float16*>(P.img[1])[vi]);
+    }
+    s[0] += 1.f;
+    s[1] += is;
+    s[2] += is * is;
+    s[3] += is > 0.f;
+    s[4] += it;
+    s[5] += it * it;
+    s[6] += it > 0.f;
+    s[7] += (is - it) * (is - it);
+  }
+  for (int k = 0; k < 8; k++)
+    for (int d = 32; d >= 1; d >>= 1) s[k] += __shfl_xor(s[k], d, 64);
+  if (lane == 0) {
+    const float n = s[0], inv_n = n > 0.f ? 1.f / n : 0.f;
+    const float ms = s[1] * inv_n, mt = s[4] * inv_n;
+    float* o = stats + 8 * tet;
+    o[0] = ms;
+    o[1] = sqrtf(fmaxf(s[2] * inv_n - ms * ms, 0.f));
+    o[2] = s[3] * inv_n;
+    o[3] = mt;
+    o[4] = sqrtf(fmaxf(s[5] * inv_n - mt * mt, 0.f));
+    o[5] = s[6] * inv_n;
+    o[6] = s[7] * inv_n;
+    o[7] = n * inv_mean;
+    counts[tet] = static_cast<int>(n);
+  }
+}
+
+__global__ void k_features(ProblemView P, const float* pts, int pop, const float* stats, float* feats) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = lane_id();
+  if (row >= pop * P.n_tets || lane >= 2) return;
+  const int cand = row / P.n_tets, tet = row % P.n_tets;
+  float f[12];
+  row_features(P, pts + static_cast<size_t>(cand) * 6 * P.n_points, tet, stats, lane, f);
+  float* o = feats + static_cast<size_t>(row) * kIn;
+  if (lane == 0)
+    for (int k = 0; k < 12; k++) o[k] = f[k];
+  else
+    for (int k = 0; k < 8; k++) o[12 + k] = f[k];
+}
+
+// Per-tet target: mean h per sample over both directions, from a cache.
+__global__ void k_targets(const Record* rec, int rows, float* t) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  const Record a = rec[2 * static_cast<size_t>(r)], b = rec[2 * static_cast<size_t>(r) + 1];
+  const uint32_t n = a.n + b.n;
+  t[r] = n ? (a.h + b.h) / static_cast<float>(n) : 0.f;
+}
+
+// ------------------------------------------------------------ prescreen
+
+// Score of each candidate: the predicted intensity objective,
+// sum_tet pred_tet * n_tet / sum_tet n_tet with n_tet the reference voxel
+// counts.  One block (4 waves) per candidate; fixed-order reductions.
+__global__ __launch_bounds__(256) void k_prescreen(ProblemView P, const float* pts, const float* stats,
+                                                    const int* counts, const bf16* w1b, const bf16* w2b,
+                                                    const float* params, float* score) {
+  __shared__ NetLds N;
+  __shared__ TileLds Tl[4];
+  __shared__ float wsum[4], wcnt[4];
+  load_net(&N, w1b, w2b, params);
+  __syncthreads();
+  const int cand = blockIdx.x, wave = threadIdx.x >> 6, lane = lane_id();
+  TileLds* T = &Tl[wave];
+  const float* cp = pts + static_cast<size_t>(cand) * 6 * P.n_points;
+  const int i = lane & 31, kh = lane >> 5;
+  float acc = 0.f, cnt = 0.f;
+  const int n_tiles = (P.n_tets + kRowTile - 1) / kRowTile;
+  for (int tile = wave; tile < n_tiles; tile += 4) {
+    const int tet = tile * kRowTile + i;
+    float f[12];
+    if (tet < P.n_tets) {
+      row_features(P, cp, tet, stats, kh, f);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 12; k++) f[k] = 0.f;
+    }
+    if (kh == 0) {
+#pragma unroll
+      for (int k = 0; k < 12; k++) T->x[i][k] = f2bf(f[k]);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 8; k++) T->x[i][12 + k] = f2bf(f[k]);
+#pragma unroll
+      for (int k = kIn; k < kInPad; k++) T->x[i][k] = 0;
+    }
+    wave_sync();
+    f16v z2[4];
+    tile_forward(&N, T, T->red, z2);
+    if (lane < kRowTile && tet < P.n_tets) {
+      const float c = static_cast<float>(counts[tet]);
+      acc = fmaf(T->y[lane], c, acc);
+      cnt += c;
+    }
+    wave_sync();
+  }
+  for (int d = 32; d >= 1; d >>= 1) {
+    acc += __shfl_xor(acc, d, 64);
+    cnt += __shfl_xor(cnt, d, 64);
+  }
+  if (lane == 0) {
+    wsum[wave] = acc;
+    wcnt[wave] = cnt;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const float c = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+    score[cand] = c > 0.f ? (wsum[0] + wsum[1] + wsum[2] + wsum[3]) / c : 0.f;
+  }
+}
+
+// Predictions for explicit feature rows (one wave per 32 rows).
+__global__ __launch_bounds__(256) void k_predict_rows(const float* X, int n, const bf16* w1b,
+                                                       const bf16* w2b, const float* params, float* y) {
+  __shared__ NetLds N;
+  __shared__ TileLds Tl[4];
+  load_net(&N, w1b, w2b, params);
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = lane_id(), i = lane & 31, kh = lane >> 5;
+  const int row0 = (blockIdx.x * 4 + wave) * kRowTile;
+  if (row0 >= n) return;
+  TileLds* T = &Tl[wave];
+  const bool valid = row0 + i < n;
+  for (int k = kh * 12; k < (kh ? kInPad : 12); k++)
+    T->x[i][k] = f2bf(valid && k < kIn ? X[static_cast<size_t>(row0 + i) * kIn + k] : 0.f);
+  wave_sync();
+  f16v z2[4];
+  tile_forward(&N, T, T->red, z2);
+  if (lane < kRowTile && row0 + lane < n) y[row0 + lane] = T->y[lane];
+}
+
+// ------------------------------------------------------------- training
+
+struct TrainBuf {
+  bf16* xT;     // [kInPad][Bpad]
+  bf16* h1T;    // [kHid][Bpad]
+  bf16* dz2T;   // [kHid][Bpad]
+  bf16* dz1T;   // [kHid][Bpad]
+  float* wpart; // [n_waves][kWavePart]
+  float* gpart; // [kSplitK][kGradTiles][32][32]
+  int bpad;
+};
+
+// Forward and backward (data) pass of one tile of 32 training rows.
+__global__ __launch_bounds__(128) void k_train_rows(const float* X, const float* t, int n,
+                                                     const bf16* w1b, const bf16* w2b,
+                                                     const float* params, TrainBuf B) {
+  __shared__ NetLds N;
+  __shared__ TileLds Tl[2];
+  __shared__ alignas(16) bf16 w2t[kHid][kHid];     // W2 transposed: w2t[k][j] = W2[j][k]
+  __shared__ alignas(16) bf16 dz2s[2][kRowTile][kHid];
+  __shared__ float dys[2][kRowTile];
+  __shared__ RedTile reds[2];
+  load_net(&N, w1b, w2b, params);
+  for (int q = threadIdx.x; q < kHid * kHid; q += blockDim.x) {
+    const int j = q / kHid, k = q % kHid;
+    w2t[k][j] = w2b[q];
+  }
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = lane_id(), i = lane & 31, kh = lane >> 5;
+  const int gw = blockIdx.x * 2 + wave;
+  const int row0 = gw * kRowTile;
+  float* wp = B.wpart + static_cast<size_t>(gw) * kWavePart;
+  if (row0 >= B.bpad) return;
+  TileLds* T = &Tl[wave];
+  const bool valid = row0 + i < n;
+  for (int k = kh * 12; k < (kh ? kInPad : 12); k++) {
+    const bf16 v = f2bf(valid && k < kIn ? X[static_cast<size_t>(row0 + i) * kIn + k] : 0.f);
+    T->x[i][k] = v;
+    B.xT[static_cast<size_t>(k) * B.bpad + row0 + i] = v;
+  }
+  wave_sync();
+  f16v z2[4];
+  tile_forward(&N, T, reds[wave], z2);
+  // output gradient of the mean squared error
+  float lossp = 0.f, dyp = 0.f;
+  if (lane < kRowTile) {
+    const bool v = row0 + lane < n;
+    const float diff = v ? T->y[lane] - t[row0 + lane] : 0.f;
+    dys[wave][lane] = 2.f * diff / static_cast<float>(n);
+    lossp = diff * diff;
+    dyp = 2.f * diff / static_cast<float>(n);
+  }
+  wave_sync();
+  // layer 2 backward: dz2 = dy w3 relu'(z2); dw3 = sum dy h2; db2 = sum dz2
+#pragma unroll
+  for (int nt = 0; nt < 4; nt++) {
+    const int col = 32 * nt + i;
+    const float w = N.w3[col];
+    float gw3 = 0.f, gb2 = 0.f;
+#pragma unroll
+    for (int r = 0; r < 16; r++) {
+      const int row = acc_row(r, kh);
+      const float z = z2[nt][r];
+      const float dy = dys[wave][row];
+      const float dz = z > 0.f ? dy * w : 0.f;
+      gw3 = fmaf(dy, fmaxf(z, 0.f), gw3);
+      gb2 += dz;
+      const bf16 dzb = f2bf(dz);
+      dz2s[wave][row][col] = dzb;
+      B.dz2T[static_cast<size_t>(col) * B.bpad + row0 + row] = dzb;
+    }
+    gw3 += __shfl_xor(gw3, 32, 64);
+    gb2 += __shfl_xor(gb2, 32, 64);
+    if (kh == 0) {
+      wp[col] = gw3;
+      wp[kHid + col] = gb2;
+    }
+  }
+  // h1 transposed for the weight gradients
+  for (int q = lane; q < kRowTile * kHid; q += 64) {
+    const int row = q % kRowTile, k = q / kRowTile;
+    B.h1T[static_cast<size_t>(k) * B.bpad + row0 + row] = T->h1[row][k];
+  }
+  wave_sync();
+  // layer 1 backward: dh1 = dz2 W2 (MFMA with B[k=j][col] = W2[j][col]),
+  // dz1 = dh1 relu'(z1); db1 = sum dz1
+#pragma unroll
+  for (int nt = 0; nt < 4; nt++) {
+    f16v acc = {};
+#pragma unroll
+    for (int s = 0; s < kHid / 8; s++)
+      acc = mma(ld4(&dz2s[wave][i][8 * s + 4 * kh]), ld4(&w2t[32 * nt + i][8 * s + 4 * kh]), acc);
+    const int col = 32 * nt + i;
+    float gb1 = 0.f;
+#pragma unroll
+    for (int r = 0; r < 16; r++) {
+      const int row = acc_row(r, kh);
+      const float dz = bf2f(T->h1[row][col]) > 0.f ? acc[r] : 0.f;
+      gb1 += dz;
+      B.dz1T[static_cast<size_t>(col) * B.bpad + row0 + row] = f2bf(dz);
+    }
+    gb1 += __shfl_xor(gb1, 32, 64);
+    if (kh == 0) wp[2 * kHid + col] = gb1;
+  }
+  for (int d = 32; d >= 1; d >>= 1) {
+    lossp += __shfl_xor(lossp, d, 64);
+    dyp += __shfl_xor(dyp, d, 64);
+  }
+  if (lane == 0) {
+    wp[3 * kHid] = dyp;
+    wp[3 * kHid + 1] = lossp;
+  }
+}
+
+// Weight gradients as GEMMs over the batch (K = rows), split into kSplitK
+// chunks: tile 0..15 = W2 (32 x 32 blocks), 16..19 = W1 (rows 32 tr..).
+__global__ __launch_bounds__(64) void k_weight_grads(TrainBuf B) {
+  const int tile = blockIdx.x % kGradTiles, split = blockIdx.x / kGradTiles;
+  const int lane = lane_id(), i = lane & 31, kh = lane >> 5;
+  const int chunk = (B.bpad / kSplitK + 7) / 8 * 8;
+  const int k0 = split * chunk, k1 = min(B.bpad, k0 + chunk);
+  const bf16 *A, *Bm;
+  bool bvalid = true;
+  if (tile < 16) {
+    const int tr = tile / 4, tc = tile % 4;
+    A = B.dz2T + static_cast<size_t>(32 * tr + i) * B.bpad;
+    Bm = B.h1T + static_cast<size_t>(32 * tc + i) * B.bpad;
+  } else {
+    const int tr = tile - 16;
+    A = B.dz1T + static_cast<size_t>(32 * tr + i) * B.bpad;
+    bvalid = i < kInPad;
+    Bm = B.xT + static_cast<size_t>(bvalid ? i : 0) * B.bpad;
+  }
+  f16v acc = {};
+  const s4 zero = {0, 0, 0, 0};
+  for (int k = k0; k < k1; k += 8) {
+    const s4 a = ld4(A + k + 4 * kh);
+    const s4 b = bvalid ? ld4(Bm + k + 4 * kh) : zero;
+    acc = mma(a, b, acc);
+  }
+  float* out = B.gpart + (static_cast<size_t>(split) * kGradTiles + tile) * 1024;
+#pragma unroll
+  for (int r = 0; r < 16; r++) out[acc_row(r, kh) * 32 + i] = acc[r];
+}
+
+// Gradient of every parameter (fixed-order sums of the partials), then
+// either the Adam update (FP32 master, BF16 copies refreshed) or a copy of
+// the gradient to `grad_out`.
+__global__ void k_reduce_update(TrainBuf B, int n_waves, float* params, float* m, float* v,
+                                bf16* w1b, bf16* w2b, float lr, float c1, float c2, float* grad_out,
+                                float* loss_out, int n) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p == 0 && loss_out) {
+    float l = 0.f;
+    for (int w = 0; w < n_waves; w++) l += B.wpart[static_cast<size_t>(w) * kWavePart + 3 * kHid + 1];
+    *loss_out = l / static_cast<float>(n);
+  }
+  if (p >= kParams) return;
+  float g = 0.f;
+  if (p < oB1) {                       // W1[j][k]
+    const int j = (p - oW1) / kIn, k = (p - oW1) % kIn;
+    for (int s = 0; s < kSplitK; s++)
+      g += B.gpart[(static_cast<size_t>(s) * kGradTiles + 16 + j / 32) * 1024 + (j % 32) * 32 + k];
+  } else if (p < oW2) {                // b1
+    for (int w = 0; w < n_waves; w++) g += B.wpart[static_cast<size_t>(w) * kWavePart + 2 * kHid + (p - oB1)];
+  } else if (p < oB2) {                // W2[j][k]
+    const int j = (p - oW2) / kHid, k = (p - oW2) % kHid;
+    const int tile = (j / 32) * 4 + k / 32;
+    for (int s = 0; s < kSplitK; s++)
+      g += B.gpart[(static_cast<size_t>(s) * kGradTiles + tile) * 1024 + (j % 32) * 32 + (k % 32)];
+  } else if (p < oW3) {                // b2
+    for (int w = 0; w < n_waves; w++) g += B.wpart[static_cast<size_t>(w) * kWavePart + kHid + (p - oB2)];
+  } else if (p < oB3) {                // w3
+    for (int w = 0; w < n_waves; w++) g += B.wpart[static_cast<size_t>(w) * kWavePart + (p - oW3)];
+  } else {                             // b3
+    for (int w = 0; w < n_waves; w++) g += B.wpart[static_cast<size_t>(w) * kWavePart + 3 * kHid];
+  }
+  if (grad_out) {
+    grad_out[p] = g;
+    return;
+  }
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float mm = b1 * m[p] + (1.f - b1) * g;
+  const float vv = b2 * v[p] + (1.f - b2) * g * g;
+  m[p] = mm;
+  v[p] = vv;
+  const float w = params[p] - lr * (mm * c1) / (sqrtf(vv * c2) + 1e-8f);
+  params[p] = w;
+  if (p < oB1) {
+    const int j = (p - oW1) / kIn, k = (p - oW1) % kIn;
+    w1b[j * kInPad + k] = f2bf(w);
+  } else if (p >= oW2 && p < oB2) {
+    w2b[p - oW2] = f2bf(w);
+  }
+}
+
+__global__ void k_refresh_bf16(const float* params, bf16* w1b, bf16* w2b) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < kHid * kInPad) {
+    const int j = q / kInPad, k = q % kInPad;
+    w1b[q] = k < kIn ? f2bf(params[oW1 + j * kIn + k]) : static_cast<bf16>(0);
+  }
+  if (q < kHid * kHid) w2b[q] = f2bf(params[oW2 + q]);
+}
+
+// --------------------------------------------------------- selection
+
+// Indices of the k lowest scores (ties: lower index first), one block,
+// bitonic sort of (score, index) pairs in LDS; n <= 8192.
+__global__ __launch_bounds__(1024) void k_select(const float* score, int n, int k, int* idx_out) {
+  __shared__ float key[8192];
+  __shared__ int val[8192];
+  int m = 1;
+  while (m < n) m <<= 1;
+  for (int q = threadIdx.x; q < m; q += blockDim.x) {
+    key[q] = q < n ? score[q] : INFINITY;
+    val[q] = q;
+  }
+  __syncthreads();
+  for (int size = 2; size <= m; size <<= 1)
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int q = threadIdx.x; q < m; q += blockDim.x) {
+        const int o = q ^ stride;
+        if (o > q) {
+          const bool up = (q & size) == 0;
+          const float a = key[q], b = key[o];
+          const int ia = val[q], ib = val[o];
+          const bool greater = (a > b) || (a == b && ia > ib) || (a != a && b == b);
+          if (greater == up) {
+            key[q] = b; key[o] = a;
+            val[q] = ib; val[o] = ia;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  for (int q = threadIdx.x; q < k; q += blockDim.x) idx_out[q] = val[q];
+}
+
+__global__ void k_gather(const float* pts, const int* idx, int k, int per_cand, float* out) {
+  for (size_t q = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x;
+       q < static_cast<size_t>(k) * per_cand; q += static_cast<size_t>(gridDim.x) * blockDim.x) {
+    const size_t c = q / per_cand, e = q % per_cand;
+    out[q] = pts[static_cast<size_t>(idx[c]) * per_cand + e];
+  }
+}
+
+}  // namespace surr
+}  // namespace morea
+
+using namespace morea;
+using namespace morea::surr;
+
+struct morea_surrogate {
+  morea_problem* p = nullptr;
+  int max_rows = 0;
+  float* params = nullptr;
+  float* adam_m = nullptr;
+  float* adam_v = nullptr;
+  bf16* w1b = nullptr;
+  bf16* w2b = nullptr;
+  float* stats = nullptr;
+  int* counts = nullptr;
+  TrainBuf tb{};
+  int steps = 0;
+  std::vector<void*> allocs;
+};
+
+namespace {
+thread_local std::string s_error;
+morea_status sfail(morea_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  s_error = buf;
+  morea::set_error(buf);
+  return s;
+}
+
+template <typename T>
+morea_status salloc(morea_surrogate* s, T** dst, size_t bytes) {
+  void* d = nullptr;
+  hipError_t e = hipMalloc(&d, bytes ? bytes : 4);
+  if (e != hipSuccess) return sfail(MOREA_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+  s->allocs.push_back(d);
+  *dst = static_cast<T*>(d);
+  return MOREA_OK;
+}
+
+morea_status sdev(hipError_t e, const char* what) {
+  if (e == hipSuccess) return MOREA_OK;
+  return sfail(MOREA_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+hipError_t launch_stats(morea_surrogate* s, const float* ref_dev) {
+  const ProblemView& P = s->p->view;
+  const float inv_mean = static_cast<float>(P.n_tets) / static_cast<float>(P.nx * P.ny * P.nz);
+  switch (s->p->storage) {
+    case kF32: hipLaunchKernelGGL(k_tet_stats<kF32>, dim3(P.n_tets), dim3(64), 0, 0, P, ref_dev, s->stats, s->counts, inv_mean); break;
+    case kBF16: hipLaunchKernelGGL(k_tet_stats<kBF16>, dim3(P.n_tets), dim3(64), 0, 0, P, ref_dev, s->stats, s->counts, inv_mean); break;
+    default: hipLaunchKernelGGL(k_tet_stats<kF16>, dim3(P.n_tets), dim3(64), 0, 0, P, ref_dev, s->stats, s->counts, inv_mean); break;
+  }
+  return hipGetLastError();
+}
+
+morea_status train_launch(morea_surrogate* s, const float* X, const float* t, int n, float lr,
+                          float* grad_out, float* loss_out, hipStream_t st) {
+  if (!s || !X || !t) return sfail(MOREA_EINVAL, "NULL argument");
+  if (n < 1 || n > s->max_rows) return sfail(MOREA_ERANGE, "rows %d outside [1, %d]", n, s->max_rows);
+  TrainBuf B = s->tb;
+  B.bpad = (n + kRowTile - 1) / kRowTile * kRowTile;
+  B.bpad = (B.bpad + 8 * kSplitK - 1) / (8 * kSplitK) * (8 * kSplitK);
+  const int n_waves = B.bpad / kRowTile;
+  hipLaunchKernelGGL(k_train_rows, dim3((n_waves + 1) / 2), dim3(128), 0, st, X, t, n, s->w1b, s->w2b,
+                     s->params, B);
+  hipLaunchKernelGGL(k_weight_grads, dim3(kGradTiles * kSplitK), dim3(64), 0, st, B);
+  float c1 = 1.f, c2 = 1.f;
+  if (!grad_out) {
+    s->steps += 1;
+    c1 = 1.f / (1.f - powf(0.9f, static_cast<float>(s->steps)));
+    c2 = 1.f / (1.f - powf(0.999f, static_cast<float>(s->steps)));
+  }
+  hipLaunchKernelGGL(k_reduce_update, dim3((kParams + 255) / 256), dim3(256), 0, st, B, n_waves,
+                     s->params, s->adam_m, s->adam_v, s->w1b, s->w2b, lr, c1, c2, grad_out, loss_out, n);
+  return sdev(hipGetLastError(), "training kernels");
+}
+}  // namespace
+
+extern "C" {
+
+int32_t morea_surrogate_num_params(void) { return kParams; }
+
+morea_status morea_surrogate_create(morea_problem* p, int32_t max_rows, uint64_t seed,
+                                    morea_surrogate** out) {
+  if (!out) return sfail(MOREA_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!p) return sfail(MOREA_EINVAL, "problem is NULL");
+  if (max_rows < 1 || max_rows > (1 << 24)) return sfail(MOREA_EINVAL, "max_rows %d outside [1, 2^24]", max_rows);
+  morea_surrogate* s = new morea_surrogate();
+  s->p = p;
+  s->max_rows = max_rows;
+  const int NT = p->view.n_tets;
+  const int bmax = ((max_rows + 8 * kSplitK - 1) / (8 * kSplitK) + 1) * (8 * kSplitK) + kRowTile;
+  s->tb.bpad = bmax;
+  morea_status st = MOREA_OK;
+  auto ok = [&](morea_status r) { if (st == MOREA_OK) st = r; return st == MOREA_OK; };
+  ok(salloc(s, &s->params, sizeof(float) * kParams));
+  ok(salloc(s, &s->adam_m, sizeof(float) * kParams));
+  ok(salloc(s, &s->adam_v, sizeof(float) * kParams));
+  ok(salloc(s, &s->w1b, sizeof(bf16) * kHid * kInPad));
+  ok(salloc(s, &s->w2b, sizeof(bf16) * kHid * kHid));
+  ok(salloc(s, &s->stats, sizeof(float) * 8 * NT));
+  ok(salloc(s, &s->counts, sizeof(int) * NT));
+  ok(salloc(s, &s->tb.xT, sizeof(bf16) * kInPad * static_cast<size_t>(bmax)));
+  ok(salloc(s, &s->tb.h1T, sizeof(bf16) * kHid * static_cast<size_t>(bmax)));
+  ok(salloc(s, &s->tb.dz2T, sizeof(bf16) * kHid * static_cast<size_t>(bmax)));
+  ok(salloc(s, &s->tb.dz1T, sizeof(bf16) * kHid * static_cast<size_t>(bmax)));
+  ok(salloc(s, &s->tb.wpart, sizeof(float) * kWavePart * static_cast<size_t>(bmax / kRowTile + 4)));
+  ok(salloc(s, &s->tb.gpart, sizeof(float) * kSplitK * kGradTiles * 1024));
+  float* ref_dev = nullptr;
+  ok(salloc(s, &ref_dev, sizeof(float) * 3 * p->view.n_points));
+  if (st == MOREA_OK) {
+    // He-normal initial weights, zero biases, from the given seed
+    std::vector<float> h(kParams, 0.f);
+    std::mt19937_64 rng(seed);
+    std::normal_distribution<float> n1(0.f, sqrtf(2.f / kIn)), n2(0.f, sqrtf(2.f / kHid)), n3(0.f, sqrtf(1.f / kHid));
+    for (int q = oW1; q < oB1; q++) h[q] = n1(rng);
+    for (int q = oW2; q < oB2; q++) h[q] = n2(rng);
+    for (int q = oW3; q < oB3; q++) h[q] = n3(rng);
+    std::vector<float> z(kParams, 0.f);
+    ok(sdev(hipMemcpy(s->params, h.data(), sizeof(float) * kParams, hipMemcpyHostToDevice), "upload"));
+    ok(sdev(hipMemcpy(s->adam_m, z.data(), sizeof(float) * kParams, hipMemcpyHostToDevice), "upload"));
+    ok(sdev(hipMemcpy(s->adam_v, z.data(), sizeof(float) * kParams, hipMemcpyHostToDevice), "upload"));
+    ok(sdev(hipMemcpy(ref_dev, p->ref_host.data(), sizeof(float) * p->ref_host.size(), hipMemcpyHostToDevice), "upload"));
+  }
+  if (st == MOREA_OK) {
+    hipLaunchKernelGGL(k_refresh_bf16, dim3((kHid * kHid + 255) / 256), dim3(256), 0, 0, s->params, s->w1b, s->w2b);
+    ok(sdev(hipGetLastError(), "refresh"));
+    ok(sdev(launch_stats(s, ref_dev), "tet statistics"));
+    ok(sdev(hipDeviceSynchronize(), "surrogate set-up"));
+  }
+  if (st != MOREA_OK) {
+    for (void* a : s->allocs) (void)hipFree(a);
+    delete s;
+    return st;
+  }
+  *out = s;
+  return MOREA_OK;
+}
+
+void morea_surrogate_destroy(morea_surrogate* s) {
+  if (!s) return;
+  (void)hipDeviceSynchronize();
+  for (void* a : s->allocs) (void)hipFree(a);
+  delete s;
+}
+
+morea_status morea_surrogate_features(morea_surrogate* s, const float* pts, int32_t pop, float* feats,
+                                      void* stream) {
+  if (!s || !pts || !feats || pop < 0) return sfail(MOREA_EINVAL, "bad argument");
+  const long long rows = static_cast<long long>(pop) * s->p->view.n_tets;
+  if (rows == 0) return MOREA_OK;
+  if (rows > (1LL << 31) / 4) return sfail(MOREA_ERANGE, "too many rows");
+  hipLaunchKernelGGL(k_features, dim3(static_cast<unsigned>((rows + 3) / 4)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), s->p->view, pts, pop, s->stats, feats);
+  return sdev(hipGetLastError(), "features");
+}
+
+morea_status morea_surrogate_targets(morea_surrogate* s, const void* cache, int32_t pop, float* targets,
+                                     void* stream) {
+  if (!s || !cache || !targets || pop < 0) return sfail(MOREA_EINVAL, "bad argument");
+  const int rows = pop * s->p->view.n_tets;
+  if (rows == 0) return MOREA_OK;
+  hipLaunchKernelGGL(k_targets, dim3((rows + 255) / 256), dim3(256), 0, static_cast<hipStream_t>(stream),
+                     static_cast<const Record*>(cache), rows, targets);
+  return sdev(hipGetLastError(), "targets");
+}
+
+morea_status morea_surrogate_train_step(morea_surrogate* s, const float* feats, const float* targets,
+                                        int32_t n_rows, float lr, float* loss_out, void* stream) {
+  return train_launch(s, feats, targets, n_rows, lr, nullptr, loss_out, static_cast<hipStream_t>(stream));
+}
+
+morea_status morea_surrogate_gradients(morea_surrogate* s, const float* feats, const float* targets,
+                                       int32_t n_rows, float* grads, float* loss_out, void* stream) {
+  if (!grads) return sfail(MOREA_EINVAL, "grads is NULL");
+  return train_launch(s, feats, targets, n_rows, 0.f, grads, loss_out, static_cast<hipStream_t>(stream));
+}
+
+morea_status morea_surrogate_predict_rows(morea_surrogate* s, const float* feats, int32_t n_rows,
+                                          float* pred, void* stream) {
+  if (!s || !feats || !pred || n_rows < 0) return sfail(MOREA_EINVAL, "bad argument");
+  if (n_rows == 0) return MOREA_OK;
+  const int waves = (n_rows + kRowTile - 1) / kRowTile;
+  hipLaunchKernelGGL(k_predict_rows, dim3((waves + 3) / 4), dim3(256), 0, static_cast<hipStream_t>(stream),
+                     feats, n_rows, s->w1b, s->w2b, s->params, pred);
+  return sdev(hipGetLastError(), "predict");
+}
+
+morea_status morea_surrogate_prescreen(morea_surrogate* s, const float* pts, int32_t pop, float* score,
+                                       void* stream) {
+  if (!s || !pts || !score || pop < 0) return sfail(MOREA_EINVAL, "bad argument");
+  if (pop == 0) return MOREA_OK;
+  hipLaunchKernelGGL(k_prescreen, dim3(pop), dim3(256), 0, static_cast<hipStream_t>(stream), s->p->view,
+                     pts, s->stats, s->counts, s->w1b, s->w2b, s->params, score);
+  return sdev(hipGetLastError(), "prescreen");
+}
+
+morea_status morea_surrogate_select(const float* score, int32_t n, int32_t k, const float* pts,
+                                    int32_t n_points, int32_t* idx_out, float* selected_pts, void* stream) {
+  if (!score || !idx_out || n < 1 || n > 8192 || k < 1 || k > n)
+    return sfail(MOREA_EINVAL, "need 1 <= k <= n <= 8192 and non-NULL arrays");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, st, score, n, k, idx_out);
+  if (pts && selected_pts) {
+    const int per = 6 * n_points;
+    hipLaunchKernelGGL(k_gather, dim3(1024), dim3(256), 0, st, pts, idx_out, k, per, selected_pts);
+  }
+  return sdev(hipGetLastError(), "select");
+}
+
+morea_status morea_surrogate_get_params(morea_surrogate* s, float* host_params) {
+  if (!s || !host_params) return sfail(MOREA_EINVAL, "bad argument");
+  return sdev(hipMemcpy(host_params, s->params, sizeof(float) * kParams, hipMemcpyDeviceToHost), "copy");
+}
+
+morea_status morea_surrogate_set_params(morea_surrogate* s, const float* host_params) {
+  if (!s || !host_params) return sfail(MOREA_EINVAL, "bad argument");
+  morea_status st = sdev(hipMemcpy(s->params, host_params, sizeof(float) * kParams, hipMemcpyHostToDevice), "copy");
+  if (st != MOREA_OK) return st;
+  hipLaunchKernelGGL(k_refresh_bf16, dim3((kHid * kHid + 255) / 256), dim3(256), 0, 0, s->params, s->w1b, s->w2b);
+  st = sdev(hipGetLastError(), "refresh");
+  if (st == MOREA_OK) st = sdev(hipDeviceSynchronize(), "set params");
+  return st;
+}
+
+morea_status morea_surrogate_stats(morea_surrogate* s, float* host_stats, int32_t* host_counts) {
+  if (!s || !host_stats) return sfail(MOREA_EINVAL, "bad argument");
+  const int NT = s->p->view.n_tets;
+  morea_status st = sdev(hipMemcpy(host_stats, s->stats, sizeof(float) * 8 * NT, hipMemcpyDeviceToHost), "copy");
+  if (st == MOREA_OK && host_counts)
+    st = sdev(hipMemcpy(host_counts, s->counts, sizeof(int) * NT, hipMemcpyDeviceToHost), "copy");
+  return st;
+}
+
+}  // extern "C"
