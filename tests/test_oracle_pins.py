@@ -367,3 +367,62 @@ def test_map_vertices_and_centroid():
                                                             for a in range(3)]
     q, _ = oracle.map_point(own, oth, cen.astype(int))
     assert np.allclose(q, oth.mean(axis=0), rtol=0, atol=1e-15)
+
+
+def test_flat_tet_is_a_fold():
+    """A candidate tet of exactly zero volume violates the constraint (a zero
+    signed volume cannot have the reference sign); its severity adds 0."""
+    ref = np.array([[1, 1, 1], [9, 2, 1], [2, 10, 3], [3, 2, 12]], np.float32)
+    flat = ref.copy()
+    flat[3] = (ref[0] + ref[1]) / 2                    # on the edge v0-v1: exactly coplanar
+    assert oracle.orient(flat) == 0.0
+    dims = (16, 16, 16)
+    img = np.full(dims[::-1], 0.5, np.float32)
+    op = make_oracle(dims, img, img, ref, np.array([[0, 1, 2, 3]], np.int32))
+    out = op.evaluate(candidates(flat, ref))
+    assert out["flags"][0] == 1 and out["severity"][0] == 0.0
+    out = op.evaluate(candidates(ref, ref))
+    assert out["flags"][0] == 0
+
+
+def test_full_box_translation_brute_force(c1):
+    """Mesh over the whole image translated by t: mapped points leave the
+    grid, so zero padding (intensity) and edge clamping (distance maps) both
+    matter; both sums equal a brute-force voxel evaluation."""
+    dims = c1.dims
+    S = c1.ref_points.astype(np.float64)
+    t = np.array([615, -307, 461]) / 1024.0
+    r = 3.0
+    cs, ct = c1.sets_src[0], c1.sets_tgt[0]
+    # foreground up to the border, so that padding and clamping differ
+    img_s = (c1.image_src + 0.25).astype(np.float32)
+    img_t = (c1.image_tgt + 0.125).astype(np.float32)
+    op = make_oracle(dims, img_s, img_t, c1.ref_points, c1.tets, [cs], [ct], radius=r)
+    out = op.evaluate(candidates(S, S + t))
+    zz, yy, xx = np.meshgrid(*[np.arange(n) for n in dims[::-1]], indexing="ij")
+    P = np.stack([xx.ravel(), yy.ravel(), zz.ravel()], -1).astype(np.float64)
+    lo, hi = -0.5, np.array(dims) - 0.5
+    ins_t = np.all((P - t > lo) & (P - t < hi), axis=1)
+    assert out["counts"][0].tolist() == [len(P), int(ins_t.sum())]
+
+    def samp(img, q, mode):
+        return ndimage.map_coordinates(img.astype(np.float64), q[:, ::-1].T, order=1, mode=mode,
+                                       cval=0.0)
+
+    hs = _h(img_s.ravel().astype(np.float64), samp(img_t, P + t, "grid-constant")).sum()
+    ht = _h(img_t.ravel()[ins_t].astype(np.float64), samp(img_s, P[ins_t] - t, "grid-constant")).sum()
+    N = len(P) + ins_t.sum()
+    assert rel_err(out["obj"][0, 0], (hs + ht) / N) < 1e-12
+    snap = lambda a: np.rint(a.astype(np.float64) * 1024) / 1024
+    Ds = cKDTree(snap(cs)).query(P)[0].astype(np.float32).astype(np.float64)
+    Dt = cKDTree(snap(ct)).query(P)[0].astype(np.float32).astype(np.float64)
+    Ds_img, Dt_img = Ds.reshape(dims[::-1]), Dt.reshape(dims[::-1])
+
+    def g(d_own, q, map_oth):
+        d2 = samp(map_oth, q, "nearest")
+        band = d_own < r
+        return np.sum(((r - d_own) / r * (d_own - d2) ** 2)[band])
+
+    gs = g(Ds, P + t, Dt_img)
+    gt = g(Dt[ins_t], P[ins_t] - t, Ds_img)
+    assert rel_err(out["obj"][0, 2], (gs + gt) / N) < 1e-10
