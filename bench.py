@@ -150,11 +150,11 @@ def form_surrogate(full_evals_per_s, steps):
     t0 = time.perf_counter()
     gen = torch.Generator(device="cpu").manual_seed(0)
     loss = torch.empty(1, device="cuda")
-    for epoch in range(6):
+    for epoch in range(10):
         perm = torch.randperm(n, generator=gen).cuda()
         for b in range(0, n - 8191, 8192):
             sel = perm[b:b + 8192]
-            sur.train_step(X[sel].contiguous(), t[sel].contiguous(), 2e-3 if epoch < 4 else 5e-4,
+            sur.train_step(X[sel].contiguous(), t[sel].contiguous(), 2e-3 if epoch < 6 else 5e-4,
                            loss_out=loss)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0

@@ -202,8 +202,8 @@ morea_status morea_partial_shape(const morea_problem *p, int32_t *blocks, int32_
  * Learned pre-screen of offspring.  A per-tetrahedron multilayer perceptron
  * 20 -> 128 -> 128 -> 1 (ReLU) predicts each tet's mean intensity term, the
  * sum of h (Sec. 4.1.2) over the tet's samples in both directions divided by
- * their number.  Inputs per (candidate, tet): the 12 target-mesh vertex
- * coordinates of the tet scaled to [-1, 1] by the image extent, and 8
+ * their number.  Inputs per (candidate, tet): the deformation of the tet's 4
+ * target-mesh vertices, (T_v - ref_v) / 4 voxels (12 values), and 8
  * statistics of the tet's region in the reference mesh (mean, std and
  * foreground fraction of I_s and of I_t over its voxels, their mean squared
  * difference, its voxel count over the mean count).  A candidate's score is

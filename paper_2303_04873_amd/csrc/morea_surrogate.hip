@@ -135,22 +135,24 @@ __device__ void tile_forward(const NetLds* N, TileLds* T, RedTile& red, f16v z2[
 
 // ------------------------------------------------------------- features
 
-// Features of (candidate, tet): the 12 target-mesh vertex coordinates of the
-// tet scaled to [-1, 1] by the image extent, then the tet's 8 source-region
-// statistics.  Lane half kh = 0 writes the coordinates, kh = 1 the
-// statistics and the zero padding.
-__device__ __forceinline__ void row_features(const ProblemView& P, const float* cand, int tet,
-                                             const float* stats, int kh, float* out) {
+// Features of (candidate, tet): the deformation of the tet's 4 target-mesh
+// vertices, (T_v - ref_v) / 4 voxels (12 values: the deformed vertex
+// coordinates relative to the reference mesh, at a scale where a fraction of
+// a voxel stays well resolved in BF16), then the tet's 8 source-region
+// statistics.  Lane half kh = 0 writes the deformation, kh = 1 the
+// statistics.
+constexpr float kDispScale = 0.25f;
+
+__device__ __forceinline__ void row_features(const ProblemView& P, const float* cand, const float* ref,
+                                             int tet, const float* stats, int kh, float* out) {
   if (kh == 0) {
     const int4 tv = P.tets[tet];
     const int vs[4] = {tv.x, tv.y, tv.z, tv.w};
-    const float sc[3] = {2.f / (P.nx - 1 > 0 ? P.nx - 1 : 1), 2.f / (P.ny - 1 > 0 ? P.ny - 1 : 1),
-                         2.f / (P.nz - 1 > 0 ? P.nz - 1 : 1)};
 #pragma unroll
     for (int v = 0; v < 4; v++)
 #pragma unroll
       for (int a = 0; a < 3; a++)
-        out[3 * v + a] = cand[(3 + a) * P.n_points + vs[v]] * sc[a] - 1.f;
+        out[3 * v + a] = (cand[(3 + a) * P.n_points + vs[v]] - ref[3 * vs[v] + a]) * kDispScale;
   } else {
 #pragma unroll
     for (int f = 0; f < 8; f++) out[f] = stats[8 * tet + f];
@@ -159,8 +161,10 @@ __device__ __forceinline__ void row_features(const ProblemView& P, const float* 
 
 // Source-region statistics of each tet of the reference mesh: voxel count,
 // mean / std / foreground fraction of I_s and of I_t over the voxel centres
-// inside the tet, and the mean squared difference.  (Features only: the
-// containment test is a plain FP64 barycentric one.)  One wave per tet.
+// inside the tet, and the mean squared difference.  Containment uses the
+// snapped coordinates and the same tie rule as the evaluator (a centre on a
+// face belongs to the tet holding p + (e, e^2, e^3)), so the counts of a
+// fold-free mesh tile the grid.  One wave per tet.
 template <int ST>
 __global__ void k_tet_stats(ProblemView P, const float* ref, float* stats, int* counts, float inv_mean) {
   const int tet = blockIdx.x;
@@ -169,13 +173,30 @@ __global__ void k_tet_stats(ProblemView P, const float* ref, float* stats, int* 
   const int vs[4] = {tv.x, tv.y, tv.z, tv.w};
   double v[4][3];
   for (int i = 0; i < 4; i++)
-    for (int a = 0; a < 3; a++) v[i][a] = ref[3 * vs[i] + a];
+    for (int a = 0; a < 3; a++) v[i][a] = rint(static_cast<double>(ref[3 * vs[i] + a]) * 1024.0);
   double e[3][3];
   for (int i = 0; i < 3; i++)
     for (int a = 0; a < 3; a++) e[i][a] = v[i + 1][a] - v[0][a];
   const double det = e[0][0] * (e[1][1] * e[2][2] - e[1][2] * e[2][1]) -
                      e[0][1] * (e[1][0] * e[2][2] - e[1][2] * e[2][0]) +
                      e[0][2] * (e[1][0] * e[2][1] - e[1][1] * e[2][0]);
+  const double sg = det > 0 ? 1.0 : -1.0;
+  // inward face normals n_i and a vertex r_i on each face (face i omits v_i)
+  double n[4][3], r[4][3];
+  for (int i = 0; i < 4; i++) {
+    const int b0 = i == 0 ? 1 : 0, u0 = i == 0 ? 2 : (i == 1 ? 2 : (i == 2 ? 3 : 1)),
+              w0 = i == 0 ? 3 : (i == 1 ? 3 : (i == 2 ? 1 : 2));
+    double u[3], w[3];
+    for (int a = 0; a < 3; a++) {
+      r[i][a] = v[b0][a];
+      u[a] = v[u0][a] - v[b0][a];
+      w[a] = v[w0][a] - v[b0][a];
+    }
+    const double f = (i == 0 ? -sg : sg);
+    n[i][0] = f * (u[1] * w[2] - u[2] * w[1]);
+    n[i][1] = f * (u[2] * w[0] - u[0] * w[2]);
+    n[i][2] = f * (u[0] * w[1] - u[1] * w[0]);
+  }
   int lo[3], hi[3];
   const int dims[3] = {P.nx, P.ny, P.nz};
   for (int a = 0; a < 3; a++) {
@@ -184,31 +205,24 @@ __global__ void k_tet_stats(ProblemView P, const float* ref, float* stats, int* 
       mn = fmin(mn, v[i][a]);
       mx = fmax(mx, v[i][a]);
     }
-    lo[a] = max(0, static_cast<int>(ceil(mn)));
-    hi[a] = min(dims[a] - 1, static_cast<int>(floor(mx)));
+    lo[a] = max(0, static_cast<int>(ceil(mn / 1024.0)));
+    hi[a] = min(dims[a] - 1, static_cast<int>(floor(mx / 1024.0)));
   }
-  // inverse of the edge matrix (rows: barycentric 1..3)
-  double inv[3][3];
-  inv[0][0] = (e[1][1] * e[2][2] - e[1][2] * e[2][1]) / det;
-  inv[0][1] = (e[1][2] * e[2][0] - e[1][0] * e[2][2]) / det;
-  inv[0][2] = (e[1][0] * e[2][1] - e[1][1] * e[2][0]) / det;
-  inv[1][0] = (e[2][1] * e[0][2] - e[2][2] * e[0][1]) / det;
-  inv[1][1] = (e[2][2] * e[0][0] - e[2][0] * e[0][2]) / det;
-  inv[1][2] = (e[2][0] * e[0][1] - e[2][1] * e[0][0]) / det;
-  inv[2][0] = (e[0][1] * e[1][2] - e[0][2] * e[1][1]) / det;
-  inv[2][1] = (e[0][2] * e[1][0] - e[0][0] * e[1][2]) / det;
-  inv[2][2] = (e[0][0] * e[1][1] - e[0][1] * e[1][0]) / det;
   const int wx = max(0, hi[0] - lo[0] + 1), wy = max(0, hi[1] - lo[1] + 1), wz = max(0, hi[2] - lo[2] + 1);
-  const long long nbox = static_cast<long long>(wx) * wy * wz;
+  const long long nbox = det != 0.0 ? static_cast<long long>(wx) * wy * wz : 0;
   float s[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // n, Is, Is^2, fg_s, It, It^2, fg_t, (Is-It)^2
   for (long long q = lane; q < nbox; q += 64) {
     const int x = lo[0] + static_cast<int>(q % wx), y = lo[1] + static_cast<int>((q / wx) % wy),
               z = lo[2] + static_cast<int>(q / (static_cast<long long>(wx) * wy));
-    const double d[3] = {x - v[0][0], y - v[0][1], z - v[0][2]};
-    double l1 = inv[0][0] * d[0] + inv[0][1] * d[1] + inv[0][2] * d[2];
-    double l2 = inv[1][0] * d[0] + inv[1][1] * d[1] + inv[1][2] * d[2];
-    double l3 = inv[2][0] * d[0] + inv[2][1] * d[1] + inv[2][2] * d[2];
-    if (!(det != 0.0 && l1 >= 0 && l2 >= 0 && l3 >= 0 && l1 + l2 + l3 <= 1)) continue;
+    const double p[3] = {x * 1024.0, y * 1024.0, z * 1024.0};
+    bool in = true;
+    for (int i = 0; i < 4 && in; i++) {
+      const double val = n[i][0] * (p[0] - r[i][0]) + n[i][1] * (p[1] - r[i][1]) + n[i][2] * (p[2] - r[i][2]);
+      if (val < 0) in = false;
+      else if (val == 0)
+        in = n[i][0] > 0 || (n[i][0] == 0 && (n[i][1] > 0 || (n[i][1] == 0 && n[i][2] > 0)));
+    }
+    if (!in) continue;
     const int vi = (z * P.ny + y) * P.nx + x;
     float is, it;
     if constexpr (ST == kF32) {
@@ -233,7 +247,7 @@ __global__ void k_tet_stats(ProblemView P, const float* ref, float* stats, int* 
   for (int k = 0; k < 8; k++)
     for (int d = 32; d >= 1; d >>= 1) s[k] += __shfl_xor(s[k], d, 64);
   if (lane == 0) {
-    const float n = s[0], inv_n = n > 0.f ? 1.f / n : 0.f;
+    const float cnt = s[0], inv_n = cnt > 0.f ? 1.f / cnt : 0.f;
     const float ms = s[1] * inv_n, mt = s[4] * inv_n;
     float* o = stats + 8 * tet;
     o[0] = ms;
@@ -243,18 +257,19 @@ __global__ void k_tet_stats(ProblemView P, const float* ref, float* stats, int* 
     o[4] = sqrtf(fmaxf(s[5] * inv_n - mt * mt, 0.f));
     o[5] = s[6] * inv_n;
     o[6] = s[7] * inv_n;
-    o[7] = n * inv_mean;
-    counts[tet] = static_cast<int>(n);
+    o[7] = cnt * inv_mean;
+    counts[tet] = static_cast<int>(cnt);
   }
 }
 
-__global__ void k_features(ProblemView P, const float* pts, int pop, const float* stats, float* feats) {
+__global__ void k_features(ProblemView P, const float* pts, const float* ref, int pop, const float* stats,
+                           float* feats) {
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = lane_id();
   if (row >= pop * P.n_tets || lane >= 2) return;
   const int cand = row / P.n_tets, tet = row % P.n_tets;
   float f[12];
-  row_features(P, pts + static_cast<size_t>(cand) * 6 * P.n_points, tet, stats, lane, f);
+  row_features(P, pts + static_cast<size_t>(cand) * 6 * P.n_points, ref, tet, stats, lane, f);
   float* o = feats + static_cast<size_t>(row) * kIn;
   if (lane == 0)
     for (int k = 0; k < 12; k++) o[k] = f[k];
@@ -276,7 +291,8 @@ __global__ void k_targets(const Record* rec, int rows, float* t) {
 // Score of each candidate: the predicted intensity objective,
 // sum_tet pred_tet * n_tet / sum_tet n_tet with n_tet the reference voxel
 // counts.  One block (4 waves) per candidate; fixed-order reductions.
-__global__ __launch_bounds__(256) void k_prescreen(ProblemView P, const float* pts, const float* stats,
+__global__ __launch_bounds__(256) void k_prescreen(ProblemView P, const float* pts, const float* ref,
+                                                    const float* stats,
                                                     const int* counts, const bf16* w1b, const bf16* w2b,
                                                     const float* params, float* score) {
   __shared__ NetLds N;
@@ -294,7 +310,7 @@ __global__ __launch_bounds__(256) void k_prescreen(ProblemView P, const float* p
     const int tet = tile * kRowTile + i;
     float f[12];
     if (tet < P.n_tets) {
-      row_features(P, cp, tet, stats, kh, f);
+      row_features(P, cp, ref, tet, stats, kh, f);
     } else {
 #pragma unroll
       for (int k = 0; k < 12; k++) f[k] = 0.f;
@@ -616,6 +632,7 @@ struct morea_surrogate {
   bf16* w2b = nullptr;
   float* stats = nullptr;
   int* counts = nullptr;
+  float* ref = nullptr;
   TrainBuf tb{};
   int steps = 0;
   std::vector<void*> allocs;
@@ -714,8 +731,8 @@ morea_status morea_surrogate_create(morea_problem* p, int32_t max_rows, uint64_t
   ok(salloc(s, &s->tb.dz1T, sizeof(bf16) * kHid * static_cast<size_t>(bmax)));
   ok(salloc(s, &s->tb.wpart, sizeof(float) * kWavePart * static_cast<size_t>(bmax / kRowTile + 4)));
   ok(salloc(s, &s->tb.gpart, sizeof(float) * kSplitK * kGradTiles * 1024));
-  float* ref_dev = nullptr;
-  ok(salloc(s, &ref_dev, sizeof(float) * 3 * p->view.n_points));
+  ok(salloc(s, &s->ref, sizeof(float) * 3 * p->view.n_points));
+  float* ref_dev = s->ref;
   if (st == MOREA_OK) {
     // He-normal initial weights, zero biases, from the given seed
     std::vector<float> h(kParams, 0.f);
@@ -759,7 +776,7 @@ morea_status morea_surrogate_features(morea_surrogate* s, const float* pts, int3
   if (rows == 0) return MOREA_OK;
   if (rows > (1LL << 31) / 4) return sfail(MOREA_ERANGE, "too many rows");
   hipLaunchKernelGGL(k_features, dim3(static_cast<unsigned>((rows + 3) / 4)), dim3(256), 0,
-                     static_cast<hipStream_t>(stream), s->p->view, pts, pop, s->stats, feats);
+                     static_cast<hipStream_t>(stream), s->p->view, pts, s->ref, pop, s->stats, feats);
   return sdev(hipGetLastError(), "features");
 }
 
@@ -799,7 +816,7 @@ morea_status morea_surrogate_prescreen(morea_surrogate* s, const float* pts, int
   if (!s || !pts || !score || pop < 0) return sfail(MOREA_EINVAL, "bad argument");
   if (pop == 0) return MOREA_OK;
   hipLaunchKernelGGL(k_prescreen, dim3(pop), dim3(256), 0, static_cast<hipStream_t>(stream), s->p->view,
-                     pts, s->stats, s->counts, s->w1b, s->w2b, s->params, score);
+                     pts, s->ref, s->stats, s->counts, s->w1b, s->w2b, s->params, score);
   return sdev(hipGetLastError(), "prescreen");
 }
 
