@@ -266,7 +266,7 @@ def main():
                 op.evaluate(pop_np[n_done:n_done + chunk])
                 n_done += chunk
                 t_cpu = time.perf_counter() - t1
-            cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count()))
+            cores = oracle.threads()
             cpu = {"value": n_done / t_cpu, "unit": "candidate evals/s", "cores": cores,
                    "kind": "oracle",
                    "sample": f"first {n_done} of {pop} candidates of the same population "

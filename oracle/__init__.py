@@ -57,6 +57,8 @@ def lib():
         L.oracle_trilinear.restype = ctypes.c_double
         L.oracle_orient.argtypes = [P]
         L.oracle_orient.restype = ctypes.c_double
+        L.oracle_threads.argtypes = []
+        L.oracle_threads.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -200,6 +202,11 @@ def quantize(img, storage: str) -> np.ndarray:
         rounded = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
         return (rounded.astype(np.uint32) << 16).view(np.float32)
     raise ValueError(storage)
+
+
+def threads() -> int:
+    """Threads the oracle's OpenMP loops use."""
+    return int(lib().oracle_threads())
 
 
 def timed_evaluate(problem: Problem, pts):

@@ -38,6 +38,7 @@
  *   - magnitude is in voxel units (isotropic voxels).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -496,3 +497,7 @@ double oracle_orient(const float v[12]) {
     for (int k = 0; k < 3; k++) w[i][k] = snap(v[3 * i + k]);
   return (double)orient(w);
 }
+
+/* Number of threads the OpenMP loops above run with (reported beside the
+ * oracle's timings). */
+int oracle_threads(void) { return omp_get_max_threads(); }

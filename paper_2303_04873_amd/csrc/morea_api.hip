@@ -170,6 +170,10 @@ morea_status morea_problem_create(const morea_problem_desc* d, morea_problem** o
   P.nx = nx;
   P.ny = ny;
   P.nz = nz;
+  P.px = nx + 2;
+  P.pxy = (nx + 2) * (ny + 2);
+  const size_t PV = static_cast<size_t>(nx + 2) * (ny + 2) * (nz + 2);
+  P.pvox = static_cast<unsigned>(PV);
   P.n_points = d->n_points;
   P.n_tets = d->n_tets;
   P.n_sets = d->n_sets;
@@ -186,19 +190,18 @@ morea_status morea_problem_create(const morea_problem_desc* d, morea_problem** o
   for (int m = 0; m < 2 && st == MOREA_OK; m++) {
     const float* img = m == 0 ? d->image_src : d->image_tgt;
     void* dst = nullptr;
-    // kImagePad zero elements before and after the voxels: the paired corner
-    // loads of the evaluator read one element past either end of a row
+    // padded copy: a border of zeros one voxel wide on every side
+    std::vector<float> pad(PV, 0.f);
+    for (int z = 0; z < nz; z++)
+      for (int y = 0; y < ny; y++)
+        memcpy(pad.data() + ((static_cast<size_t>(z) + 1) * (ny + 2) + (y + 1)) * (nx + 2) + 1,
+               img + (static_cast<size_t>(z) * ny + y) * nx, nx * sizeof(float));
     if (d->storage == kF32) {
-      std::vector<float> q(V + 2 * kImagePad, 0.f);
-      memcpy(q.data() + kImagePad, img, V * sizeof(float));
-      guard(upload(p, &dst, q.data(), q.size() * sizeof(float)));
-      if (dst) dst = static_cast<float*>(dst) + kImagePad;
+      guard(upload(p, &dst, pad.data(), PV * sizeof(float)));
     } else {
-      std::vector<uint16_t> q(V + 2 * kImagePad, 0);
-      for (size_t i = 0; i < V; i++)
-        q[kImagePad + i] = d->storage == kBF16 ? to_bf16(img[i]) : to_f16(img[i]);
-      guard(upload(p, &dst, q.data(), q.size() * sizeof(uint16_t)));
-      if (dst) dst = static_cast<uint16_t*>(dst) + kImagePad;
+      std::vector<uint16_t> q(PV);
+      for (size_t i = 0; i < PV; i++) q[i] = d->storage == kBF16 ? to_bf16(pad[i]) : to_f16(pad[i]);
+      guard(upload(p, &dst, q.data(), PV * sizeof(uint16_t)));
     }
     P.img[m] = dst;
   }
@@ -214,8 +217,8 @@ morea_status morea_problem_create(const morea_problem_desc* d, morea_problem** o
   for (int m = 0; m < 2 && st == MOREA_OK; m++) {
     float* dm = nullptr;
     uint8_t* band = nullptr;
-    guard(upload(p, &dm, nullptr, sizeof(float) * V * std::max(d->n_sets, 1)));
-    if (st == MOREA_OK) guard(upload(p, &band, nullptr, V));
+    guard(upload(p, &dm, nullptr, sizeof(float) * PV * std::max(d->n_sets, 1)));
+    if (st == MOREA_OK) guard(upload(p, &band, nullptr, PV));
     if (st != MOREA_OK) break;
     if (d->n_sets > 0) {
       int* doff = nullptr;
@@ -226,7 +229,7 @@ morea_status morea_problem_create(const morea_problem_desc* d, morea_problem** o
       e = launch_distance_maps(nx, ny, nz, d->n_sets, doff, dpts, radius, dm, band, nullptr);
       if (e != hipSuccess) guard(hip_fail(e, "distance map kernel"));
     } else {
-      e = hipMemset(band, 0, V);
+      e = hipMemset(band, 0, PV);
       if (e != hipSuccess) guard(hip_fail(e, "hipMemset"));
     }
     P.dmap[m] = dm;
@@ -298,11 +301,22 @@ morea_status morea_debug_distance_map(morea_problem* p, int32_t image, int32_t s
                                       uint8_t* band_out) {
   if (!p || !host_out || image < 0 || image > 1 || set < 0 || set >= p->view.n_sets)
     return fail(MOREA_EINVAL, "bad argument");
-  hipError_t e = hipMemcpy(host_out, p->view.dmap[image] + static_cast<size_t>(set) * p->voxels,
-                           p->voxels * sizeof(float), hipMemcpyDeviceToHost);
+  // the stored volumes are padded: copy them whole and return the grid part
+  const ProblemView& P = p->view;
+  std::vector<float> dm(P.pvox);
+  std::vector<uint8_t> bd(P.pvox);
+  hipError_t e = hipMemcpy(dm.data(), P.dmap[image] + static_cast<size_t>(set) * P.pvox,
+                           P.pvox * sizeof(float), hipMemcpyDeviceToHost);
   if (e == hipSuccess && band_out)
-    e = hipMemcpy(band_out, p->view.band[image], p->voxels, hipMemcpyDeviceToHost);
+    e = hipMemcpy(bd.data(), P.band[image], P.pvox, hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+  for (int z = 0; z < P.nz; z++)
+    for (int y = 0; y < P.ny; y++) {
+      const size_t src = (static_cast<size_t>(z + 1) * (P.ny + 2) + (y + 1)) * P.px + 1;
+      const size_t dst = (static_cast<size_t>(z) * P.ny + y) * P.nx;
+      memcpy(host_out + dst, dm.data() + src, P.nx * sizeof(float));
+      if (band_out) memcpy(band_out + dst, bd.data() + src, P.nx);
+    }
   return MOREA_OK;
 }
 

@@ -127,9 +127,18 @@ struct DirConst {
   double qlo[3];
   double guard[3];                             // FP64 error bound of q per axis (x1000 margin)
   double gthr[3];                              // 0.5 - guard: near-grid iff |frac(q) - 0.5| >= gthr
+  float thr_f[3];                              // the same test on the FP32 fraction (wider margin)
   int64_t absD;
   int fast;                                    // extent <= 2^16: FP64 plane arithmetic
-  int pad;
+  int sigma;                                   // orientation sign of the rasterized tet
+  // bounding box of the rasterized tet on its grid and the row count
+  int lo[3], hi[3];
+  int W, NYb, R;                               // box width - 1, rows per slice, rows
+  int active;                                  // the direction has voxels to visit
+  int inner;                                   // mapped points stay inside the padded volume
+  // the direction's record, completed by the sample loop
+  float h, g, mag, vol;
+  uint32_t samples, bits;
 };
 
 // 6 x signed volume in FP64: exact when every coordinate difference is
@@ -146,7 +155,8 @@ constexpr int kDeferCap = 128;
 // LDS scratch of one wave.
 struct WaveLds {
   DirConst c[2];
-  int4 row[kWave];         // x, y | z << 16, first sample, jx | jy << 10 | jz << 20
+  int4 row[kWave];         // padded element of the first sample, its offset in the sample
+                           // stream, jx | jy << 10 | jz << 20 (box-relative), unused
   double rowq[kWave][4];   // mapped point of each row's first sample (x, y, z, unused)
   int mark[kWave];
   int4 defer[kDeferCap];   // near-grid samples: (jx | jy << 10 | jz << 20 | dir << 30, a, b, axes)
@@ -162,9 +172,10 @@ struct WaveLds {
 // axis, otherwise corners k and k + 1 do.  Returns whether any supported
 // in-grid corner is > 0.
 template <int ST>
-__device__ __forceinline__ bool exact_foreground(const void* img, int nx, int ny, int nz,
+__device__ __forceinline__ bool exact_foreground(const ProblemView& P, const void* img,
                                                  const WaveLds* L, int d, int jx, int jy, int jz,
                                                  const double q[3], int amb) {
+  const int nx = P.nx, ny = P.ny, nz = P.nz;
   const DirConst& c = L->c[d];
   const int* oth = L->vert + (d == 0 ? 12 : 0);
   int64_t s[4];
@@ -180,7 +191,7 @@ __device__ __forceinline__ bool exact_foreground(const void* img, int nx, int ny
   int lo[3], hi[3];
 #pragma unroll
   for (int a = 0; a < 3; a++) {
-    int k = static_cast<int>(floor(q[a]));
+    int k = static_cast<int>(floor(q[a])) - 1;     // q is in padded coordinates
     bool on_grid = false;
     if (amb & (1 << a)) {
       __int128 num = 0;
@@ -201,7 +212,7 @@ __device__ __forceinline__ bool exact_foreground(const void* img, int nx, int ny
     for (int cy = lo[1]; cy <= hi[1]; cy++)
       for (int cx = lo[0]; cx <= hi[0]; cx++)
         if (cx >= 0 && cy >= 0 && cz >= 0 && cx < nx && cy < ny && cz < nz)
-          fg |= ld_img<ST>(img, (cz * ny + cy) * nx + cx) > 0.0f;
+          fg |= ld_img<ST>(img, (cz + 1) * P.pxy + (cy + 1) * P.px + cx + 1) > 0.0f;
   return fg;
 }
 
@@ -257,22 +268,26 @@ __device__ __forceinline__ void row_span(const DirConst& c, int yr, int zr, int 
   }
 }
 
-// Buffer resource over a stored image including its padding, so that
-// element index i (from -kImagePad) is byte offset (i + kImagePad) * size.
+// Buffer resources over padded volumes: element i is byte offset i * size.
+// A buffer load outside the resource returns 0 instead of faulting.
 template <int ST>
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t image_rsrc(const void* img, unsigned voxels) {
-  constexpr int esize = ST == kF32 ? 4 : 2;
-  char* base = const_cast<char*>(static_cast<const char*>(img)) - kImagePad * esize;
-  return __builtin_amdgcn_make_buffer_rsrc(base, static_cast<short>(0),
-                                           static_cast<int>((voxels + 2 * kImagePad) * esize), 0x00020000);
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t image_rsrc(const void* img, unsigned pvox) {
+  constexpr unsigned esize = ST == kF32 ? 4 : 2;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(img), static_cast<short>(0),
+                                           static_cast<int>(pvox * esize), 0x00020000);
+}
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t byte_rsrc(const uint8_t* p, unsigned n) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(p), static_cast<short>(0),
+                                           static_cast<int>(n), 0x00020000);
 }
 
 template <int ST>
 __device__ __forceinline__ float ld_buf(__amdgpu_buffer_rsrc_t r, int idx) {
   if constexpr (ST == kF32) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (idx + kImagePad) * 4, 0, 0));
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, static_cast<unsigned>(idx) * 4u, 0, 0));
   } else {
-    const unsigned short u = __builtin_amdgcn_raw_buffer_load_b16(r, (idx + kImagePad) * 2, 0, 0);
+    const unsigned short u = __builtin_amdgcn_raw_buffer_load_b16(r, static_cast<unsigned>(idx) * 2u, 0, 0);
     if constexpr (ST == kBF16)
       return __uint_as_float(static_cast<uint32_t>(u) << 16);
     else
@@ -280,75 +295,126 @@ __device__ __forceinline__ float ld_buf(__amdgpu_buffer_rsrc_t r, int idx) {
   }
 }
 
-// Two consecutive FP32 voxels (idx, idx + 1) in one 8-byte buffer load.
-__device__ __forceinline__ F2 ld_pair(__amdgpu_buffer_rsrc_t r, int idx) {
+// Two consecutive FP32 voxels (idx, idx + 1) in one 8-byte buffer load; the
+// scalar offset `soff` (bytes) selects the row of the pair.
+__device__ __forceinline__ F2 ld_pair(__amdgpu_buffer_rsrc_t r, int idx, int soff) {
   typedef float f2v __attribute__((ext_vector_type(2)));
-  const f2v v = __builtin_bit_cast(f2v, __builtin_amdgcn_raw_buffer_load_b64(r, (idx + kImagePad) * 4, 0, 0));
+  const f2v v = __builtin_bit_cast(
+      f2v, __builtin_amdgcn_raw_buffer_load_b64(r, static_cast<unsigned>(idx) * 4u, soff, 0));
   return F2{v.x, v.y};
 }
 
-// One voxel sample: the centre p = (x, y, z) of direction d whose mapped
-// point is q = q_row + k * M[:, 0] (q_row of the sample's row, k its offset
-// in the row).  Samples the other image trilinearly with zero padding, adds
-// h (Sec. 4.1.2) and, inside the guidance band, the set-weighted guidance
-// term (Sec. 4.1.3, App. A.3).
-// INTERIOR: every corner of every mapped point lies inside the grid, so no
-// clamping is needed.  Returns the axes on which the mapped point is within
-// its error bound of a grid plane; such a sample's h is left to the caller
-// (a_out, b_out carry what it needs).
-template <int ST, bool INTERIOR>
-__device__ __forceinline__ int sample_one(const ProblemView& P, const DirConst& C,
-                                          __amdgpu_buffer_rsrc_t r_own, __amdgpu_buffer_rsrc_t r_oth,
-                                          int d, int x, int yy, int zz, const double qr[3], int k,
-                                          float& h_acc, float& g_acc, float& a_out, float& b_out) {
-  const int nx = P.nx, ny = P.ny, nz = P.nz;
-  const int sy = nx, sz = nx * ny;
-  const int vi = __umul24(__umul24(zz, ny) + yy, nx) + x;
+template <int ST>
+__device__ __forceinline__ float ld_soff(__amdgpu_buffer_rsrc_t r, int idx, int soff) {
+  constexpr unsigned esize = ST == kF32 ? 4 : 2;
+  if constexpr (ST == kF32) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, static_cast<unsigned>(idx) * esize, soff, 0));
+  } else {
+    const unsigned short u = __builtin_amdgcn_raw_buffer_load_b16(r, static_cast<unsigned>(idx) * esize, soff, 0);
+    if constexpr (ST == kBF16)
+      return __uint_as_float(static_cast<uint32_t>(u) << 16);
+    else
+      return static_cast<float>(__builtin_bit_cast(_Float16, u));
+  }
+}
+
+__device__ __forceinline__ double uniform_d(double v) {
+  const uint64_t b = static_cast<uint64_t>(__double_as_longlong(v));
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(b));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(b >> 32));
+  return __longlong_as_double(static_cast<long long>((static_cast<uint64_t>(hi) << 32) | lo));
+}
+
+__device__ __forceinline__ float uniform_f(float v) {
+  return __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(v)));
+}
+
+// Wave-uniform constants of one direction's sample loop (scalar registers).
+struct SampleConst {
+  double m0, m1, m2;    // M[:, 0]: step of the mapped point per voxel along x
+  float thr;            // near-grid threshold on max_a |frac(q_a) - 1/2|
+  int sy, sz;           // padded strides in bytes of the sampled image: row, slice
+};
+
+// One voxel sample of direction d: the centre at padded element vi, whose
+// mapped point (padded coordinates) is q = q_row + k * M[:, 0] (q_row of the
+// sample's row, k its offset in the row).  Samples the other image
+// trilinearly (zero outside the grid), adds h (Sec. 4.1.2) and, inside the
+// guidance band, the set-weighted guidance term (Sec. 4.1.3, App. A.3).
+// INNER: every trilinear corner of every mapped point lies in the padded
+// volume (q > 0 and q < n + 1 per axis), so no clamping is needed.
+// Returns true when the mapped point is within its error bound of a grid
+// plane on some axis: that sample's h is left to the exact path (a_out and
+// b_out carry what it needs).
+template <int ST, bool INNER>
+__device__ __forceinline__ bool sample_one(const ProblemView& P, const SampleConst& U,
+                                           __amdgpu_buffer_rsrc_t r_own, __amdgpu_buffer_rsrc_t r_oth,
+                                           __amdgpu_buffer_rsrc_t r_band, int d, int vi,
+                                           const double qr[3], int k, float& h_acc, float& g_acc,
+                                           float& a_out, float& b_out) {
   const float a = ld_buf<ST>(r_own, vi);
-  const double kd = k;
-  double qd[3];
+  const double kd = static_cast<double>(k);
+  const double q[3] = {fma(U.m0, kd, qr[0]), fma(U.m1, kd, qr[1]), fma(U.m2, kd, qr[2])};
   float f[3];
   int c[3];
-  int amb = 0;
 #pragma unroll
   for (int t = 0; t < 3; t++) {
-    qd[t] = fma(C.M[t][0], kd, qr[t]);
-    const double fl = floor(qd[t]);
-    const double fr = qd[t] - fl;
-    f[t] = static_cast<float>(fr);
-    c[t] = static_cast<int>(fl);
-    if (fabs(fr - 0.5) >= C.gthr[t]) amb |= 1 << t;
+    if constexpr (INNER) {
+      // q > 0: truncation is the floor, and the fraction is exact
+      c[t] = static_cast<int>(q[t]);
+      f[t] = static_cast<float>(__builtin_amdgcn_fract(q[t]));
+    } else {
+      const double fl = floor(q[t]);
+      c[t] = static_cast<int>(fl);
+      f[t] = static_cast<float>(q[t] - fl);
+    }
   }
-  int cx0, cx1, cy0, cy1, cz0, cz1;
-  if constexpr (INTERIOR) {
-    cx0 = c[0]; cx1 = c[0] + 1; cy0 = c[1]; cy1 = c[1] + 1; cz0 = c[2]; cz1 = c[2] + 1;
-  } else {
-    cx0 = min(max(c[0], 0), nx - 1); cx1 = min(max(c[0] + 1, 0), nx - 1);
-    cy0 = min(max(c[1], 0), ny - 1); cy1 = min(max(c[1] + 1, 0), ny - 1);
-    cz0 = min(max(c[2], 0), nz - 1); cz1 = min(max(c[2] + 1, 0), nz - 1);
-  }
-  const int z0 = __umul24(cz0, sz), z1 = __umul24(cz1, sz);
-  const int r00 = z0 + __umul24(cy0, sy), r01 = z0 + __umul24(cy1, sy);
-  const int r10 = z1 + __umul24(cy0, sy), r11 = z1 + __umul24(cy1, sy);
+  const bool amb = fabsf(f[0] - 0.5f) >= U.thr || fabsf(f[1] - 0.5f) >= U.thr || fabsf(f[2] - 0.5f) >= U.thr;
+
+  // corner indices (padded elements): x pair ix0/ix1, row offsets ry0/ry1,
+  // slice offsets rz0/rz1
+  int ix0, ix1, ry0, ry1, rz0, rz1;
   float v000, v001, v010, v011, v100, v101, v110, v111;
-  if constexpr (ST == kF32) {
-    // one 8-byte load per corner pair (x, x+1); the padding keeps x = -1
-    // and x = nx - 1 inside the buffer
-    const int xs = INTERIOR ? c[0] : min(max(c[0], -1), nx - 1);
-    const F2 p00 = ld_pair(r_oth, r00 + xs), p01 = ld_pair(r_oth, r01 + xs);
-    const F2 p10 = ld_pair(r_oth, r10 + xs), p11 = ld_pair(r_oth, r11 + xs);
-    v000 = p00.a; v001 = p00.b; v010 = p01.a; v011 = p01.b;
-    v100 = p10.a; v101 = p10.b; v110 = p11.a; v111 = p11.b;
+  constexpr int esize = ST == kF32 ? 4 : 2;
+  if constexpr (INNER) {
+    ix0 = c[0];
+    ix1 = c[0] + 1;
+    ry0 = __umul24(c[1], P.px);
+    ry1 = ry0 + P.px;
+    rz0 = __umul24(c[2], P.pxy);
+    rz1 = rz0 + P.pxy;
+    const int base = rz0 + ry0 + ix0;
+    if constexpr (ST == kF32) {
+      const F2 p00 = ld_pair(r_oth, base, 0), p01 = ld_pair(r_oth, base, U.sy);
+      const F2 p10 = ld_pair(r_oth, base, U.sz), p11 = ld_pair(r_oth, base, U.sy + U.sz);
+      v000 = p00.a; v001 = p00.b; v010 = p01.a; v011 = p01.b;
+      v100 = p10.a; v101 = p10.b; v110 = p11.a; v111 = p11.b;
+    } else {
+      v000 = ld_soff<ST>(r_oth, base, 0); v001 = ld_soff<ST>(r_oth, base + 1, 0);
+      v010 = ld_soff<ST>(r_oth, base, U.sy); v011 = ld_soff<ST>(r_oth, base + 1, U.sy);
+      v100 = ld_soff<ST>(r_oth, base, U.sz); v101 = ld_soff<ST>(r_oth, base + 1, U.sz);
+      v110 = ld_soff<ST>(r_oth, base, U.sy + U.sz); v111 = ld_soff<ST>(r_oth, base + 1, U.sy + U.sz);
+    }
+    (void)esize;
   } else {
-    v000 = ld_buf<ST>(r_oth, r00 + cx0); v001 = ld_buf<ST>(r_oth, r00 + cx1);
-    v010 = ld_buf<ST>(r_oth, r01 + cx0); v011 = ld_buf<ST>(r_oth, r01 + cx1);
-    v100 = ld_buf<ST>(r_oth, r10 + cx0); v101 = ld_buf<ST>(r_oth, r10 + cx1);
-    v110 = ld_buf<ST>(r_oth, r11 + cx0); v111 = ld_buf<ST>(r_oth, r11 + cx1);
-  }
-  if constexpr (!INTERIOR) {
-    const bool vx0 = c[0] >= 0 && c[0] < nx, vx1 = c[0] >= -1 && c[0] < nx - 1;
-    const bool vy0 = c[1] >= 0 && c[1] < ny, vy1 = c[1] >= -1 && c[1] < ny - 1;
-    const bool vz0 = c[2] >= 0 && c[2] < nz, vz1 = c[2] >= -1 && c[2] < nz - 1;
+    // padded index range per axis is [0, n + 1]; corners beyond it are
+    // outside the image (value 0) and clamp for the distance maps
+    const int n0 = P.nx + 1, n1 = P.ny + 1, n2 = P.nz + 1;
+    ix0 = min(max(c[0], 0), n0);
+    ix1 = min(max(c[0] + 1, 0), n0);
+    const int cy0 = min(max(c[1], 0), n1), cy1 = min(max(c[1] + 1, 0), n1);
+    const int cz0 = min(max(c[2], 0), n2), cz1 = min(max(c[2] + 1, 0), n2);
+    ry0 = __umul24(cy0, P.px);
+    ry1 = __umul24(cy1, P.px);
+    rz0 = __umul24(cz0, P.pxy);
+    rz1 = __umul24(cz1, P.pxy);
+    const bool vx0 = c[0] >= 0 && c[0] <= n0, vx1 = c[0] >= -1 && c[0] < n0;
+    const bool vy0 = c[1] >= 0 && c[1] <= n1, vy1 = c[1] >= -1 && c[1] < n1;
+    const bool vz0 = c[2] >= 0 && c[2] <= n2, vz1 = c[2] >= -1 && c[2] < n2;
+    v000 = ld_buf<ST>(r_oth, rz0 + ry0 + ix0); v001 = ld_buf<ST>(r_oth, rz0 + ry0 + ix1);
+    v010 = ld_buf<ST>(r_oth, rz0 + ry1 + ix0); v011 = ld_buf<ST>(r_oth, rz0 + ry1 + ix1);
+    v100 = ld_buf<ST>(r_oth, rz1 + ry0 + ix0); v101 = ld_buf<ST>(r_oth, rz1 + ry0 + ix1);
+    v110 = ld_buf<ST>(r_oth, rz1 + ry1 + ix0); v111 = ld_buf<ST>(r_oth, rz1 + ry1 + ix1);
     v000 = (vz0 && vy0 && vx0) ? v000 : 0.f;
     v001 = (vz0 && vy0 && vx1) ? v001 : 0.f;
     v010 = (vz0 && vy1 && vx0) ? v010 : 0.f;
@@ -362,27 +428,28 @@ __device__ __forceinline__ int sample_one(const ProblemView& P, const DirConst& 
   const float e10 = fmaf(f[0], v101 - v100, v100), e11 = fmaf(f[0], v111 - v110, v110);
   const float e0 = fmaf(f[1], e01 - e00, e00), e1 = fmaf(f[1], e11 - e10, e10);
   const float b = fmaf(f[2], e1 - e0, e0);
-  const bool fg8 = (fmaxf(fmaxf(fmaxf(v000, v001), fmaxf(v010, v011)),
-                         fmaxf(fmaxf(v100, v101), fmaxf(v110, v111))) > 0.f);
+  // any corner > 0: the images are >= 0, so any non-zero magnitude bit
+  const uint32_t ob = __float_as_uint(v000) | __float_as_uint(v001) | __float_as_uint(v010) |
+                      __float_as_uint(v011) | __float_as_uint(v100) | __float_as_uint(v101) |
+                      __float_as_uint(v110) | __float_as_uint(v111);
+  const bool fg8 = (ob << 1) != 0u;
 
   if (P.n_sets > 0) {
-    unsigned bandbits = (d ? P.band[1] : P.band[0])[vi];
+    unsigned bandbits = __builtin_amdgcn_raw_buffer_load_b8(r_band, static_cast<unsigned>(vi), 0, 0);
     if (bandbits) {
-      // the other distance map is edge-clamped: the clamped corners above
-      // are exactly that (and interior corners need no clamping)
-      const unsigned V = static_cast<unsigned>(nx * ny * nz);
       const float r = P.radius, inv_r = P.inv_radius;
       const float* map_own = d ? P.dmap[1] : P.dmap[0];
       const float* map_oth = d ? P.dmap[0] : P.dmap[1];
+      const int i00 = rz0 + ry0, i01 = rz0 + ry1, i10 = rz1 + ry0, i11 = rz1 + ry1;
       while (bandbits) {
         const int sidx = __builtin_ctz(bandbits);
         bandbits &= bandbits - 1;
-        const float* mo = map_oth + static_cast<size_t>(sidx) * V;
-        const float dist = map_own[static_cast<size_t>(sidx) * V + vi];
-        const float u00 = fmaf(f[0], mo[r00 + cx1] - mo[r00 + cx0], mo[r00 + cx0]);
-        const float u01 = fmaf(f[0], mo[r01 + cx1] - mo[r01 + cx0], mo[r01 + cx0]);
-        const float u10 = fmaf(f[0], mo[r10 + cx1] - mo[r10 + cx0], mo[r10 + cx0]);
-        const float u11 = fmaf(f[0], mo[r11 + cx1] - mo[r11 + cx0], mo[r11 + cx0]);
+        const float* mo = map_oth + static_cast<size_t>(sidx) * P.pvox;
+        const float dist = map_own[static_cast<size_t>(sidx) * P.pvox + vi];
+        const float u00 = fmaf(f[0], mo[i00 + ix1] - mo[i00 + ix0], mo[i00 + ix0]);
+        const float u01 = fmaf(f[0], mo[i01 + ix1] - mo[i01 + ix0], mo[i01 + ix0]);
+        const float u10 = fmaf(f[0], mo[i10 + ix1] - mo[i10 + ix0], mo[i10 + ix0]);
+        const float u11 = fmaf(f[0], mo[i11 + ix1] - mo[i11 + ix0], mo[i11 + ix0]);
         const float u0 = fmaf(f[1], u01 - u00, u00), u1 = fmaf(f[1], u11 - u10, u10);
         const float d2 = fmaf(f[2], u1 - u0, u0);
         const float diff = dist - d2;
@@ -395,19 +462,20 @@ __device__ __forceinline__ int sample_one(const ProblemView& P, const DirConst& 
   // exact support decides, later, from the deferred queue
   a_out = a;
   b_out = b;
-  if (amb) return amb;
+  if (amb) return true;
   const bool fg_a = a > 0.f;
   const float dd = a - b;
   h_acc += (fg_a && fg8) ? dd * dd : ((fg_a != fg8) ? 1.f : 0.f);
-  return 0;
+  return false;
 }
 
 // Resolve the deferred near-grid samples of a wave: one sample per lane,
-// the mapped point recomputed from the item constants, foreground decided
-// on the exact support; h is added to the accumulator of its direction.
+// the mapped point recomputed from the item constants, the axes near a grid
+// plane found again in FP64, foreground decided on the exact support; h is
+// added to the accumulator.
 template <int ST>
 __device__ __forceinline__ void flush_deferred(const ProblemView& P, const WaveLds* L, int count,
-                                               float& h0, float& h1) {
+                                               float& h_acc) {
   const int lane = lane_id();
   for (int base = 0; base < count; base += kWave) {
     const int e = base + lane;
@@ -417,16 +485,17 @@ __device__ __forceinline__ void flush_deferred(const ProblemView& P, const WaveL
     const float a = __int_as_float(q4.y), b = __int_as_float(q4.z);
     const DirConst& C = L->c[d];
     double q[3];
+    int axes = 0;
 #pragma unroll
-    for (int k = 0; k < 3; k++)
+    for (int k = 0; k < 3; k++) {
       q[k] = fma(C.M[k][0], static_cast<double>(jx),
                  fma(C.M[k][1], static_cast<double>(jy), fma(C.M[k][2], static_cast<double>(jz), C.qlo[k])));
-    const bool fg_b = exact_foreground<ST>(d ? P.img[0] : P.img[1], P.nx, P.ny, P.nz, L, d, jx, jy,
-                                           jz, q, q4.w);
+      if (fabs(q[k] - floor(q[k]) - 0.5) >= C.gthr[k]) axes |= 1 << k;
+    }
+    const bool fg_b = exact_foreground<ST>(P, d ? P.img[0] : P.img[1], L, d, jx, jy, jz, q, axes);
     const bool fg_a = a > 0.f;
     const float dd = a - (fg_b ? b : 0.f);
-    const float h = (fg_a && fg_b) ? dd * dd : ((fg_a != fg_b) ? 1.f : 0.f);
-    if (d) h1 += h; else h0 += h;
+    h_acc += (fg_a && fg_b) ? dd * dd : ((fg_a != fg_b) ? 1.f : 0.f);
   }
 }
 
@@ -454,40 +523,58 @@ __device__ void eval_tet(const ProblemView& P, int tet, float coord, WaveLds* L,
       for (int k = 0; k < 3; k++) V[m][i][k] = __builtin_amdgcn_readlane(fix, 12 * m + 3 * i + k);
   wave_sync();
 
-  // ---- per direction: box on its grid, fold check (App. A.4), interior flag
+  // ---- per direction: box on its grid, fold check (App. A.4), interior
+  // flag.  The values are wave-uniform; they go to the wave's LDS block so
+  // that only the current direction's copy is live in the sample loop.
   const int dims[3] = {P.nx, P.ny, P.nz};
   const int ref = P.ref_sign[tet];
-  int lo[2][3], hi[2][3], R[2], NYb[2], W[2];
-  bool fast[2], interior[2], active[2];
-  int64_t D[2];
-  Record rec[2];
+  bool any_active = false;
 #pragma unroll
   for (int m = 0; m < 2; m++) {
-    int ext = 0;
-    interior[m] = true;
+    int ext = 0, lo[3], hi[3];
+    bool interior = true;
 #pragma unroll
     for (int k = 0; k < 3; k++) {
       const int mn = min(min(V[m][0][k], V[m][1][k]), min(V[m][2][k], V[m][3][k]));
       const int mx = max(max(V[m][0][k], V[m][1][k]), max(V[m][2][k], V[m][3][k]));
       ext = max(ext, mx - mn);
-      lo[m][k] = max(0, -static_cast<int>(floor_div_pos(-static_cast<int64_t>(mn), 1024)));
-      hi[m][k] = min(dims[k] - 1, static_cast<int>(floor_div_pos(mx, 1024)));
-      // the tet of mesh m is sampled by direction 1 - m: all trilinear
-      // corners are valid voxels when it is >= 2^-10 voxel inside the grid
-      interior[m] = interior[m] && mn >= 1 && mx <= 1024 * (dims[k] - 1) - 1;
+      lo[k] = max(0, -static_cast<int>(floor_div_pos(-static_cast<int64_t>(mn), 1024)));
+      hi[k] = min(dims[k] - 1, static_cast<int>(floor_div_pos(mx, 1024)));
+      // the tet of mesh m is sampled by direction 1 - m: every trilinear
+      // corner of a mapped point lies in the padded volume when the tet is
+      // inside (-1, n) by at least 2^-10 voxel
+      interior = interior && mn >= -1023 && mx <= 1024 * dims[k] - 1;
     }
-    fast[m] = ext <= kFastExtent;
+    const bool fast = ext <= kFastExtent;
     // FP64 is exact for extents <= 2^16: |6V| <= 6 E^3 < 2^53
-    D[m] = fast[m] ? static_cast<int64_t>(det_f64(V[m])) : det_i64(V[m]);
-    const int sg = (D[m] > 0) - (D[m] < 0);
+    const int64_t D = fast ? static_cast<int64_t>(det_f64(V[m])) : det_i64(V[m]);
+    const int sg = (D > 0) - (D < 0);
     const bool viol = (sg == 0) || (sg != ref);
-    const int64_t absD = D[m] < 0 ? -D[m] : D[m];
-    rec[m] = Record{0.f, 0.f, 0u, 0.f, 0.f, viol ? 1u : 0u};
-    if (viol) rec[m].vol = static_cast<float>(static_cast<double>(absD) * (1.0 / (6.0 * 1073741824.0)));
-    active[m] = D[m] != 0 && lo[m][0] <= hi[m][0] && lo[m][1] <= hi[m][1] && lo[m][2] <= hi[m][2];
-    W[m] = hi[m][0] - lo[m][0];
-    NYb[m] = hi[m][1] - lo[m][1] + 1;
-    R[m] = active[m] ? NYb[m] * (hi[m][2] - lo[m][2] + 1) : 0;
+    const int64_t absD = D < 0 ? -D : D;
+    const bool active = D != 0 && lo[0] <= hi[0] && lo[1] <= hi[1] && lo[2] <= hi[2];
+    any_active = any_active || active;
+    if (lane == 0) {
+      DirConst& C = L->c[m];
+      C.absD = absD;
+      C.fast = fast ? 1 : 0;
+      C.sigma = D > 0 ? 1 : -1;
+#pragma unroll
+      for (int k = 0; k < 3; k++) {
+        C.lo[k] = lo[k];
+        C.hi[k] = hi[k];
+      }
+      C.W = hi[0] - lo[0];
+      C.NYb = hi[1] - lo[1] + 1;
+      C.R = active ? C.NYb * (hi[2] - lo[2] + 1) : 0;
+      C.active = active ? 1 : 0;
+      L->c[1 - m].inner = interior ? 1 : 0;
+      C.h = 0.f;
+      C.g = 0.f;
+      C.samples = 0u;
+      C.mag = 0.f;
+      C.vol = viol ? static_cast<float>(static_cast<double>(absD) * (1.0 / (6.0 * 1073741824.0))) : 0.f;
+      C.bits = viol ? 1u : 0u;
+    }
   }
 
   // ---- deformation magnitude (Sec. 4.1.1), one edge per lane:
@@ -526,10 +613,15 @@ __device__ void eval_tet(const ProblemView& P, int tet, float coord, WaveLds* L,
       const float dd = den > 0.f ? static_cast<float>(ls - lt) / den * scale : 0.f;
       term = dd * dd;
     }
-    rec[0].mag = P.elasticity[tet] * wave_sum(term);
+    const float mag = P.elasticity[tet] * wave_sum(term);
+    if (lane == 0) L->c[0].mag = mag;
   }
-  if (!active[0] && !active[1]) {
-    if (lane < 2) out[lane] = rec[lane];
+  wave_sync();
+  if (!any_active) {
+    if (lane < 2) {
+      const DirConst& C = L->c[lane];
+      out[lane] = Record{0.f, 0.f, 0u, C.mag, C.vol, C.bits};
+    }
     return;
   }
 
@@ -540,7 +632,7 @@ __device__ void eval_tet(const ProblemView& P, int tet, float coord, WaveLds* L,
     const int d = lane >> 2, i = lane & 3;
     DirConst& C = L->c[d];
     const int* own = L->vert + 12 * d;
-    const int sigma = D[d] > 0 ? 1 : -1;
+    const int sigma = C.sigma;
     const int b0 = i == 0 ? 1 : 0;                            // base vertex on the face
     const int u0 = i == 0 ? 2 : (i == 1 ? 2 : (i == 2 ? 3 : 1));
     const int w0 = i == 0 ? 3 : (i == 1 ? 3 : (i == 2 ? 1 : 2));
@@ -561,8 +653,7 @@ __device__ void eval_tet(const ProblemView& P, int tet, float coord, WaveLds* L,
     C.n[i][1] = ny_;
     C.n[i][2] = nz_;
     const int lex = (nx_ > 0 || (nx_ == 0 && (ny_ > 0 || (ny_ == 0 && nz_ > 0)))) ? 1 : 0;
-    const int* lod = lo[d];
-    const double ox = 1024.0 * lod[0] - r[0], oy = 1024.0 * lod[1] - r[1], oz = 1024.0 * lod[2] - r[2];
+    const double ox = 1024.0 * C.lo[0] - r[0], oy = 1024.0 * C.lo[1] - r[1], oz = 1024.0 * C.lo[2] - r[2];
     const double A = nx_ * 1024.0, PY = ny_ * 1024.0, PZ = nz_ * 1024.0;
     C.A[i] = A;
     C.PY[i] = PY;
@@ -572,7 +663,7 @@ __device__ void eval_tet(const ProblemView& P, int tet, float coord, WaveLds* L,
     const int kind = (nx_ > 0) - (nx_ < 0);
     C.kind[i] = kind;
     C.lex[i] = lex;
-    if (fast[d]) {
+    if (C.fast) {
       // |terms| <= 2 E^3 <= 2^49: exact
       const double B0 = fma(nx_, ox, fma(ny_, oy, nz_ * oz)) + lex;
       C.B0[i] = B0;
@@ -581,7 +672,7 @@ __device__ void eval_tet(const ProblemView& P, int tet, float coord, WaveLds* L,
         C.TA[i] = ta;
         C.TB[i] = tb;
         C.TG[i] = tg;
-        C.TE[i] = (fabs(ta) * NYb[d] + fabs(tb) * (hi[d][2] - lo[d][2] + 1) + fabs(tg) + 128.0) * 0x1p-48;
+        C.TE[i] = (fabs(ta) * C.NYb + fabs(tb) * (C.hi[2] - C.lo[2] + 1) + fabs(tg) + 128.0) * 0x1p-48;
       } else {
         C.TA[i] = PY;
         C.TB[i] = PZ;
@@ -597,10 +688,6 @@ __device__ void eval_tet(const ProblemView& P, int tet, float coord, WaveLds* L,
       C.B0i[i] = nxi * static_cast<long long>(ox) + nyi * static_cast<long long>(oy) +
                  nzi * static_cast<long long>(oz) + lex;
     }
-    if (i == 0) {
-      C.absD = D[d] < 0 ? -D[d] : D[d];
-      C.fast = fast[d] ? 1 : 0;
-    }
   }
   wave_sync();
   // phase 2, lanes 0..17: map entry M[a][c] of direction d = lane / 9:
@@ -610,8 +697,8 @@ __device__ void eval_tet(const ProblemView& P, int tet, float coord, WaveLds* L,
     const int d = lane / 9, a = (lane % 9) / 3, cc = lane % 3;
     DirConst& C = L->c[d];
     const int* oth = L->vert + 12 * (1 - d);
-    const double sigma = D[d] > 0 ? 1.0 : -1.0;
-    const double invD = 1.0 / static_cast<double>(D[d] != 0 ? D[d] : 1);
+    const double sigma = C.sigma;
+    const double invD = sigma / static_cast<double>(C.absD != 0 ? C.absD : 1);
     const double oth0 = oth[a];
     double num = 0.0, mag = 0.0;
 #pragma unroll
@@ -625,38 +712,105 @@ __device__ void eval_tet(const ProblemView& P, int tet, float coord, WaveLds* L,
     C.Mabs[a][cc] = mag * fabs(invD);
   }
   wave_sync();
-  // phase 3, lanes 0..5: q at the box corner and the FP64 error bound of q
+  // phase 3, lanes 0..5: q at the box corner (padded coordinates: grid
+  // coordinate + 1) and the FP64 error bound of q
   if (lane < 6) {
     const int d = lane / 3, a = lane % 3;
     DirConst& C = L->c[d];
     const int* own = L->vert + 12 * d;
     const int* oth = L->vert + 12 * (1 - d);
-    double q = oth[a] * (1.0 / 1024.0);
+    double q = oth[a] * (1.0 / 1024.0) + 1.0;
     double bound = fabs(q) + 1.0;
 #pragma unroll
     for (int cc = 0; cc < 3; cc++) {
-      const double off = lo[d][cc] - own[cc] * (1.0 / 1024.0);
+      const double off = C.lo[cc] - own[cc] * (1.0 / 1024.0);
       q += C.M[a][cc] * off;
-      bound += C.Mabs[a][cc] * (fabs(off) + (hi[d][cc] - lo[d][cc]));
+      bound += C.Mabs[a][cc] * (fabs(off) + (C.hi[cc] - C.lo[cc]));
     }
     C.qlo[a] = q;
     C.guard[a] = bound * 0x1p-40;
     C.gthr[a] = 0.5 - bound * 0x1p-40;
+    // FP32 fraction: rounding it and subtracting 1/2 moves the test value by
+    // < 2^-24; the margin 2^-22 also covers rounding the threshold
+    C.thr_f[a] = static_cast<float>(0.5 - bound * 0x1p-40 - 0x1p-22);
   }
   wave_sync();
 
-  // ---- rows and samples, one direction at a time (wave-uniform d)
+  // ---- rows and samples, one direction at a time (wave-uniform d).  Rows
+  // are solved 64 at a time; non-empty rows enter a table of up to 64 rows
+  // whose samples form one stream, consumed in full batches of 64 (the
+  // stream carries over from one chunk of rows to the next, so only the
+  // direction's last batch runs part-empty).
   for (int d = 0; d < 2; d++) {
-    if (!active[d]) continue;
-    const int Rd = R[d], nyb = NYb[d], Wd = W[d];
-    const int lox = lo[d][0], loy = lo[d][1], loz = lo[d][2];
-    const float inv_nyb = 1.0f / static_cast<float>(nyb);
     const DirConst& Cd = L->c[d];
-    const unsigned nvox = static_cast<unsigned>(P.nx * P.ny * P.nz);
-    const __amdgpu_buffer_rsrc_t r_own = image_rsrc<ST>(P.img[d], nvox);
-    const __amdgpu_buffer_rsrc_t r_oth = image_rsrc<ST>(P.img[1 - d], nvox);
+    if (!uniform_i(Cd.active)) continue;
+    const int Rd = uniform_i(Cd.R), nyb = uniform_i(Cd.NYb), Wd = uniform_i(Cd.W);
+    const int lox = uniform_i(Cd.lo[0]), loy = uniform_i(Cd.lo[1]), loz = uniform_i(Cd.lo[2]);
+    const float inv_nyb = 1.0f / static_cast<float>(nyb);
+    const bool inner = uniform_i(Cd.inner) != 0;
+    SampleConst U;
+    U.m0 = uniform_d(Cd.M[0][0]);
+    U.m1 = uniform_d(Cd.M[1][0]);
+    U.m2 = uniform_d(Cd.M[2][0]);
+    U.thr = uniform_f(fminf(fminf(Cd.thr_f[0], Cd.thr_f[1]), Cd.thr_f[2]));
+    constexpr int esize = ST == kF32 ? 4 : 2;
+    U.sy = P.px * esize;
+    U.sz = P.pxy * esize;
+    const __amdgpu_buffer_rsrc_t r_own = image_rsrc<ST>(P.img[d], P.pvox);
+    const __amdgpu_buffer_rsrc_t r_oth = image_rsrc<ST>(P.img[1 - d], P.pvox);
+    const __amdgpu_buffer_rsrc_t r_band = byte_rsrc(P.band[d], P.pvox);
     float h = 0.f, g = 0.f;
     int n = 0, n_defer = 0;
+    int n_tab = 0;      // rows in the table
+    int tab_total = 0;  // samples of the table rows not yet consumed
+
+    // consume samples [0, limit) of the table's stream in batches of 64
+    auto run_batches = [&](int limit) {
+      const int my_off = lane < n_tab ? L->row[lane].y : 0x7fffffff;
+      for (int sb = 0; sb < limit; sb += kWave) {
+        // row of each lane's sample: rows starting at or before sb, plus
+        // rows starting inside (sb, sb + lane]
+        const int first = __popcll(__ballot(my_off <= sb)) - 1;
+        L->mark[lane] = 0;
+        wave_sync();
+        const int rel = my_off - sb;
+        if (rel > 0 && rel < kWave) L->mark[rel] = 1;
+        wave_sync();
+        const uint64_t starts = __ballot(L->mark[lane] != 0);
+        const int ri = first + bits_below(starts) + static_cast<int>((starts >> lane) & 1ull);
+        const int s = sb + lane;
+        bool amb = false;
+        int jpack = 0;
+        float a = 0.f, b = 0.f;
+        if (s < limit) {
+          const int4 rw = L->row[ri];
+          const int k = s - rw.y;
+          const double qr[3] = {L->rowq[ri][0], L->rowq[ri][1], L->rowq[ri][2]};
+          if (inner)
+            amb = sample_one<ST, true>(P, U, r_own, r_oth, r_band, d, rw.x + k, qr, k, h, g, a, b);
+          else
+            amb = sample_one<ST, false>(P, U, r_own, r_oth, r_band, d, rw.x + k, qr, k, h, g, a, b);
+          n += 1;
+          jpack = (rw.z + k) | (d << 30);
+        }
+        const uint64_t amb_mask = __ballot(amb);
+        if (amb_mask) {
+          if (amb) {
+            const int slot = n_defer + bits_below(amb_mask);
+            L->defer[slot] = make_int4(jpack, __float_as_int(a), __float_as_int(b), 0);
+          }
+          n_defer += __popcll(amb_mask);
+        }
+        if (n_defer > kDeferCap - kWave) {
+          wave_sync();
+          flush_deferred<ST>(P, L, n_defer, h);
+          n_defer = 0;
+        }
+        wave_sync();
+      }
+      return my_off;
+    };
+
     for (int rb = 0; rb < Rd; rb += kWave) {
       const int rr = rb + lane;
       int js = 1, je = 0, yr = 0, zr = 0;
@@ -668,74 +822,84 @@ __device__ void eval_tet(const ProblemView& P, int tet, float coord, WaveLds* L,
         row_span(Cd, yr, zr, Wd, js, je);
       }
       const int len = max(0, je - js + 1);
-      const uint64_t rows_mask = __ballot(len > 0);
-      if (rows_mask == 0) continue;
-      const int nrows = __popcll(rows_mask);
-      const int off = wave_excl_scan(len);
-      const int total = __shfl(off + len, 63, 64);
-      if (len > 0) {
-        const int ci = bits_below(rows_mask);
-        L->row[ci] = make_int4(lox + js, (loy + yr) | ((loz + zr) << 16), off,
-                               js | (yr << 10) | (zr << 20));
-        const double jx = js, jy = yr, jz = zr;
+      // the row's box-relative position, packed (it stays live while the
+      // table is consumed)
+      const int jp = js | (yr << 10) | (zr << 20);
+      uint64_t want = __ballot(len > 0);
+      while (want) {
+        // append as many of this chunk's rows as the table holds
+        const int space = kWave - n_tab;
+        const int ci = bits_below(want);
+        const bool take = ((want >> lane) & 1ull) && ci < space;
+        const uint64_t took = __ballot(take);
+        const int tl = take ? len : 0;
+        const int excl = wave_excl_scan(tl);
+        const int added = __shfl(excl + tl, 63, 64);
+        if (take) {
+          const int slot = n_tab + ci;
+          const int jx = jp & 1023, jy = (jp >> 10) & 1023, jz = jp >> 20;
+          const int vi_row = __umul24(loz + jz + 1, P.pxy) + __umul24(loy + jy + 1, P.px) + lox + jx + 1;
+          L->row[slot] = make_int4(vi_row, tab_total + excl, jp, 0);
 #pragma unroll
-        for (int t = 0; t < 3; t++)
-          L->rowq[ci][t] = fma(Cd.M[t][0], jx, fma(Cd.M[t][1], jy, fma(Cd.M[t][2], jz, Cd.qlo[t])));
-      }
-      wave_sync();
-      const int my_off = lane < nrows ? L->row[lane].z : 0x7fffffff;
-
-      for (int sb = 0; sb < total; sb += kWave) {
-        // row of each lane's sample: rows starting at or before sb, plus rows
-        // starting inside (sb, sb + lane]
-        const int first = __popcll(__ballot(my_off <= sb)) - 1;
-        L->mark[lane] = 0;
-        wave_sync();
-        const int rel = my_off - sb;
-        if (rel > 0 && rel < kWave) L->mark[rel] = 1;
-        wave_sync();
-        const uint64_t starts = __ballot(L->mark[lane] != 0);
-        const int ri = first + bits_below(starts) + static_cast<int>((starts >> lane) & 1ull);
-        const int s = sb + lane;
-        int amb = 0, jpack = 0;
-        float a = 0.f, b = 0.f;
-        if (s < total) {
-          const int4 rw = L->row[ri];
-          const int k = s - rw.z;
-          const int x = rw.x + k, yy = rw.y & 0xffff, zz = rw.y >> 16;
-          const double qr[3] = {L->rowq[ri][0], L->rowq[ri][1], L->rowq[ri][2]};
-          if (interior[1 - d])
-            amb = sample_one<ST, true>(P, Cd, r_own, r_oth, d, x, yy, zz, qr, k, h, g, a, b);
-          else
-            amb = sample_one<ST, false>(P, Cd, r_own, r_oth, d, x, yy, zz, qr, k, h, g, a, b);
-          n += 1;
-          jpack = (rw.w + k) | (d << 30);
+          for (int t = 0; t < 3; t++)
+            L->rowq[slot][t] = fma(Cd.M[t][0], static_cast<double>(jx),
+                                   fma(Cd.M[t][1], static_cast<double>(jy),
+                                       fma(Cd.M[t][2], static_cast<double>(jz), Cd.qlo[t])));
         }
-        const uint64_t amb_mask = __ballot(amb != 0);
-        if (amb_mask) {
-          if (amb) {
-            const int slot = n_defer + bits_below(amb_mask);
-            L->defer[slot] = make_int4(jpack, __float_as_int(a), __float_as_int(b), amb);
+        n_tab += __popcll(took);
+        tab_total += added;
+        want &= ~took;
+        wave_sync();
+        if (tab_total >= kWave) {
+          const int consumed = tab_total & ~(kWave - 1);
+          const int my_off = run_batches(consumed);
+          // drop the rows that end within the consumed samples (a prefix),
+          // move the rest to the front and rebase their offsets
+          const int nxt = __shfl_down(my_off, 1, 64);
+          const int end = lane == n_tab - 1 ? tab_total : nxt;
+          const int done = __popcll(__ballot(lane < n_tab && end <= consumed));
+          const bool mv = lane + done < n_tab;
+          int4 rw = make_int4(0, 0, 0, 0);
+          double q0 = 0.0, q1 = 0.0, q2 = 0.0;
+          if (mv) {
+            rw = L->row[lane + done];
+            q0 = L->rowq[lane + done][0];
+            q1 = L->rowq[lane + done][1];
+            q2 = L->rowq[lane + done][2];
           }
-          n_defer += __popcll(amb_mask);
-        }
-        if (n_defer > kDeferCap - kWave) {
           wave_sync();
-          flush_deferred<ST>(P, L, n_defer, h, h);
-          n_defer = 0;
+          if (mv) {
+            rw.y -= consumed;
+            L->row[lane] = rw;
+            L->rowq[lane][0] = q0;
+            L->rowq[lane][1] = q1;
+            L->rowq[lane][2] = q2;
+          }
+          wave_sync();
+          n_tab -= done;
+          tab_total -= consumed;
         }
-        wave_sync();
       }
     }
+    if (tab_total > 0) run_batches(tab_total);
     if (n_defer > 0) {
       wave_sync();
-      flush_deferred<ST>(P, L, n_defer, h, h);
+      flush_deferred<ST>(P, L, n_defer, h);
     }
-    rec[d].h = wave_sum(h);
-    rec[d].g = wave_sum(g);
-    rec[d].n = static_cast<uint32_t>(wave_sum_i(n));
+    h = wave_sum(h);
+    g = wave_sum(g);
+    n = wave_sum_i(n);
+    if (lane == 0) {
+      L->c[d].h = h;
+      L->c[d].g = g;
+      L->c[d].samples = static_cast<uint32_t>(n);
+    }
   }
-  if (lane < 2) out[lane] = rec[lane];
+  wave_sync();
+  if (lane < 2) {
+    const DirConst& C = L->c[lane];
+    out[lane] = Record{C.h, C.g, C.samples, C.mag, C.vol, C.bits};
+  }
 }
 
 // Block index remap so that each of the 8 XCDs (which receive blocks
@@ -752,7 +916,7 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 // Full evaluation: one wave per (candidate, tet), item = tet * pop + candidate,
 // so the 4 waves of a block are 4 candidates of one tet.
 template <int ST>
-__global__ __launch_bounds__(256, 5) void k_eval_full(ProblemView P, FullItems F, Record* rec,
+__global__ __launch_bounds__(256, 4) void k_eval_full(ProblemView P, FullItems F, Record* rec,
                                                     int n_items) {
   __shared__ WaveLds lds[4];
   const int wave = threadIdx.x >> 6;
@@ -861,25 +1025,28 @@ __global__ __launch_bounds__(256) void k_finalize(ProblemView P, const float* pt
 // Guidance distance maps: d(p, C) for every set and voxel centre, from the
 // set points snapped like mesh coordinates (exact squared distances in
 // int64, square root in FP64, rounded to FP32), plus the per-voxel band mask
-// of the sets with d < r.
+// of the sets with d < r.  Both are written padded: a border element holds
+// the value of the nearest grid voxel (edge clamping).
 __global__ void k_distance_maps(int nx, int ny, int nz, int n_sets, const int* set_off,
                                 const int* pts_fix, float radius, float* dmap, uint8_t* band) {
-  const size_t V = static_cast<size_t>(nx) * ny * nz;
-  for (size_t v = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; v < V;
+  const int px = nx + 2, py = ny + 2;
+  const size_t PV = static_cast<size_t>(px) * py * (nz + 2);
+  for (size_t v = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; v < PV;
        v += static_cast<size_t>(gridDim.x) * blockDim.x) {
-    const int x = static_cast<int>(v % nx), y = static_cast<int>((v / nx) % ny),
-              z = static_cast<int>(v / (static_cast<size_t>(nx) * ny));
-    const int64_t px = (int64_t)x * 1024, py = (int64_t)y * 1024, pz = (int64_t)z * 1024;
+    const int x = min(max(static_cast<int>(v % px) - 1, 0), nx - 1);
+    const int y = min(max(static_cast<int>((v / px) % py) - 1, 0), ny - 1);
+    const int z = min(max(static_cast<int>(v / (static_cast<size_t>(px) * py)) - 1, 0), nz - 1);
+    const int64_t qx = (int64_t)x * 1024, qy = (int64_t)y * 1024, qz = (int64_t)z * 1024;
     unsigned bits = 0;
     for (int s = 0; s < n_sets; s++) {
       int64_t best = INT64_MAX;
       for (int j = set_off[s]; j < set_off[s + 1]; j++) {
-        const int64_t dx = px - pts_fix[3 * j], dy = py - pts_fix[3 * j + 1], dz = pz - pts_fix[3 * j + 2];
+        const int64_t dx = qx - pts_fix[3 * j], dy = qy - pts_fix[3 * j + 1], dz = qz - pts_fix[3 * j + 2];
         const int64_t d2 = dx * dx + dy * dy + dz * dz;
         best = d2 < best ? d2 : best;
       }
       const float d = static_cast<float>(sqrt(static_cast<double>(best)) / 1024.0);
-      dmap[static_cast<size_t>(s) * V + v] = d;
+      dmap[static_cast<size_t>(s) * PV + v] = d;
       if (d < radius) bits |= 1u << s;
     }
     band[v] = static_cast<uint8_t>(bits);
@@ -893,8 +1060,8 @@ namespace morea {
 hipError_t launch_distance_maps(int nx, int ny, int nz, int n_sets, const int* set_off,
                                 const int* pts_fix, float radius, float* dmap, uint8_t* band,
                                 hipStream_t s) {
-  const size_t V = static_cast<size_t>(nx) * ny * nz;
-  const int blocks = static_cast<int>(std::min<size_t>((V + 255) / 256, 65536));
+  const size_t PV = static_cast<size_t>(nx + 2) * (ny + 2) * (nz + 2);
+  const int blocks = static_cast<int>(std::min<size_t>((PV + 255) / 256, 65536));
   hipLaunchKernelGGL(k_distance_maps, dim3(blocks), dim3(256), 0, s, nx, ny, nz, n_sets, set_off,
                      pts_fix, radius, dmap, band);
   return hipGetLastError();

@@ -16,7 +16,6 @@ constexpr float kCoordLimit = 512.0f;         // |x| < 512 voxels keeps every ex
 constexpr int kFastExtent = 1 << 16;          // tets up to 64 voxels: exact plane tests in FP64
 constexpr int kMaxSets = 8;
 constexpr int kWave = 64;
-constexpr int kImagePad = 16;                // zero elements around each stored image
 
 // Per-(candidate, tet, direction) partial objective record.  Direction 0
 // rasterizes the source tet on I_s and samples I_t; direction 1 rasterizes
@@ -45,13 +44,22 @@ static_assert(sizeof(Totals) == 64, "totals layout");
 enum Store { kF32 = 0, kBF16 = 1, kF16 = 2 };
 
 // Device view of a problem, passed by value to kernels.
+//
+// Every stored volume (images, distance maps, band masks) carries a border of
+// one voxel on each side: padded dimensions (nx + 2, ny + 2, nz + 2), voxel
+// (x, y, z) of the grid at element (z + 1) * pxy + (y + 1) * px + (x + 1).
+// Image borders hold 0 (the zero padding of the intensity term), distance map
+// borders repeat the edge value (edge clamping), so trilinear corners in
+// [-1, n] per axis need no clamping.
 struct ProblemView {
   int nx, ny, nz;
+  int px, pxy;                   // padded row and slice strides: nx + 2, (nx + 2)(ny + 2)
+  unsigned pvox;                 // padded voxels per volume
   int n_points, n_tets, n_sets;
   float radius, inv_radius;
-  const void* img[2];            // [0] = I_s, [1] = I_t, storage type
-  const float* dmap[2];          // [n_sets][V] distance maps on each image grid
-  const uint8_t* band[2];        // [V] bit s set where dmap[s] < radius
+  const void* img[2];            // [0] = I_s, [1] = I_t, storage type, padded
+  const float* dmap[2];          // [n_sets][pvox] distance maps on each image grid, padded
+  const uint8_t* band[2];        // [pvox] bit s set where dmap[s] < radius
   float set_w[2][kMaxSets];      // |C_i| / |G| per direction
   const int4* tets;
   const int8_t* ref_sign;

@@ -223,7 +223,7 @@ __global__ void k_tet_stats(ProblemView P, const float* ref, float* stats, int* 
         in = n[i][0] > 0 || (n[i][0] == 0 && (n[i][1] > 0 || (n[i][1] == 0 && n[i][2] > 0)));
     }
     if (!in) continue;
-    const int vi = (z * P.ny + y) * P.nx + x;
+    const int vi = (z + 1) * P.pxy + (y + 1) * P.px + x + 1;   // padded volumes
     float is, it;
     if constexpr (ST == kF32) {
       is = static_cast<const float*>(P.img[0])[vi];
