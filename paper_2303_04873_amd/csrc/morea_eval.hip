@@ -150,16 +150,17 @@ __device__ __forceinline__ double det_f64(const int v[4][3]) {
   return a0 * (b1 * c2 - b2 * c1) - a1 * (b0 * c2 - b2 * c0) + a2 * (b0 * c1 - b1 * c0);
 }
 
-constexpr int kDeferCap = 128;
+constexpr int kDeferCap = 192;
 
 // LDS scratch of one wave.
 struct WaveLds {
   DirConst c[2];
-  int4 row[kWave];         // padded element of the first sample, its offset in the sample
-                           // stream, jx | jy << 10 | jz << 20 (box-relative), unused
+  int4 row[kWave];         // padded element of the first sample, the row's first unit in
+                           // the unit stream, jx | jy << 10 | jz << 20 (box-relative), length
   double rowq[kWave][4];   // mapped point of each row's first sample (x, y, z, unused)
-  int mark[kWave];
-  int4 defer[kDeferCap];   // near-grid samples: (jx | jy << 10 | jz << 20 | dir << 30, a, b, axes)
+  int4 slice[kWave];       // non-empty slices of a group: z, first row y, first row index, rows
+  int mark[kWave];         // row starts inside the current batch, tagged with the batch
+  int4 defer[kDeferCap];   // near-grid samples: (jx | jy << 10 | jz << 20 | dir << 30, a, b, 0)
   int vert[24];            // snapped S (12), then T (12)
 };
 
@@ -266,6 +267,39 @@ __device__ __forceinline__ void row_span(const DirConst& c, int yr, int zr, int 
       clip_face<long long>(c.kind[i], c.Ai[i], c.invA[i], b, W, js, je);
     }
   }
+}
+
+// Rows of one slice that can hold samples: the y-range of the cross-section
+// of the tet (vertices `v`, fixed point) with the plane z = Z, from the
+// intersections of its 6 edges with the plane, widened by 1/16 voxel (the
+// FP32 error is below one fixed-point unit) and clipped to [ylo, yhi].
+// Every sample of the slice lies in this range; the row spans decide
+// exactly.  Returns the first row relative to ylo and the row count.
+__device__ __forceinline__ void slice_rows(const int* v, int Z, int ylo, int yhi, int& y0, int& cnt) {
+  const int zf = Z * 1024;
+  float mn = 3.0e38f, mx = -3.0e38f;
+#pragma unroll
+  for (int e = 0; e < 6; e++) {
+    const int i = e < 3 ? 0 : (e < 5 ? 1 : 2);
+    const int j = e < 3 ? e + 1 : (e < 5 ? e - 1 : 3);
+    const int zi = v[3 * i + 2] - zf, zj = v[3 * j + 2] - zf;
+    const float yi = static_cast<float>(v[3 * i + 1]), yj = static_cast<float>(v[3 * j + 1]);
+    if ((zi <= 0 && zj >= 0) || (zi >= 0 && zj <= 0)) {
+      if (zi == zj) {
+        mn = fminf(mn, fminf(yi, yj));
+        mx = fmaxf(mx, fmaxf(yi, yj));
+      } else {
+        const float t = static_cast<float>(-zi) / static_cast<float>(zj - zi);
+        const float y = fmaf(t, yj - yi, yi);
+        mn = fminf(mn, y);
+        mx = fmaxf(mx, y);
+      }
+    }
+  }
+  const int a = max(ylo, static_cast<int>(ceilf((mn - 64.f) * (1.f / 1024.f))));
+  const int b = min(yhi, static_cast<int>(floorf((mx + 64.f) * (1.f / 1024.f))));
+  y0 = a - ylo;
+  cnt = max(0, b - a + 1);
 }
 
 // Buffer resources over padded volumes: element i is byte offset i * size.
@@ -737,16 +771,19 @@ __device__ void eval_tet(const ProblemView& P, int tet, float coord, WaveLds* L,
   wave_sync();
 
   // ---- rows and samples, one direction at a time (wave-uniform d).  Rows
-  // are solved 64 at a time; non-empty rows enter a table of up to 64 rows
-  // whose samples form one stream, consumed in full batches of 64 (the
-  // stream carries over from one chunk of rows to the next, so only the
-  // direction's last batch runs part-empty).
+  // are solved 64 at a time; non-empty rows enter a table of up to 64 rows.
+  // Each row is cut into units of two consecutive samples (the last unit of
+  // an odd row holds one); the units of the table form one stream, consumed
+  // in batches of 64 units, one per lane.  The stream carries over from one
+  // chunk of rows to the next, so only the direction's last batch runs
+  // part-empty.
+  L->mark[lane] = 0;
+  int tag = 0;          // batch tags: unique within the item
   for (int d = 0; d < 2; d++) {
     const DirConst& Cd = L->c[d];
     if (!uniform_i(Cd.active)) continue;
-    const int Rd = uniform_i(Cd.R), nyb = uniform_i(Cd.NYb), Wd = uniform_i(Cd.W);
+    const int nyb = uniform_i(Cd.NYb), Wd = uniform_i(Cd.W);
     const int lox = uniform_i(Cd.lo[0]), loy = uniform_i(Cd.lo[1]), loz = uniform_i(Cd.lo[2]);
-    const float inv_nyb = 1.0f / static_cast<float>(nyb);
     const bool inner = uniform_i(Cd.inner) != 0;
     SampleConst U;
     U.m0 = uniform_d(Cd.M[0][0]);
@@ -762,46 +799,56 @@ __device__ void eval_tet(const ProblemView& P, int tet, float coord, WaveLds* L,
     float h = 0.f, g = 0.f;
     int n = 0, n_defer = 0;
     int n_tab = 0;      // rows in the table
-    int tab_total = 0;  // samples of the table rows not yet consumed
+    int tab_total = 0;  // units of the table rows not yet consumed
 
-    // consume samples [0, limit) of the table's stream in batches of 64
+    // one sample of the current batch; a near-grid one joins the deferred queue
+    auto sample = [&](bool valid, int vi, const double qr[3], int k, int jbase) {
+      bool amb = false;
+      float a = 0.f, b = 0.f;
+      if (valid) {
+        if (inner)
+          amb = sample_one<ST, true>(P, U, r_own, r_oth, r_band, d, vi + k, qr, k, h, g, a, b);
+        else
+          amb = sample_one<ST, false>(P, U, r_own, r_oth, r_band, d, vi + k, qr, k, h, g, a, b);
+        n += 1;
+      }
+      const uint64_t amb_mask = __ballot(amb);
+      if (amb_mask) {
+        if (amb) {
+          const int slot = n_defer + bits_below(amb_mask);
+          L->defer[slot] = make_int4((jbase + k) | (d << 30), __float_as_int(a), __float_as_int(b), 0);
+        }
+        n_defer += __popcll(amb_mask);
+      }
+    };
+
+    // consume units [0, limit) of the table's stream in batches of 64
     auto run_batches = [&](int limit) {
       const int my_off = lane < n_tab ? L->row[lane].y : 0x7fffffff;
       for (int sb = 0; sb < limit; sb += kWave) {
-        // row of each lane's sample: rows starting at or before sb, plus
-        // rows starting inside (sb, sb + lane]
+        // row of each lane's unit: rows starting at or before sb, plus rows
+        // starting inside (sb, sb + lane] (marked with this batch's tag)
+        tag += 1;
         const int first = __popcll(__ballot(my_off <= sb)) - 1;
-        L->mark[lane] = 0;
-        wave_sync();
         const int rel = my_off - sb;
-        if (rel > 0 && rel < kWave) L->mark[rel] = 1;
+        if (rel > 0 && rel < kWave) L->mark[rel] = tag;
         wave_sync();
-        const uint64_t starts = __ballot(L->mark[lane] != 0);
+        const uint64_t starts = __ballot(L->mark[lane] == tag);
         const int ri = first + bits_below(starts) + static_cast<int>((starts >> lane) & 1ull);
-        const int s = sb + lane;
-        bool amb = false;
-        int jpack = 0;
-        float a = 0.f, b = 0.f;
-        if (s < limit) {
-          const int4 rw = L->row[ri];
-          const int k = s - rw.y;
-          const double qr[3] = {L->rowq[ri][0], L->rowq[ri][1], L->rowq[ri][2]};
-          if (inner)
-            amb = sample_one<ST, true>(P, U, r_own, r_oth, r_band, d, rw.x + k, qr, k, h, g, a, b);
-          else
-            amb = sample_one<ST, false>(P, U, r_own, r_oth, r_band, d, rw.x + k, qr, k, h, g, a, b);
-          n += 1;
-          jpack = (rw.z + k) | (d << 30);
+        const int u = sb + lane;
+        const bool ok = u < limit;
+        int4 rw = make_int4(0, 0, 0, 0);
+        double qr[3] = {0.0, 0.0, 0.0};
+        if (ok) {
+          rw = L->row[ri];
+          qr[0] = L->rowq[ri][0];
+          qr[1] = L->rowq[ri][1];
+          qr[2] = L->rowq[ri][2];
         }
-        const uint64_t amb_mask = __ballot(amb);
-        if (amb_mask) {
-          if (amb) {
-            const int slot = n_defer + bits_below(amb_mask);
-            L->defer[slot] = make_int4(jpack, __float_as_int(a), __float_as_int(b), 0);
-          }
-          n_defer += __popcll(amb_mask);
-        }
-        if (n_defer > kDeferCap - kWave) {
+        const int k = 2 * (u - rw.y);
+        sample(ok, rw.x, qr, k, rw.z);
+        sample(ok && k + 1 < rw.w, rw.x, qr, k + 1, rw.z);
+        if (n_defer > kDeferCap - 2 * kWave) {
           wave_sync();
           flush_deferred<ST>(P, L, n_defer, h);
           n_defer = 0;
@@ -811,14 +858,35 @@ __device__ void eval_tet(const ProblemView& P, int tet, float coord, WaveLds* L,
       return my_off;
     };
 
-    for (int rb = 0; rb < Rd; rb += kWave) {
+    // rows: slices in groups of 64 (one per lane), the rows of the non-empty
+    // slices of a group enumerated 64 at a time
+    const int nzb = uniform_i(Cd.hi[2]) - loz + 1;
+    const int* own_v = L->vert + 12 * d;
+    for (int zb = 0; zb < nzb; zb += kWave) {
+      int y0 = 0, cnt = 0;
+      if (zb + lane < nzb) slice_rows(own_v, loz + zb + lane, loy, loy + nyb - 1, y0, cnt);
+      const uint64_t ne = __ballot(cnt > 0);
+      const int ns = __popcll(ne);
+      const int sexcl = wave_excl_scan(cnt);
+      const int Rg = __shfl(sexcl + cnt, 63, 64);
+      if (cnt > 0) L->slice[bits_below(ne)] = make_int4(zb + lane, y0, sexcl, cnt);
+      wave_sync();
+      const int my_soff = lane < ns ? L->slice[lane].z : 0x7fffffff;
+    for (int rb = 0; rb < Rg; rb += kWave) {
       const int rr = rb + lane;
+      // slice of each lane's row: the mark trick over the slices' first rows
+      tag += 1;
+      const int sfirst = __popcll(__ballot(my_soff <= rb)) - 1;
+      const int srel = my_soff - rb;
+      if (srel > 0 && srel < kWave) L->mark[srel] = tag;
+      wave_sync();
+      const uint64_t sst = __ballot(L->mark[lane] == tag);
+      const int si = sfirst + bits_below(sst) + static_cast<int>((sst >> lane) & 1ull);
       int js = 1, je = 0, yr = 0, zr = 0;
-      if (rr < Rd) {
-        zr = static_cast<int>(static_cast<float>(rr) * inv_nyb);
-        if (zr * nyb > rr) zr -= 1;
-        else if ((zr + 1) * nyb <= rr) zr += 1;
-        yr = rr - zr * nyb;
+      if (rr < Rg) {
+        const int4 sl = L->slice[si];
+        zr = sl.x;
+        yr = sl.y + (rr - sl.z);
         row_span(Cd, yr, zr, Wd, js, je);
       }
       const int len = max(0, je - js + 1);
@@ -832,14 +900,14 @@ __device__ void eval_tet(const ProblemView& P, int tet, float coord, WaveLds* L,
         const int ci = bits_below(want);
         const bool take = ((want >> lane) & 1ull) && ci < space;
         const uint64_t took = __ballot(take);
-        const int tl = take ? len : 0;
+        const int tl = take ? (len + 1) >> 1 : 0;     // units of the row
         const int excl = wave_excl_scan(tl);
         const int added = __shfl(excl + tl, 63, 64);
         if (take) {
           const int slot = n_tab + ci;
           const int jx = jp & 1023, jy = (jp >> 10) & 1023, jz = jp >> 20;
           const int vi_row = __umul24(loz + jz + 1, P.pxy) + __umul24(loy + jy + 1, P.px) + lox + jx + 1;
-          L->row[slot] = make_int4(vi_row, tab_total + excl, jp, 0);
+          L->row[slot] = make_int4(vi_row, tab_total + excl, jp, len);
 #pragma unroll
           for (int t = 0; t < 3; t++)
             L->rowq[slot][t] = fma(Cd.M[t][0], static_cast<double>(jx),
@@ -853,7 +921,7 @@ __device__ void eval_tet(const ProblemView& P, int tet, float coord, WaveLds* L,
         if (tab_total >= kWave) {
           const int consumed = tab_total & ~(kWave - 1);
           const int my_off = run_batches(consumed);
-          // drop the rows that end within the consumed samples (a prefix),
+          // drop the rows that end within the consumed units (a prefix),
           // move the rest to the front and rebase their offsets
           const int nxt = __shfl_down(my_off, 1, 64);
           const int end = lane == n_tab - 1 ? tab_total : nxt;
@@ -880,6 +948,8 @@ __device__ void eval_tet(const ProblemView& P, int tet, float coord, WaveLds* L,
           tab_total -= consumed;
         }
       }
+    }
+      wave_sync();   // the slice table is rewritten by the next group
     }
     if (tab_total > 0) run_batches(tab_total);
     if (n_defer > 0) {
@@ -1161,7 +1231,7 @@ __device__ __forceinline__ int find_eval(const int* item_off, int n_evals, int i
 // device work queue until the list is exhausted.  Every wave leaves the loop
 // once the queue passes the end of the list.
 template <int ST>
-__global__ __launch_bounds__(256) void k_eval_partial(ProblemView P, PartialItems I, Record* out,
+__global__ __launch_bounds__(256, 3) void k_eval_partial(ProblemView P, PartialItems I, Record* out,
                                                        int* queue, int chunk) {
   __shared__ WaveLds lds[4];
   const int wave = threadIdx.x >> 6;
