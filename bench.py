@@ -25,6 +25,41 @@ SAMPLE_OPS = 60           # algorithmic VALU lane-ops per voxel sample (map, tri
 SAMPLE_BYTES = 9          # algorithmic bytes per sample at FP32 storage (own voxel, footprint, band)
 VALU_PEAK = 256 * 64 * 2.4e9   # lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz (packed FP32 disabled)
 HBM_PEAK = 8.0e12
+# HBM traffic of the evaluation kernel, from two rocprofv3 --pmc runs
+# (FETCH_SIZE, WRITE_SIZE) summarised in this file together with the hash of
+# the kernel sources they were taken on; a different hash means the kernel has
+# changed since, and the traffic is reported as null
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_eval_full_128x128x96_pop512_counters.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2303_04873_amd", "csrc", f)
+                  for f in ("morea_eval.hip", "morea_internal.h")]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def profiled_traffic():
+    """HBM bytes per launch of k_eval_full from the committed counter
+    summary, or None when it is missing or was taken on other sources."""
+    try:
+        fields = {}
+        with open(TRAFFIC_PROFILE) as fh:
+            for line in fh:
+                if ":" in line and line.startswith("- `"):
+                    k, v = line[3:].split("`", 1)
+                    fields[k] = v.split(":", 1)[1].strip().split()[0]
+        if fields.get("kernel_source_sha256") != kernel_source_hash():
+            return None
+        kib = (float(fields["fetch_kib_per_launch"]) * float(fields["fetch_scale"]) +
+               float(fields["write_kib_per_launch"]) * float(fields["write_scale"]))
+        return kib * 1024.0
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def parse():
@@ -301,7 +336,7 @@ def main():
         "samples_per_s": samples_per_s,
         "samples_per_step": samples,
         "roofline": {"bound": "alu", "achieved": achieved_ops / 1e12, "peak": VALU_PEAK / 1e12,
-                     "unit": "T lane-ops/s", "frac": achieved_ops / VALU_PEAK, "traffic": None,
+                     "unit": "T lane-ops/s", "frac": achieved_ops / VALU_PEAK, "traffic": profiled_traffic(),
                      "kernel": "k_eval_full (event-timed launch incl. k_finalize)",
                      "launch_ms": launch_ms,
                      "hbm_algorithmic_frac": samples * SAMPLE_BYTES / (launch_ms * 1e-3) / HBM_PEAK},

@@ -170,9 +170,9 @@ morea_status morea_problem_create(const morea_problem_desc* d, morea_problem** o
   P.nx = nx;
   P.ny = ny;
   P.nz = nz;
-  P.px = nx + 2;
-  P.pxy = (nx + 2) * (ny + 2);
-  const size_t PV = static_cast<size_t>(nx + 2) * (ny + 2) * (nz + 2);
+  P.px = padded_row(nx);
+  P.pxy = P.px * (ny + 2);
+  const size_t PV = static_cast<size_t>(P.pxy) * (nz + 2);
   P.pvox = static_cast<unsigned>(PV);
   P.n_points = d->n_points;
   P.n_tets = d->n_tets;
@@ -194,7 +194,7 @@ morea_status morea_problem_create(const morea_problem_desc* d, morea_problem** o
     std::vector<float> pad(PV, 0.f);
     for (int z = 0; z < nz; z++)
       for (int y = 0; y < ny; y++)
-        memcpy(pad.data() + ((static_cast<size_t>(z) + 1) * (ny + 2) + (y + 1)) * (nx + 2) + 1,
+        memcpy(pad.data() + ((static_cast<size_t>(z) + 1) * (ny + 2) + (y + 1)) * P.px + 1,
                img + (static_cast<size_t>(z) * ny + y) * nx, nx * sizeof(float));
     if (d->storage == kF32) {
       guard(upload(p, &dst, pad.data(), PV * sizeof(float)));

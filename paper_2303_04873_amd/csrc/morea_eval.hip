@@ -52,14 +52,17 @@ __device__ __forceinline__ void wave_sync() {
 
 __device__ __forceinline__ int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Exclusive prefix sum over the 64 lanes: inclusive scan within each row of
+// 16 lanes by DPP row shifts (1, 2, 4, 8), then the row broadcasts of lanes
+// 15 and 31 carry it across rows.  Lanes a DPP source does not reach add 0.
 __device__ __forceinline__ int wave_excl_scan(int v) {
-  const int lane = lane_id();
   int x = v;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    int y = __shfl_up(x, d, 64);
-    if (lane >= d) x += y;
-  }
+  x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);   // row_shr:1
+  x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);   // row_shr:2
+  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);   // row_shr:4
+  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);   // row_shr:8
+  x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);   // row_bcast:15 -> rows 1, 3
+  x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);   // row_bcast:31 -> rows 2, 3
   return x - v;
 }
 
@@ -240,32 +243,51 @@ __device__ __forceinline__ void clip_face(int kind, T A, double invA, T b, int W
 }
 
 // x-interval [js, je] (relative to the box start, within [0, W]) of row
-// (yr, zr) of one direction.  Extents <= 2^16: the FP64 boundary estimate
-// decides away from integers, the exact test near them.  Wider tets: int64.
-__device__ __forceinline__ void row_span(const DirConst& c, int yr, int zr, int W, int& js, int& je) {
+// (yr, zr) of one direction, for tets with extent <= 2^16 (exact FP64 plane
+// values).  Face i with kind != 0 crosses zero at the box-relative x position
+// t_i = TA yr + TB zr + TG.  The first voxel inside a face with kind > 0 is
+// floor(t) + 1 and the last inside a face with kind < 0 is ceil(t) - 1 (a
+// centre on the plane is outside once the tie-break bit is folded in), unless
+// t is within its FP64 error bound TE of an integer r: then the exact plane
+// value at r decides between r and its neighbour.  Branch-free per face;
+// `kind` is wave-uniform.
+__device__ __forceinline__ void row_span_fast(const DirConst& c, const int kind[4], int yr, int zr, int W,
+                                              int& js, int& je) {
   js = 0;
   je = W;
-  if (c.fast) {
-    const double y = yr, z = zr;
+  const double y = yr, z = zr;
 #pragma unroll
-    for (int i = 0; i < 4; i++) {
-      const int kind = c.kind[i];
-      const double t = fma(c.TA[i], y, fma(c.TB[i], z, c.TG[i]));
-      if (kind != 0 && fabs(t - rint(t)) <= c.TE[i] && t > -3.0 && t < W + 3.0) {
-        const double b = fma(c.PY[i], y, fma(c.PZ[i], z, c.B0[i]));
-        clip_face<double>(kind, c.A[i], c.invA[i], b, W, js, je);
-      } else {
-        const int fl = static_cast<int>(floor(fmin(fmax(t, -2.0), W + 1.0)));
-        js = kind > 0 ? max(js, fl + 1) : js;
-        je = kind < 0 ? min(je, fl) : ((kind == 0 && !(t > 0.0)) ? -1 : je);
-      }
+  for (int i = 0; i < 4; i++) {
+    const double t = fma(c.TA[i], y, fma(c.TB[i], z, c.TG[i]));
+    if (kind[i] == 0) {
+      // face parallel to x: t holds the plane value itself
+      if (!(t > 0.0)) je = -1;
+      continue;
     }
-  } else {
+    const double tc = fmin(fmax(t, -2.0), W + 1.0);
+    const double r = rint(tc);
+    const bool near = fabs(tc - r) <= c.TE[i];
+    // exact plane value (+ tie-break bit) at x = r: |terms| < 2^50
+    const double e = fma(c.A[i], r, fma(c.PY[i], y, fma(c.PZ[i], z, c.B0[i])));
+    const int ri = static_cast<int>(r);
+    if (kind[i] > 0) {
+      const int j = near ? (e > 0.0 ? ri : ri + 1) : static_cast<int>(floor(tc)) + 1;
+      js = max(js, j);
+    } else {
+      const int j = near ? (e > 0.0 ? ri : ri - 1) : static_cast<int>(ceil(tc)) - 1;
+      je = min(je, j);
+    }
+  }
+}
+
+// The same for wider tets, in int64 (extent < 2^20 keeps |s_i| < 2^63).
+__device__ __forceinline__ void row_span_wide(const DirConst& c, int yr, int zr, int W, int& js, int& je) {
+  js = 0;
+  je = W;
 #pragma unroll
-    for (int i = 0; i < 4; i++) {
-      const long long b = c.PYi[i] * yr + c.PZi[i] * zr + c.B0i[i];
-      clip_face<long long>(c.kind[i], c.Ai[i], c.invA[i], b, W, js, je);
-    }
+  for (int i = 0; i < 4; i++) {
+    const long long b = c.PYi[i] * yr + c.PZi[i] * zr + c.B0i[i];
+    clip_face<long long>(c.kind[i], c.Ai[i], c.invA[i], b, W, js, je);
   }
 }
 
@@ -336,6 +358,33 @@ __device__ __forceinline__ F2 ld_pair(__amdgpu_buffer_rsrc_t r, int idx, int sof
   const f2v v = __builtin_bit_cast(
       f2v, __builtin_amdgcn_raw_buffer_load_b64(r, static_cast<unsigned>(idx) * 4u, soff, 0));
   return F2{v.x, v.y};
+}
+
+// Two consecutive 2-byte voxels (idx, idx + 1) as one 32-bit word (idx in
+// the low half): one 8-byte load of the 4-element window that starts at the
+// even element idx & ~1 (4-byte aligned, as every row and slice offset `soff`
+// of a 2-byte volume), then a 16-bit funnel shift when idx is odd.
+__device__ __forceinline__ uint32_t ld_pair16(__amdgpu_buffer_rsrc_t r, int idx, int soff, uint32_t shift) {
+  typedef unsigned u2v __attribute__((ext_vector_type(2)));
+  const u2v w = __builtin_bit_cast(
+      u2v, __builtin_amdgcn_raw_buffer_load_b64(r, static_cast<unsigned>(idx & ~1) * 2u, soff, 0));
+  return __builtin_amdgcn_alignbit(w.y, w.x, shift);
+}
+
+template <int ST>
+__device__ __forceinline__ float lo16(uint32_t w) {
+  if constexpr (ST == kBF16)
+    return __uint_as_float(w << 16);
+  else
+    return static_cast<float>(__builtin_bit_cast(_Float16, static_cast<unsigned short>(w)));
+}
+
+template <int ST>
+__device__ __forceinline__ float hi16(uint32_t w) {
+  if constexpr (ST == kBF16)
+    return __uint_as_float(w & 0xffff0000u);
+  else
+    return static_cast<float>(__builtin_bit_cast(_Float16, static_cast<unsigned short>(w >> 16)));
 }
 
 template <int ST>
@@ -409,7 +458,7 @@ __device__ __forceinline__ bool sample_one(const ProblemView& P, const SampleCon
   // slice offsets rz0/rz1
   int ix0, ix1, ry0, ry1, rz0, rz1;
   float v000, v001, v010, v011, v100, v101, v110, v111;
-  constexpr int esize = ST == kF32 ? 4 : 2;
+  bool fg8;   // any of the 8 corners > 0 (the images are >= 0: any non-zero magnitude bit)
   if constexpr (INNER) {
     ix0 = c[0];
     ix1 = c[0] + 1;
@@ -423,13 +472,18 @@ __device__ __forceinline__ bool sample_one(const ProblemView& P, const SampleCon
       const F2 p10 = ld_pair(r_oth, base, U.sz), p11 = ld_pair(r_oth, base, U.sy + U.sz);
       v000 = p00.a; v001 = p00.b; v010 = p01.a; v011 = p01.b;
       v100 = p10.a; v101 = p10.b; v110 = p11.a; v111 = p11.b;
+      const uint32_t ob = __float_as_uint(v000) | __float_as_uint(v001) | __float_as_uint(v010) |
+                          __float_as_uint(v011) | __float_as_uint(v100) | __float_as_uint(v101) |
+                          __float_as_uint(v110) | __float_as_uint(v111);
+      fg8 = (ob << 1) != 0u;
     } else {
-      v000 = ld_soff<ST>(r_oth, base, 0); v001 = ld_soff<ST>(r_oth, base + 1, 0);
-      v010 = ld_soff<ST>(r_oth, base, U.sy); v011 = ld_soff<ST>(r_oth, base + 1, U.sy);
-      v100 = ld_soff<ST>(r_oth, base, U.sz); v101 = ld_soff<ST>(r_oth, base + 1, U.sz);
-      v110 = ld_soff<ST>(r_oth, base, U.sy + U.sz); v111 = ld_soff<ST>(r_oth, base + 1, U.sy + U.sz);
+      const uint32_t sh = static_cast<uint32_t>(base & 1) << 4;
+      const uint32_t w00 = ld_pair16(r_oth, base, 0, sh), w01 = ld_pair16(r_oth, base, U.sy, sh);
+      const uint32_t w10 = ld_pair16(r_oth, base, U.sz, sh), w11 = ld_pair16(r_oth, base, U.sy + U.sz, sh);
+      v000 = lo16<ST>(w00); v001 = hi16<ST>(w00); v010 = lo16<ST>(w01); v011 = hi16<ST>(w01);
+      v100 = lo16<ST>(w10); v101 = hi16<ST>(w10); v110 = lo16<ST>(w11); v111 = hi16<ST>(w11);
+      fg8 = ((w00 | w01 | w10 | w11) & 0x7fff7fffu) != 0u;
     }
-    (void)esize;
   } else {
     // padded index range per axis is [0, n + 1]; corners beyond it are
     // outside the image (value 0) and clamp for the distance maps
@@ -457,16 +511,15 @@ __device__ __forceinline__ bool sample_one(const ProblemView& P, const SampleCon
     v101 = (vz1 && vy0 && vx1) ? v101 : 0.f;
     v110 = (vz1 && vy1 && vx0) ? v110 : 0.f;
     v111 = (vz1 && vy1 && vx1) ? v111 : 0.f;
+    const uint32_t ob = __float_as_uint(v000) | __float_as_uint(v001) | __float_as_uint(v010) |
+                        __float_as_uint(v011) | __float_as_uint(v100) | __float_as_uint(v101) |
+                        __float_as_uint(v110) | __float_as_uint(v111);
+    fg8 = (ob << 1) != 0u;
   }
   const float e00 = fmaf(f[0], v001 - v000, v000), e01 = fmaf(f[0], v011 - v010, v010);
   const float e10 = fmaf(f[0], v101 - v100, v100), e11 = fmaf(f[0], v111 - v110, v110);
   const float e0 = fmaf(f[1], e01 - e00, e00), e1 = fmaf(f[1], e11 - e10, e10);
   const float b = fmaf(f[2], e1 - e0, e0);
-  // any corner > 0: the images are >= 0, so any non-zero magnitude bit
-  const uint32_t ob = __float_as_uint(v000) | __float_as_uint(v001) | __float_as_uint(v010) |
-                      __float_as_uint(v011) | __float_as_uint(v100) | __float_as_uint(v101) |
-                      __float_as_uint(v110) | __float_as_uint(v111);
-  const bool fg8 = (ob << 1) != 0u;
 
   if (P.n_sets > 0) {
     unsigned bandbits = __builtin_amdgcn_raw_buffer_load_b8(r_band, static_cast<unsigned>(vi), 0, 0);
@@ -785,6 +838,9 @@ __device__ void eval_tet(const ProblemView& P, int tet, float coord, WaveLds* L,
     const int nyb = uniform_i(Cd.NYb), Wd = uniform_i(Cd.W);
     const int lox = uniform_i(Cd.lo[0]), loy = uniform_i(Cd.lo[1]), loz = uniform_i(Cd.lo[2]);
     const bool inner = uniform_i(Cd.inner) != 0;
+    const bool fast = uniform_i(Cd.fast) != 0;
+    const int kinds[4] = {uniform_i(Cd.kind[0]), uniform_i(Cd.kind[1]), uniform_i(Cd.kind[2]),
+                          uniform_i(Cd.kind[3])};
     SampleConst U;
     U.m0 = uniform_d(Cd.M[0][0]);
     U.m1 = uniform_d(Cd.M[1][0]);
@@ -798,8 +854,10 @@ __device__ void eval_tet(const ProblemView& P, int tet, float coord, WaveLds* L,
     const __amdgpu_buffer_rsrc_t r_band = byte_rsrc(P.band[d], P.pvox);
     float h = 0.f, g = 0.f;
     int n = 0, n_defer = 0;
-    int n_tab = 0;      // rows in the table
-    int tab_total = 0;  // units of the table rows not yet consumed
+    // row table: a ring of 64 slots; the row of rank r (in stream order)
+    // sits in slot (head + r) & 63.  Units are numbered from the start of
+    // the direction; `cons` units are consumed, `tab_end` appended.
+    int head = 0, n_tab = 0, cons = 0, tab_end = 0;
 
     // one sample of the current batch; a near-grid one joins the deferred queue
     auto sample = [&](bool valid, int vi, const double qr[3], int k, int jbase) {
@@ -822,11 +880,13 @@ __device__ void eval_tet(const ProblemView& P, int tet, float coord, WaveLds* L,
       }
     };
 
-    // consume units [0, limit) of the table's stream in batches of 64
+    // consume units [cons, limit) in batches of 64 (one unit per lane), then
+    // drop the rows that end by `limit` (a prefix of the ring)
     auto run_batches = [&](int limit) {
-      const int my_off = lane < n_tab ? L->row[lane].y : 0x7fffffff;
-      for (int sb = 0; sb < limit; sb += kWave) {
-        // row of each lane's unit: rows starting at or before sb, plus rows
+      const bool valid = ((lane - head) & (kWave - 1)) < n_tab;
+      const int my_off = valid ? L->row[lane].y : 0x7fffffff;
+      for (int sb = cons; sb < limit; sb += kWave) {
+        // rank of each lane's row: rows starting at or before sb, plus rows
         // starting inside (sb, sb + lane] (marked with this batch's tag)
         tag += 1;
         const int first = __popcll(__ballot(my_off <= sb)) - 1;
@@ -834,17 +894,12 @@ __device__ void eval_tet(const ProblemView& P, int tet, float coord, WaveLds* L,
         if (rel > 0 && rel < kWave) L->mark[rel] = tag;
         wave_sync();
         const uint64_t starts = __ballot(L->mark[lane] == tag);
-        const int ri = first + bits_below(starts) + static_cast<int>((starts >> lane) & 1ull);
+        const int rank = first + bits_below(starts) + static_cast<int>((starts >> lane) & 1ull);
+        const int slot = (head + rank) & (kWave - 1);
         const int u = sb + lane;
         const bool ok = u < limit;
-        int4 rw = make_int4(0, 0, 0, 0);
-        double qr[3] = {0.0, 0.0, 0.0};
-        if (ok) {
-          rw = L->row[ri];
-          qr[0] = L->rowq[ri][0];
-          qr[1] = L->rowq[ri][1];
-          qr[2] = L->rowq[ri][2];
-        }
+        const int4 rw = L->row[slot];
+        const double qr[3] = {L->rowq[slot][0], L->rowq[slot][1], L->rowq[slot][2]};
         const int k = 2 * (u - rw.y);
         sample(ok, rw.x, qr, k, rw.z);
         sample(ok && k + 1 < rw.w, rw.x, qr, k + 1, rw.z);
@@ -855,7 +910,14 @@ __device__ void eval_tet(const ProblemView& P, int tet, float coord, WaveLds* L,
         }
         wave_sync();
       }
-      return my_off;
+      // a row ends where the next one (in ring order) starts; the last at tab_end
+      const int nxt = __shfl(my_off, (lane + 1) & (kWave - 1), 64);
+      const int last = (head + n_tab - 1) & (kWave - 1);
+      const int end = lane == last ? tab_end : nxt;
+      const int done = __popcll(__ballot(valid && end <= limit));
+      head = (head + done) & (kWave - 1);
+      n_tab -= done;
+      cons = limit;
     };
 
     // rows: slices in groups of 64 (one per lane), the rows of the non-empty
@@ -868,90 +930,65 @@ __device__ void eval_tet(const ProblemView& P, int tet, float coord, WaveLds* L,
       const uint64_t ne = __ballot(cnt > 0);
       const int ns = __popcll(ne);
       const int sexcl = wave_excl_scan(cnt);
-      const int Rg = __shfl(sexcl + cnt, 63, 64);
+      const int Rg = __builtin_amdgcn_readlane(sexcl + cnt, 63);
       if (cnt > 0) L->slice[bits_below(ne)] = make_int4(zb + lane, y0, sexcl, cnt);
       wave_sync();
       const int my_soff = lane < ns ? L->slice[lane].z : 0x7fffffff;
-    for (int rb = 0; rb < Rg; rb += kWave) {
-      const int rr = rb + lane;
-      // slice of each lane's row: the mark trick over the slices' first rows
-      tag += 1;
-      const int sfirst = __popcll(__ballot(my_soff <= rb)) - 1;
-      const int srel = my_soff - rb;
-      if (srel > 0 && srel < kWave) L->mark[srel] = tag;
-      wave_sync();
-      const uint64_t sst = __ballot(L->mark[lane] == tag);
-      const int si = sfirst + bits_below(sst) + static_cast<int>((sst >> lane) & 1ull);
-      int js = 1, je = 0, yr = 0, zr = 0;
-      if (rr < Rg) {
-        const int4 sl = L->slice[si];
-        zr = sl.x;
-        yr = sl.y + (rr - sl.z);
-        row_span(Cd, yr, zr, Wd, js, je);
-      }
-      const int len = max(0, je - js + 1);
-      // the row's box-relative position, packed (it stays live while the
-      // table is consumed)
-      const int jp = js | (yr << 10) | (zr << 20);
-      uint64_t want = __ballot(len > 0);
-      while (want) {
-        // append as many of this chunk's rows as the table holds
-        const int space = kWave - n_tab;
-        const int ci = bits_below(want);
-        const bool take = ((want >> lane) & 1ull) && ci < space;
-        const uint64_t took = __ballot(take);
-        const int tl = take ? (len + 1) >> 1 : 0;     // units of the row
-        const int excl = wave_excl_scan(tl);
-        const int added = __shfl(excl + tl, 63, 64);
-        if (take) {
-          const int slot = n_tab + ci;
-          const int jx = jp & 1023, jy = (jp >> 10) & 1023, jz = jp >> 20;
-          const int vi_row = __umul24(loz + jz + 1, P.pxy) + __umul24(loy + jy + 1, P.px) + lox + jx + 1;
-          L->row[slot] = make_int4(vi_row, tab_total + excl, jp, len);
-#pragma unroll
-          for (int t = 0; t < 3; t++)
-            L->rowq[slot][t] = fma(Cd.M[t][0], static_cast<double>(jx),
-                                   fma(Cd.M[t][1], static_cast<double>(jy),
-                                       fma(Cd.M[t][2], static_cast<double>(jz), Cd.qlo[t])));
-        }
-        n_tab += __popcll(took);
-        tab_total += added;
-        want &= ~took;
+      for (int rb = 0; rb < Rg; rb += kWave) {
+        const int rr = rb + lane;
+        // slice of each lane's row: the mark trick over the slices' first rows
+        tag += 1;
+        const int sfirst = __popcll(__ballot(my_soff <= rb)) - 1;
+        const int srel = my_soff - rb;
+        if (srel > 0 && srel < kWave) L->mark[srel] = tag;
         wave_sync();
-        if (tab_total >= kWave) {
-          const int consumed = tab_total & ~(kWave - 1);
-          const int my_off = run_batches(consumed);
-          // drop the rows that end within the consumed units (a prefix),
-          // move the rest to the front and rebase their offsets
-          const int nxt = __shfl_down(my_off, 1, 64);
-          const int end = lane == n_tab - 1 ? tab_total : nxt;
-          const int done = __popcll(__ballot(lane < n_tab && end <= consumed));
-          const bool mv = lane + done < n_tab;
-          int4 rw = make_int4(0, 0, 0, 0);
-          double q0 = 0.0, q1 = 0.0, q2 = 0.0;
-          if (mv) {
-            rw = L->row[lane + done];
-            q0 = L->rowq[lane + done][0];
-            q1 = L->rowq[lane + done][1];
-            q2 = L->rowq[lane + done][2];
+        const uint64_t sst = __ballot(L->mark[lane] == tag);
+        const int si = sfirst + bits_below(sst) + static_cast<int>((sst >> lane) & 1ull);
+        int js = 1, je = 0, yr = 0, zr = 0;
+        if (rr < Rg) {
+          const int4 sl = L->slice[si];
+          zr = sl.x;
+          yr = sl.y + (rr - sl.z);
+          if (fast)
+            row_span_fast(Cd, kinds, yr, zr, Wd, js, je);
+          else
+            row_span_wide(Cd, yr, zr, Wd, js, je);
+        }
+        const int len = max(0, je - js + 1);
+        // the row's box-relative position, packed (it stays live while the
+        // table is consumed)
+        const int jp = js | (yr << 10) | (zr << 20);
+        uint64_t want = __ballot(len > 0);
+        while (want) {
+          // append as many of this chunk's rows as the ring holds
+          const int space = kWave - n_tab;
+          const int ci = bits_below(want);
+          const bool take = ((want >> lane) & 1ull) && ci < space;
+          const uint64_t took = __ballot(take);
+          const int tl = take ? (len + 1) >> 1 : 0;     // units of the row
+          const int excl = wave_excl_scan(tl);
+          const int added = __builtin_amdgcn_readlane(excl + tl, 63);
+          if (take) {
+            const int slot = (head + n_tab + ci) & (kWave - 1);
+            const int jx = jp & 1023, jy = (jp >> 10) & 1023, jz = jp >> 20;
+            const int vi_row = __umul24(loz + jz + 1, P.pxy) + __umul24(loy + jy + 1, P.px) + lox + jx + 1;
+            L->row[slot] = make_int4(vi_row, tab_end + excl, jp, len);
+#pragma unroll
+            for (int t = 0; t < 3; t++)
+              L->rowq[slot][t] = fma(Cd.M[t][0], static_cast<double>(jx),
+                                     fma(Cd.M[t][1], static_cast<double>(jy),
+                                         fma(Cd.M[t][2], static_cast<double>(jz), Cd.qlo[t])));
           }
+          n_tab += __popcll(took);
+          tab_end += added;
+          want &= ~took;
           wave_sync();
-          if (mv) {
-            rw.y -= consumed;
-            L->row[lane] = rw;
-            L->rowq[lane][0] = q0;
-            L->rowq[lane][1] = q1;
-            L->rowq[lane][2] = q2;
-          }
-          wave_sync();
-          n_tab -= done;
-          tab_total -= consumed;
+          if (tab_end - cons >= kWave) run_batches(cons + ((tab_end - cons) & ~(kWave - 1)));
         }
       }
-    }
       wave_sync();   // the slice table is rewritten by the next group
     }
-    if (tab_total > 0) run_batches(tab_total);
+    if (tab_end > cons) run_batches(tab_end);
     if (n_defer > 0) {
       wave_sync();
       flush_deferred<ST>(P, L, n_defer, h);
@@ -1099,7 +1136,7 @@ __global__ __launch_bounds__(256) void k_finalize(ProblemView P, const float* pt
 // the value of the nearest grid voxel (edge clamping).
 __global__ void k_distance_maps(int nx, int ny, int nz, int n_sets, const int* set_off,
                                 const int* pts_fix, float radius, float* dmap, uint8_t* band) {
-  const int px = nx + 2, py = ny + 2;
+  const int px = padded_row(nx), py = ny + 2;
   const size_t PV = static_cast<size_t>(px) * py * (nz + 2);
   for (size_t v = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; v < PV;
        v += static_cast<size_t>(gridDim.x) * blockDim.x) {
@@ -1130,7 +1167,7 @@ namespace morea {
 hipError_t launch_distance_maps(int nx, int ny, int nz, int n_sets, const int* set_off,
                                 const int* pts_fix, float radius, float* dmap, uint8_t* band,
                                 hipStream_t s) {
-  const size_t PV = static_cast<size_t>(nx + 2) * (ny + 2) * (nz + 2);
+  const size_t PV = static_cast<size_t>(padded_row(nx)) * (ny + 2) * (nz + 2);
   const int blocks = static_cast<int>(std::min<size_t>((PV + 255) / 256, 65536));
   hipLaunchKernelGGL(k_distance_maps, dim3(blocks), dim3(256), 0, s, nx, ny, nz, n_sets, set_off,
                      pts_fix, radius, dmap, band);

@@ -46,14 +46,18 @@ enum Store { kF32 = 0, kBF16 = 1, kF16 = 2 };
 // Device view of a problem, passed by value to kernels.
 //
 // Every stored volume (images, distance maps, band masks) carries a border of
-// one voxel on each side: padded dimensions (nx + 2, ny + 2, nz + 2), voxel
-// (x, y, z) of the grid at element (z + 1) * pxy + (y + 1) * px + (x + 1).
-// Image borders hold 0 (the zero padding of the intensity term), distance map
-// borders repeat the edge value (edge clamping), so trilinear corners in
-// [-1, n] per axis need no clamping.
+// at least one voxel on each side: padded dimensions (px, ny + 2, nz + 2) with
+// the row length px = nx + 2 rounded up to even (so that every row and slice
+// of a 2-byte volume starts 4-byte aligned), voxel (x, y, z) of the grid at
+// element (z + 1) * pxy + (y + 1) * px + (x + 1).  Image borders hold 0 (the
+// zero padding of the intensity term), distance map borders repeat the
+// nearest grid value (edge clamping), so trilinear corners in [-1, n] per
+// axis need no clamping.
+__host__ __device__ inline int padded_row(int nx) { return (nx + 3) & ~1; }
+
 struct ProblemView {
   int nx, ny, nz;
-  int px, pxy;                   // padded row and slice strides: nx + 2, (nx + 2)(ny + 2)
+  int px, pxy;                   // padded row and slice strides: padded_row(nx), px (ny + 2)
   unsigned pvox;                 // padded voxels per volume
   int n_points, n_tets, n_sets;
   float radius, inv_radius;
