@@ -153,14 +153,14 @@ __device__ __forceinline__ double det_f64(const int v[4][3]) {
   return a0 * (b1 * c2 - b2 * c1) - a1 * (b0 * c2 - b2 * c0) + a2 * (b0 * c1 - b1 * c0);
 }
 
-constexpr int kDeferCap = 192;
+constexpr int kDeferCap = 128;
 
 // LDS scratch of one wave.
 struct WaveLds {
   DirConst c[2];
   int4 row[kWave];         // padded element of the first sample, the row's first unit in
                            // the unit stream, jx | jy << 10 | jz << 20 (box-relative), length
-  double rowq[kWave][4];   // mapped point of each row's first sample (x, y, z, unused)
+  double rowq[kWave][3];   // mapped point of each row's first sample
   int4 slice[kWave];       // non-empty slices of a group: z, first row y, first row index, rows
   int mark[kWave];         // row starts inside the current batch, tagged with the batch
   int4 defer[kDeferCap];   // near-grid samples: (jx | jy << 10 | jz << 20 | dir << 30, a, b, 0)
@@ -556,6 +556,129 @@ __device__ __forceinline__ bool sample_one(const ProblemView& P, const SampleCon
   return false;
 }
 
+// Guidance term of one in-band sample (Sec. 4.1.3, App. A.3): for every set
+// whose band holds the sample, the set-weighted (r - d)/r (d - d')^2 with d
+// from the own map at vi and d' the trilinear value of the other map (corner
+// rows i00..i11, x pair ix0/ix1, fractions f).
+__device__ __forceinline__ void guidance(const ProblemView& P, int d, unsigned bandbits, int vi, int i00,
+                                         int i01, int i10, int i11, int ix0, int ix1, const float f[3],
+                                         float& g_acc) {
+  const float r = P.radius, inv_r = P.inv_radius;
+  const float* map_own = d ? P.dmap[1] : P.dmap[0];
+  const float* map_oth = d ? P.dmap[0] : P.dmap[1];
+  while (bandbits) {
+    const int sidx = __builtin_ctz(bandbits);
+    bandbits &= bandbits - 1;
+    const float* mo = map_oth + static_cast<size_t>(sidx) * P.pvox;
+    const float dist = map_own[static_cast<size_t>(sidx) * P.pvox + vi];
+    const float u00 = fmaf(f[0], mo[i00 + ix1] - mo[i00 + ix0], mo[i00 + ix0]);
+    const float u01 = fmaf(f[0], mo[i01 + ix1] - mo[i01 + ix0], mo[i01 + ix0]);
+    const float u10 = fmaf(f[0], mo[i10 + ix1] - mo[i10 + ix0], mo[i10 + ix0]);
+    const float u11 = fmaf(f[0], mo[i11 + ix1] - mo[i11 + ix0], mo[i11 + ix0]);
+    const float u0 = fmaf(f[1], u01 - u00, u00), u1 = fmaf(f[1], u11 - u10, u10);
+    const float d2 = fmaf(f[2], u1 - u0, u0);
+    const float diff = dist - d2;
+    g_acc += P.set_w[d][sidx] * ((r - dist) * inv_r) * diff * diff;
+  }
+}
+
+// Two consecutive samples of one row (x offsets k and k + 1, padded
+// elements vi + k and vi + k + 1) for a direction whose mapped points stay
+// inside the padded volume.  Straight-line: both samples' loads are issued
+// before either is interpolated; loads for an invalid sample read whatever
+// in-resource memory its address names (a buffer load cannot fault) and are
+// discarded.  For each valid sample: h is added unless the mapped point is
+// within its error bound of a grid plane (amb: left to the exact path with
+// a, b), and the guidance term inside the band.
+template <int ST>
+__device__ __forceinline__ void sample_pair_inner(const ProblemView& P, const SampleConst& U,
+                                                  __amdgpu_buffer_rsrc_t r_own, __amdgpu_buffer_rsrc_t r_oth,
+                                                  __amdgpu_buffer_rsrc_t r_band, int d, int vi, const double qr[3],
+                                                  int k, bool v0, bool v1, float& h_acc, float& g_acc,
+                                                  bool amb[2], float a[2], float b[2]) {
+  const int e0 = vi + k;
+  float f[2][3];
+  int base[2];
+#pragma unroll
+  for (int s = 0; s < 2; s++) {
+    const double kd = static_cast<double>(k + s);
+    int c[3];
+#pragma unroll
+    for (int t = 0; t < 3; t++) {
+      const double q = fma(t == 0 ? U.m0 : (t == 1 ? U.m1 : U.m2), kd, qr[t]);
+      c[t] = static_cast<int>(q);     // q > 0 for a valid sample: truncation is the floor
+      f[s][t] = static_cast<float>(__builtin_amdgcn_fract(q));
+    }
+    base[s] = __umul24(c[2], P.pxy) + __umul24(c[1], P.px) + c[0];
+    amb[s] = fabsf(f[s][0] - 0.5f) >= U.thr || fabsf(f[s][1] - 0.5f) >= U.thr || fabsf(f[s][2] - 0.5f) >= U.thr;
+  }
+  // loads: own voxels (one pair), the 2 x 4 corner pairs, the two band bytes
+  float v[2][8];
+  bool fg8[2];
+  if constexpr (ST == kF32) {
+    const F2 own = ld_pair(r_own, e0, 0);
+    a[0] = own.a;
+    a[1] = own.b;
+#pragma unroll
+    for (int s = 0; s < 2; s++) {
+      const F2 p00 = ld_pair(r_oth, base[s], 0), p01 = ld_pair(r_oth, base[s], U.sy);
+      const F2 p10 = ld_pair(r_oth, base[s], U.sz), p11 = ld_pair(r_oth, base[s], U.sy + U.sz);
+      v[s][0] = p00.a; v[s][1] = p00.b; v[s][2] = p01.a; v[s][3] = p01.b;
+      v[s][4] = p10.a; v[s][5] = p10.b; v[s][6] = p11.a; v[s][7] = p11.b;
+    }
+  } else {
+    const uint32_t own = ld_pair16(r_own, e0, 0, static_cast<uint32_t>(e0 & 1) << 4);
+    a[0] = lo16<ST>(own);
+    a[1] = hi16<ST>(own);
+#pragma unroll
+    for (int s = 0; s < 2; s++) {
+      const uint32_t sh = static_cast<uint32_t>(base[s] & 1) << 4;
+      const uint32_t w00 = ld_pair16(r_oth, base[s], 0, sh), w01 = ld_pair16(r_oth, base[s], U.sy, sh);
+      const uint32_t w10 = ld_pair16(r_oth, base[s], U.sz, sh), w11 = ld_pair16(r_oth, base[s], U.sy + U.sz, sh);
+      v[s][0] = lo16<ST>(w00); v[s][1] = hi16<ST>(w00); v[s][2] = lo16<ST>(w01); v[s][3] = hi16<ST>(w01);
+      v[s][4] = lo16<ST>(w10); v[s][5] = hi16<ST>(w10); v[s][6] = lo16<ST>(w11); v[s][7] = hi16<ST>(w11);
+      fg8[s] = ((w00 | w01 | w10 | w11) & 0x7fff7fffu) != 0u;
+    }
+  }
+  unsigned band[2] = {0u, 0u};
+  if (P.n_sets > 0) {
+    band[0] = __builtin_amdgcn_raw_buffer_load_b8(r_band, static_cast<unsigned>(e0), 0, 0);
+    band[1] = __builtin_amdgcn_raw_buffer_load_b8(r_band, static_cast<unsigned>(e0) + 1u, 0, 0);
+  }
+#pragma unroll
+  for (int s = 0; s < 2; s++) {
+    const float* w = v[s];
+    if constexpr (ST == kF32) {
+      const uint32_t ob = __float_as_uint(w[0]) | __float_as_uint(w[1]) | __float_as_uint(w[2]) |
+                          __float_as_uint(w[3]) | __float_as_uint(w[4]) | __float_as_uint(w[5]) |
+                          __float_as_uint(w[6]) | __float_as_uint(w[7]);
+      fg8[s] = (ob << 1) != 0u;
+    }
+    const float e00 = fmaf(f[s][0], w[1] - w[0], w[0]), e01 = fmaf(f[s][0], w[3] - w[2], w[2]);
+    const float e10 = fmaf(f[s][0], w[5] - w[4], w[4]), e11 = fmaf(f[s][0], w[7] - w[6], w[6]);
+    const float ea = fmaf(f[s][1], e01 - e00, e00), eb = fmaf(f[s][1], e11 - e10, e10);
+    b[s] = fmaf(f[s][2], eb - ea, ea);
+    const bool fg_a = a[s] > 0.f;
+    const float dd = a[s] - b[s];
+    const float hv = (fg_a && fg8[s]) ? dd * dd : ((fg_a != fg8[s]) ? 1.f : 0.f);
+    const bool valid = s == 0 ? v0 : v1;
+    amb[s] = amb[s] && valid;
+    if (valid && !amb[s]) h_acc += hv;
+  }
+  // guidance inside the band (a few % of the samples)
+#pragma unroll
+  for (int s = 0; s < 2; s++) {
+    const bool valid = s == 0 ? v0 : v1;
+    if (valid && band[s] != 0u) {
+      const int rz0 = (base[s] / P.pxy) * P.pxy;
+      const int ry0 = base[s] - rz0 - (base[s] - rz0) % P.px;
+      const int ix0 = base[s] - rz0 - ry0;
+      guidance(P, d, band[s], e0 + s, rz0 + ry0, rz0 + ry0 + P.px, rz0 + P.pxy + ry0,
+               rz0 + P.pxy + ry0 + P.px, ix0, ix0 + 1, f[s], g_acc);
+    }
+  }
+}
+
 // Resolve the deferred near-grid samples of a wave: one sample per lane,
 // the mapped point recomputed from the item constants, the axes near a grid
 // plane found again in FP64, foreground decided on the exact support; h is
@@ -901,12 +1024,33 @@ __device__ void eval_tet(const ProblemView& P, int tet, float coord, WaveLds* L,
         const int4 rw = L->row[slot];
         const double qr[3] = {L->rowq[slot][0], L->rowq[slot][1], L->rowq[slot][2]};
         const int k = 2 * (u - rw.y);
-        sample(ok, rw.x, qr, k, rw.z);
-        sample(ok && k + 1 < rw.w, rw.x, qr, k + 1, rw.z);
+        // a batch defers at most 2 * 64 samples: resolve earlier ones first
         if (n_defer > kDeferCap - 2 * kWave) {
-          wave_sync();
           flush_deferred<ST>(P, L, n_defer, h);
           n_defer = 0;
+          wave_sync();
+        }
+        const bool ok2 = ok && k + 1 < rw.w;
+        if (inner) {
+          bool amb[2];
+          float a[2], b[2];
+          sample_pair_inner<ST>(P, U, r_own, r_oth, r_band, d, rw.x, qr, k, ok, ok2, h, g, amb, a, b);
+          n += static_cast<int>(ok) + static_cast<int>(ok2);
+#pragma unroll
+          for (int s2 = 0; s2 < 2; s2++) {
+            const uint64_t amb_mask = __ballot(amb[s2]);
+            if (amb_mask) {
+              if (amb[s2]) {
+                const int slot2 = n_defer + bits_below(amb_mask);
+                L->defer[slot2] = make_int4((rw.z + k + s2) | (d << 30), __float_as_int(a[s2]),
+                                            __float_as_int(b[s2]), 0);
+              }
+              n_defer += __popcll(amb_mask);
+            }
+          }
+        } else {
+          sample(ok, rw.x, qr, k, rw.z);
+          sample(ok2, rw.x, qr, k + 1, rw.z);
         }
         wave_sync();
       }
