@@ -163,7 +163,11 @@ struct WaveLds {
   double rowq[kWave][3];   // mapped point of each row's first sample
   int4 slice[kWave];       // non-empty slices of a group: z, first row y, first row index, rows
   int mark[kWave];         // row starts inside the current batch, tagged with the batch
-  int4 defer[kDeferCap];   // near-grid samples: (jx | jy << 10 | jz << 20 | dir << 30, a, b, 0)
+  // samples left to the slow paths, resolved a wave at a time; the first
+  // word is the box-relative position jx | jy << 10 | jz << 20 | dir << 30:
+  //   near-grid: (position, a, b, 0)
+  //   in band:   (position, band bits, 0, 1)
+  int4 defer[kDeferCap];
   int vert[24];            // snapped S (12), then T (12)
 };
 
@@ -587,15 +591,16 @@ __device__ __forceinline__ void guidance(const ProblemView& P, int d, unsigned b
 // inside the padded volume.  Straight-line: both samples' loads are issued
 // before either is interpolated; loads for an invalid sample read whatever
 // in-resource memory its address names (a buffer load cannot fault) and are
-// discarded.  For each valid sample: h is added unless the mapped point is
+// discarded.  For each valid sample h is added unless the mapped point is
 // within its error bound of a grid plane (amb: left to the exact path with
-// a, b), and the guidance term inside the band.
+// a, b); its band bits are returned for the guidance term, which the
+// slow-path queue adds (band is 0 for an invalid sample).
 template <int ST>
 __device__ __forceinline__ void sample_pair_inner(const ProblemView& P, const SampleConst& U,
                                                   __amdgpu_buffer_rsrc_t r_own, __amdgpu_buffer_rsrc_t r_oth,
                                                   __amdgpu_buffer_rsrc_t r_band, int d, int vi, const double qr[3],
-                                                  int k, bool v0, bool v1, float& h_acc, float& g_acc,
-                                                  bool amb[2], float a[2], float b[2]) {
+                                                  int k, bool v0, bool v1, float& h_acc, bool amb[2],
+                                                  float a[2], float b[2], unsigned band[2]) {
   const int e0 = vi + k;
   float f[2][3];
   int base[2];
@@ -640,7 +645,8 @@ __device__ __forceinline__ void sample_pair_inner(const ProblemView& P, const Sa
       fg8[s] = ((w00 | w01 | w10 | w11) & 0x7fff7fffu) != 0u;
     }
   }
-  unsigned band[2] = {0u, 0u};
+  band[0] = 0u;
+  band[1] = 0u;
   if (P.n_sets > 0) {
     band[0] = __builtin_amdgcn_raw_buffer_load_b8(r_band, static_cast<unsigned>(e0), 0, 0);
     band[1] = __builtin_amdgcn_raw_buffer_load_b8(r_band, static_cast<unsigned>(e0) + 1u, 0, 0);
@@ -663,45 +669,51 @@ __device__ __forceinline__ void sample_pair_inner(const ProblemView& P, const Sa
     const float hv = (fg_a && fg8[s]) ? dd * dd : ((fg_a != fg8[s]) ? 1.f : 0.f);
     const bool valid = s == 0 ? v0 : v1;
     amb[s] = amb[s] && valid;
+    if (!valid) band[s] = 0u;
     if (valid && !amb[s]) h_acc += hv;
-  }
-  // guidance inside the band (a few % of the samples)
-#pragma unroll
-  for (int s = 0; s < 2; s++) {
-    const bool valid = s == 0 ? v0 : v1;
-    if (valid && band[s] != 0u) {
-      const int rz0 = (base[s] / P.pxy) * P.pxy;
-      const int ry0 = base[s] - rz0 - (base[s] - rz0) % P.px;
-      const int ix0 = base[s] - rz0 - ry0;
-      guidance(P, d, band[s], e0 + s, rz0 + ry0, rz0 + ry0 + P.px, rz0 + P.pxy + ry0,
-               rz0 + P.pxy + ry0 + P.px, ix0, ix0 + 1, f[s], g_acc);
-    }
   }
 }
 
-// Resolve the deferred near-grid samples of a wave: one sample per lane,
-// the mapped point recomputed from the item constants, the axes near a grid
-// plane found again in FP64, foreground decided on the exact support; h is
-// added to the accumulator.
+// Resolve the queued samples of a wave, one per lane; the mapped point is
+// recomputed in FP64 from the item constants.  Near-grid samples: the axes
+// near a grid plane are found again and the foreground is decided on the
+// exact support; h is added.  In-band samples (queued only by directions
+// whose mapped points stay inside the padded volume): the guidance term is
+// added.
 template <int ST>
 __device__ __forceinline__ void flush_deferred(const ProblemView& P, const WaveLds* L, int count,
-                                               float& h_acc) {
+                                               float& h_acc, float& g_acc) {
   const int lane = lane_id();
   for (int base = 0; base < count; base += kWave) {
     const int e = base + lane;
     if (e >= count) continue;
     const int4 q4 = L->defer[e];
     const int jx = q4.x & 1023, jy = (q4.x >> 10) & 1023, jz = (q4.x >> 20) & 1023, d = (q4.x >> 30) & 1;
-    const float a = __int_as_float(q4.y), b = __int_as_float(q4.z);
     const DirConst& C = L->c[d];
     double q[3];
-    int axes = 0;
 #pragma unroll
-    for (int k = 0; k < 3; k++) {
+    for (int k = 0; k < 3; k++)
       q[k] = fma(C.M[k][0], static_cast<double>(jx),
                  fma(C.M[k][1], static_cast<double>(jy), fma(C.M[k][2], static_cast<double>(jz), C.qlo[k])));
-      if (fabs(q[k] - floor(q[k]) - 0.5) >= C.gthr[k]) axes |= 1 << k;
+    if (q4.w != 0) {
+      int c[3];
+      float f[3];
+#pragma unroll
+      for (int k = 0; k < 3; k++) {
+        c[k] = static_cast<int>(q[k]);
+        f[k] = static_cast<float>(__builtin_amdgcn_fract(q[k]));
+      }
+      const int vi = (C.lo[2] + jz + 1) * P.pxy + (C.lo[1] + jy + 1) * P.px + C.lo[0] + jx + 1;
+      const int i00 = c[2] * P.pxy + c[1] * P.px;
+      guidance(P, d, static_cast<unsigned>(q4.y), vi, i00, i00 + P.px, i00 + P.pxy, i00 + P.pxy + P.px, c[0],
+               c[0] + 1, f, g_acc);
+      continue;
     }
+    const float a = __int_as_float(q4.y), b = __int_as_float(q4.z);
+    int axes = 0;
+#pragma unroll
+    for (int k = 0; k < 3; k++)
+      if (fabs(q[k] - floor(q[k]) - 0.5) >= C.gthr[k]) axes |= 1 << k;
     const bool fg_b = exact_foreground<ST>(P, d ? P.img[0] : P.img[1], L, d, jx, jy, jz, q, axes);
     const bool fg_a = a > 0.f;
     const float dd = a - (fg_b ? b : 0.f);
@@ -995,6 +1007,12 @@ __device__ void eval_tet(const ProblemView& P, int tet, float coord, WaveLds* L,
       }
       const uint64_t amb_mask = __ballot(amb);
       if (amb_mask) {
+        if (n_defer + __popcll(amb_mask) > kDeferCap) {
+          wave_sync();
+          flush_deferred<ST>(P, L, n_defer, h, g);
+          n_defer = 0;
+          wave_sync();
+        }
         if (amb) {
           const int slot = n_defer + bits_below(amb_mask);
           L->defer[slot] = make_int4((jbase + k) | (d << 30), __float_as_int(a), __float_as_int(b), 0);
@@ -1024,28 +1042,37 @@ __device__ void eval_tet(const ProblemView& P, int tet, float coord, WaveLds* L,
         const int4 rw = L->row[slot];
         const double qr[3] = {L->rowq[slot][0], L->rowq[slot][1], L->rowq[slot][2]};
         const int k = 2 * (u - rw.y);
-        // a batch defers at most 2 * 64 samples: resolve earlier ones first
-        if (n_defer > kDeferCap - 2 * kWave) {
-          flush_deferred<ST>(P, L, n_defer, h);
-          n_defer = 0;
-          wave_sync();
-        }
         const bool ok2 = ok && k + 1 < rw.w;
         if (inner) {
           bool amb[2];
           float a[2], b[2];
-          sample_pair_inner<ST>(P, U, r_own, r_oth, r_band, d, rw.x, qr, k, ok, ok2, h, g, amb, a, b);
+          unsigned band[2];
+          sample_pair_inner<ST>(P, U, r_own, r_oth, r_band, d, rw.x, qr, k, ok, ok2, h, amb, a, b, band);
           n += static_cast<int>(ok) + static_cast<int>(ok2);
+          // near-grid and in-band samples join the queue (a flush first when
+          // they would not fit)
 #pragma unroll
           for (int s2 = 0; s2 < 2; s2++) {
-            const uint64_t amb_mask = __ballot(amb[s2]);
-            if (amb_mask) {
+            const uint64_t m_near = __ballot(amb[s2]);
+            const uint64_t m_band = __ballot(band[s2] != 0u);
+            if (m_near | m_band) {
+              const int nn = __popcll(m_near), nb = __popcll(m_band);
+              if (n_defer + nn + nb > kDeferCap) {
+                wave_sync();
+                flush_deferred<ST>(P, L, n_defer, h, g);
+                n_defer = 0;
+                wave_sync();
+              }
               if (amb[s2]) {
-                const int slot2 = n_defer + bits_below(amb_mask);
+                const int slot2 = n_defer + bits_below(m_near);
                 L->defer[slot2] = make_int4((rw.z + k + s2) | (d << 30), __float_as_int(a[s2]),
                                             __float_as_int(b[s2]), 0);
               }
-              n_defer += __popcll(amb_mask);
+              if (band[s2] != 0u) {
+                const int slot2 = n_defer + nn + bits_below(m_band);
+                L->defer[slot2] = make_int4((rw.z + k + s2) | (d << 30), static_cast<int>(band[s2]), 0, 1);
+              }
+              n_defer += nn + nb;
             }
           }
         } else {
@@ -1135,7 +1162,7 @@ __device__ void eval_tet(const ProblemView& P, int tet, float coord, WaveLds* L,
     if (tab_end > cons) run_batches(tab_end);
     if (n_defer > 0) {
       wave_sync();
-      flush_deferred<ST>(P, L, n_defer, h);
+      flush_deferred<ST>(P, L, n_defer, h, g);
     }
     h = wave_sum(h);
     g = wave_sum(g);
