@@ -268,19 +268,24 @@ __device__ __forceinline__ void row_span_fast(const DirConst& c, const int kind[
       if (!(t > 0.0)) je = -1;
       continue;
     }
+    // a crossing beyond [-2, W + 1] leaves the row full or empty either way:
+    // floor / ceil of the clamped value decide it without the exact test
     const double tc = fmin(fmax(t, -2.0), W + 1.0);
     const double r = rint(tc);
-    const bool near = fabs(tc - r) <= c.TE[i];
-    // exact plane value (+ tie-break bit) at x = r: |terms| < 2^50
-    const double e = fma(c.A[i], r, fma(c.PY[i], y, fma(c.PZ[i], z, c.B0[i])));
-    const int ri = static_cast<int>(r);
-    if (kind[i] > 0) {
-      const int j = near ? (e > 0.0 ? ri : ri + 1) : static_cast<int>(floor(tc)) + 1;
-      js = max(js, j);
-    } else {
-      const int j = near ? (e > 0.0 ? ri : ri - 1) : static_cast<int>(ceil(tc)) - 1;
-      je = min(je, j);
+    const bool near = tc == t && fabs(tc - r) <= c.TE[i];
+    int j = kind[i] > 0 ? static_cast<int>(floor(tc)) + 1 : static_cast<int>(ceil(tc)) - 1;
+    if (__ballot(near)) {
+      // rare: the exact plane value (+ tie-break bit) at x = r decides;
+      // |terms| < 2^50
+      const double e = fma(c.A[i], r, fma(c.PY[i], y, fma(c.PZ[i], z, c.B0[i])));
+      const int ri = static_cast<int>(r);
+      const int je_ = kind[i] > 0 ? (e > 0.0 ? ri : ri + 1) : (e > 0.0 ? ri : ri - 1);
+      j = near ? je_ : j;
     }
+    if (kind[i] > 0)
+      js = max(js, j);
+    else
+      je = min(je, j);
   }
 }
 
@@ -1197,11 +1202,21 @@ template <int ST>
 __global__ __launch_bounds__(256, 4) void k_eval_full(ProblemView P, FullItems F, Record* rec,
                                                     int n_items) {
   __shared__ WaveLds lds[4];
-  const int wave = threadIdx.x >> 6;
+  const int wave = uniform_i(static_cast<int>(threadIdx.x >> 6));
   const int item = xcd_block(blockIdx.x, gridDim.x) * 4 + wave;
   if (item >= n_items) return;
-  const int cand = item % F.pop;
-  const int tet = item / F.pop;
+  // item = tet * pop + cand, split with the reciprocal (wave-uniform values)
+  int tet = static_cast<int>(static_cast<double>(item) * F.inv_pop);
+  int cand = item - tet * F.pop;
+  if (cand < 0) {
+    tet -= 1;
+    cand += F.pop;
+  } else if (cand >= F.pop) {
+    tet += 1;
+    cand -= F.pop;
+  }
+  tet = uniform_i(tet);
+  cand = uniform_i(cand);
   const int lane = lane_id();
   float coord = 0.f;
   if (lane < 24) {
@@ -1350,7 +1365,7 @@ hipError_t launch_eval_full(const ProblemView& P, int storage, const float* pts,
   const size_t n_items = static_cast<size_t>(pop) * P.n_tets;
   if (n_items == 0) return hipSuccess;
   const int blocks = static_cast<int>((n_items + 3) / 4);
-  FullItems F{pts, pop};
+  FullItems F{pts, pop, 1.0 / pop};
   switch (storage) {
     case kF32:
       hipLaunchKernelGGL(k_eval_full<kF32>, dim3(blocks), dim3(256), 0, s, P, F, rec, (int)n_items);

@@ -74,6 +74,7 @@ struct ProblemView {
 struct FullItems {
   const float* pts;   // [pop][2][3][n_points]
   int pop;
+  double inv_pop;     // 1 / pop, for the item -> (tet, candidate) split
 };
 
 struct PartialItems {
