@@ -35,11 +35,17 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2303_04873_amd", "csrc", f)
 
 
 def kernel_source_hash():
+    """SHA-256 of the kernel sources with comments and whitespace removed (a
+    comment-only edit does not change the kernel)."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(f, "rb") as fh:
-            h.update(fh.read())
+        with open(f) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()
 
 

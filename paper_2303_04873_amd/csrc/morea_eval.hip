@@ -1,12 +1,13 @@
-// Device code of libmorea: per-(candidate, tetrahedron, direction) evaluation
-// by one 64-lane wavefront, per-candidate reductions, and the set-up kernel
-// that builds the guidance distance maps.
+// Device code of libmorea: per-(candidate, tetrahedron) evaluation by one
+// 64-lane wavefront, per-candidate reductions, partial evaluation, and the
+// set-up kernel that builds the guidance distance maps.
 //
-// One wave owns one work item: a tetrahedron of one candidate in one
-// direction.  Direction 0 rasterizes the source tet on I_s's voxel grid, maps
-// each sample into the target tet and samples I_t; direction 1 does the same
-// with the roles of the two meshes and images exchanged (the symmetric
-// objective of Sec. 4.1.2 and the dual-dynamic model of Sec. 4.2.1).
+// One wave owns one work item: a tetrahedron of one candidate, evaluated in
+// both directions.  Direction 0 rasterizes the source tet on I_s's voxel
+// grid, maps each sample into the target tet and samples I_t; direction 1
+// does the same with the roles of the two meshes and images exchanged (the
+// symmetric objective of Sec. 4.1.2 and the dual-dynamic model of
+// Sec. 4.2.1).
 //
 // Rasterization is exact.  Coordinates are snapped to 2^-10 voxel; each face
 // plane value s_i(p) = D * lambda_i(p) is an integer (units 2^-30 voxel^3),
@@ -16,10 +17,12 @@
 // belongs to the tet iff the face's inward normal is lexicographically
 // positive, i.e. p + (e, e^2, e^3) is strictly inside.
 //
-// Each wave walks the bounding box row by row: 64 rows at a time, one per
-// lane, it solves the x-interval of each row exactly (a division estimate
-// corrected by exact evaluation), compacts the non-empty rows into LDS and
-// then streams the row samples 64 at a time, so every lane holds one voxel.
+// Per direction the rows of each slice that can meet the tet are solved 64
+// at a time (one per lane); non-empty rows enter a ring in LDS whose samples
+// form one stream of two-sample units, consumed 64 units per batch (one per
+// lane).  Samples whose mapped point lies within its error bound of a grid
+// plane, and samples inside a guidance band, are queued and resolved a full
+// wave at a time.
 #include "morea_internal.h"
 
 namespace morea {
