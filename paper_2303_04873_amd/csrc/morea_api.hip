@@ -103,10 +103,13 @@ morea_status morea_problem_create(const morea_problem_desc* d, morea_problem** o
   const size_t V = static_cast<size_t>(nx) * ny * nz;
   if (V > (static_cast<size_t>(1) << 29))
     return fail(MOREA_EINVAL, "%zu voxels per image exceed the limit 2^29", V);
+  float min_pos = INFINITY;   // smallest positive value of either image
   for (size_t i = 0; i < V; i++) {
     float a = d->image_src[i], b = d->image_tgt[i];
     if (!(a >= 0.f && a < INFINITY) || !(b >= 0.f && b < INFINITY))
       return fail(MOREA_EINVAL, "image value at %zu is negative or not finite", i);
+    if (a > 0.f && a < min_pos) min_pos = a;
+    if (b > 0.f && b < min_pos) min_pos = b;
   }
   for (int i = 0; i < 3 * d->n_points; i++)
     if (!coord_ok(d->ref_points[i])) return fail(MOREA_EINVAL, "ref_points[%d] out of range", i);
@@ -179,6 +182,9 @@ morea_status morea_problem_create(const morea_problem_desc* d, morea_problem** o
   P.n_sets = d->n_sets;
   P.radius = radius;
   P.inv_radius = 1.0f / radius;
+  // inputs >= 2^-39 stay >= 2^-40 after BF16 rounding; FP16 keeps positive
+  // values >= 2^-24 or rounds them to 0
+  P.fg_from_b = min_pos >= 0x1p-39f ? 1 : 0;
   memcpy(P.set_w, set_w, sizeof(set_w));
 
   morea_status st = MOREA_OK;

@@ -82,6 +82,15 @@ __device__ __forceinline__ int wave_sum_i(int v) {
   return v;
 }
 
+// 1 / x in FP64: the hardware estimate refined by two Newton steps (relative
+// error near 2^-52; every use below carries a margin of at least 2^4 ulp).
+__device__ __forceinline__ double rcp64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(fma(-x, r, 1.0), r, r);
+  r = fma(fma(-x, r, 1.0), r, r);
+  return r;
+}
+
 __device__ __forceinline__ int64_t floor_div_pos(int64_t a, int64_t b) {  // b > 0
   int64_t q = a / b;
   return (q * b > a) ? q - 1 : q;
@@ -323,7 +332,7 @@ __device__ __forceinline__ void slice_rows(const int* v, int Z, int ylo, int yhi
         mn = fminf(mn, fminf(yi, yj));
         mx = fmaxf(mx, fmaxf(yi, yj));
       } else {
-        const float t = static_cast<float>(-zi) / static_cast<float>(zj - zi);
+        const float t = static_cast<float>(-zi) * __builtin_amdgcn_rcpf(static_cast<float>(zj - zi));
         const float y = fmaf(t, yj - yi, yi);
         mn = fminf(mn, y);
         mx = fmaxf(mx, y);
@@ -650,7 +659,7 @@ __device__ __forceinline__ void sample_pair_inner(const ProblemView& P, const Sa
       const uint32_t w10 = ld_pair16(r_oth, base[s], U.sz, sh), w11 = ld_pair16(r_oth, base[s], U.sy + U.sz, sh);
       v[s][0] = lo16<ST>(w00); v[s][1] = hi16<ST>(w00); v[s][2] = lo16<ST>(w01); v[s][3] = hi16<ST>(w01);
       v[s][4] = lo16<ST>(w10); v[s][5] = hi16<ST>(w10); v[s][6] = lo16<ST>(w11); v[s][7] = hi16<ST>(w11);
-      fg8[s] = ((w00 | w01 | w10 | w11) & 0x7fff7fffu) != 0u;
+      if (!P.fg_from_b) fg8[s] = ((w00 | w01 | w10 | w11) & 0x7fff7fffu) != 0u;
     }
   }
   band[0] = 0u;
@@ -662,16 +671,18 @@ __device__ __forceinline__ void sample_pair_inner(const ProblemView& P, const Sa
 #pragma unroll
   for (int s = 0; s < 2; s++) {
     const float* w = v[s];
-    if constexpr (ST == kF32) {
+    const float e00 = fmaf(f[s][0], w[1] - w[0], w[0]), e01 = fmaf(f[s][0], w[3] - w[2], w[2]);
+    const float e10 = fmaf(f[s][0], w[5] - w[4], w[4]), e11 = fmaf(f[s][0], w[7] - w[6], w[6]);
+    const float ea = fmaf(f[s][1], e01 - e00, e00), eb = fmaf(f[s][1], e11 - e10, e10);
+    b[s] = fmaf(f[s][2], eb - ea, ea);
+    if (P.fg_from_b) {
+      fg8[s] = b[s] > 0.f;
+    } else if constexpr (ST == kF32) {
       const uint32_t ob = __float_as_uint(w[0]) | __float_as_uint(w[1]) | __float_as_uint(w[2]) |
                           __float_as_uint(w[3]) | __float_as_uint(w[4]) | __float_as_uint(w[5]) |
                           __float_as_uint(w[6]) | __float_as_uint(w[7]);
       fg8[s] = (ob << 1) != 0u;
     }
-    const float e00 = fmaf(f[s][0], w[1] - w[0], w[0]), e01 = fmaf(f[s][0], w[3] - w[2], w[2]);
-    const float e10 = fmaf(f[s][0], w[5] - w[4], w[4]), e11 = fmaf(f[s][0], w[7] - w[6], w[6]);
-    const float ea = fmaf(f[s][1], e01 - e00, e00), eb = fmaf(f[s][1], e11 - e10, e10);
-    b[s] = fmaf(f[s][2], eb - ea, ea);
     const bool fg_a = a[s] > 0.f;
     const float dd = a[s] - b[s];
     const float hv = (fg_a && fg8[s]) ? dd * dd : ((fg_a != fg8[s]) ? 1.f : 0.f);
@@ -839,8 +850,9 @@ __device__ void eval_tet(const ProblemView& P, int tet, float coord, WaveLds* L,
         }
         scale = 1.0f / (4.0f * kFixOne);
       }
-      const float den = sqrtf(static_cast<float>(ls)) + sqrtf(static_cast<float>(lt));
-      const float dd = den > 0.f ? static_cast<float>(ls - lt) / den * scale : 0.f;
+      // hardware square root and reciprocal (about 1 ulp each)
+      const float den = __builtin_amdgcn_sqrtf(static_cast<float>(ls)) + __builtin_amdgcn_sqrtf(static_cast<float>(lt));
+      const float dd = den > 0.f ? static_cast<float>(ls - lt) * __builtin_amdgcn_rcpf(den) * scale : 0.f;
       term = dd * dd;
     }
     const float mag = P.elasticity[tet] * wave_sum(term);
@@ -888,7 +900,7 @@ __device__ void eval_tet(const ProblemView& P, int tet, float coord, WaveLds* L,
     C.A[i] = A;
     C.PY[i] = PY;
     C.PZ[i] = PZ;
-    const double invA = nx_ != 0 ? 1.0 / A : 0.0;
+    const double invA = nx_ != 0 ? rcp64(A) : 0.0;
     C.invA[i] = invA;
     const int kind = (nx_ > 0) - (nx_ < 0);
     C.kind[i] = kind;
@@ -928,7 +940,7 @@ __device__ void eval_tet(const ProblemView& P, int tet, float coord, WaveLds* L,
     DirConst& C = L->c[d];
     const int* oth = L->vert + 12 * (1 - d);
     const double sigma = C.sigma;
-    const double invD = sigma / static_cast<double>(C.absD != 0 ? C.absD : 1);
+    const double invD = sigma * rcp64(static_cast<double>(C.absD != 0 ? C.absD : 1));
     const double oth0 = oth[a];
     double num = 0.0, mag = 0.0;
 #pragma unroll

@@ -61,6 +61,10 @@ struct ProblemView {
   unsigned pvox;                 // padded voxels per volume
   int n_points, n_tets, n_sets;
   float radius, inv_radius;
+  // every positive stored image value is >= 2^-40: then a sample whose
+  // mapped point is not near a grid plane (trilinear weights >= 2^-22) has
+  // b > 0 exactly when one of its 8 corners is > 0 (b >= 2^-106 stays normal)
+  int fg_from_b;
   const void* img[2];            // [0] = I_s, [1] = I_t, storage type, padded
   const float* dmap[2];          // [n_sets][pvox] distance maps on each image grid, padded
   const uint8_t* band[2];        // [pvox] bit s set where dmap[s] < radius

@@ -71,6 +71,24 @@ def test_c1_identity_and_exact_paths():
     assert_parity(run(prob2, pts), oracle_problem(1).evaluate(pts), what="integer shift")
 
 
+def test_tiny_intensities_take_corner_test():
+    """Positive intensities below 2^-39 (here 1e-30 and 1e-37, both normal
+    FP32) switch the foreground test of ordinary samples from b > 0 to the
+    corners' bits: b of a sample whose only positive corner holds 1e-37
+    underflows to 0 while the exact support still says foreground."""
+    p = synth_problem(1)
+    img = p.image_src.copy()
+    bg = np.argwhere(img == 0)
+    rs = np.random.default_rng(7)
+    pick = bg[rs.choice(len(bg), 400, replace=False)]
+    img[tuple(pick[:200].T)] = 1e-30
+    img[tuple(pick[200:].T)] = 1e-37
+    pop = synth.make_population(p, pop=8, seed=17, perturb_source=True)
+    g = run(gpu_problem(p, image_src=img), pop)
+    o = oracle.Problem.from_synth(p, image_src=img).evaluate(pop)
+    assert_parity(g, o, what="tiny intensities")
+
+
 def test_large_tets_take_int64_path():
     """Tets wider than 64 voxels use the int64 plane arithmetic."""
     dims = (100, 90, 80)
