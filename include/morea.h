@@ -184,7 +184,7 @@ morea_status morea_debug_distance_map(morea_problem *p, int32_t image, int32_t s
 /* Autotuner of the persistent partial-evaluation launch: with the same
  * arguments as morea_eval_partial, times every launch shape (persistent
  * blocks per compute unit up to the occupancy limit x work items taken per
- * queue pop in {1, 2, 4}) on the given inputs with HIP events and keeps the
+ * queue pop in {1, 2, 4, 8, 16}) on the given inputs with HIP events and keeps the
  * fastest for later morea_eval_partial calls.  Synchronous; overwrites the
  * output arrays.  *best_ms (may be NULL) receives the best time.  Errors as
  * morea_eval_partial. */

@@ -361,6 +361,7 @@ void drop_partial(morea_problem* p) {
   p->max_evals = 0;
   p->d_row_off = p->d_item_off = p->d_queue = nullptr;
   p->d_partial_records = nullptr;
+  p->d_item_info = nullptr;
 }
 
 }  // namespace
@@ -447,6 +448,9 @@ morea_status morea_reserve_partial(morea_problem* p, int32_t max_evals) {
   if (st == MOREA_OK)
     st = upload_to(p->partial_allocs, &p->d_partial_records, nullptr,
                    sizeof(Record) * 2 * static_cast<size_t>(max_evals) * p->max_dep);
+  if (st == MOREA_OK)
+    st = upload_to(p->partial_allocs, &p->d_item_info, nullptr,
+                   sizeof(int4) * static_cast<size_t>(max_evals) * p->max_dep);
   if (st != MOREA_OK) {
     free_list(p->partial_allocs);
     return st;
@@ -500,6 +504,7 @@ static hipError_t partial_launch(morea_problem* p, const float* parent_pts, int3
   I.dep_off = p->d_dep_off;
   I.dep_tet = p->d_dep_tet;
   I.dep_local = p->d_dep_local;
+  I.item_info = p->d_item_info;
   I.n_evals = n_evals;
   const Record* prec = static_cast<const Record*>(parent_cache);
   const Totals* ptot = reinterpret_cast<const Totals*>(
@@ -575,9 +580,9 @@ morea_status morea_tune_partial(morea_problem* p, const float* parent_pts, int32
     return fail(MOREA_EDEVICE, "hipEventCreate");
   float best = 1e30f;
   int best_blocks = p->partial_blocks, best_chunk = p->partial_chunk;
-  const int chunks[3] = {1, 2, 4};
+  const int chunks[5] = {1, 2, 4, 8, 16};
   for (int bpc = 1; bpc <= per_cu; bpc++)
-    for (int c = 0; c < 3; c++) {
+    for (int c = 0; c < 5; c++) {
       const int blocks = bpc * cus, chunk = chunks[c];
       float total = 0.f;
       hipError_t e = hipSuccess;

@@ -1455,13 +1455,21 @@ __global__ __launch_bounds__(1024) void k_partial_prep(const int* eval_parent, c
   if (tid == 0) *queue = 0;
 }
 
-__device__ __forceinline__ int find_eval(const int* item_off, int n_evals, int idx) {
-  int lo = 0, hi = n_evals;   // largest e with item_off[e] <= idx
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (item_off[mid] <= idx) lo = mid; else hi = mid;
-  }
-  return lo;
+// Per-item records of the partial launch, one wave per evaluation (after the
+// prefix sums): for each of the evaluation's dependent tets, its slot in the
+// group's dependent-tet list, the tet, the parent and the evaluation's first
+// new-coordinate row.  Evaluations with an out-of-range parent or group own
+// no items (the prefix sums gave them none).
+__global__ __launch_bounds__(256) void k_partial_items(PartialItems I, int n_parents, int n_groups) {
+  const int e = blockIdx.x * 4 + static_cast<int>(threadIdx.x >> 6);
+  const int lane = lane_id();
+  if (e >= I.n_evals) return;
+  const int g = I.eval_group[e], par = I.eval_parent[e];
+  if (g < 0 || g >= n_groups || par < 0 || par >= n_parents) return;
+  const int first = I.dep_off[g], n = I.dep_off[g + 1] - first;
+  const int base = I.item_off[e], row = I.row_off[e];
+  for (int j = lane; j < n; j += kWave)
+    I.item_info[base + j] = make_int4(first + j, I.dep_tet[first + j], par, row);
 }
 
 // Persistent evaluation of all (evaluation, dependent tet) items, both
@@ -1482,18 +1490,15 @@ __global__ __launch_bounds__(256, 3) void k_eval_partial(ProblemView P, PartialI
     if (base >= total) break;
     const int end = min(total, base + chunk);
     for (int idx = base; idx < end; idx++) {
-      const int e = find_eval(I.item_off, I.n_evals, idx);
-      const int j = idx - I.item_off[e];
-      const int g = I.eval_group[e], par = I.eval_parent[e];
-      const int slot = I.dep_off[g] + j;
-      const int tet = I.dep_tet[slot];
+      const int4 it = I.item_info[idx];
+      const int slot = uniform_i(it.x), tet = uniform_i(it.y), par = uniform_i(it.z), row = uniform_i(it.w);
       float coord = 0.f;
       if (lane < 24) {
         const int i = (lane % 12) / 3, k = lane % 3;
         const int mesh = lane < 12 ? 0 : 1;
         const int loc = I.dep_local[4 * slot + i];
         if (loc >= 0) {
-          coord = I.new_coords[((static_cast<size_t>(I.row_off[e]) + loc) * 2 + mesh) * 3 + k];
+          coord = I.new_coords[((static_cast<size_t>(row) + loc) * 2 + mesh) * 3 + k];
         } else {
           const int4 tv = P.tets[tet];
           const int v = i == 0 ? tv.x : (i == 1 ? tv.y : (i == 2 ? tv.z : tv.w));
@@ -1615,6 +1620,7 @@ hipError_t launch_partial(const ProblemView& P, int storage, const PartialItems&
   hipLaunchKernelGGL(k_partial_prep, dim3(1), dim3(1024), 0, s, I.eval_parent, I.eval_group,
                      I.n_evals, n_parents, n_groups, I.grp_off, I.dep_off,
                      const_cast<int*>(I.row_off), const_cast<int*>(I.item_off), queue);
+  hipLaunchKernelGGL(k_partial_items, dim3((I.n_evals + 3) / 4), dim3(256), 0, s, I, n_parents, n_groups);
   switch (storage) {
     case kF32:
       hipLaunchKernelGGL(k_eval_partial<kF32>, dim3(blocks), dim3(256), 0, s, P, I, new_rec, queue, chunk);

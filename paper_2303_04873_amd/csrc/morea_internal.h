@@ -93,6 +93,7 @@ struct PartialItems {
   const int* dep_off;          // [n_groups + 1] CSR into dep_tet / dep_local
   const int* dep_tet;          // dependent tets per group
   const int8_t* dep_local;     // [.][4] position of each tet vertex in the group, -1 if none
+  int4* item_info;             // [items]: dependent-tet slot, tet, parent, first new-coordinate row
   int n_evals;
 };
 
@@ -125,6 +126,7 @@ struct morea_problem {
   int* d_row_off = nullptr;
   int* d_item_off = nullptr;
   morea::Record* d_partial_records = nullptr;  // [max_evals * max_dep][2]
+  int4* d_item_info = nullptr;                 // [max_evals * max_dep]
   int* d_queue = nullptr;
   hipStream_t capture_stream = nullptr;
   // autotuned persistent launch shape
