@@ -287,65 +287,168 @@ __global__ void k_targets(const Record* rec, int rows, float* t) {
 }
 
 // ------------------------------------------------------------ prescreen
+// The pre-screen runs both dense layers transposed, Z^T = W X^T, on
+// v_mfma_f32_32x32x16_bf16 (BF16 operands, FP32 accumulation): the weights
+// are the A operand (lane l: output unit 32 n + l % 32, k = 8 (l / 32) .. +7
+// of a 16-wide slice), the tets the B operand (lane l: tet l % 32 of the
+// tile, the same k range), and the accumulator of lane l holds tet l % 32
+// and units 8 (r / 4) + 4 (l / 32) + r % 4 of the output tile (r = 0..15).
+// Accumulators r = 8 g .. 8 g + 7 of layer 1 are therefore, after bias, ReLU
+// and BF16 rounding, one 16-wide k-slice of layer 2's B operand, in the unit
+// order  slot kk of lane half h -> unit 4 h + kk (kk < 4), 8 + 4 h + kk - 4
+// (kk >= 4)  within the slice; W2's columns are stored in that order, so no
+// activation passes through LDS.  Layer 1's bias rides on constant features
+// (features 20..22 = 1, W1 columns 20..22 = b1 split into three BF16 terms
+// that sum to it in the FP32 accumulator); layer 2's accumulators start at b2.
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned u4v __attribute__((ext_vector_type(4)));
+
+constexpr int kPreIn = 32;                 // features padded: 20 + three constant 1s + zeros
+constexpr int kW1Row = kPreIn + 8;         // LDS row strides padded against bank conflicts
+constexpr int kW2Row = kHid + 8;
+
+struct alignas(16) PreLds {
+  bf16 w1[kHid][kW1Row];   // W1 | b1 (three terms) | 0
+  bf16 w2[kHid][kW2Row];   // W2, columns permuted per 16-wide slice
+  float b2[kHid];
+  float w3[kHid];
+};
+
+__device__ __forceinline__ int slot_unit(int j) {   // 16-wide slice: slot j -> unit
+  const int h = j >> 3, kk = j & 7;
+  return kk < 4 ? 4 * h + kk : 8 + 4 * h + (kk - 4);
+}
+
+__device__ __forceinline__ bf8 ld8(const bf16* p) { return *reinterpret_cast<const bf8*>(p); }
+
+__device__ __forceinline__ bf8 pack8(const float v[8]) {
+  u4v w;
+  w.x = static_cast<uint32_t>(f2bf(v[0])) | (static_cast<uint32_t>(f2bf(v[1])) << 16);
+  w.y = static_cast<uint32_t>(f2bf(v[2])) | (static_cast<uint32_t>(f2bf(v[3])) << 16);
+  w.z = static_cast<uint32_t>(f2bf(v[4])) | (static_cast<uint32_t>(f2bf(v[5])) << 16);
+  w.w = static_cast<uint32_t>(f2bf(v[6])) | (static_cast<uint32_t>(f2bf(v[7])) << 16);
+  return __builtin_bit_cast(bf8, w);
+}
 
 // Score of each candidate: the predicted intensity objective,
 // sum_tet pred_tet * n_tet / sum_tet n_tet with n_tet the reference voxel
-// counts.  One block (4 waves) per candidate; fixed-order reductions.
-__global__ __launch_bounds__(256) void k_prescreen(ProblemView P, const float* pts, const float* ref,
-                                                    const float* stats,
-                                                    const int* counts, const bf16* w1b, const bf16* w2b,
-                                                    const float* params, float* score) {
-  __shared__ NetLds N;
-  __shared__ TileLds Tl[4];
+// counts.  Blocks of 4 waves loop over candidates; each wave takes tiles of
+// 32 tets; fixed-order reductions.
+__global__ __launch_bounds__(256, 3) void k_prescreen(ProblemView P, const float* pts, const float* ref,
+                                                    const float* stats, const int* counts, const float* params,
+                                                    int pop, float* score) {
+  __shared__ PreLds N;
   __shared__ float wsum[4], wcnt[4];
-  load_net(&N, w1b, w2b, params);
+  for (int e = threadIdx.x; e < kHid * kPreIn; e += blockDim.x) {
+    const int j = e / kPreIn, k = e % kPreIn;
+    if (k < kIn) {
+      N.w1[j][k] = f2bf(params[oW1 + j * kIn + k]);
+    } else if (k < kIn + 3) {
+      // b1 = hi + mid + lo, three BF16 terms carrying its 24-bit mantissa
+      const float b = params[oB1 + j];
+      const bf16 hi = f2bf(b), mid = f2bf(b - bf2f(hi)), lo = f2bf(b - bf2f(hi) - bf2f(mid));
+      N.w1[j][k] = k == kIn ? hi : (k == kIn + 1 ? mid : lo);
+    } else {
+      N.w1[j][k] = 0;
+    }
+  }
+  for (int e = threadIdx.x; e < kHid * kHid; e += blockDim.x) {
+    const int j = e / kHid, k = e % kHid;
+    N.w2[j][k] = f2bf(params[oW2 + j * kHid + (k & ~15) + slot_unit(k & 15)]);
+  }
+  for (int e = threadIdx.x; e < kHid; e += blockDim.x) {
+    N.b2[e] = params[oB2 + e];
+    N.w3[e] = params[oW3 + e];
+  }
+  const float b3 = params[oB3];
   __syncthreads();
-  const int cand = blockIdx.x, wave = threadIdx.x >> 6, lane = lane_id();
-  TileLds* T = &Tl[wave];
-  const float* cp = pts + static_cast<size_t>(cand) * 6 * P.n_points;
-  const int i = lane & 31, kh = lane >> 5;
-  float acc = 0.f, cnt = 0.f;
+  const int wave = threadIdx.x >> 6, lane = lane_id(), i = lane & 31, h = lane >> 5;
   const int n_tiles = (P.n_tets + kRowTile - 1) / kRowTile;
-  for (int tile = wave; tile < n_tiles; tile += 4) {
-    const int tet = tile * kRowTile + i;
-    float f[12];
-    if (tet < P.n_tets) {
-      row_features(P, cp, ref, tet, stats, kh, f);
-    } else {
+  for (int cand = blockIdx.x; cand < pop; cand += gridDim.x) {
+    const float* cp = pts + static_cast<size_t>(cand) * 6 * P.n_points;
+    float acc_s = 0.f, cnt = 0.f;
+    for (int tile = wave; tile < n_tiles; tile += 4) {
+      const int tet = tile * kRowTile + i;
+      // this lane's half of the tet's features (natural order: 12 deformation
+      // values, 8 statistics, three constant 1s, zeros)
+      float f0[8], f1[8];
 #pragma unroll
-      for (int k = 0; k < 12; k++) f[k] = 0.f;
+      for (int k = 0; k < 8; k++) f0[k] = f1[k] = 0.f;
+      if (tet < P.n_tets) {
+        const int4 tv = P.tets[tet];
+        const int vs[4] = {tv.x, tv.y, tv.z, tv.w};
+        if (h == 0) {   // features 0..7, 16..23
+#pragma unroll
+          for (int k = 0; k < 8; k++) {
+            const int v = vs[k / 3], a = k % 3;
+            f0[k] = (cp[(3 + a) * P.n_points + v] - ref[3 * v + a]) * kDispScale;
+          }
+#pragma unroll
+          for (int k = 0; k < 4; k++) f1[k] = stats[8 * tet + 4 + k];
+          f1[4] = f1[5] = f1[6] = 1.f;   // the three terms of b1
+        } else {        // features 8..15, 24..31
+#pragma unroll
+          for (int k = 0; k < 4; k++) {
+            const int fk = 8 + k, v = vs[fk / 3], a = fk % 3;
+            f0[k] = (cp[(3 + a) * P.n_points + v] - ref[3 * v + a]) * kDispScale;
+          }
+#pragma unroll
+          for (int k = 0; k < 4; k++) f0[4 + k] = stats[8 * tet + k];
+        }
+      }
+      const bf8 xb0 = pack8(f0), xb1 = pack8(f1);
+      // layer 1: 4 output tiles of 32 units, K = 32 (two slices)
+      bf8 hb[8];
+#pragma unroll
+      for (int n = 0; n < 4; n++) {
+        f16v z = {};
+        z = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ld8(&N.w1[32 * n + i][8 * h]), xb0, z, 0, 0, 0);
+        z = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ld8(&N.w1[32 * n + i][16 + 8 * h]), xb1, z, 0, 0, 0);
+        float v0[8], v1[8];
+#pragma unroll
+        for (int r = 0; r < 8; r++) {
+          v0[r] = fmaxf(z[r], 0.f);
+          v1[r] = fmaxf(z[8 + r], 0.f);
+        }
+        hb[2 * n] = pack8(v0);
+        hb[2 * n + 1] = pack8(v1);
+      }
+      // layer 2 (K = 128, eight slices) and the output layer
+      float part = 0.f;
+#pragma unroll 1
+      for (int n = 0; n < 4; n++) {
+        f16v z;
+#pragma unroll
+        for (int r = 0; r < 16; r++) z[r] = N.b2[32 * n + 8 * (r >> 2) + 4 * h + (r & 3)];
+#pragma unroll
+        for (int sl = 0; sl < 8; sl++)
+          z = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ld8(&N.w2[32 * n + i][16 * sl + 8 * h]), hb[sl], z, 0, 0,
+                                                      0);
+#pragma unroll
+        for (int r = 0; r < 16; r++)
+          part = fmaf(fmaxf(z[r], 0.f), N.w3[32 * n + 8 * (r >> 2) + 4 * h + (r & 3)], part);
+      }
+      const float y = part + __shfl_xor(part, 32, 64) + b3;   // the two halves hold different units
+      if (h == 0 && tet < P.n_tets) {
+        const float c = static_cast<float>(counts[tet]);
+        acc_s = fmaf(y, c, acc_s);
+        cnt += c;
+      }
     }
-    if (kh == 0) {
-#pragma unroll
-      for (int k = 0; k < 12; k++) T->x[i][k] = f2bf(f[k]);
-    } else {
-#pragma unroll
-      for (int k = 0; k < 8; k++) T->x[i][12 + k] = f2bf(f[k]);
-#pragma unroll
-      for (int k = kIn; k < kInPad; k++) T->x[i][k] = 0;
+    for (int d = 32; d >= 1; d >>= 1) {
+      acc_s += __shfl_xor(acc_s, d, 64);
+      cnt += __shfl_xor(cnt, d, 64);
     }
-    wave_sync();
-    f16v z2[4];
-    tile_forward(&N, T, T->red, z2);
-    if (lane < kRowTile && tet < P.n_tets) {
-      const float c = static_cast<float>(counts[tet]);
-      acc = fmaf(T->y[lane], c, acc);
-      cnt += c;
+    if (lane == 0) {
+      wsum[wave] = acc_s;
+      wcnt[wave] = cnt;
     }
-    wave_sync();
-  }
-  for (int d = 32; d >= 1; d >>= 1) {
-    acc += __shfl_xor(acc, d, 64);
-    cnt += __shfl_xor(cnt, d, 64);
-  }
-  if (lane == 0) {
-    wsum[wave] = acc;
-    wcnt[wave] = cnt;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const float c = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
-    score[cand] = c > 0.f ? (wsum[0] + wsum[1] + wsum[2] + wsum[3]) / c : 0.f;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const float c = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+      score[cand] = c > 0.f ? (wsum[0] + wsum[1] + wsum[2] + wsum[3]) / c : 0.f;
+    }
+    __syncthreads();
   }
 }
 
@@ -815,8 +918,9 @@ morea_status morea_surrogate_prescreen(morea_surrogate* s, const float* pts, int
                                        void* stream) {
   if (!s || !pts || !score || pop < 0) return sfail(MOREA_EINVAL, "bad argument");
   if (pop == 0) return MOREA_OK;
-  hipLaunchKernelGGL(k_prescreen, dim3(pop), dim3(256), 0, static_cast<hipStream_t>(stream), s->p->view,
-                     pts, s->ref, s->stats, s->counts, s->w1b, s->w2b, s->params, score);
+  const int blocks = std::min<int>(pop, 1024);
+  hipLaunchKernelGGL(k_prescreen, dim3(blocks), dim3(256), 0, static_cast<hipStream_t>(stream), s->p->view,
+                     pts, s->ref, s->stats, s->counts, s->params, pop, score);
   return sdev(hipGetLastError(), "prescreen");
 }
 
