@@ -265,40 +265,36 @@ __device__ __forceinline__ void clip_face(int kind, T A, double invA, T b, int W
 // floor(t) + 1 and the last inside a face with kind < 0 is ceil(t) - 1 (a
 // centre on the plane is outside once the tie-break bit is folded in), unless
 // t is within its FP64 error bound TE of an integer r: then the exact plane
-// value at r decides between r and its neighbour.  Branch-free per face;
-// `kind` is wave-uniform.
-__device__ __forceinline__ void row_span_fast(const DirConst& c, const int kind[4], int yr, int zr, int W,
-                                              int& js, int& je) {
+// value at r decides between r and its neighbour.  Branch-free per face.
+__device__ __forceinline__ void row_span_fast(const DirConst& c, int yr, int zr, int W, int& js, int& je) {
   js = 0;
   je = W;
   const double y = yr, z = zr;
+  bool empty = false;
 #pragma unroll
   for (int i = 0; i < 4; i++) {
+    const int kind = c.kind[i];
     const double t = fma(c.TA[i], y, fma(c.TB[i], z, c.TG[i]));
-    if (kind[i] == 0) {
-      // face parallel to x: t holds the plane value itself
-      if (!(t > 0.0)) je = -1;
-      continue;
-    }
+    // face parallel to x (kind 0): t holds the plane value itself
+    empty = empty || (kind == 0 && !(t > 0.0));
     // a crossing beyond [-2, W + 1] leaves the row full or empty either way:
     // floor / ceil of the clamped value decide it without the exact test
     const double tc = fmin(fmax(t, -2.0), W + 1.0);
     const double r = rint(tc);
-    const bool near = tc == t && fabs(tc - r) <= c.TE[i];
-    int j = kind[i] > 0 ? static_cast<int>(floor(tc)) + 1 : static_cast<int>(ceil(tc)) - 1;
+    const bool near = kind != 0 && tc == t && fabs(tc - r) <= c.TE[i];
+    int j = kind > 0 ? static_cast<int>(floor(tc)) + 1 : static_cast<int>(ceil(tc)) - 1;
     if (__ballot(near)) {
       // rare: the exact plane value (+ tie-break bit) at x = r decides;
       // |terms| < 2^50
       const double e = fma(c.A[i], r, fma(c.PY[i], y, fma(c.PZ[i], z, c.B0[i])));
       const int ri = static_cast<int>(r);
-      const int je_ = kind[i] > 0 ? (e > 0.0 ? ri : ri + 1) : (e > 0.0 ? ri : ri - 1);
-      j = near ? je_ : j;
+      const int jx = kind > 0 ? (e > 0.0 ? ri : ri + 1) : (e > 0.0 ? ri : ri - 1);
+      j = near ? jx : j;
     }
-    if (kind[i] > 0)
-      js = max(js, j);
-    else
-      je = min(je, j);
+    js = kind > 0 ? max(js, j) : js;
+    je = kind < 0 ? min(je, j) : je;
   }
+  if (empty) je = -1;
 }
 
 // The same for wider tets, in int64 (extent < 2^20 keeps |s_i| < 2^63).
@@ -994,8 +990,6 @@ __device__ void eval_tet(const ProblemView& P, int tet, float coord, WaveLds* L,
     const int lox = uniform_i(Cd.lo[0]), loy = uniform_i(Cd.lo[1]), loz = uniform_i(Cd.lo[2]);
     const bool inner = uniform_i(Cd.inner) != 0;
     const bool fast = uniform_i(Cd.fast) != 0;
-    const int kinds[4] = {uniform_i(Cd.kind[0]), uniform_i(Cd.kind[1]), uniform_i(Cd.kind[2]),
-                          uniform_i(Cd.kind[3])};
     SampleConst U;
     U.m0 = uniform_d(Cd.M[0][0]);
     U.m1 = uniform_d(Cd.M[1][0]);
@@ -1141,7 +1135,7 @@ __device__ void eval_tet(const ProblemView& P, int tet, float coord, WaveLds* L,
           zr = sl.x;
           yr = sl.y + (rr - sl.z);
           if (fast)
-            row_span_fast(Cd, kinds, yr, zr, Wd, js, je);
+            row_span_fast(Cd, yr, zr, Wd, js, je);
           else
             row_span_wide(Cd, yr, zr, Wd, js, je);
         }
