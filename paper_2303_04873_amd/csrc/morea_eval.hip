@@ -741,7 +741,11 @@ __device__ __forceinline__ void flush_deferred(const ProblemView& P, const WaveL
 // target tet's (`coord`).  The wave writes out[0] (direction 0) and out[1].
 template <int ST>
 __device__ void eval_tet(const ProblemView& P, int tet, float coord, WaveLds* L, Record* out) {
-  const int lane = lane_id();
+  // the lane index is made opaque so that values derived from it are not
+  // hoisted out of the persistent partial-evaluation loop (they would stay
+  // live across every item and cost registers, i.e. occupancy)
+  int lane = lane_id();
+  asm volatile("" : "+v"(lane));
   // ---- snap and validate (the loading lane snaps its own coordinate)
   const bool in_range = lane >= 24 || fabsf(coord) < kCoordLimit;
   const bool all_ok = __ballot(in_range) == ~0ull;
@@ -1471,7 +1475,7 @@ __global__ __launch_bounds__(256) void k_partial_items(PartialItems I, int n_par
 // device work queue until the list is exhausted.  Every wave leaves the loop
 // once the queue passes the end of the list.
 template <int ST>
-__global__ __launch_bounds__(256, 3) void k_eval_partial(ProblemView P, PartialItems I, Record* out,
+__global__ __launch_bounds__(256, 4) void k_eval_partial(ProblemView P, PartialItems I, Record* out,
                                                        int* queue, int chunk) {
   __shared__ WaveLds lds[4];
   const int wave = threadIdx.x >> 6;
