@@ -362,6 +362,7 @@ void drop_partial(morea_problem* p) {
   p->d_row_off = p->d_item_off = p->d_queue = nullptr;
   p->d_partial_records = nullptr;
   p->d_item_info = nullptr;
+  p->d_item_dest = p->d_grp_count = p->d_grp_base = p->d_eval_rank = nullptr;
 }
 
 }  // namespace
@@ -451,6 +452,12 @@ morea_status morea_reserve_partial(morea_problem* p, int32_t max_evals) {
   if (st == MOREA_OK)
     st = upload_to(p->partial_allocs, &p->d_item_info, nullptr,
                    sizeof(int4) * static_cast<size_t>(max_evals) * p->max_dep);
+  if (st == MOREA_OK)
+    st = upload_to(p->partial_allocs, &p->d_item_dest, nullptr,
+                   sizeof(int) * static_cast<size_t>(max_evals) * p->max_dep);
+  if (st == MOREA_OK) st = upload_to(p->partial_allocs, &p->d_grp_count, nullptr, sizeof(int) * p->n_groups);
+  if (st == MOREA_OK) st = upload_to(p->partial_allocs, &p->d_grp_base, nullptr, sizeof(int) * p->n_groups);
+  if (st == MOREA_OK) st = upload_to(p->partial_allocs, &p->d_eval_rank, nullptr, sizeof(int) * max_evals);
   if (st != MOREA_OK) {
     free_list(p->partial_allocs);
     return st;
@@ -505,6 +512,10 @@ static hipError_t partial_launch(morea_problem* p, const float* parent_pts, int3
   I.dep_tet = p->d_dep_tet;
   I.dep_local = p->d_dep_local;
   I.item_info = p->d_item_info;
+  I.item_dest = p->d_item_dest;
+  I.grp_count = p->d_grp_count;
+  I.grp_base = p->d_grp_base;
+  I.eval_rank = p->d_eval_rank;
   I.n_evals = n_evals;
   const Record* prec = static_cast<const Record*>(parent_cache);
   const Totals* ptot = reinterpret_cast<const Totals*>(

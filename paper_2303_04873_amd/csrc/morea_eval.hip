@@ -1408,28 +1408,31 @@ hipError_t launch_finalize(const ProblemView& P, const float* pts, int pop, cons
 namespace morea {
 
 // Prefix sums of the evaluation list (one block, fixed order): first
-// new-coordinate row of each evaluation and first work item (dependent tet).
+// new-coordinate row of each evaluation and first record (dependent tet).
 // An evaluation with an out-of-range group owns no new-coordinate rows; one
 // with an out-of-range parent or group gets no work items and is reported
-// invalid by the finalize kernel.  Also resets the work queue.
-__global__ __launch_bounds__(1024) void k_partial_prep(const int* eval_parent, const int* eval_group,
-                                                        int n_evals, int n_parents, int n_groups,
-                                                        const int* grp_off, const int* dep_off,
-                                                        int* row_off, int* item_off, int* queue) {
+// invalid by the finalize kernel.  Then the evaluations are bucketed by
+// group (rank within the group; the ranks' order does not affect any
+// result) and each group's first processing position is the prefix of
+// evaluations x dependent tets over the groups.  Also resets the work queue.
+__global__ __launch_bounds__(1024) void k_partial_prep(PartialItems I, int n_parents, int n_groups,
+                                                        int* queue) {
   __shared__ int s_rows[1024], s_items[1024];
   const int tid = threadIdx.x;
+  const int n_evals = I.n_evals;
   const int per = (n_evals + 1023) / 1024;
   const int b = tid * per, e_end = min(n_evals, b + per);
   int rows = 0, items = 0;
   for (int e = b; e < e_end; e++) {
-    const int g = eval_group[e], par = eval_parent[e];
+    const int g = I.eval_group[e], par = I.eval_parent[e];
     if (g >= 0 && g < n_groups) {
-      rows += grp_off[g + 1] - grp_off[g];
-      if (par >= 0 && par < n_parents) items += dep_off[g + 1] - dep_off[g];
+      rows += I.grp_off[g + 1] - I.grp_off[g];
+      if (par >= 0 && par < n_parents) items += I.dep_off[g + 1] - I.dep_off[g];
     }
   }
   s_rows[tid] = rows;
   s_items[tid] = items;
+  for (int g = tid; g < n_groups; g += 1024) I.grp_count[g] = 0;
   __syncthreads();
   for (int d = 1; d < 1024; d <<= 1) {
     int r = tid >= d ? s_rows[tid - d] : 0, it = tid >= d ? s_items[tid - d] : 0;
@@ -1440,24 +1443,52 @@ __global__ __launch_bounds__(1024) void k_partial_prep(const int* eval_parent, c
   }
   rows = s_rows[tid] - rows;
   items = s_items[tid] - items;
+  int* row_off = const_cast<int*>(I.row_off);
+  int* item_off = const_cast<int*>(I.item_off);
   for (int e = b; e < e_end; e++) {
     row_off[e] = rows;
     item_off[e] = items;
-    const int g = eval_group[e], par = eval_parent[e];
+    const int g = I.eval_group[e], par = I.eval_parent[e];
     if (g >= 0 && g < n_groups) {
-      rows += grp_off[g + 1] - grp_off[g];
-      if (par >= 0 && par < n_parents) items += dep_off[g + 1] - dep_off[g];
+      rows += I.grp_off[g + 1] - I.grp_off[g];
+      if (par >= 0 && par < n_parents) {
+        items += I.dep_off[g + 1] - I.dep_off[g];
+        I.eval_rank[e] = atomicAdd(&I.grp_count[g], 1);
+      }
     }
   }
   if (tid == 1023) item_off[n_evals] = s_items[1023];
   if (tid == 0) *queue = 0;
+  __threadfence();
+  __syncthreads();
+  // group bases: exclusive prefix of count x dependent tets, 1024 groups per pass
+  int carry = 0;
+  for (int g0 = 0; g0 < n_groups; g0 += 1024) {
+    const int g = g0 + tid;
+    int v = 0;
+    if (g < n_groups)
+      v = __hip_atomic_load(&I.grp_count[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) *
+          (I.dep_off[g + 1] - I.dep_off[g]);
+    s_items[tid] = v;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+      const int t = tid >= d ? s_items[tid - d] : 0;
+      __syncthreads();
+      s_items[tid] += t;
+      __syncthreads();
+    }
+    if (g < n_groups) I.grp_base[g] = carry + s_items[tid] - v;
+    carry += s_items[1023];
+    __syncthreads();
+  }
 }
 
-// Per-item records of the partial launch, one wave per evaluation (after the
-// prefix sums): for each of the evaluation's dependent tets, its slot in the
-// group's dependent-tet list, the tet, the parent and the evaluation's first
-// new-coordinate row.  Evaluations with an out-of-range parent or group own
-// no items (the prefix sums gave them none).
+// Per-item records of the partial launch, one wave per evaluation: for
+// dependent tet j of evaluation e (rank r in its group g of c evaluations)
+// the processing position is grp_base[g] + j c + r; the record there names
+// the dependent-tet slot, the tet, the parent and the evaluation's first
+// new-coordinate row, and its destination item_off[e] + j.  Evaluations with
+// an out-of-range parent or group own no items.
 __global__ __launch_bounds__(256) void k_partial_items(PartialItems I, int n_parents, int n_groups) {
   const int e = blockIdx.x * 4 + static_cast<int>(threadIdx.x >> 6);
   const int lane = lane_id();
@@ -1465,9 +1496,13 @@ __global__ __launch_bounds__(256) void k_partial_items(PartialItems I, int n_par
   const int g = I.eval_group[e], par = I.eval_parent[e];
   if (g < 0 || g >= n_groups || par < 0 || par >= n_parents) return;
   const int first = I.dep_off[g], n = I.dep_off[g + 1] - first;
-  const int base = I.item_off[e], row = I.row_off[e];
-  for (int j = lane; j < n; j += kWave)
-    I.item_info[base + j] = make_int4(first + j, I.dep_tet[first + j], par, row);
+  const int c = I.grp_count[g], pos0 = I.grp_base[g] + I.eval_rank[e];
+  const int dest0 = I.item_off[e], row = I.row_off[e];
+  for (int j = lane; j < n; j += kWave) {
+    const int pos = pos0 + j * c;
+    I.item_info[pos] = make_int4(first + j, I.dep_tet[first + j], par, row);
+    I.item_dest[pos] = dest0 + j;
+  }
 }
 
 // Persistent evaluation of all (evaluation, dependent tet) items, both
@@ -1503,7 +1538,8 @@ __global__ __launch_bounds__(256, 4) void k_eval_partial(ProblemView P, PartialI
           coord = I.parent_pts[((static_cast<size_t>(par) * 2 + mesh) * 3 + k) * P.n_points + v];
         }
       }
-      eval_tet<ST>(P, tet, coord, &lds[wave], &out[static_cast<size_t>(idx) * 2]);
+      const int dest = uniform_i(I.item_dest[idx]);
+      eval_tet<ST>(P, tet, coord, &lds[wave], &out[static_cast<size_t>(dest) * 2]);
     }
   }
 }
@@ -1615,9 +1651,7 @@ hipError_t launch_partial(const ProblemView& P, int storage, const PartialItems&
                           Record* new_rec, int* queue, int blocks, int chunk, float* obj,
                           uint8_t* flags, float* severity, uint32_t* counts, hipStream_t s) {
   if (I.n_evals == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_partial_prep, dim3(1), dim3(1024), 0, s, I.eval_parent, I.eval_group,
-                     I.n_evals, n_parents, n_groups, I.grp_off, I.dep_off,
-                     const_cast<int*>(I.row_off), const_cast<int*>(I.item_off), queue);
+  hipLaunchKernelGGL(k_partial_prep, dim3(1), dim3(1024), 0, s, I, n_parents, n_groups, queue);
   hipLaunchKernelGGL(k_partial_items, dim3((I.n_evals + 3) / 4), dim3(256), 0, s, I, n_parents, n_groups);
   switch (storage) {
     case kF32:

@@ -93,7 +93,14 @@ struct PartialItems {
   const int* dep_off;          // [n_groups + 1] CSR into dep_tet / dep_local
   const int* dep_tet;          // dependent tets per group
   const int8_t* dep_local;     // [.][4] position of each tet vertex in the group, -1 if none
-  int4* item_info;             // [items]: dependent-tet slot, tet, parent, first new-coordinate row
+  // items are processed group by group, dependent tet by dependent tet, the
+  // group's evaluations innermost (neighbouring waves share a tet's image
+  // region); a record still lands at item_off[e] + j
+  int4* item_info;             // [items] in processing order: dependent-tet slot, tet, parent, first row
+  int* item_dest;              // [items] in processing order: record index item_off[e] + j
+  int* grp_count;              // [n_groups] evaluations of each group
+  int* grp_base;               // [n_groups] first processing position of each group
+  int* eval_rank;              // [n_evals] rank of each evaluation within its group
   int n_evals;
 };
 
@@ -127,6 +134,10 @@ struct morea_problem {
   int* d_item_off = nullptr;
   morea::Record* d_partial_records = nullptr;  // [max_evals * max_dep][2]
   int4* d_item_info = nullptr;                 // [max_evals * max_dep]
+  int* d_item_dest = nullptr;                  // [max_evals * max_dep]
+  int* d_grp_count = nullptr;                  // [n_groups]
+  int* d_grp_base = nullptr;                   // [n_groups]
+  int* d_eval_rank = nullptr;                  // [max_evals]
   int* d_queue = nullptr;
   hipStream_t capture_stream = nullptr;
   // autotuned persistent launch shape
