@@ -404,20 +404,6 @@ __device__ __forceinline__ float hi16(uint32_t w) {
     return static_cast<float>(__builtin_bit_cast(_Float16, static_cast<unsigned short>(w >> 16)));
 }
 
-template <int ST>
-__device__ __forceinline__ float ld_soff(__amdgpu_buffer_rsrc_t r, int idx, int soff) {
-  constexpr unsigned esize = ST == kF32 ? 4 : 2;
-  if constexpr (ST == kF32) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, static_cast<unsigned>(idx) * esize, soff, 0));
-  } else {
-    const unsigned short u = __builtin_amdgcn_raw_buffer_load_b16(r, static_cast<unsigned>(idx) * esize, soff, 0);
-    if constexpr (ST == kBF16)
-      return __uint_as_float(static_cast<uint32_t>(u) << 16);
-    else
-      return static_cast<float>(__builtin_bit_cast(_Float16, u));
-  }
-}
-
 __device__ __forceinline__ double uniform_d(double v) {
   const uint64_t b = static_cast<uint64_t>(__double_as_longlong(v));
   const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(b));
@@ -436,17 +422,16 @@ struct SampleConst {
   int sy, sz;           // padded strides in bytes of the sampled image: row, slice
 };
 
-// One voxel sample of direction d: the centre at padded element vi, whose
-// mapped point (padded coordinates) is q = q_row + k * M[:, 0] (q_row of the
-// sample's row, k its offset in the row).  Samples the other image
-// trilinearly (zero outside the grid), adds h (Sec. 4.1.2) and, inside the
-// guidance band, the set-weighted guidance term (Sec. 4.1.3, App. A.3).
-// INNER: every trilinear corner of every mapped point lies in the padded
-// volume (q > 0 and q < n + 1 per axis), so no clamping is needed.
-// Returns true when the mapped point is within its error bound of a grid
-// plane on some axis: that sample's h is left to the exact path (a_out and
-// b_out carry what it needs).
-template <int ST, bool INNER>
+// One voxel sample of direction d whose mapped points may leave the padded
+// volume (a tet near or beyond the image border): the centre at padded
+// element vi, its mapped point (padded coordinates) q = q_row + k * M[:, 0]
+// (q_row of the sample's row, k its offset in the row).  Samples the other
+// image trilinearly (zero outside the grid, corners clamped for the distance
+// maps), adds h (Sec. 4.1.2) and, inside the guidance band, the set-weighted
+// guidance term (Sec. 4.1.3, App. A.3).  Returns true when the mapped point
+// is within its error bound of a grid plane on some axis: that sample's h is
+// left to the exact path (a_out and b_out carry what it needs).
+template <int ST>
 __device__ __forceinline__ bool sample_one(const ProblemView& P, const SampleConst& U,
                                            __amdgpu_buffer_rsrc_t r_own, __amdgpu_buffer_rsrc_t r_oth,
                                            __amdgpu_buffer_rsrc_t r_band, int d, int vi,
@@ -459,80 +444,42 @@ __device__ __forceinline__ bool sample_one(const ProblemView& P, const SampleCon
   int c[3];
 #pragma unroll
   for (int t = 0; t < 3; t++) {
-    if constexpr (INNER) {
-      // q > 0: truncation is the floor, and the fraction is exact
-      c[t] = static_cast<int>(q[t]);
-      f[t] = static_cast<float>(__builtin_amdgcn_fract(q[t]));
-    } else {
-      const double fl = floor(q[t]);
-      c[t] = static_cast<int>(fl);
-      f[t] = static_cast<float>(q[t] - fl);
-    }
+    const double fl = floor(q[t]);
+    c[t] = static_cast<int>(fl);
+    f[t] = static_cast<float>(q[t] - fl);
   }
   const bool amb = fabsf(f[0] - 0.5f) >= U.thr || fabsf(f[1] - 0.5f) >= U.thr || fabsf(f[2] - 0.5f) >= U.thr;
 
   // corner indices (padded elements): x pair ix0/ix1, row offsets ry0/ry1,
-  // slice offsets rz0/rz1
-  int ix0, ix1, ry0, ry1, rz0, rz1;
-  float v000, v001, v010, v011, v100, v101, v110, v111;
-  bool fg8;   // any of the 8 corners > 0 (the images are >= 0: any non-zero magnitude bit)
-  if constexpr (INNER) {
-    ix0 = c[0];
-    ix1 = c[0] + 1;
-    ry0 = __umul24(c[1], P.px);
-    ry1 = ry0 + P.px;
-    rz0 = __umul24(c[2], P.pxy);
-    rz1 = rz0 + P.pxy;
-    const int base = rz0 + ry0 + ix0;
-    if constexpr (ST == kF32) {
-      const F2 p00 = ld_pair(r_oth, base, 0), p01 = ld_pair(r_oth, base, U.sy);
-      const F2 p10 = ld_pair(r_oth, base, U.sz), p11 = ld_pair(r_oth, base, U.sy + U.sz);
-      v000 = p00.a; v001 = p00.b; v010 = p01.a; v011 = p01.b;
-      v100 = p10.a; v101 = p10.b; v110 = p11.a; v111 = p11.b;
-      const uint32_t ob = __float_as_uint(v000) | __float_as_uint(v001) | __float_as_uint(v010) |
-                          __float_as_uint(v011) | __float_as_uint(v100) | __float_as_uint(v101) |
-                          __float_as_uint(v110) | __float_as_uint(v111);
-      fg8 = (ob << 1) != 0u;
-    } else {
-      const uint32_t sh = static_cast<uint32_t>(base & 1) << 4;
-      const uint32_t w00 = ld_pair16(r_oth, base, 0, sh), w01 = ld_pair16(r_oth, base, U.sy, sh);
-      const uint32_t w10 = ld_pair16(r_oth, base, U.sz, sh), w11 = ld_pair16(r_oth, base, U.sy + U.sz, sh);
-      v000 = lo16<ST>(w00); v001 = hi16<ST>(w00); v010 = lo16<ST>(w01); v011 = hi16<ST>(w01);
-      v100 = lo16<ST>(w10); v101 = hi16<ST>(w10); v110 = lo16<ST>(w11); v111 = hi16<ST>(w11);
-      fg8 = ((w00 | w01 | w10 | w11) & 0x7fff7fffu) != 0u;
-    }
-  } else {
-    // padded index range per axis is [0, n + 1]; corners beyond it are
-    // outside the image (value 0) and clamp for the distance maps
-    const int n0 = P.nx + 1, n1 = P.ny + 1, n2 = P.nz + 1;
-    ix0 = min(max(c[0], 0), n0);
-    ix1 = min(max(c[0] + 1, 0), n0);
-    const int cy0 = min(max(c[1], 0), n1), cy1 = min(max(c[1] + 1, 0), n1);
-    const int cz0 = min(max(c[2], 0), n2), cz1 = min(max(c[2] + 1, 0), n2);
-    ry0 = __umul24(cy0, P.px);
-    ry1 = __umul24(cy1, P.px);
-    rz0 = __umul24(cz0, P.pxy);
-    rz1 = __umul24(cz1, P.pxy);
-    const bool vx0 = c[0] >= 0 && c[0] <= n0, vx1 = c[0] >= -1 && c[0] < n0;
-    const bool vy0 = c[1] >= 0 && c[1] <= n1, vy1 = c[1] >= -1 && c[1] < n1;
-    const bool vz0 = c[2] >= 0 && c[2] <= n2, vz1 = c[2] >= -1 && c[2] < n2;
-    v000 = ld_buf<ST>(r_oth, rz0 + ry0 + ix0); v001 = ld_buf<ST>(r_oth, rz0 + ry0 + ix1);
-    v010 = ld_buf<ST>(r_oth, rz0 + ry1 + ix0); v011 = ld_buf<ST>(r_oth, rz0 + ry1 + ix1);
-    v100 = ld_buf<ST>(r_oth, rz1 + ry0 + ix0); v101 = ld_buf<ST>(r_oth, rz1 + ry0 + ix1);
-    v110 = ld_buf<ST>(r_oth, rz1 + ry1 + ix0); v111 = ld_buf<ST>(r_oth, rz1 + ry1 + ix1);
-    v000 = (vz0 && vy0 && vx0) ? v000 : 0.f;
-    v001 = (vz0 && vy0 && vx1) ? v001 : 0.f;
-    v010 = (vz0 && vy1 && vx0) ? v010 : 0.f;
-    v011 = (vz0 && vy1 && vx1) ? v011 : 0.f;
-    v100 = (vz1 && vy0 && vx0) ? v100 : 0.f;
-    v101 = (vz1 && vy0 && vx1) ? v101 : 0.f;
-    v110 = (vz1 && vy1 && vx0) ? v110 : 0.f;
-    v111 = (vz1 && vy1 && vx1) ? v111 : 0.f;
-    const uint32_t ob = __float_as_uint(v000) | __float_as_uint(v001) | __float_as_uint(v010) |
-                        __float_as_uint(v011) | __float_as_uint(v100) | __float_as_uint(v101) |
-                        __float_as_uint(v110) | __float_as_uint(v111);
-    fg8 = (ob << 1) != 0u;
-  }
+  // slice offsets rz0/rz1.  The padded index range per axis is [0, n + 1];
+  // corners beyond it are outside the image (value 0) and clamp for the
+  // distance maps
+  const int n0 = P.nx + 1, n1 = P.ny + 1, n2 = P.nz + 1;
+  const int ix0 = min(max(c[0], 0), n0), ix1 = min(max(c[0] + 1, 0), n0);
+  const int cy0 = min(max(c[1], 0), n1), cy1 = min(max(c[1] + 1, 0), n1);
+  const int cz0 = min(max(c[2], 0), n2), cz1 = min(max(c[2] + 1, 0), n2);
+  const int ry0 = __umul24(cy0, P.px), ry1 = __umul24(cy1, P.px);
+  const int rz0 = __umul24(cz0, P.pxy), rz1 = __umul24(cz1, P.pxy);
+  const bool vx0 = c[0] >= 0 && c[0] <= n0, vx1 = c[0] >= -1 && c[0] < n0;
+  const bool vy0 = c[1] >= 0 && c[1] <= n1, vy1 = c[1] >= -1 && c[1] < n1;
+  const bool vz0 = c[2] >= 0 && c[2] <= n2, vz1 = c[2] >= -1 && c[2] < n2;
+  float v000 = ld_buf<ST>(r_oth, rz0 + ry0 + ix0), v001 = ld_buf<ST>(r_oth, rz0 + ry0 + ix1);
+  float v010 = ld_buf<ST>(r_oth, rz0 + ry1 + ix0), v011 = ld_buf<ST>(r_oth, rz0 + ry1 + ix1);
+  float v100 = ld_buf<ST>(r_oth, rz1 + ry0 + ix0), v101 = ld_buf<ST>(r_oth, rz1 + ry0 + ix1);
+  float v110 = ld_buf<ST>(r_oth, rz1 + ry1 + ix0), v111 = ld_buf<ST>(r_oth, rz1 + ry1 + ix1);
+  v000 = (vz0 && vy0 && vx0) ? v000 : 0.f;
+  v001 = (vz0 && vy0 && vx1) ? v001 : 0.f;
+  v010 = (vz0 && vy1 && vx0) ? v010 : 0.f;
+  v011 = (vz0 && vy1 && vx1) ? v011 : 0.f;
+  v100 = (vz1 && vy0 && vx0) ? v100 : 0.f;
+  v101 = (vz1 && vy0 && vx1) ? v101 : 0.f;
+  v110 = (vz1 && vy1 && vx0) ? v110 : 0.f;
+  v111 = (vz1 && vy1 && vx1) ? v111 : 0.f;
+  // any corner > 0 (the images are >= 0: any non-zero magnitude bit)
+  const uint32_t ob = __float_as_uint(v000) | __float_as_uint(v001) | __float_as_uint(v010) |
+                      __float_as_uint(v011) | __float_as_uint(v100) | __float_as_uint(v101) |
+                      __float_as_uint(v110) | __float_as_uint(v111);
+  const bool fg8 = (ob << 1) != 0u;
   const float e00 = fmaf(f[0], v001 - v000, v000), e01 = fmaf(f[0], v011 - v010, v010);
   const float e10 = fmaf(f[0], v101 - v100, v100), e11 = fmaf(f[0], v111 - v110, v110);
   const float e0 = fmaf(f[1], e01 - e00, e00), e1 = fmaf(f[1], e11 - e10, e10);
@@ -1012,15 +959,13 @@ __device__ void eval_tet(const ProblemView& P, int tet, float coord, WaveLds* L,
     // the direction; `cons` units are consumed, `tab_end` appended.
     int head = 0, n_tab = 0, cons = 0, tab_end = 0;
 
-    // one sample of the current batch; a near-grid one joins the deferred queue
+    // one sample of the current batch for directions whose mapped points may
+    // leave the padded volume; a near-grid one joins the deferred queue
     auto sample = [&](bool valid, int vi, const double qr[3], int k, int jbase) {
       bool amb = false;
       float a = 0.f, b = 0.f;
       if (valid) {
-        if (inner)
-          amb = sample_one<ST, true>(P, U, r_own, r_oth, r_band, d, vi + k, qr, k, h, g, a, b);
-        else
-          amb = sample_one<ST, false>(P, U, r_own, r_oth, r_band, d, vi + k, qr, k, h, g, a, b);
+        amb = sample_one<ST>(P, U, r_own, r_oth, r_band, d, vi + k, qr, k, h, g, a, b);
         n += 1;
       }
       const uint64_t amb_mask = __ballot(amb);
