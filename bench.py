@@ -184,7 +184,7 @@ def form_surrogate(full_evals_per_s, steps):
     tr = torch.from_numpy(train).cuda()
     cache = prob.new_cache(len(train))
     prob.eval_full(tr, cache=cache)
-    X = sur.features(tr).reshape(-1, 20).contiguous()
+    X = sur.features(tr).reshape(-1, sur.n_features).contiguous()
     t = sur.targets(cache, len(train)).reshape(-1).contiguous()
     n = t.numel()
     torch.cuda.synchronize()

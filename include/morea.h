@@ -200,35 +200,41 @@ morea_status morea_partial_shape(const morea_problem *p, int32_t *blocks, int32_
 
 /* ------------------------------------------------------------------------
  * Learned pre-screen of offspring.  A per-tetrahedron multilayer perceptron
- * 20 -> 128 -> 128 -> 1 (ReLU) predicts each tet's mean intensity term, the
+ * 23 -> 128 -> 128 -> 1 (ReLU) predicts each tet's mean intensity term, the
  * sum of h (Sec. 4.1.2) over the tet's samples in both directions divided by
  * their number.  Inputs per (candidate, tet): the deformation of the tet's 4
- * target-mesh vertices, (T_v - ref_v) / 4 voxels (12 values), and 8
- * statistics of the tet's region in the reference mesh (mean, std and
- * foreground fraction of I_s and of I_t over its voxels, their mean squared
- * difference, its voxel count over the mean count).  A candidate's score is
+ * target-mesh vertices, (T_v - ref_v) / 4 voxels (12 values); 8 statistics
+ * of the tet's region in the reference mesh (mean, std and foreground
+ * fraction of I_s and of I_t over its voxels, their mean squared difference,
+ * its voxel count over the mean count); and 3 samples of I_t around the
+ * deformed tet: at the centroid c of its 4 target-mesh vertices, the mean
+ * over those 4 vertices, and max - min over the 5 points (each sample the
+ * trilinear interpolant at the point clamped into [0, n - 1] per axis, in
+ * the cell below it capped at n - 2).  A candidate's score is
  * the voxel-count-weighted mean of its tets' predictions (a predicted
  * f_intensity); the best-scoring offspring are then evaluated exactly.  Dense
  * layers run on the matrix cores with BF16 operands and FP32 accumulation;
  * master weights, gradients and Adam state are FP32.  The surrogate is an
  * addition of this library; the paper has no counterpart.  Parameters are
- * one FP32 vector: W1 [128][20], b1 [128], W2 [128][128], b2 [128],
- * w3 [128], b3 [1] (19,329 values).
+ * one FP32 vector: W1 [128][23], b1 [128], W2 [128][128], b2 [128],
+ * w3 [128], b3 [1] (19,713 values).
  * All array arguments are device pointers unless named host_*; calls with a
  * stream are asynchronous on it. */
 typedef struct morea_surrogate morea_surrogate;
 
-int32_t morea_surrogate_num_params(void);
+int32_t morea_surrogate_num_params(void);     /* 19,713 */
+int32_t morea_surrogate_num_features(void);   /* 23 inputs per row */
 
 /* Create a surrogate for problem p (which must outlive it): He-normal
  * weights from `seed`, zero Adam state, the per-tet statistics of the
- * reference mesh, and a training workspace for batches of up to max_rows
- * rows.  Synchronous.  Errors: MOREA_EINVAL, MOREA_ENOMEM, MOREA_EDEVICE. */
+ * reference mesh, a padded FP32 copy of I_t (whatever the problem's image
+ * storage), and a training workspace for batches of up to max_rows rows.
+ * Synchronous.  Errors: MOREA_EINVAL, MOREA_ENOMEM, MOREA_EDEVICE. */
 morea_status morea_surrogate_create(morea_problem *p, int32_t max_rows, uint64_t seed,
                                     morea_surrogate **out);
 void morea_surrogate_destroy(morea_surrogate *s);
 
-/* Input rows of every (candidate, tet): feats [pop][n_tets][20] FP32. */
+/* Input rows of every (candidate, tet): feats [pop][n_tets][23] FP32. */
 morea_status morea_surrogate_features(morea_surrogate *s, const float *pts, int32_t pop,
                                       float *feats, void *stream);
 
@@ -244,7 +250,7 @@ morea_status morea_surrogate_train_step(morea_surrogate *s, const float *feats,
                                         const float *targets, int32_t n_rows, float lr,
                                         float *loss_out, void *stream);
 
-/* Gradient of that loss without an update: grads [19,329] FP32 (device). */
+/* Gradient of that loss without an update: grads [19,713] FP32 (device). */
 morea_status morea_surrogate_gradients(morea_surrogate *s, const float *feats,
                                        const float *targets, int32_t n_rows, float *grads,
                                        float *loss_out, void *stream);
@@ -265,7 +271,7 @@ morea_status morea_surrogate_select(const float *score, int32_t n, int32_t k, co
                                     int32_t n_points, int32_t *idx_out, float *selected_pts,
                                     void *stream);
 
-/* Copy the FP32 parameter vector out / in (host arrays of 19,329 floats;
+/* Copy the FP32 parameter vector out / in (host arrays of 19,713 floats;
  * checkpoints).  Synchronous. */
 morea_status morea_surrogate_get_params(morea_surrogate *s, float *host_params);
 morea_status morea_surrogate_set_params(morea_surrogate *s, const float *host_params);

@@ -1,22 +1,22 @@
 """FP64 reference of the surrogate MLP (test infrastructure).
 
 The surrogate that pre-screens offspring is a per-tetrahedron multilayer
-perceptron 20 -> 128 -> 128 -> 1 with ReLU activations and mean squared
+perceptron 23 -> 128 -> 128 -> 1 with ReLU activations and mean squared
 error loss.  This module evaluates it and its exact gradient with plain NumPy
 in FP64 so that the GPU kernels' forward pass and backward pass can be
 checked against it.  The surrogate is this build's own addition (no
 counterpart in the paper), so there is no passage of the paper to cite; the
 mathematics is the textbook chain rule for a dense network.
 
-Parameter order (a flat vector of 19,329 values), shared with the library's
+Parameter order (a flat vector of 19,713 values), shared with the library's
 parameter buffer:
-    W1 [128][20], b1 [128], W2 [128][128], b2 [128], w3 [128], b3 [1]
+    W1 [128][23], b1 [128], W2 [128][128], b2 [128], w3 [128], b3 [1]
 where layer k computes h_k = relu(W_k h_{k-1} + b_k) and the output is
 y = w3 . h_2 + b3.
 """
 import numpy as np
 
-N_IN, N_HID = 20, 128
+N_IN, N_HID = 23, 128
 SHAPES = [("W1", (N_HID, N_IN)), ("b1", (N_HID,)), ("W2", (N_HID, N_HID)), ("b2", (N_HID,)),
           ("w3", (N_HID,)), ("b3", (1,))]
 N_PARAMS = sum(int(np.prod(s)) for _, s in SHAPES)
@@ -37,7 +37,7 @@ def pack(p):
 
 
 def forward(theta, X):
-    """Predictions y [n] for inputs X [n][20], and the activations."""
+    """Predictions y [n] for inputs X [n][23], and the activations."""
     p = unpack(theta)
     X = np.asarray(X, np.float64)
     z1 = X @ p["W1"].T + p["b1"]

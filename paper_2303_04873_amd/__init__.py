@@ -23,8 +23,9 @@ STORE = {"f32": 0, "bf16": 1, "f16": 2}
 EXPORTS = ["morea_problem_create", "morea_problem_destroy", "morea_cache_bytes", "morea_eval_full",
            "morea_set_groups", "morea_reserve_partial", "morea_eval_partial",
            "morea_debug_distance_map", "morea_tune_partial", "morea_partial_shape",
-           "morea_surrogate_num_params", "morea_surrogate_create", "morea_surrogate_destroy",
-           "morea_surrogate_features", "morea_surrogate_targets", "morea_surrogate_train_step",
+           "morea_surrogate_num_params", "morea_surrogate_num_features", "morea_surrogate_create",
+           "morea_surrogate_destroy", "morea_surrogate_features", "morea_surrogate_targets",
+           "morea_surrogate_train_step",
            "morea_surrogate_gradients", "morea_surrogate_predict_rows", "morea_surrogate_prescreen",
            "morea_surrogate_select", "morea_surrogate_get_params", "morea_surrogate_set_params",
            "morea_surrogate_stats", "morea_last_error"]
@@ -83,6 +84,8 @@ def load_library():
     L.morea_debug_distance_map.restype = I32
     L.morea_surrogate_num_params.argtypes = []
     L.morea_surrogate_num_params.restype = I32
+    L.morea_surrogate_num_features.argtypes = []
+    L.morea_surrogate_num_features.restype = I32
     L.morea_surrogate_create.argtypes = [P, I32, ctypes.c_uint64, ctypes.POINTER(P)]
     L.morea_surrogate_create.restype = I32
     L.morea_surrogate_destroy.argtypes = [P]
@@ -320,6 +323,7 @@ class Surrogate:
     def __init__(self, problem: "Problem", max_rows: int = 1 << 16, seed: int = 0):
         self.problem = problem
         self.n_params = load_library().morea_surrogate_num_params()
+        self.n_features = load_library().morea_surrogate_num_features()
         h = ctypes.c_void_p()
         _check(load_library().morea_surrogate_create(problem.handle, int(max_rows), int(seed),
                                                      ctypes.byref(h)))
@@ -339,7 +343,8 @@ class Surrogate:
 
     def features(self, pts, stream=None):
         import torch
-        out = torch.empty((pts.shape[0], self.problem.n_tets, 20), dtype=torch.float32, device="cuda")
+        out = torch.empty((pts.shape[0], self.problem.n_tets, self.n_features), dtype=torch.float32,
+                          device="cuda")
         _check(load_library().morea_surrogate_features(self.handle, _dev_ptr(pts), pts.shape[0],
                                                        _dev_ptr(out), _stream_ptr(stream)))
         return out
@@ -368,7 +373,7 @@ class Surrogate:
 
     def predict_rows(self, feats, stream=None):
         import torch
-        n = feats.numel() // 20
+        n = feats.numel() // self.n_features
         y = torch.empty(n, dtype=torch.float32, device="cuda")
         _check(load_library().morea_surrogate_predict_rows(self.handle, _dev_ptr(feats), n, _dev_ptr(y),
                                                            _stream_ptr(stream)))

@@ -1,5 +1,5 @@
 // Learned pre-screen of offspring: a per-tetrahedron multilayer perceptron
-// 20 -> 128 -> 128 -> 1 (ReLU) that predicts each tet's mean intensity term
+// 23 -> 128 -> 128 -> 1 (ReLU) that predicts each tet's mean intensity term
 // (the sum of h over the tet's samples in both directions divided by their
 // number, Sec. 4.1.2), trained on records produced by the exact evaluator and
 // used to rank a batch of offspring before only the best are evaluated
@@ -25,9 +25,9 @@
 namespace morea {
 namespace surr {
 
-constexpr int kIn = 20, kInPad = 24, kHid = 128;
+constexpr int kIn = 23, kInPad = 24, kHid = 128;
 constexpr int oW1 = 0, oB1 = oW1 + kHid * kIn, oW2 = oB1 + kHid, oB2 = oW2 + kHid * kHid,
-              oW3 = oB2 + kHid, oB3 = oW3 + kHid, kParams = oB3 + 1;   // 19,329
+              oW3 = oB2 + kHid, oB3 = oW3 + kHid, kParams = oB3 + 1;   // 19,713
 constexpr int kRowTile = 32;
 constexpr int kWavePart = 3 * kHid + 2;   // per-wave partials: dw3, db2, db1, db3, loss
 constexpr int kSplitK = 16;
@@ -138,33 +138,102 @@ __device__ void tile_forward(const NetLds* N, TileLds* T, RedTile& red, f16v z2[
 // Features of (candidate, tet): the deformation of the tet's 4 target-mesh
 // vertices, (T_v - ref_v) / 4 voxels (12 values: the deformed vertex
 // coordinates relative to the reference mesh, at a scale where a fraction of
-// a voxel stays well resolved in BF16), then the tet's 8 source-region
-// statistics.  Lane half kh = 0 writes the deformation, kh = 1 the
-// statistics.
+// a voxel stays well resolved in BF16), the tet's 8 source-region
+// statistics, then 3 samples of the target image around the deformed tet:
+// I_t at the centroid c of the 4 deformed vertices, the mean of I_t over the
+// 4 deformed vertices, and max - min of I_t over those 5 points.  Each sample
+// is the trilinear interpolant at the point clamped into the image box, so
+// all three are continuous in the vertex positions.
 constexpr float kDispScale = 0.25f;
+constexpr int kImgFeat = 20;   // index of the first image feature
 
+// Trilinear I_t at (x, y, z) clamped into [0, n - 1] on each axis, from the
+// padded FP32 copy `img` (voxel (i, j, k) at (k + 1) pxy + (j + 1) px + i + 1).
+// The cell is the one below the point, capped at n - 2, so the upper corner
+// always lies in the volume or, for an axis of size 1, on its zero border
+// with weight 0.
+__device__ __forceinline__ float it_clamped(const ProblemView& P, const float* img, float x, float y, float z) {
+  const float q[3] = {fminf(fmaxf(x, 0.f), static_cast<float>(P.nx - 1)),
+                      fminf(fmaxf(y, 0.f), static_cast<float>(P.ny - 1)),
+                      fminf(fmaxf(z, 0.f), static_cast<float>(P.nz - 1))};
+  const int n[3] = {P.nx, P.ny, P.nz};
+  int c[3];
+  float f[3];
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    c[a] = max(min(static_cast<int>(floorf(q[a])), n[a] - 2), 0);
+    f[a] = q[a] - static_cast<float>(c[a]);
+  }
+  const float* b = img + static_cast<size_t>(c[2] + 1) * P.pxy + static_cast<size_t>(c[1] + 1) * P.px + c[0] + 1;
+  const float* b1 = b + P.pxy;
+  const float x00 = fmaf(f[0], b[1] - b[0], b[0]), x10 = fmaf(f[0], b[P.px + 1] - b[P.px], b[P.px]);
+  const float x01 = fmaf(f[0], b1[1] - b1[0], b1[0]), x11 = fmaf(f[0], b1[P.px + 1] - b1[P.px], b1[P.px]);
+  const float y0 = fmaf(f[1], x10 - x00, x00), y1 = fmaf(f[1], x11 - x01, x01);
+  return fmaf(f[2], y1 - y0, y0);
+}
+
+// The deformed vertices' target-mesh coordinates d[v][a] of a tet.
+__device__ __forceinline__ void deformed_vertices(const ProblemView& P, const float* cand, int tet, float d[4][3]) {
+  const int4 tv = P.tets[tet];
+  const int vs[4] = {tv.x, tv.y, tv.z, tv.w};
+#pragma unroll
+  for (int v = 0; v < 4; v++)
+#pragma unroll
+    for (int a = 0; a < 3; a++) d[v][a] = cand[(3 + a) * P.n_points + vs[v]];
+}
+
+__device__ __forceinline__ void centroid(const float d[4][3], float c[3]) {
+#pragma unroll
+  for (int a = 0; a < 3; a++) c[a] = ((d[0][a] + d[1][a]) + (d[2][a] + d[3][a])) * 0.25f;
+}
+
+// Row features 0..11 (kh = 0), 12..19 (kh = 1) or 20..22 (kh = 2) into out.
 __device__ __forceinline__ void row_features(const ProblemView& P, const float* cand, const float* ref,
-                                             int tet, const float* stats, int kh, float* out) {
+                                             const float* img, int tet, const float* stats, int kh, float* out) {
+  const int4 tv = P.tets[tet];
+  const int vs[4] = {tv.x, tv.y, tv.z, tv.w};
   if (kh == 0) {
-    const int4 tv = P.tets[tet];
-    const int vs[4] = {tv.x, tv.y, tv.z, tv.w};
 #pragma unroll
     for (int v = 0; v < 4; v++)
 #pragma unroll
       for (int a = 0; a < 3; a++)
         out[3 * v + a] = (cand[(3 + a) * P.n_points + vs[v]] - ref[3 * vs[v] + a]) * kDispScale;
-  } else {
+  } else if (kh == 1) {
 #pragma unroll
     for (int f = 0; f < 8; f++) out[f] = stats[8 * tet + f];
+  } else {
+    float d[4][3], c[3];
+    deformed_vertices(P, cand, tet, d);
+    centroid(d, c);
+    const float ic = it_clamped(P, img, c[0], c[1], c[2]);
+    float sum = 0.f, mn = ic, mx = ic;
+#pragma unroll
+    for (int v = 0; v < 4; v++) {
+      const float iv = it_clamped(P, img, d[v][0], d[v][1], d[v][2]);
+      sum += iv;
+      mn = fminf(mn, iv);
+      mx = fmaxf(mx, iv);
+    }
+    out[0] = ic;
+    out[1] = sum * 0.25f;
+    out[2] = mx - mn;
   }
 }
 
-// Source-region statistics of each tet of the reference mesh: voxel count,
-// mean / std / foreground fraction of I_s and of I_t over the voxel centres
-// inside the tet, and the mean squared difference.  Containment uses the
-// snapped coordinates and the same tie rule as the evaluator (a centre on a
-// face belongs to the tet holding p + (e, e^2, e^3)), so the counts of a
-// fold-free mesh tile the grid.  One wave per tet.
+// Padded FP32 copy of the target image (any storage), read by the features.
+template <int ST>
+__global__ void k_target_f32(ProblemView P, float* out) {
+  const size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= P.pvox) return;
+  if constexpr (ST == kF32) {
+    out[i] = static_cast<const float*>(P.img[1])[i];
+  } else if constexpr (ST == kBF16) {
+    out[i] = bf2f(static_cast<const bf16*>(P.img[1])[i]);
+  } else {
+    out[i] = static_cast<float>(static_cast<const _Float16*>(P.img[1])[i]);
+  }
+}
+
 template <int ST>
 __global__ void k_tet_stats(ProblemView P, const float* ref, float* stats, int* counts, float inv_mean) {
   const int tet = blockIdx.x;
@@ -262,19 +331,21 @@ __global__ void k_tet_stats(ProblemView P, const float* ref, float* stats, int* 
   }
 }
 
-__global__ void k_features(ProblemView P, const float* pts, const float* ref, int pop, const float* stats,
-                           float* feats) {
+__global__ void k_features(ProblemView P, const float* pts, const float* ref, const float* img, int pop,
+                           const float* stats, float* feats) {
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = lane_id();
-  if (row >= pop * P.n_tets || lane >= 2) return;
+  if (row >= pop * P.n_tets || lane >= 3) return;
   const int cand = row / P.n_tets, tet = row % P.n_tets;
   float f[12];
-  row_features(P, pts + static_cast<size_t>(cand) * 6 * P.n_points, ref, tet, stats, lane, f);
+  row_features(P, pts + static_cast<size_t>(cand) * 6 * P.n_points, ref, img, tet, stats, lane, f);
   float* o = feats + static_cast<size_t>(row) * kIn;
   if (lane == 0)
     for (int k = 0; k < 12; k++) o[k] = f[k];
-  else
+  else if (lane == 1)
     for (int k = 0; k < 8; k++) o[12 + k] = f[k];
+  else
+    for (int k = 0; k < 3; k++) o[kImgFeat + k] = f[k];
 }
 
 // Per-tet target: mean h per sample over both directions, from a cache.
@@ -298,12 +369,12 @@ __global__ void k_targets(const Record* rec, int rows, float* t) {
 // order  slot kk of lane half h -> unit 4 h + kk (kk < 4), 8 + 4 h + kk - 4
 // (kk >= 4)  within the slice; W2's columns are stored in that order, so no
 // activation passes through LDS.  Layer 1's bias rides on constant features
-// (features 20..22 = 1, W1 columns 20..22 = b1 split into three BF16 terms
+// (features 23..25 = 1, W1 columns 23..25 = b1 split into three BF16 terms
 // that sum to it in the FP32 accumulator); layer 2's accumulators start at b2.
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef unsigned u4v __attribute__((ext_vector_type(4)));
 
-constexpr int kPreIn = 32;                 // features padded: 20 + three constant 1s + zeros
+constexpr int kPreIn = 32;                 // features padded: 23 + three constant 1s + zeros
 constexpr int kW1Row = kPreIn + 8;         // LDS row strides padded against bank conflicts
 constexpr int kW2Row = kHid + 8;
 
@@ -335,8 +406,8 @@ __device__ __forceinline__ bf8 pack8(const float v[8]) {
 // counts.  Blocks of 4 waves loop over candidates; each wave takes tiles of
 // 32 tets; fixed-order reductions.
 __global__ __launch_bounds__(256, 3) void k_prescreen(ProblemView P, const float* pts, const float* ref,
-                                                    const float* stats, const int* counts, const float* params,
-                                                    int pop, float* score) {
+                                                    const float* img, const float* stats, const int* counts,
+                                                    const float* params, int pop, float* score) {
   __shared__ PreLds N;
   __shared__ float wsum[4], wcnt[4];
   for (int e = threadIdx.x; e < kHid * kPreIn; e += blockDim.x) {
@@ -370,30 +441,58 @@ __global__ __launch_bounds__(256, 3) void k_prescreen(ProblemView P, const float
     for (int tile = wave; tile < n_tiles; tile += 4) {
       const int tet = tile * kRowTile + i;
       // this lane's half of the tet's features (natural order: 12 deformation
-      // values, 8 statistics, three constant 1s, zeros)
+      // values, 8 statistics, 3 image samples, three constant 1s, zeros);
+      // the 5 image samples are split over the halves (h = 0: centroid and
+      // vertices 0, 1; h = 1: vertices 2, 3) and combined across them
       float f0[8], f1[8];
 #pragma unroll
       for (int k = 0; k < 8; k++) f0[k] = f1[k] = 0.f;
+      float ic = 0.f, isum = 0.f, imn = 0.f, imx = 0.f;
       if (tet < P.n_tets) {
         const int4 tv = P.tets[tet];
         const int vs[4] = {tv.x, tv.y, tv.z, tv.w};
+        float d[4][3];
+        deformed_vertices(P, cp, tet, d);
         if (h == 0) {   // features 0..7, 16..23
 #pragma unroll
           for (int k = 0; k < 8; k++) {
-            const int v = vs[k / 3], a = k % 3;
-            f0[k] = (cp[(3 + a) * P.n_points + v] - ref[3 * v + a]) * kDispScale;
+            const int v = k / 3, a = k % 3;
+            f0[k] = (d[v][a] - ref[3 * vs[v] + a]) * kDispScale;
           }
 #pragma unroll
           for (int k = 0; k < 4; k++) f1[k] = stats[8 * tet + 4 + k];
-          f1[4] = f1[5] = f1[6] = 1.f;   // the three terms of b1
+          f1[7] = 1.f;   // the first term of b1
+          float c[3];
+          centroid(d, c);
+          ic = it_clamped(P, img, c[0], c[1], c[2]);
+          const float i0 = it_clamped(P, img, d[0][0], d[0][1], d[0][2]);
+          const float i1 = it_clamped(P, img, d[1][0], d[1][1], d[1][2]);
+          isum = i0 + i1;
+          imn = fminf(ic, fminf(i0, i1));
+          imx = fmaxf(ic, fmaxf(i0, i1));
         } else {        // features 8..15, 24..31
 #pragma unroll
           for (int k = 0; k < 4; k++) {
-            const int fk = 8 + k, v = vs[fk / 3], a = fk % 3;
-            f0[k] = (cp[(3 + a) * P.n_points + v] - ref[3 * v + a]) * kDispScale;
+            const int fk = 8 + k, v = fk / 3, a = fk % 3;
+            f0[k] = (d[v][a] - ref[3 * vs[v] + a]) * kDispScale;
           }
 #pragma unroll
           for (int k = 0; k < 4; k++) f0[4 + k] = stats[8 * tet + k];
+          f1[0] = f1[1] = 1.f;   // the other two terms of b1
+          const float i2 = it_clamped(P, img, d[2][0], d[2][1], d[2][2]);
+          const float i3 = it_clamped(P, img, d[3][0], d[3][1], d[3][2]);
+          isum = i2 + i3;
+          imn = fminf(i2, i3);
+          imx = fmaxf(i2, i3);
+        }
+      }
+      {
+        const float osum = __shfl_xor(isum, 32, 64), omn = __shfl_xor(imn, 32, 64),
+                    omx = __shfl_xor(imx, 32, 64);
+        if (h == 0) {
+          f1[4] = ic;
+          f1[5] = (isum + osum) * 0.25f;
+          f1[6] = fmaxf(imx, omx) - fminf(imn, omn);
         }
       }
       const bf8 xb0 = pack8(f0), xb1 = pack8(f1);
@@ -736,6 +835,7 @@ struct morea_surrogate {
   float* stats = nullptr;
   int* counts = nullptr;
   float* ref = nullptr;
+  float* img_t = nullptr;   // padded FP32 copy of the target image
   TrainBuf tb{};
   int steps = 0;
   std::vector<void*> allocs;
@@ -780,6 +880,17 @@ hipError_t launch_stats(morea_surrogate* s, const float* ref_dev) {
   return hipGetLastError();
 }
 
+hipError_t launch_target_copy(morea_surrogate* s) {
+  const ProblemView& P = s->p->view;
+  const dim3 grid((P.pvox + 255) / 256);
+  switch (s->p->storage) {
+    case kF32: hipLaunchKernelGGL(k_target_f32<kF32>, grid, dim3(256), 0, 0, P, s->img_t); break;
+    case kBF16: hipLaunchKernelGGL(k_target_f32<kBF16>, grid, dim3(256), 0, 0, P, s->img_t); break;
+    default: hipLaunchKernelGGL(k_target_f32<kF16>, grid, dim3(256), 0, 0, P, s->img_t); break;
+  }
+  return hipGetLastError();
+}
+
 morea_status train_launch(morea_surrogate* s, const float* X, const float* t, int n, float lr,
                           float* grad_out, float* loss_out, hipStream_t st) {
   if (!s || !X || !t) return sfail(MOREA_EINVAL, "NULL argument");
@@ -806,6 +917,7 @@ morea_status train_launch(morea_surrogate* s, const float* X, const float* t, in
 extern "C" {
 
 int32_t morea_surrogate_num_params(void) { return kParams; }
+int32_t morea_surrogate_num_features(void) { return kIn; }
 
 morea_status morea_surrogate_create(morea_problem* p, int32_t max_rows, uint64_t seed,
                                     morea_surrogate** out) {
@@ -835,6 +947,7 @@ morea_status morea_surrogate_create(morea_problem* p, int32_t max_rows, uint64_t
   ok(salloc(s, &s->tb.wpart, sizeof(float) * kWavePart * static_cast<size_t>(bmax / kRowTile + 4)));
   ok(salloc(s, &s->tb.gpart, sizeof(float) * kSplitK * kGradTiles * 1024));
   ok(salloc(s, &s->ref, sizeof(float) * 3 * p->view.n_points));
+  ok(salloc(s, &s->img_t, sizeof(float) * static_cast<size_t>(p->view.pvox)));
   float* ref_dev = s->ref;
   if (st == MOREA_OK) {
     // He-normal initial weights, zero biases, from the given seed
@@ -854,6 +967,7 @@ morea_status morea_surrogate_create(morea_problem* p, int32_t max_rows, uint64_t
     hipLaunchKernelGGL(k_refresh_bf16, dim3((kHid * kHid + 255) / 256), dim3(256), 0, 0, s->params, s->w1b, s->w2b);
     ok(sdev(hipGetLastError(), "refresh"));
     ok(sdev(launch_stats(s, ref_dev), "tet statistics"));
+    ok(sdev(launch_target_copy(s), "target image copy"));
     ok(sdev(hipDeviceSynchronize(), "surrogate set-up"));
   }
   if (st != MOREA_OK) {
@@ -879,7 +993,7 @@ morea_status morea_surrogate_features(morea_surrogate* s, const float* pts, int3
   if (rows == 0) return MOREA_OK;
   if (rows > (1LL << 31) / 4) return sfail(MOREA_ERANGE, "too many rows");
   hipLaunchKernelGGL(k_features, dim3(static_cast<unsigned>((rows + 3) / 4)), dim3(256), 0,
-                     static_cast<hipStream_t>(stream), s->p->view, pts, s->ref, pop, s->stats, feats);
+                     static_cast<hipStream_t>(stream), s->p->view, pts, s->ref, s->img_t, pop, s->stats, feats);
   return sdev(hipGetLastError(), "features");
 }
 
@@ -920,7 +1034,7 @@ morea_status morea_surrogate_prescreen(morea_surrogate* s, const float* pts, int
   if (pop == 0) return MOREA_OK;
   const int blocks = std::min<int>(pop, 1024);
   hipLaunchKernelGGL(k_prescreen, dim3(blocks), dim3(256), 0, static_cast<hipStream_t>(stream), s->p->view,
-                     pts, s->ref, s->stats, s->counts, s->params, pop, score);
+                     pts, s->ref, s->img_t, s->stats, s->counts, s->params, pop, score);
   return sdev(hipGetLastError(), "prescreen");
 }
 

@@ -7,6 +7,7 @@ import pytest
 
 import synth
 from conftest import synth_problem
+import oracle
 from oracle import mlp
 
 pytestmark = pytest.mark.gpu
@@ -46,7 +47,7 @@ def test_forward_matches_reference(c1_surrogate):
     theta = random_theta(1)
     s.set_params(theta)
     rs = np.random.default_rng(2)
-    X = rs.normal(0, 1, (1000, 20)).astype(np.float32)        # 1000: ragged last tile
+    X = rs.normal(0, 1, (1000, mlp.N_IN)).astype(np.float32)        # 1000: ragged last tile
     y = s.predict_rows(torch.from_numpy(X).cuda()).cpu().numpy()
     ref = mixed_forward(theta, X.astype(np.float64))
     assert np.max(np.abs(y - ref)) <= 1e-3 * (np.std(ref) + 1e-3)
@@ -59,7 +60,7 @@ def test_gradients_match_oracle(c1_surrogate):
     theta = random_theta(4)
     s.set_params(theta)
     rs = np.random.default_rng(5)
-    X = rs.normal(0, 1, (777, 20)).astype(np.float32)
+    X = rs.normal(0, 1, (777, mlp.N_IN)).astype(np.float32)
     t = rs.normal(0, 1, 777).astype(np.float32)
     g, loss = s.gradients(torch.from_numpy(X).cuda(), torch.from_numpy(t).cuda())
     g = g.cpu().numpy().astype(np.float64)
@@ -87,7 +88,7 @@ def test_training_reduces_loss(c1_surrogate):
     pop = torch.from_numpy(synth.make_population(p)).cuda()
     cache = prob.new_cache(16)
     prob.eval_full(pop, cache=cache)
-    X = s.features(pop).reshape(-1, 20).contiguous()
+    X = s.features(pop).reshape(-1, s.n_features).contiguous()
     t = s.targets(cache, 16).reshape(-1).contiguous()
     loss = torch.empty(1, device="cuda")
     losses = []
@@ -100,13 +101,34 @@ def test_training_reduces_loss(c1_surrogate):
 
 def test_features_and_stats(c1_surrogate):
     p, prob, s = c1_surrogate
+    assert s.n_features == mlp.N_IN == 23
     pop = synth.make_population(p)
     F = s.features(torch.from_numpy(pop).cuda()).cpu().numpy()
     st, cnt = s.stats()
     T = pop[:, 1].transpose(0, 2, 1)                      # [pop][P][3]
-    coords = (T[:, p.tets] - p.ref_points[p.tets]) * 0.25  # [pop][tets][4][3]
+    verts = T[:, p.tets]                                  # [pop][tets][4][3] float32
+    coords = (verts - p.ref_points[p.tets]) * 0.25
     np.testing.assert_allclose(F[..., :12], coords.reshape(len(pop), -1, 12), rtol=1e-6, atol=1e-6)
-    np.testing.assert_array_equal(F[..., 12:], np.broadcast_to(st, F[..., 12:].shape))
+    np.testing.assert_array_equal(F[..., 12:20], np.broadcast_to(st, F[..., 12:20].shape))
+    # image samples: the oracle's edge-replicating trilinear is the
+    # interpolant at the point clamped into the box
+    c = ((verts[:, :, 0] + verts[:, :, 1]) + (verts[:, :, 2] + verts[:, :, 3])) * np.float32(0.25)
+    img = p.image_tgt
+    want = np.empty((len(pop), p.n_tets, 3))
+    for k in range(len(pop)):
+        for j in range(p.n_tets):
+            ic = oracle.trilinear(img, c[k, j], clamp=True)
+            iv = [oracle.trilinear(img, verts[k, j, v], clamp=True) for v in range(4)]
+            want[k, j] = [ic, np.mean(iv), max(iv + [ic]) - min(iv + [ic])]
+    scale = float(np.abs(img).max())
+    np.testing.assert_allclose(F[..., 20:], want, rtol=1e-5, atol=1e-5 * scale)
+    # a tet pushed outside the box samples the clamped edge value
+    out = pop[:1].copy()
+    out[0, 1] += np.float32(3.0 * max(p.dims))
+    Fo = s.features(torch.from_numpy(out).cuda()).cpu().numpy()[0]
+    corner = float(img[-1, -1, -1])
+    np.testing.assert_allclose(Fo[:, 20:22], corner, rtol=1e-6, atol=1e-6 * scale)
+    np.testing.assert_allclose(Fo[:, 22], 0.0, atol=1e-6 * scale)
     V = int(np.prod(p.dims))
     assert cnt.sum() == V            # the reference mesh tiles the grid exactly
     assert np.all((st[:, 2] >= 0) & (st[:, 2] <= 1))
@@ -128,7 +150,7 @@ def test_prescreen_equals_weighted_row_predictions(c1_surrogate):
     s.set_params(random_theta(9, scale=0.5))
     pop = torch.from_numpy(synth.make_population(p)).cuda()
     score = s.prescreen(pop).cpu().numpy()
-    y = s.predict_rows(s.features(pop).reshape(-1, 20).contiguous()).cpu().numpy().reshape(16, -1)
+    y = s.predict_rows(s.features(pop).reshape(-1, s.n_features).contiguous()).cpu().numpy().reshape(16, -1)
     _, cnt = s.stats()
     want = (y * cnt).sum(axis=1) / cnt.sum()
     np.testing.assert_allclose(score, want, rtol=1e-4, atol=1e-6)
@@ -152,7 +174,7 @@ def test_surrogate_gain_config5():
     tr = torch.from_numpy(train).cuda()
     cache = prob.new_cache(len(train))
     prob.eval_full(tr, cache=cache)
-    X = s.features(tr).reshape(-1, 20).contiguous()
+    X = s.features(tr).reshape(-1, s.n_features).contiguous()
     t = s.targets(cache, len(train)).reshape(-1).contiguous()
     n = t.numel()
     assert n > 1_000_000

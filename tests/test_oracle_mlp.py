@@ -7,7 +7,7 @@ from oracle import mlp
 
 
 def test_param_count():
-    assert mlp.N_PARAMS == 19329
+    assert mlp.N_PARAMS == 19713
 
 
 def test_gradient_matches_finite_differences():
@@ -17,7 +17,7 @@ def test_gradient_matches_finite_differences():
     t = rs.normal(0, 1, 37)
     g = mlp.gradient(theta, X, t)
     idx = rs.choice(mlp.N_PARAMS, 60, replace=False)
-    idx = np.concatenate([idx, [mlp.N_PARAMS - 1, 0, 20 * 128 + 5]])   # b3, W1[0,0], b1[5]
+    idx = np.concatenate([idx, [mlp.N_PARAMS - 1, 0, mlp.N_IN * mlp.N_HID + 5]])   # b3, W1[0,0], b1[5]
     eps = 1e-6
     for i in idx:
         tp, tm = theta.copy(), theta.copy()
