@@ -24,11 +24,13 @@ LIB = os.path.join(HERE, "libmorea_oracle.so")
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc -O2 -fopenmp (no fast-math)."""
+    """Compile the oracle with gcc -O2 -fopenmp (no fast-math, no contraction
+    of a * b + c into one rounding: the Sobol sample points are formed with
+    explicit fmaf only)."""
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
         tmp = LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall",
-                               "-o", tmp, SRC, "-lm"])
+                               "-ffp-contract=off", "-o", tmp, SRC, "-lm"])
         os.replace(tmp, LIB)
     return LIB
 
@@ -59,6 +61,15 @@ def lib():
         L.oracle_orient.restype = ctypes.c_double
         L.oracle_threads.argtypes = []
         L.oracle_threads.restype = ctypes.c_int
+        L.oracle_eval_sobol.argtypes = [P, P, ctypes.c_int, ctypes.c_double, ctypes.c_uint64, P, P, P, P, P]
+        L.oracle_eval_sobol.restype = ctypes.c_int
+        L.oracle_sobol_coord.argtypes = [ctypes.c_int, ctypes.c_uint32]
+        L.oracle_sobol_coord.restype = ctypes.c_uint32
+        L.oracle_neg_ln_f32.argtypes = [ctypes.c_float]
+        L.oracle_neg_ln_f32.restype = ctypes.c_float
+        L.oracle_sobol_points.argtypes = [P, P, ctypes.c_int, ctypes.c_uint64, ctypes.c_double, P, P,
+                                          ctypes.c_int64]
+        L.oracle_sobol_points.restype = ctypes.c_int64
         _lib = L
     return _lib
 
@@ -153,6 +164,27 @@ class Problem:
             out["records"] = rec
         return out
 
+    def evaluate_sobol(self, pts, rate=1.0, seed=0, records=False):
+        """The same outputs from the Sobol-sampled estimator (App. A.2):
+        round(rate * volume) random barycentric points per tet and direction,
+        the sequence seeded from ``seed`` and the tet's coordinates; counts
+        are the numbers of points."""
+        pts = np.ascontiguousarray(pts, dtype=np.float32)
+        pop = pts.shape[0]
+        assert pts.shape[1:] == (2, 3, self.n_points), pts.shape
+        obj = np.empty((pop, 3), np.float64)
+        flags = np.empty(pop, np.uint8)
+        sev = np.empty(pop, np.float64)
+        counts = np.empty((pop, 2), np.int64)
+        rec = np.empty((pop, self.n_tets, 2, 5), np.float64) if records else None
+        if lib().oracle_eval_sobol(ctypes.byref(self._c), _ptr(pts), pop, float(rate), int(seed), _ptr(obj),
+                                   _ptr(flags), _ptr(sev), _ptr(counts), _ptr(rec)) != 0:
+            raise ValueError("rate must be > 0")
+        out = dict(obj=obj, flags=flags, severity=sev, counts=counts)
+        if records:
+            out["records"] = rec
+        return out
+
 
 def tet_voxels(verts, dims) -> np.ndarray:
     """Flat indices of the voxel centres inside one tet (tie rule applied)."""
@@ -202,6 +234,32 @@ def quantize(img, storage: str) -> np.ndarray:
         rounded = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
         return (rounded.astype(np.uint32) << 16).view(np.float32)
     raise ValueError(storage)
+
+
+def sobol_coord(j: int, n: int) -> int:
+    """Coordinate j (0..3) of point n of the unshifted 4-D Sobol sequence, as
+    a 32-bit integer (natural order)."""
+    return int(lib().oracle_sobol_coord(int(j), int(n)))
+
+
+def neg_ln_f32(r: float) -> float:
+    """-ln(r) as the Sobol estimator computes it in FP32."""
+    return float(lib().oracle_neg_ln_f32(float(r)))
+
+
+def sobol_points(own, oth, direction=0, seed=0, rate=1.0, cap=1 << 20):
+    """Sample points of one tet: p [N][3] in ``own``, q [N][3] in ``oth``
+    (vertices float32 [4][3])."""
+    a = np.ascontiguousarray(own, dtype=np.float32).reshape(12)
+    b = np.ascontiguousarray(oth, dtype=np.float32).reshape(12)
+    p = np.empty((cap, 3), np.float32)
+    q = np.empty((cap, 3), np.float32)
+    n = lib().oracle_sobol_points(_ptr(a), _ptr(b), int(direction), int(seed), float(rate), _ptr(p), _ptr(q),
+                                  int(cap))
+    if n < 0:
+        raise ValueError("rate must be > 0")
+    m = min(n, cap)
+    return p[:m].copy(), q[:m].copy(), int(n)
 
 
 def threads() -> int:

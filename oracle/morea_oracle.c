@@ -36,6 +36,10 @@
  *     FP32 distance map, and set weights are |C|/|G| as printed;
  *   - spokes join the centroid to each vertex; a zero volume is a fold;
  *   - magnitude is in voxel units (isotropic voxels).
+ *
+ * oracle_eval_sobol evaluates the same objectives from the paper's own
+ * estimator, random barycentric samples from a seeded Sobol sequence
+ * (App. A.2); its readings are listed where it is defined below.
  */
 #include <math.h>
 #include <omp.h>
@@ -280,6 +284,214 @@ static void eval_direction(const oracle_problem *P, const int64_t own[4][3], con
       }
 }
 
+/* ------------------------------------------- Sobol-sampled estimator
+ *
+ * App. A.2: each tet is sampled at N points drawn uniformly through its
+ * barycentric coordinates, N set by the tet's volume; each point takes four
+ * numbers r_j in (0, 1], e_j = -log(r_j), lambda_j = e_j / sum(e), from a
+ * Sobol sequence seeded from the tet's coordinates.  Sec. 4.1.2 and 4.1.3
+ * then give h and the guidance term at each point, as for the rasterized
+ * samples.  Readings where the paper leaves the construction open:
+ *   - N = floor(rate * |V| + 1/2), |V| the exact volume in voxel^3, at most
+ *     2^20 per tet and direction (rate = 1 in the paper's configuration);
+ *   - the 4-dimensional Sobol sequence in natural order (point n XORs the
+ *     direction numbers of the set bits of n), 32-bit direction numbers from
+ *     the primitive polynomials 1 (van der Corput), x + 1, x^2 + x + 1 and
+ *     x^3 + x + 1 with initial numbers (1), (1, 3), (1, 3, 1) -- the first
+ *     four dimensions of Joe and Kuo's table -- randomised by a digital
+ *     shift: XOR with four 32-bit words of a SplitMix64 hash of a global
+ *     seed, the direction and the tet's 12 snapped coordinates;
+ *   - r_j = (2 floor(u_j / 2^9) + 1) 2^-24, exact in FP32;
+ *   - the point is p = v_0 + sum_{i=1..3} lambda_i (v_i - v_0) in the
+ *     sampled tet and q = w_0 + sum_{i=1..3} lambda_i (w_i - w_0) in the
+ *     other one.  Which corners support a value depends on the bits of p and
+ *     q, so they are formed in FP32 in the order written here (the GPU forms
+ *     the same bits), with -log from the atanh series below;
+ *   - both values are trilinear with zero padding and the exact-support
+ *     foreground rule; the guidance band test d < r uses the interpolated own
+ *     distance; both distance maps are read edge-clamped. */
+
+#define SOBOL_MAX_N ((int64_t)1 << 20)
+#define SM_GAMMA 0x9e3779b97f4a7c15ULL
+
+static uint32_t sobol_dir[4][32];
+static int sobol_dir_ready = 0;
+
+static void sobol_init(void) {
+  if (sobol_dir_ready) return;
+  const int degree[4] = {0, 1, 2, 3};
+  const uint32_t inner[4] = {0, 0, 1, 1};        /* a_1 .. a_{s-1}, a_1 the high bit */
+  const uint64_t m_first[4][3] = {{1, 0, 0}, {1, 0, 0}, {1, 3, 0}, {1, 3, 1}};
+  for (int b = 0; b < 32; b++) sobol_dir[0][b] = 1u << (31 - b);
+  for (int j = 1; j < 4; j++) {
+    const int s = degree[j];
+    uint64_t m[33];
+    for (int k = 1; k <= s; k++) m[k] = m_first[j][k - 1];
+    for (int k = s + 1; k <= 32; k++) {
+      /* m_k = 2 a_1 m_{k-1} ^ ... ^ 2^{s-1} a_{s-1} m_{k-s+1} ^ 2^s m_{k-s} ^ m_{k-s} */
+      uint64_t v = m[k - s] ^ (m[k - s] << s);
+      for (int i = 1; i < s; i++)
+        if ((inner[j] >> (s - 1 - i)) & 1u) v ^= m[k - i] << i;
+      m[k] = v;
+    }
+    for (int k = 1; k <= 32; k++) sobol_dir[j][k - 1] = (uint32_t)(m[k] << (32 - k));
+  }
+  sobol_dir_ready = 1;
+}
+
+static uint32_t sobol_coord(int j, uint32_t n) {
+  uint32_t x = 0;
+  for (int b = 0; n != 0; b++, n >>= 1)
+    if (n & 1u) x ^= sobol_dir[j][b];
+  return x;
+}
+
+static uint64_t splitmix_mix(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+  return z ^ (z >> 31);
+}
+
+/* -ln(r), r in (0, 1], in FP32: r = m 2^k with m in [sqrt(1/2), sqrt(2)],
+ * ln m = 2 atanh(s), s = (m - 1) / (m + 1), by the series s + s^3/3 + ... +
+ * s^11/11 (|s| <= 0.172: truncation below 2e-11). */
+static float neg_ln_f32(float r) {
+  uint32_t bits;
+  memcpy(&bits, &r, sizeof(bits));
+  int k = (int)(bits >> 23) - 127;
+  const uint32_t mbits = (bits & 0x7fffffu) | 0x3f800000u;
+  float m;
+  memcpy(&m, &mbits, sizeof(m));
+  if (m > 0x1.6a09e6p+0f) {
+    m = m * 0.5f;
+    k += 1;
+  }
+  const float s = (m - 1.0f) / (m + 1.0f);
+  const float t = s * s;
+  float poly = fmaf(t, 0x1.745d18p-4f, 0x1.c71c72p-4f);   /* 1/11, 1/9 */
+  poly = fmaf(t, poly, 0x1.24924ap-3f);                   /* 1/7 */
+  poly = fmaf(t, poly, 0x1.99999ap-3f);                   /* 1/5 */
+  poly = fmaf(t, poly, 0x1.555556p-2f);                   /* 1/3 */
+  poly = fmaf(t, poly, 1.0f);
+  const float ln_m = (s + s) * poly;
+  return -fmaf((float)k, 0x1.62e430p-1f, ln_m);           /* ln 2 */
+}
+
+/* Sample count of a tet (|D| = 6 |V| 2^30) at the given rate. */
+static int64_t sobol_count(i128 absD, double rate) {
+  const double scale = rate / 6442450944.0;   /* rate / (6 * 2^30) */
+  const double x = floor((double)absD * scale + 0.5);
+  if (!(x > 0.0)) return 0;
+  return x >= (double)SOBOL_MAX_N ? SOBOL_MAX_N : (int64_t)x;
+}
+
+/* The four shift words of a tet's sequence. */
+static void sobol_shift(const int64_t own[4][3], int dir, uint64_t seed, uint32_t shift[4]) {
+  uint64_t h = splitmix_mix(seed + SM_GAMMA * (uint64_t)(dir + 1));
+  for (int i = 0; i < 4; i++)
+    for (int k = 0; k < 3; k++) h = splitmix_mix(h + SM_GAMMA + (uint64_t)(uint32_t)(int32_t)own[i][k]);
+  const uint64_t w0 = splitmix_mix(h + SM_GAMMA), w1 = splitmix_mix(h + 2 * SM_GAMMA);
+  shift[0] = (uint32_t)w0;
+  shift[1] = (uint32_t)(w0 >> 32);
+  shift[2] = (uint32_t)w1;
+  shift[3] = (uint32_t)(w1 >> 32);
+}
+
+/* Point n of a tet's sequence: p in the sampled tet, q in the other. */
+static void sobol_point(uint32_t n, const uint32_t shift[4], const float base_own[3],
+                        const float edge_own[3][3], const float base_oth[3], const float edge_oth[3][3],
+                        float p[3], float q[3]) {
+  float e[4];
+  for (int j = 0; j < 4; j++) {
+    const uint32_t u = sobol_coord(j, n) ^ shift[j];
+    const float r = (float)(2u * (u >> 9) + 1u) * 0x1p-24f;
+    e[j] = neg_ln_f32(r);
+  }
+  const float sum = ((e[0] + e[1]) + e[2]) + e[3];
+  const float l1 = e[1] / sum, l2 = e[2] / sum, l3 = e[3] / sum;
+  for (int a = 0; a < 3; a++) {
+    p[a] = fmaf(l3, edge_own[2][a], fmaf(l2, edge_own[1][a], fmaf(l1, edge_own[0][a], base_own[a])));
+    q[a] = fmaf(l3, edge_oth[2][a], fmaf(l2, edge_oth[1][a], fmaf(l1, edge_oth[0][a], base_oth[a])));
+  }
+}
+
+/* FP32 base vertex and edge vectors of a snapped tet, in voxels (exact). */
+static void tet_f32(const int64_t v[4][3], float base[3], float edge[3][3]) {
+  for (int a = 0; a < 3; a++) {
+    base[a] = (float)v[0][a] * 0x1p-10f;
+    for (int i = 0; i < 3; i++) edge[i][a] = (float)(v[i + 1][a] - v[0][a]) * 0x1p-10f;
+  }
+}
+
+/* Cell and fractions of an FP32 point: k = floor(x), f = x - k (exact). */
+static void cell_of(const float x[3], int64_t k[3], double f[3]) {
+  for (int a = 0; a < 3; a++) {
+    const double xd = (double)x[a];
+    const double fl = floor(xd);
+    k[a] = (int64_t)fl;
+    f[a] = xd - fl;
+  }
+}
+
+/* Foreground by the exact support: a corner with positive weight (the lower
+ * corner always, the upper one where f > 0) holding a value > 0. */
+static int support_foreground(const float *img, int nx, int ny, int nz, const int64_t k[3],
+                              const double f[3]) {
+  for (int cz = 0; cz < 2; cz++)
+    for (int cy = 0; cy < 2; cy++)
+      for (int cx = 0; cx < 2; cx++) {
+        if ((cx && !(f[0] > 0.0)) || (cy && !(f[1] > 0.0)) || (cz && !(f[2] > 0.0))) continue;
+        if (fetch_zero(img, nx, ny, nz, k[0] + cx, k[1] + cy, k[2] + cz) > 0.0) return 1;
+      }
+  return 0;
+}
+
+static void eval_direction_sobol(const oracle_problem *P, const int64_t own[4][3], const int64_t oth[4][3],
+                                 int ref_sign, int dir, const double *set_w, double rate, uint64_t seed,
+                                 dir_record *rec) {
+  const float *img_own = dir == 0 ? P->img_s : P->img_t;
+  const float *img_oth = dir == 0 ? P->img_t : P->img_s;
+  const float *map_own = dir == 0 ? P->dmap_s : P->dmap_t;
+  const float *map_oth = dir == 0 ? P->dmap_t : P->dmap_s;
+  const size_t V = (size_t)P->nx * P->ny * P->nz;
+  memset(rec, 0, sizeof(*rec));
+  const i128 D = orient(own);
+  rec->viol = (sgn128(D) == 0) || (sgn128(D) != ref_sign);
+  const i128 absD = D < 0 ? -D : D;
+  rec->vol = (double)absD / 6.0 / (double)((int64_t)1 << (3 * FRAC_BITS));
+  const int64_t N = D == 0 ? 0 : sobol_count(absD, rate);
+  rec->n = N;
+  if (N == 0) return;
+  uint32_t shift[4];
+  sobol_shift(own, dir, seed, shift);
+  float bo[3], eo[3][3], bt[3], et[3][3];
+  tet_f32(own, bo, eo);
+  tet_f32(oth, bt, et);
+  const double radius = (double)P->radius;
+  for (int64_t n = 0; n < N; n++) {
+    float p[3], q[3];
+    sobol_point((uint32_t)n, shift, bo, eo, bt, et, p, q);
+    int64_t kp[3], kq[3];
+    double fp[3], fq[3];
+    cell_of(p, kp, fp);
+    cell_of(q, kq, fq);
+    const int fa = support_foreground(img_own, P->nx, P->ny, P->nz, kp, fp);
+    const int fb = support_foreground(img_oth, P->nx, P->ny, P->nz, kq, fq);
+    const double a = fa ? trilinear(img_own, P->nx, P->ny, P->nz, kp, fp, 0) : 0.0;
+    const double b = fb ? trilinear(img_oth, P->nx, P->ny, P->nz, kq, fq, 0) : 0.0;
+    /* h of Sec. 4.1.2: squared difference inside both foregrounds, 0 in
+     * both backgrounds, 1 across */
+    rec->h += (fa && fb) ? (a - b) * (a - b) : (fa == fb ? 0.0 : 1.0);
+    for (int s = 0; s < P->n_sets; s++) {
+      const double d_own = trilinear(map_own + (size_t)s * V, P->nx, P->ny, P->nz, kp, fp, 1);
+      if (d_own >= radius) continue;
+      const double d_oth = trilinear(map_oth + (size_t)s * V, P->nx, P->ny, P->nz, kq, fq, 1);
+      const double diff = d_own - d_oth;
+      rec->g += set_w[s] * (radius - d_own) / radius * diff * diff;
+    }
+  }
+}
+
 static double edge_len(const int64_t a[3], const int64_t b[3], double scale) {
   double s = 0.0;
   for (int k = 0; k < 3; k++) {
@@ -326,8 +538,13 @@ static int candidate_valid(const float *cand, int n_points) {
 
 /* Records per (candidate, tet, direction): h, g, n, magnitude (direction 0
  * only), violation volume (0 when no violation). */
-int oracle_eval(const oracle_problem *P, const float *pts, int pop, double *obj, uint8_t *flags,
-                double *severity, int64_t *counts, double *tet_rec) {
+typedef struct {
+  double rate;
+  uint64_t seed;
+} sobol_cfg;
+
+static int eval_all(const oracle_problem *P, const float *pts, int pop, const sobol_cfg *sc, double *obj,
+                    uint8_t *flags, double *severity, int64_t *counts, double *tet_rec) {
   const int NP = P->n_points, NT = P->n_tets;
   int *ref = (int *)malloc(sizeof(int) * (NT > 0 ? NT : 1));
   for (int t = 0; t < NT; t++) {
@@ -365,8 +582,13 @@ int oracle_eval(const oracle_problem *P, const float *pts, int pop, double *obj,
         T[i][k] = snap(cand[(1 * 3 + k) * NP + v]);
       }
     }
-    eval_direction(P, S, T, ref[t], 0, w_s, &recs[2 * it + 0]);
-    eval_direction(P, T, S, ref[t], 1, w_t, &recs[2 * it + 1]);
+    if (sc) {
+      eval_direction_sobol(P, S, T, ref[t], 0, w_s, sc->rate, sc->seed, &recs[2 * it + 0]);
+      eval_direction_sobol(P, T, S, ref[t], 1, w_t, sc->rate, sc->seed, &recs[2 * it + 1]);
+    } else {
+      eval_direction(P, S, T, ref[t], 0, w_s, &recs[2 * it + 0]);
+      eval_direction(P, T, S, ref[t], 1, w_t, &recs[2 * it + 1]);
+    }
     mags[it] = tet_magnitude(S, T, (double)P->elasticity[t]);
   }
 
@@ -417,6 +639,21 @@ int oracle_eval(const oracle_problem *P, const float *pts, int pop, double *obj,
   free(mags);
   free(valid);
   return 0;
+}
+
+int oracle_eval(const oracle_problem *P, const float *pts, int pop, double *obj, uint8_t *flags,
+                double *severity, int64_t *counts, double *tet_rec) {
+  return eval_all(P, pts, pop, NULL, obj, flags, severity, counts, tet_rec);
+}
+
+/* The same objectives from the Sobol-sampled estimator (counts are the
+ * numbers of sample points). */
+int oracle_eval_sobol(const oracle_problem *P, const float *pts, int pop, double rate, uint64_t seed,
+                      double *obj, uint8_t *flags, double *severity, int64_t *counts, double *tet_rec) {
+  if (!(rate > 0.0)) return -1;
+  sobol_init();
+  const sobol_cfg sc = {rate, seed};
+  return eval_all(P, pts, pop, &sc, obj, flags, severity, counts, tet_rec);
 }
 
 /* ------------------------------------------------- probes used by the pins */
@@ -501,3 +738,35 @@ double oracle_orient(const float v[12]) {
 /* Number of threads the OpenMP loops above run with (reported beside the
  * oracle's timings). */
 int oracle_threads(void) { return omp_get_max_threads(); }
+
+/* Coordinate j of point n of the unshifted Sobol sequence (natural order). */
+uint32_t oracle_sobol_coord(int j, uint32_t n) {
+  sobol_init();
+  return sobol_coord(j, n);
+}
+
+float oracle_neg_ln_f32(float r) { return neg_ln_f32(r); }
+
+/* The sample points p (in the sampled tet own) and q (in oth) of one tet and
+ * direction: writes min(N, cap) points and returns N (-1 on a bad rate). */
+int64_t oracle_sobol_points(const float own_f[12], const float oth_f[12], int dir, uint64_t seed, double rate,
+                            float *p_out, float *q_out, int64_t cap) {
+  if (!(rate > 0.0)) return -1;
+  sobol_init();
+  int64_t own[4][3], oth[4][3];
+  for (int i = 0; i < 4; i++)
+    for (int k = 0; k < 3; k++) {
+      own[i][k] = snap(own_f[3 * i + k]);
+      oth[i][k] = snap(oth_f[3 * i + k]);
+    }
+  const i128 D = orient(own);
+  const int64_t N = D == 0 ? 0 : sobol_count(D < 0 ? -D : D, rate);
+  uint32_t shift[4];
+  sobol_shift(own, dir, seed, shift);
+  float bo[3], eo[3][3], bt[3], et[3][3];
+  tet_f32(own, bo, eo);
+  tet_f32(oth, bt, et);
+  for (int64_t n = 0; n < N && n < cap; n++)
+    sobol_point((uint32_t)n, shift, bo, eo, bt, et, p_out + 3 * n, q_out + 3 * n);
+  return N;
+}

@@ -9,6 +9,8 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "morea_oracle.c")
+PINS = os.path.join(ROOT, "tests", "test_oracle_pins.py")
+SOBOL = os.path.join(ROOT, "tests", "test_oracle_sobol.py")
 
 MUTATIONS = [
     ("directions swapped in the target->source pass",
@@ -44,20 +46,47 @@ MUTATIONS = [
      "              : fetch_clamp(img, nx, ny, nz, k[0] + dx, k[1] + dy, k[2] + dz);"),
     ("guidance band with <= instead of <",
      "if (!(d < r)) continue;", "if (!(d <= r + 0.5)) continue;"),
+    # the Sobol-sampled estimator, against its own pins
+    ("Sobol: barycentric coordinates not normalised by the sum",
+     "const float l1 = e[1] / sum, l2 = e[2] / sum, l3 = e[3] / sum;",
+     "const float l1 = e[1] / (sum + e[0]), l2 = e[2] / (sum + e[0]), l3 = e[3] / (sum + e[0]);", SOBOL),
+    ("Sobol: mapped point built from the sampled tet's edges",
+     "q[a] = fmaf(l3, edge_oth[2][a], fmaf(l2, edge_oth[1][a], fmaf(l1, edge_oth[0][a], base_oth[a])));",
+     "q[a] = fmaf(l3, edge_own[2][a], fmaf(l2, edge_own[1][a], fmaf(l1, edge_own[0][a], base_oth[a])));", SOBOL),
+    ("Sobol: wrong ln 2 in -log",
+     "return -fmaf((float)k, 0x1.62e430p-1f, ln_m);", "return -fmaf((float)k, 0x1.6p-1f, ln_m);", SOBOL),
+    ("Sobol: series of atanh cut after s^3",
+     "poly = fmaf(t, poly, 0x1.99999ap-3f);", "poly = 0x1.99999ap-3f;", SOBOL),
+    ("Sobol: guidance without the (r - d) / r weight",
+     "rec->g += set_w[s] * (radius - d_own) / radius * diff * diff;",
+     "rec->g += set_w[s] * diff * diff;", SOBOL),
+    ("Sobol: sample count truncated instead of rounded",
+     "const double x = floor((double)absD * scale + 0.5);", "const double x = floor((double)absD * scale);",
+     SOBOL),
+    ("Sobol: no digital shift",
+     "const uint32_t u = sobol_coord(j, n) ^ shift[j];", "const uint32_t u = sobol_coord(j, n);", SOBOL),
+    ("Sobol: wrong primitive polynomial for the fourth dimension",
+     "const uint32_t inner[4] = {0, 0, 1, 1};", "const uint32_t inner[4] = {0, 0, 1, 0};", SOBOL),
+    ("Sobol: foreground/background mismatch costs 0.5",
+     "(fa == fb ? 0.0 : 1.0)", "(fa == fb ? 0.0 : 0.5)", SOBOL),
+    ("Sobol: own image read at the mapped point",
+     "const double a = fa ? trilinear(img_own, P->nx, P->ny, P->nz, kp, fp, 0) : 0.0;",
+     "const double a = fa ? trilinear(img_own, P->nx, P->ny, P->nz, kq, fq, 0) : 0.0;", SOBOL),
 ]
 
 
-@pytest.mark.parametrize("name,old,new", MUTATIONS, ids=[m[0] for m in MUTATIONS])
-def test_planted_mistake_is_caught(name, old, new, tmp_path):
+@pytest.mark.parametrize("name,old,new,pins", [m if len(m) == 4 else m + (PINS,) for m in MUTATIONS],
+                         ids=[m[0] for m in MUTATIONS])
+def test_planted_mistake_is_caught(name, old, new, pins, tmp_path):
     src = open(SRC).read()
     assert src.count(old) == 1, name
     mutant = tmp_path / "mutant.c"
     mutant.write_text(src.replace(old, new))
     lib = tmp_path / "libmutant.so"
-    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-o", str(lib),
-                           str(mutant), "-lm"])
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
+                           "-o", str(lib), str(mutant), "-lm"])
     env = dict(os.environ, MOREA_ORACLE_LIB=str(lib), OMP_NUM_THREADS="4")
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                        pins],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"no pin caught: {name}\n{r.stdout[-2000:]}"
