@@ -456,7 +456,7 @@ static void eval_direction_sobol(const oracle_problem *P, const int64_t own[4][3
   const size_t V = (size_t)P->nx * P->ny * P->nz;
   memset(rec, 0, sizeof(*rec));
   const i128 D = orient(own);
-  rec->viol = (sgn128(D) == 0) || (sgn128(D) != ref_sign);
+  rec->viol = sgn128(D) == 0 || sgn128(D) != ref_sign;   /* App. A.4, as for the voxel samples */
   const i128 absD = D < 0 ? -D : D;
   rec->vol = (double)absD / 6.0 / (double)((int64_t)1 << (3 * FRAC_BITS));
   const int64_t N = D == 0 ? 0 : sobol_count(absD, rate);
