@@ -126,6 +126,29 @@ morea_status morea_eval_full(morea_problem *p, const float *pts, int32_t pop, fl
                              uint8_t *flags, float *severity, uint32_t *counts, void *cache,
                              void *stream);
 
+/* Full evaluation with the paper's random-sampling estimator (App. A.2)
+ * instead of voxel centres: each tet of each mesh is sampled at
+ * N = floor(rate * |V| + 1/2) points (|V| its exact volume in voxel^3, at
+ * most 2^20) spread uniformly through its barycentric coordinates,
+ * lambda_j = -ln r_j / sum_k (-ln r_k) from four numbers r_j of a Sobol
+ * sequence seeded from `seed`, the direction and the tet's fixed-point
+ * coordinates (the same tet always gets the same points).  The point p in the
+ * sampled tet and its image q in the other mesh's tet are formed in FP32 from
+ * the same lambda; h (Sec. 4.1.2) compares the trilinear image values at p and
+ * q (zero padding, foreground on each stencil's exact support) and the
+ * guidance term (Sec. 4.1.3) the two distance maps (edge clamped) where the
+ * own distance is below the radius.  Magnitude, flags and severity are those
+ * of morea_eval_full; counts are the numbers of sample points.  Sequence:
+ * 4-D Sobol, natural order, direction numbers of the primitive polynomials
+ * 1, x + 1, x^2 + x + 1, x^3 + x + 1 (initial numbers (1), (1, 3),
+ * (1, 3, 1)), digital shift by four 32-bit words of a SplitMix64 hash;
+ * r_j = (2 floor(u_j / 2^9) + 1) 2^-24.  Arguments as morea_eval_full
+ * (no cache); rate finite and > 0.  Errors: MOREA_EINVAL, MOREA_ERANGE,
+ * MOREA_EDEVICE. */
+morea_status morea_eval_sobol(morea_problem *p, const float *pts, int32_t pop, float rate, uint64_t seed,
+                              float *obj, uint8_t *flags, float *severity, uint32_t *counts,
+                              void *stream);
+
 /* Register the family of subsets: n_groups point groups in CSR form (host
  * pointers).  For every group the library builds the list of dependent
  * tetrahedra, those with at least one vertex in the group (Sec. 4.2.1), and

@@ -21,6 +21,7 @@ MOREA_OK, MOREA_EINVAL, MOREA_ENOMEM, MOREA_EDEVICE, MOREA_ERANGE, MOREA_ESTATE 
 STORE = {"f32": 0, "bf16": 1, "f16": 2}
 
 EXPORTS = ["morea_problem_create", "morea_problem_destroy", "morea_cache_bytes", "morea_eval_full",
+           "morea_eval_sobol",
            "morea_set_groups", "morea_reserve_partial", "morea_eval_partial",
            "morea_debug_distance_map", "morea_tune_partial", "morea_partial_shape",
            "morea_surrogate_num_params", "morea_surrogate_num_features", "morea_surrogate_create",
@@ -70,6 +71,8 @@ def load_library():
     L.morea_cache_bytes.restype = ctypes.c_size_t
     L.morea_eval_full.argtypes = [P, P, I32, P, P, P, P, P, P]
     L.morea_eval_full.restype = I32
+    L.morea_eval_sobol.argtypes = [P, P, I32, ctypes.c_float, ctypes.c_uint64, P, P, P, P, P]
+    L.morea_eval_sobol.restype = I32
     L.morea_set_groups.argtypes = [P, I32, P, P]
     L.morea_set_groups.restype = I32
     L.morea_reserve_partial.argtypes = [P, I32]
@@ -153,6 +156,12 @@ def morea_eval_full(handle, pts, pop, obj, flags, severity, counts, cache, strea
     _check(load_library().morea_eval_full(handle, _dev_ptr(pts), pop, _dev_ptr(obj), _dev_ptr(flags),
                                           _dev_ptr(severity), _dev_ptr(counts), _dev_ptr(cache),
                                           _stream_ptr(stream)))
+
+
+def morea_eval_sobol(handle, pts, pop, rate, seed, obj, flags, severity, counts, stream):
+    _check(load_library().morea_eval_sobol(handle, _dev_ptr(pts), pop, float(rate), int(seed), _dev_ptr(obj),
+                                           _dev_ptr(flags), _dev_ptr(severity), _dev_ptr(counts),
+                                           _stream_ptr(stream)))
 
 
 def morea_set_groups(handle, grp_off, grp_pts):
@@ -287,6 +296,17 @@ class Problem:
         out = self.outputs(pop) if out is None else out
         morea_eval_full(self.handle, pts, pop, out["obj"], out["flags"], out["severity"],
                         out["counts"], cache, stream)
+        return out
+
+    def eval_sobol(self, pts, rate=1.0, seed=0, out=None, stream=None):
+        """The random-sampling estimator (App. A.2): round(rate * volume)
+        Sobol points per tet and direction; outputs as eval_full."""
+        assert pts.is_cuda and pts.dtype.is_floating_point and pts.is_contiguous()
+        pop = pts.shape[0]
+        assert tuple(pts.shape[1:]) == (2, 3, self.n_points)
+        out = self.outputs(pop) if out is None else out
+        morea_eval_sobol(self.handle, pts, pop, rate, seed, out["obj"], out["flags"], out["severity"],
+                         out["counts"], stream)
         return out
 
     def set_groups(self, grp_off, grp_pts):
