@@ -7,8 +7,11 @@ sample counts) of the population of 512 dual-dynamic mesh candidates on the
 sets.  Inputs are seeded and synthetic and already resident in HBM when the
 timed region starts.
 
-Prints one JSON line (see the design doc for every field).  --gpus above 1 is
-refused: this build evaluates on one GPU.
+Prints one JSON line: the plain full evaluation's throughput, its roofline
+(VALU-bound; HBM traffic from the committed counter summary), the oracle's
+CPU rate on a bounded sample, and the other forms (partial evaluation,
+reduced-precision storage, surrogate pre-screen, Sobol-sampled estimator).
+--gpus above 1 is refused: evaluation here runs on one GPU.
 """
 import argparse
 import json
@@ -23,6 +26,10 @@ sys.path.insert(0, ROOT)
 
 SAMPLE_OPS = 60           # algorithmic VALU lane-ops per voxel sample (map, trilinear, h, sums)
 SAMPLE_BYTES = 9          # algorithmic bytes per sample at FP32 storage (own voxel, footprint, band)
+# lane-ops per random sample: 4 Sobol numbers (5 each), 4 -logs (23 each: exponent split 6, a
+# division 6, series 8, scale 3), the sum and 3 divisions (21), p and q (18 FMA), two trilinear
+# reads with their support tests (45 each), h and the sums (6)
+SOBOL_SAMPLE_OPS = 240
 VALU_PEAK = 256 * 64 * 2.4e9   # lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz (packed FP32 disabled)
 HBM_PEAK = 8.0e12
 # HBM traffic of the evaluation kernel, from two rocprofv3 --pmc runs
@@ -79,9 +86,9 @@ def parse():
     ap.add_argument("--parity-samples", type=int, default=3)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this size first (counter calibration)")
-    ap.add_argument("--forms", default="partial,reduced,surrogate",
+    ap.add_argument("--forms", default="partial,reduced,surrogate,sobol",
                     help="comma list of the other forms to measure after the main timing "
-                         "(partial, reduced, surrogate) or 'none'")
+                         "(partial, reduced, surrogate, sobol) or 'none'")
     return ap.parse_args()
 
 
@@ -133,6 +140,36 @@ def form_partial(p, pop_np, prob_full_ms, steps):
             "vs_plain_full_evals_per_s": evals_s / (pop_np.shape[0] / (prob_full_ms * 1e-3)),
             "launch_shape": {"blocks": shape[0], "items_per_pop": shape[1], "tuned_ms": tune_ms},
             "parity": {"evals": idx, "counts_flags_exact": exact,
+                       "max_rel_err": [float(x) for x in rel.max(axis=0)]}}
+
+
+def form_sobol(p, pop_np, prob_full_ms, steps):
+    """Config 2 with the paper's random-sampling estimator (App. A.2): the
+    same 512 candidates, round(volume) Sobol points per tet and direction."""
+    import torch
+
+    import oracle
+    import paper_2303_04873_amd as morea
+    prob = morea.Problem.from_synth(p, max_population=pop_np.shape[0])
+    pts = torch.from_numpy(pop_np).cuda()
+    out = prob.outputs(pop_np.shape[0])
+    ms = timed(lambda: prob.eval_sobol(pts, rate=1.0, seed=1, out=out), steps, 2)
+    g = {k: v.cpu().numpy() for k, v in out.items()}
+    idx = [0, pop_np.shape[0] - 1]
+    o = oracle.Problem.from_synth(p).evaluate_sobol(pop_np[idx], rate=1.0, seed=1)
+    rel = np.abs(g["obj"][idx] - o["obj"]) / np.maximum(np.abs(o["obj"]), 1e-30)
+    exact = bool((g["counts"][idx] == o["counts"]).all() and (g["flags"][idx] == o["flags"]).all())
+    samples = float(g["counts"].astype(np.int64).sum())
+    evals_s = pop_np.shape[0] / (ms * 1e-3)
+    return {"workload": f"{pop_np.shape[0]} candidates, {p.n_tets} tets, rate 1 (N = round(volume) "
+                        f"points per tet and direction), seed 1",
+            "ms_per_step": ms, "evals_per_s": evals_s, "samples_per_s": samples / (ms * 1e-3),
+            "samples_per_step": int(samples),
+            "vs_plain_full_evals_per_s": evals_s / (pop_np.shape[0] / (prob_full_ms * 1e-3)),
+            "alu": {"ops_per_sample": SOBOL_SAMPLE_OPS,
+                    "achieved_T_lane_ops_per_s": samples * SOBOL_SAMPLE_OPS / (ms * 1e-3) / 1e12,
+                    "frac": samples * SOBOL_SAMPLE_OPS / (ms * 1e-3) / VALU_PEAK},
+            "parity": {"candidates": idx, "counts_flags_exact": exact,
                        "max_rel_err": [float(x) for x in rel.max(axis=0)]}}
 
 
@@ -323,6 +360,8 @@ def main():
             forms["reduced_precision_config4"] = form_reduced(max(3, args.steps // 4))
         elif name == "surrogate":
             forms["surrogate_config5"] = form_surrogate(evals_per_s, max(3, args.steps // 4))
+        elif name == "sobol":
+            forms["sobol_sampling_config2"] = form_sobol(p, pop_np, ms_per_step, max(3, args.steps // 4))
         print(f"# form {name} done in {time.time() - t_form:.1f}s", file=sys.stderr, flush=True)
 
     achieved_ops = samples * SAMPLE_OPS / (launch_ms * 1e-3)
