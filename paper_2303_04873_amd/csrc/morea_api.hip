@@ -240,6 +240,12 @@ morea_status morea_problem_create(const morea_problem_desc* d, morea_problem** o
     }
     P.dmap[m] = dm;
     P.band[m] = band;
+    uint8_t* cells = nullptr;
+    guard(upload(p, &cells, nullptr, PV));
+    if (st != MOREA_OK) break;
+    e = launch_band_cells(P, band, cells, nullptr);
+    if (e != hipSuccess) guard(hip_fail(e, "band cell kernel"));
+    p->band_cell[m] = cells;
   }
   if (st == MOREA_OK) {
     const size_t nrec = static_cast<size_t>(d->max_population) * d->n_tets * 2;

@@ -118,6 +118,9 @@ struct morea_problem {
   std::vector<int> tets_host;
   std::vector<float> ref_host;
   morea::Record* work_records = nullptr;   // [max_population][n_tets][2]
+  // per image: at padded element i (the lower corner of a grid cell), the OR
+  // of the band bits of the cell's 8 corners i + {0, 1} + {0, px} + {0, pxy}
+  uint8_t* band_cell[2] = {nullptr, nullptr};
   morea::Totals* work_totals = nullptr;    // [max_population]
   // family of subsets
   int n_groups = 0;
@@ -160,6 +163,7 @@ hipError_t launch_finalize(const ProblemView& P, const float* pts, int pop, cons
                            float* obj, uint8_t* flags, float* severity, uint32_t* counts,
                            Totals* totals, hipStream_t s);
 int partial_blocks_per_cu(int storage);
+hipError_t launch_band_cells(const ProblemView& P, const uint8_t* band, uint8_t* cells, hipStream_t s);
 void set_error(const char* msg);   // message returned by morea_last_error() on this thread
 hipError_t launch_partial(const ProblemView& P, int storage, const PartialItems& I, int n_parents,
                           int n_groups, const Record* parent_rec, const Totals* parent_tot,

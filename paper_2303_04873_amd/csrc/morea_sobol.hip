@@ -177,12 +177,6 @@ __device__ __forceinline__ float map_at(const ProblemView& P, const float* m, co
   return fmaf(c.fz, y1 - y0, y0);
 }
 
-__device__ __forceinline__ unsigned band_bits(const ProblemView& P, const uint8_t* band, const MapCell& c) {
-  const int i0 = c.i0, i1 = c.i0 + P.pxy;
-  return band[i0] | band[i0 + 1] | band[i0 + P.px] | band[i0 + P.px + 1] | band[i1] | band[i1 + 1] |
-         band[i1 + P.px] | band[i1 + P.px + 1];
-}
-
 // 6 x signed volume of snapped vertices (exact: coordinates below 2^19).
 __device__ __forceinline__ int64_t det6(const int v[4][3]) {
   const int64_t a0 = v[1][0] - v[0][0], a1 = v[1][1] - v[0][1], a2 = v[1][2] - v[0][2];
@@ -201,7 +195,8 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 
 template <int ST>
 __global__ __launch_bounds__(256) void k_eval_sobol(ProblemView P, const float* pts, int pop, double inv_pop,
-                                                  double count_scale, uint64_t seed, Record* rec, int n_items) {
+                                                  double count_scale, uint64_t seed, const uint8_t* cells0,
+                                                  const uint8_t* cells1, Record* rec, int n_items) {
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
   const int item = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
   if (item >= n_items) return;
@@ -333,7 +328,7 @@ __global__ __launch_bounds__(256) void k_eval_sobol(ProblemView P, const float* 
       }
       const void* img_own = d == 0 ? P.img[0] : P.img[1];
       const void* img_oth = d == 0 ? P.img[1] : P.img[0];
-      const uint8_t* band = d == 0 ? P.band[0] : P.band[1];
+      const uint8_t* cells = d == 0 ? cells0 : cells1;
       const float* map_own = d == 0 ? P.dmap[0] : P.dmap[1];
       const float* map_oth = d == 0 ? P.dmap[1] : P.dmap[0];
       const float* set_w = d == 0 ? P.set_w[0] : P.set_w[1];
@@ -369,7 +364,9 @@ __global__ __launch_bounds__(256) void k_eval_sobol(ProblemView P, const float* 
         h += (fa && fb) ? (a - b) * (a - b) : (fa == fb ? 0.f : 1.f);
         if (P.n_sets > 0) {
           const MapCell cp = map_cell(P, p[0], p[1], p[2]);
-          unsigned bits = band_bits(P, band, cp);
+          // sets within the radius at one of the stencil's corners (if at
+          // none, the interpolated distance is not below it either)
+          unsigned bits = cells[cp.i0];
           if (bits) {
             const MapCell cq = map_cell(P, q[0], q[1], q[2]);
             for (; bits; bits &= bits - 1u) {
@@ -392,11 +389,20 @@ __global__ __launch_bounds__(256) void k_eval_sobol(ProblemView P, const float* 
   }
 }
 
-template __global__ void k_eval_sobol<kF32>(ProblemView, const float*, int, double, double, uint64_t, Record*, int);
-template __global__ void k_eval_sobol<kBF16>(ProblemView, const float*, int, double, double, uint64_t, Record*,
-                                             int);
-template __global__ void k_eval_sobol<kF16>(ProblemView, const float*, int, double, double, uint64_t, Record*,
-                                            int);
+// Band mask per grid cell (lower corner at padded element i): the OR of the
+// band bytes of its 8 corners; elements that are no cell's lower corner hold 0.
+__global__ void k_band_cells(ProblemView P, const uint8_t* band, uint8_t* cells) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= static_cast<int>(P.pvox)) return;
+  const int x = i % P.px - 1, y = (i / P.px) % (P.ny + 2) - 1, z = i / P.pxy - 1;
+  uint8_t v = 0;
+  if (x >= 0 && y >= 0 && z >= 0 && x <= max(P.nx - 2, 0) && y <= max(P.ny - 2, 0) && z <= max(P.nz - 2, 0)) {
+    const int j = i + P.pxy;
+    v = band[i] | band[i + 1] | band[i + P.px] | band[i + P.px + 1] | band[j] | band[j + 1] | band[j + P.px] |
+        band[j + P.px + 1];
+  }
+  cells[i] = v;
+}
 
 morea_status fail(morea_status s, const char* msg) {
   set_error(msg);
@@ -411,6 +417,12 @@ morea_status device_fail(hipError_t e, const char* what) {
 }
 
 }  // namespace sobol
+
+hipError_t launch_band_cells(const ProblemView& P, const uint8_t* band, uint8_t* cells, hipStream_t s) {
+  hipLaunchKernelGGL(sobol::k_band_cells, dim3((P.pvox + 255) / 256), dim3(256), 0, s, P, band, cells);
+  return hipGetLastError();
+}
+
 }  // namespace morea
 
 using namespace morea;
@@ -438,15 +450,18 @@ extern "C" morea_status morea_eval_sobol(morea_problem* p, const float* pts, int
     switch (p->storage) {
       case kF32:
         hipLaunchKernelGGL(sobol::k_eval_sobol<kF32>, dim3(blocks), dim3(256), 0, s, P, pts, pop, inv_pop,
-                           count_scale, seed, p->work_records, static_cast<int>(n_items));
+                           count_scale, seed, p->band_cell[0], p->band_cell[1], p->work_records,
+                           static_cast<int>(n_items));
         break;
       case kBF16:
         hipLaunchKernelGGL(sobol::k_eval_sobol<kBF16>, dim3(blocks), dim3(256), 0, s, P, pts, pop, inv_pop,
-                           count_scale, seed, p->work_records, static_cast<int>(n_items));
+                           count_scale, seed, p->band_cell[0], p->band_cell[1], p->work_records,
+                           static_cast<int>(n_items));
         break;
       default:
         hipLaunchKernelGGL(sobol::k_eval_sobol<kF16>, dim3(blocks), dim3(256), 0, s, P, pts, pop, inv_pop,
-                           count_scale, seed, p->work_records, static_cast<int>(n_items));
+                           count_scale, seed, p->band_cell[0], p->band_cell[1], p->work_records,
+                           static_cast<int>(n_items));
         break;
     }
     hipError_t e = hipGetLastError();
