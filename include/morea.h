@@ -78,8 +78,8 @@ typedef struct {
   const float *image_src;       /* I_s, [nz][ny][nx], finite, >= 0 */
   const float *image_tgt;       /* I_t, same shape */
   int32_t storage;              /* morea_store */
-  int32_t n_points;             /* points per mesh (>= 4) */
-  int32_t n_tets;               /* tetrahedra (>= 1) */
+  int32_t n_points;             /* points per mesh (4 .. 2^28) */
+  int32_t n_tets;               /* tetrahedra (1 .. 2^28) */
   const int32_t *tets;          /* [n_tets][4] point indices */
   const float *ref_points;      /* [n_points][3] initial mesh: reference signs
                                    of App. A.4; no reference tet may be flat */
@@ -148,6 +148,35 @@ morea_status morea_eval_full(morea_problem *p, const float *pts, int32_t pop, fl
 morea_status morea_eval_sobol(morea_problem *p, const float *pts, int32_t pop, float rate, uint64_t seed,
                               float *obj, uint8_t *flags, float *severity, uint32_t *counts,
                               void *stream);
+
+/* Fold repair (Sec. 4.3.1) of candidates, in place.  For each point of a
+ * folded tet (App. A.4) -- the vertices of the tets folded when the call
+ * starts, mesh S then mesh T, each ascending; a point no longer in a folded
+ * tet when its turn comes is skipped -- 64 trial moves are tried, trial k of
+ * the candidate's i-th visited point moving each free axis by
+ * rint(sigma * draws[c][i][k][axis]) grid units of 2^-10 voxel (ties to even),
+ * sigma the point's distance to the centroid of its neighbours (the other
+ * vertices of its incident tets) rounded down to a power of two of grid units
+ * (1 .. 2^18).  The constraint of the point is (folded incident tets, sum of
+ * their |6V|), compared lexicographically; the trial with the smallest
+ * (constraint, k) is applied when it is strictly below the point's constraint,
+ * nothing changes when it is equal, and the candidate's repair stops when it
+ * is above (every trial worse or out of the |x| < 512 voxel range).  Moved
+ * coordinates are written as their grid values (exact FP32); all others keep
+ * their input bits.
+ *   pts     [pop][2][3][n_points] FP32, read and written
+ *   draws   [pop][n_draws][64][3] FP32 standard normal draws (finite), one
+ *           [64][3] block per visited point; at most n_draws points are
+ *           visited per candidate
+ *   pinned  [n_points] bit a set: axis a of the point never moves (e.g. the
+ *           normal axis of boundary points), or NULL
+ *   info    [pop][2] int32: moves applied, outcome (0 no fold at the start,
+ *           1 every listed point visited, 2 stopped because every trial was
+ *           worse, 3 n_draws used up, 4 invalid coordinates, left untouched)
+ * n_points <= 6144 (a candidate is held in LDS).  Asynchronous on `stream`;
+ * no allocation.  Errors: MOREA_EINVAL, MOREA_ERANGE, MOREA_EDEVICE. */
+morea_status morea_repair_folds(morea_problem *p, float *pts, int32_t pop, const float *draws, int32_t n_draws,
+                                const uint8_t *pinned, int32_t *info, void *stream);
 
 /* Register the family of subsets: n_groups point groups in CSR form (host
  * pointers).  For every group the library builds the list of dependent

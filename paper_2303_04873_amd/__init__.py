@@ -21,7 +21,7 @@ MOREA_OK, MOREA_EINVAL, MOREA_ENOMEM, MOREA_EDEVICE, MOREA_ERANGE, MOREA_ESTATE 
 STORE = {"f32": 0, "bf16": 1, "f16": 2}
 
 EXPORTS = ["morea_problem_create", "morea_problem_destroy", "morea_cache_bytes", "morea_eval_full",
-           "morea_eval_sobol",
+           "morea_eval_sobol", "morea_repair_folds",
            "morea_set_groups", "morea_reserve_partial", "morea_eval_partial",
            "morea_debug_distance_map", "morea_tune_partial", "morea_partial_shape",
            "morea_surrogate_num_params", "morea_surrogate_num_features", "morea_surrogate_create",
@@ -73,6 +73,8 @@ def load_library():
     L.morea_eval_full.restype = I32
     L.morea_eval_sobol.argtypes = [P, P, I32, ctypes.c_float, ctypes.c_uint64, P, P, P, P, P]
     L.morea_eval_sobol.restype = I32
+    L.morea_repair_folds.argtypes = [P, P, I32, P, I32, P, P, P]
+    L.morea_repair_folds.restype = I32
     L.morea_set_groups.argtypes = [P, I32, P, P]
     L.morea_set_groups.restype = I32
     L.morea_reserve_partial.argtypes = [P, I32]
@@ -308,6 +310,24 @@ class Problem:
         morea_eval_sobol(self.handle, pts, pop, rate, seed, out["obj"], out["flags"], out["severity"],
                          out["counts"], stream)
         return out
+
+    def repair_folds(self, pts, draws, pinned=None, info=None, stream=None):
+        """Fold repair in place (Sec. 4.3.1): pts float32 CUDA [pop][2][3][n_points],
+        draws float32 CUDA [pop][K][64][3] standard normal, pinned uint8 CUDA
+        [n_points] (bit a: axis a fixed) or None.  Returns info int32 [pop][2]
+        (moves, outcome)."""
+        import torch
+        assert pts.is_cuda and pts.dtype == torch.float32 and pts.is_contiguous()
+        pop = pts.shape[0]
+        assert tuple(pts.shape[1:]) == (2, 3, self.n_points)
+        assert draws.is_cuda and draws.dtype == torch.float32 and draws.is_contiguous()
+        assert draws.shape[0] == pop and tuple(draws.shape[2:]) == (64, 3)
+        if pinned is not None:
+            assert pinned.is_cuda and pinned.dtype == torch.uint8 and pinned.numel() == self.n_points
+        info = torch.empty((pop, 2), dtype=torch.int32, device="cuda") if info is None else info
+        _check(load_library().morea_repair_folds(self.handle, _dev_ptr(pts), pop, _dev_ptr(draws), draws.shape[1],
+                                                 _dev_ptr(pinned), _dev_ptr(info), _stream_ptr(stream)))
+        return info
 
     def set_groups(self, grp_off, grp_pts):
         morea_set_groups(self.handle, grp_off, grp_pts)

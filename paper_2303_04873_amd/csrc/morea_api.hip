@@ -96,6 +96,7 @@ morea_status morea_problem_create(const morea_problem_desc* d, morea_problem** o
   if (!d->image_src || !d->image_tgt) return fail(MOREA_EINVAL, "image pointer is NULL");
   if (d->storage < 0 || d->storage > 2) return fail(MOREA_EINVAL, "storage %d unknown", d->storage);
   if (d->n_points < 4 || d->n_tets < 1) return fail(MOREA_EINVAL, "need >= 4 points and >= 1 tet");
+  if (d->n_points > (1 << 28) || d->n_tets > (1 << 28)) return fail(MOREA_EINVAL, "more than 2^28 points or tets");
   if (!d->tets || !d->ref_points || !d->elasticity) return fail(MOREA_EINVAL, "mesh pointer is NULL");
   if (d->n_sets < 0 || d->n_sets > kMaxSets) return fail(MOREA_EINVAL, "n_sets %d outside [0,%d]", d->n_sets, kMaxSets);
   if (d->max_population < 1) return fail(MOREA_EINVAL, "max_population must be >= 1");
@@ -251,6 +252,34 @@ morea_status morea_problem_create(const morea_problem_desc* d, morea_problem** o
     const size_t nrec = static_cast<size_t>(d->max_population) * d->n_tets * 2;
     guard(upload(p, &p->work_records, nullptr, nrec * sizeof(Record)));
     if (st == MOREA_OK) guard(upload(p, &p->work_totals, nullptr, sizeof(Totals) * d->max_population));
+  }
+  if (st == MOREA_OK) {
+    // point -> incident tets and point -> neighbours, for fold repair
+    const int NP = d->n_points;
+    std::vector<int> inc_off(NP + 1, 0), inc(4 * static_cast<size_t>(d->n_tets));
+    for (int t = 0; t < d->n_tets; t++)
+      for (int i = 0; i < 4; i++) inc_off[p->tets_host[4 * t + i] + 1]++;
+    for (int v = 0; v < NP; v++) inc_off[v + 1] += inc_off[v];
+    std::vector<int> fill(inc_off.begin(), inc_off.end() - 1);
+    std::vector<std::vector<int>> nbs(NP);
+    for (int t = 0; t < d->n_tets; t++)
+      for (int i = 0; i < 4; i++) {
+        const int v = p->tets_host[4 * t + i];
+        inc[fill[v]++] = (t << 2) | i;
+        for (int k = 0; k < 4; k++)
+          if (k != i) nbs[v].push_back(p->tets_host[4 * t + k]);
+      }
+    std::vector<int> nb_off(NP + 1, 0), nb;
+    for (int v = 0; v < NP; v++) {
+      std::sort(nbs[v].begin(), nbs[v].end());
+      nbs[v].erase(std::unique(nbs[v].begin(), nbs[v].end()), nbs[v].end());
+      nb.insert(nb.end(), nbs[v].begin(), nbs[v].end());
+      nb_off[v + 1] = static_cast<int>(nb.size());
+    }
+    guard(upload(p, &p->d_pinc_off, inc_off.data(), sizeof(int) * inc_off.size()));
+    if (st == MOREA_OK) guard(upload(p, &p->d_pinc, inc.data(), sizeof(int) * inc.size()));
+    if (st == MOREA_OK) guard(upload(p, &p->d_nb_off, nb_off.data(), sizeof(int) * nb_off.size()));
+    if (st == MOREA_OK) guard(upload(p, &p->d_nb, nb.data(), sizeof(int) * nb.size()));
   }
   if (st == MOREA_OK) {
     e = hipDeviceSynchronize();

@@ -121,6 +121,12 @@ struct morea_problem {
   // per image: at padded element i (the lower corner of a grid cell), the OR
   // of the band bits of the cell's 8 corners i + {0, 1} + {0, px} + {0, pxy}
   uint8_t* band_cell[2] = {nullptr, nullptr};
+  // point -> incident tets (entries tet << 2 | slot) and point -> neighbours
+  // (the other vertices of its incident tets, each once, ascending), CSR
+  int* d_pinc_off = nullptr;
+  int* d_pinc = nullptr;
+  int* d_nb_off = nullptr;
+  int* d_nb = nullptr;
   morea::Totals* work_totals = nullptr;    // [max_population]
   // family of subsets
   int n_groups = 0;
