@@ -10,7 +10,8 @@ timed region starts.
 Prints one JSON line: the plain full evaluation's throughput, its roofline
 (VALU-bound; HBM traffic from the committed counter summary), the oracle's
 CPU rate on a bounded sample, and the other forms (partial evaluation,
-reduced-precision storage, surrogate pre-screen, Sobol-sampled estimator).
+reduced-precision storage, surrogate pre-screen, Sobol-sampled estimator,
+fold repair).
 --gpus above 1 is refused: evaluation here runs on one GPU.
 """
 import argparse
@@ -86,9 +87,9 @@ def parse():
     ap.add_argument("--parity-samples", type=int, default=3)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this size first (counter calibration)")
-    ap.add_argument("--forms", default="partial,reduced,surrogate,sobol",
+    ap.add_argument("--forms", default="partial,reduced,surrogate,sobol,repair",
                     help="comma list of the other forms to measure after the main timing "
-                         "(partial, reduced, surrogate, sobol) or 'none'")
+                         "(partial, reduced, surrogate, sobol, repair) or 'none'")
     return ap.parse_args()
 
 
@@ -171,6 +172,50 @@ def form_sobol(p, pop_np, prob_full_ms, steps):
                     "frac": samples * SOBOL_SAMPLE_OPS / (ms * 1e-3) / VALU_PEAK},
             "parity": {"candidates": idx, "counts_flags_exact": exact,
                        "max_rel_err": [float(x) for x in rel.max(axis=0)]}}
+
+
+def form_repair(p, pop_np, steps):
+    """Config 2: fold repair (Sec. 4.3.1) of the 512 candidates in one launch
+    (1 in 16 carries an injected fold), 16 blocks of 64 x 3 draws each."""
+    import torch
+
+    import paper_2303_04873_amd as morea
+    from oracle import repair as ref_repair
+    prob = morea.Problem.from_synth(p, max_population=pop_np.shape[0])
+    rs = np.random.default_rng(7)
+    draws_np = rs.normal(size=(pop_np.shape[0], 16, 64, 3)).astype(np.float32)
+    pinned_np = (p.fixed_axes.astype(np.uint8) * np.array([1, 2, 4], np.uint8)).sum(axis=1).astype(np.uint8)
+    draws = torch.from_numpy(draws_np).cuda()
+    pinned = torch.from_numpy(pinned_np).cuda()
+    base = torch.from_numpy(pop_np).cuda()
+    work = base.clone()
+    info = torch.empty((pop_np.shape[0], 2), dtype=torch.int32, device="cuda")
+    for _ in range(2):
+        work.copy_(base)
+        prob.repair_folds(work, draws, pinned, info=info)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a, b in ev:
+        work.copy_(base)
+        a.record()
+        prob.repair_folds(work, draws, pinned, info=info)
+        b.record()
+    torch.cuda.synchronize()
+    ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    before = prob.eval_full(base)["flags"].cpu().numpy()
+    after = prob.eval_full(work)["flags"].cpu().numpy()
+    inf = info.cpu().numpy()
+    folded = np.flatnonzero(before != 0)
+    idx = folded[:3].tolist()
+    o, moves, outcome, _ = ref_repair.repair(p.tets, p.ref_points, pop_np[idx], draws_np[idx], fixed=pinned_np)
+    exact = bool(np.array_equal(work.cpu().numpy()[idx].view(np.uint32), o.view(np.uint32)) and
+                 np.array_equal(inf[idx, 0], moves) and np.array_equal(inf[idx, 1], outcome))
+    return {"workload": f"{pop_np.shape[0]} candidates ({len(folded)} folded), 16 draw blocks of 64 trials",
+            "ms_per_launch": ms, "folded_candidates_per_s": len(folded) / (ms * 1e-3),
+            "folded_before": int(len(folded)), "fold_free_after": int((after[folded] == 0).sum()),
+            "moves": int(inf[:, 0].sum()),
+            "outcomes": {str(k): int((inf[:, 1] == k).sum()) for k in range(5)},
+            "parity": {"candidates": idx, "bit_exact": exact}}
 
 
 def form_reduced(steps):
@@ -362,6 +407,8 @@ def main():
             forms["surrogate_config5"] = form_surrogate(evals_per_s, max(3, args.steps // 4))
         elif name == "sobol":
             forms["sobol_sampling_config2"] = form_sobol(p, pop_np, ms_per_step, max(3, args.steps // 4))
+        elif name == "repair":
+            forms["fold_repair_config2"] = form_repair(p, pop_np, max(3, args.steps // 4))
         print(f"# form {name} done in {time.time() - t_form:.1f}s", file=sys.stderr, flush=True)
 
     achieved_ops = samples * SAMPLE_OPS / (launch_ms * 1e-3)
