@@ -70,6 +70,8 @@ def lib():
         L.oracle_sobol_points.argtypes = [P, P, ctypes.c_int, ctypes.c_uint64, ctypes.c_double, P, P,
                                           ctypes.c_int64]
         L.oracle_sobol_points.restype = ctypes.c_int64
+        L.oracle_dvf.argtypes = [P, P, P, P, P]
+        L.oracle_dvf.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -163,6 +165,20 @@ class Problem:
         if records:
             out["records"] = rec
         return out
+
+    def dvf(self, cand):
+        """Forward and inverse deformation vector fields of one candidate
+        cand float32 [2][3][n_points] (Sec. 5.4): fwd, inv [nz][ny][nx][3]
+        (FP64 displacements q - p in voxels), cover [2][nz][ny][nx] (tets
+        containing each voxel centre)."""
+        c = np.ascontiguousarray(cand, dtype=np.float32)
+        assert c.shape == (2, 3, self.n_points), c.shape
+        nx, ny, nz = self.dims
+        fwd = np.empty((nz, ny, nx, 3), np.float64)
+        inv = np.empty((nz, ny, nx, 3), np.float64)
+        cover = np.empty((2, nz, ny, nx), np.int32)
+        lib().oracle_dvf(ctypes.byref(self._c), _ptr(c), _ptr(fwd), _ptr(inv), _ptr(cover))
+        return fwd, inv, cover
 
     def evaluate_sobol(self, pts, rate=1.0, seed=0, records=False):
         """The same outputs from the Sobol-sampled estimator (App. A.2):

@@ -770,3 +770,78 @@ int64_t oracle_sobol_points(const float own_f[12], const float oth_f[12], int di
     sobol_point((uint32_t)n, shift, bo, eo, bt, et, p_out + 3 * n, q_out + 3 * n);
   return N;
 }
+
+/* ---------------------------------------------------- deformation vector fields
+ *
+ * Sec. 5.4 compares registrations through a forward DVF on the source grid
+ * and an inverse DVF on the target grid, rasterized from MOREA's two meshes.
+ * Readings: the voxel centres of a tet are those of the evaluation (the tie
+ * rule above); a centre p of tet t of the sampled mesh gets the displacement
+ * q - p with q its barycentric image in the other mesh (exact rational,
+ * rounded once); a centre covered by several tets (a folded mesh) takes the
+ * tet of smallest index, one covered by none the displacement 0; a tet with a
+ * vertex coordinate that is not finite or has |x| >= 512 voxels is skipped.
+ * cover[d][v] counts the tets that contain centre v. */
+int oracle_dvf(const oracle_problem *P, const float *cand, double *fwd, double *inv, int32_t *cover) {
+  const int NP = P->n_points;
+  const size_t V = (size_t)P->nx * P->ny * P->nz;
+  const int dims[3] = {P->nx, P->ny, P->nz};
+  int32_t *owner = (int32_t *)malloc(sizeof(int32_t) * (V > 0 ? V : 1));
+  for (int d = 0; d < 2; d++) {
+    double *out = d == 0 ? fwd : inv;
+    int32_t *cov = cover + (size_t)d * V;
+    for (size_t v = 0; v < V; v++) {
+      owner[v] = -1;
+      cov[v] = 0;
+      out[3 * v] = out[3 * v + 1] = out[3 * v + 2] = 0.0;
+    }
+    for (int t = 0; t < P->n_tets; t++) {
+      int64_t own[4][3], oth[4][3];
+      int good = 1;
+      for (int i = 0; i < 4; i++) {
+        const int pt = P->tets[4 * t + i];
+        for (int k = 0; k < 3; k++) {
+          const float xo = cand[(d * 3 + k) * NP + pt], xt = cand[((1 - d) * 3 + k) * NP + pt];
+          if (!(fabs((double)xo) < COORD_LIMIT) || !(fabs((double)xt) < COORD_LIMIT)) good = 0;
+          own[i][k] = good ? snap(xo) : 0;
+          oth[i][k] = good ? snap(xt) : 0;
+        }
+      }
+      if (!good) continue;
+      const i128 D = orient(own);
+      if (D == 0) continue;
+      const i128 absD = D < 0 ? -D : D;
+      int64_t lo[3], hi[3];
+      for (int a = 0; a < 3; a++) {
+        int64_t mn = own[0][a], mx = own[0][a];
+        for (int i = 1; i < 4; i++) {
+          if (own[i][a] < mn) mn = own[i][a];
+          if (own[i][a] > mx) mx = own[i][a];
+        }
+        lo[a] = ceil_div64(mn, FIX_ONE);
+        hi[a] = floor_div64(mx, FIX_ONE);
+        if (lo[a] < 0) lo[a] = 0;
+        if (hi[a] > dims[a] - 1) hi[a] = dims[a] - 1;
+      }
+      for (int64_t z = lo[2]; z <= hi[2]; z++)
+        for (int64_t y = lo[1]; y <= hi[1]; y++)
+          for (int64_t x = lo[0]; x <= hi[0]; x++) {
+            const int64_t p[3] = {x * FIX_ONE, y * FIX_ONE, z * FIX_ONE};
+            i128 lam[4];
+            if (!inside_tie(own, D, p, lam)) continue;
+            const size_t v = ((size_t)z * P->ny + y) * P->nx + x;
+            cov[v] += 1;
+            if (owner[v] >= 0) continue;
+            owner[v] = t;
+            int64_t kq[3];
+            double fq[3], q[3];
+            int ex[3];
+            map_point(lam, absD, oth, kq, fq, ex, q);
+            const int64_t pv[3] = {x, y, z};
+            for (int a = 0; a < 3; a++) out[3 * v + a] = (double)(kq[a] - pv[a]) + fq[a];
+          }
+    }
+  }
+  free(owner);
+  return 0;
+}
