@@ -178,6 +178,26 @@ morea_status morea_eval_sobol(morea_problem *p, const float *pts, int32_t pop, f
 morea_status morea_repair_folds(morea_problem *p, float *pts, int32_t pop, const float *draws, int32_t n_draws,
                                 const uint8_t *pinned, int32_t *info, void *stream);
 
+/* Deformation vector fields of one candidate (Sec. 5.4: registrations are
+ * compared through a forward DVF on the source grid and an inverse DVF on the
+ * target grid; MOREA's are rasterized from its two meshes).  A voxel centre p
+ * of a tet of the sampled mesh -- the centres of the evaluation, a centre on a
+ * face belonging to the tet that holds p + (e, e^2, e^3) -- gets the
+ * displacement q - p, q its barycentric image in the other mesh (computed in
+ * FP64 from exact signed volumes, rounded once to FP32).  A centre covered by
+ * several tets (a folded mesh) takes the tet of smallest index; one covered
+ * by none gets 0; a tet with a vertex coordinate that is not finite or has
+ * |x| >= 512 voxels is skipped.
+ *   cand   [2][3][n_points] FP32, one candidate (layout of morea_eval_full)
+ *   fwd    [nz][ny][nx][3] FP32 T(p) - p on the I_s grid
+ *   inv    [nz][ny][nx][3] FP32 T'(y) - y on the I_t grid
+ *   cover  [2][nz][ny][nx] tets containing each centre (source, target grid)
+ *   work   [2][nz][ny][nx] int32 workspace (owner of each centre)
+ * Asynchronous on `stream`; no allocation.  Errors: MOREA_EINVAL,
+ * MOREA_EDEVICE. */
+morea_status morea_rasterize_dvf(morea_problem *p, const float *cand, float *fwd, float *inv, uint32_t *cover,
+                                 int32_t *work, void *stream);
+
 /* Register the family of subsets: n_groups point groups in CSR form (host
  * pointers).  For every group the library builds the list of dependent
  * tetrahedra, those with at least one vertex in the group (Sec. 4.2.1), and

@@ -21,7 +21,7 @@ MOREA_OK, MOREA_EINVAL, MOREA_ENOMEM, MOREA_EDEVICE, MOREA_ERANGE, MOREA_ESTATE 
 STORE = {"f32": 0, "bf16": 1, "f16": 2}
 
 EXPORTS = ["morea_problem_create", "morea_problem_destroy", "morea_cache_bytes", "morea_eval_full",
-           "morea_eval_sobol", "morea_repair_folds",
+           "morea_eval_sobol", "morea_repair_folds", "morea_rasterize_dvf",
            "morea_set_groups", "morea_reserve_partial", "morea_eval_partial",
            "morea_debug_distance_map", "morea_tune_partial", "morea_partial_shape",
            "morea_surrogate_num_params", "morea_surrogate_num_features", "morea_surrogate_create",
@@ -75,6 +75,8 @@ def load_library():
     L.morea_eval_sobol.restype = I32
     L.morea_repair_folds.argtypes = [P, P, I32, P, I32, P, P, P]
     L.morea_repair_folds.restype = I32
+    L.morea_rasterize_dvf.argtypes = [P, P, P, P, P, P, P]
+    L.morea_rasterize_dvf.restype = I32
     L.morea_set_groups.argtypes = [P, I32, P, P]
     L.morea_set_groups.restype = I32
     L.morea_reserve_partial.argtypes = [P, I32]
@@ -328,6 +330,24 @@ class Problem:
         _check(load_library().morea_repair_folds(self.handle, _dev_ptr(pts), pop, _dev_ptr(draws), draws.shape[1],
                                                  _dev_ptr(pinned), _dev_ptr(info), _stream_ptr(stream)))
         return info
+
+    def rasterize_dvf(self, cand, out=None, stream=None):
+        """Forward and inverse DVF of one candidate cand float32 CUDA
+        [2][3][n_points] (Sec. 5.4): dict fwd, inv [nz][ny][nx][3], cover
+        [2][nz][ny][nx] (int32 tensor of the uint32 counts), work (owners)."""
+        import torch
+        assert cand.is_cuda and cand.dtype == torch.float32 and cand.is_contiguous()
+        assert tuple(cand.shape) == (2, 3, self.n_points)
+        nx, ny, nz = self.dims
+        if out is None:
+            out = dict(fwd=torch.empty((nz, ny, nx, 3), dtype=torch.float32, device="cuda"),
+                       inv=torch.empty((nz, ny, nx, 3), dtype=torch.float32, device="cuda"),
+                       cover=torch.empty((2, nz, ny, nx), dtype=torch.int32, device="cuda"),
+                       work=torch.empty((2, nz, ny, nx), dtype=torch.int32, device="cuda"))
+        _check(load_library().morea_rasterize_dvf(self.handle, _dev_ptr(cand), _dev_ptr(out["fwd"]),
+                                                  _dev_ptr(out["inv"]), _dev_ptr(out["cover"]),
+                                                  _dev_ptr(out["work"]), _stream_ptr(stream)))
+        return out
 
     def set_groups(self, grp_off, grp_pts):
         morea_set_groups(self.handle, grp_off, grp_pts)

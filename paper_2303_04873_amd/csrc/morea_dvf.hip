@@ -1,0 +1,193 @@
+// Deformation vector fields of one candidate, rasterized from its two meshes
+// (Sec. 5.4 compares registrations through a forward DVF on the source grid
+// and an inverse DVF on the target grid).  A voxel centre p of tet t of the
+// sampled mesh (the centres of the evaluation: exact signed volumes, a centre
+// on a face belonging to the tet that holds p + (e, e^2, e^3)) gets q - p,
+// q its barycentric image in the other mesh.  A centre covered by several
+// tets (a folded mesh) takes the tet of smallest index, a centre covered by
+// none the displacement 0; a tet with a vertex coordinate that is not finite
+// or has |x| >= 512 voxels is skipped.
+//
+// Two passes of one 64-lane wave per (direction, tet), lanes over the voxels
+// of the tet's bounding box: the first claims each covered centre with an
+// atomic minimum of the tet index and counts the covering tets, the second
+// lets the owner write the displacement (FP64 barycentric image, rounded once
+// to FP32).
+#include <math.h>
+#include <stdio.h>
+
+#include "morea_internal.h"
+
+namespace morea {
+namespace dvf {
+
+typedef __int128 i128;
+
+__device__ __forceinline__ int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
+
+// 6 x signed volume (exact in 128 bits for any coordinates below 2^21)
+__device__ __forceinline__ i128 vol6(const int64_t a[3], const int64_t b[3], const int64_t c[3], const int64_t d[3]) {
+  const i128 u0 = b[0] - a[0], u1 = b[1] - a[1], u2 = b[2] - a[2];
+  const i128 v0 = c[0] - a[0], v1 = c[1] - a[1], v2 = c[2] - a[2];
+  const i128 w0 = d[0] - a[0], w1 = d[1] - a[1], w2 = d[2] - a[2];
+  return u0 * (v1 * w2 - v2 * w1) - u1 * (v0 * w2 - v2 * w0) + u2 * (v0 * w1 - v1 * w0);
+}
+
+// Face value of vertex i (the volume with vertex i replaced by p), oriented
+// positive inside.
+__device__ __forceinline__ i128 face(const int64_t v[4][3], int i, const int64_t p[3], int sgn) {
+  const int64_t* q0 = i == 0 ? p : v[0];
+  const int64_t* q1 = i == 1 ? p : v[1];
+  const int64_t* q2 = i == 2 ? p : v[2];
+  const int64_t* q3 = i == 3 ? p : v[3];
+  const i128 s = vol6(q0, q1, q2, q3);
+  return sgn > 0 ? s : -s;
+}
+
+// Inside test with the tie rule: on a face plane the sign of the face value
+// at p + (e, e^2, e^3) decides, i.e. the first nonzero component of its
+// gradient (the change for a unit step along x, then y, then z).
+__device__ __forceinline__ bool inside(const int64_t v[4][3], int sgn, const int64_t p[3], i128 val[4]) {
+  bool in = true;
+#pragma unroll
+  for (int i = 0; i < 4; i++) {
+    val[i] = face(v, i, p, sgn);
+    if (val[i] < 0) in = false;
+  }
+  if (!in) return false;
+#pragma unroll
+  for (int i = 0; i < 4; i++) {
+    if (val[i] != 0) continue;
+    int sgrad = 0;
+    for (int k = 0; k < 3 && sgrad == 0; k++) {
+      int64_t pk[3] = {p[0], p[1], p[2]};
+      pk[k] += 1;
+      const i128 g = face(v, i, pk, sgn) - val[i];
+      sgrad = (g > 0) - (g < 0);
+    }
+    if (sgrad <= 0) return false;
+  }
+  return true;
+}
+
+__global__ void k_dvf_clear(size_t V, int* owner, uint32_t* cover, float* fwd, float* inv) {
+  const size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= 2 * V) return;
+  owner[i] = 0x7fffffff;
+  cover[i] = 0u;
+  float* out = i < V ? fwd + 3 * i : inv + 3 * (i - V);
+  out[0] = out[1] = out[2] = 0.f;
+}
+
+template <bool WRITE>
+__global__ __launch_bounds__(256) void k_dvf_pass(ProblemView P, const float* cand, int* owner, uint32_t* cover,
+                                                float* fwd, float* inv) {
+  const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+  const int item = blockIdx.x * 4 + wave;
+  if (item >= 2 * P.n_tets) return;
+  const int d = item / P.n_tets, t = item % P.n_tets;
+  const int lane = lane_id();
+  // lane l < 24: mesh (l < 12 ? sampled : other), vertex (l % 12) / 3, axis l % 3
+  const int4 tv = P.tets[t];
+  float x = 0.f;
+  if (lane < 24) {
+    const int i = (lane % 12) / 3, k = lane % 3;
+    const int pt = i == 0 ? tv.x : (i == 1 ? tv.y : (i == 2 ? tv.z : tv.w));
+    const int mesh = lane < 12 ? d : 1 - d;
+    x = cand[(mesh * 3 + k) * P.n_points + pt];
+  }
+  if (__ballot(lane < 24 && !(fabsf(x) < kCoordLimit)) != 0ull) return;
+  const int fix = lane < 24 ? static_cast<int>(rintf(x * kFixOne)) : 0;
+  int64_t own[4][3], oth[4][3];
+#pragma unroll
+  for (int i = 0; i < 4; i++)
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+      own[i][k] = __builtin_amdgcn_readlane(fix, 3 * i + k);
+      oth[i][k] = __builtin_amdgcn_readlane(fix, 12 + 3 * i + k);
+    }
+  const i128 D = vol6(own[0], own[1], own[2], own[3]);
+  if (D == 0) return;
+  const int sgn = D > 0 ? 1 : -1;
+  const double inv_absD = 1.0 / static_cast<double>(D > 0 ? D : -D);
+  const int dims[3] = {P.nx, P.ny, P.nz};
+  int lo[3], ext[3];
+#pragma unroll
+  for (int k = 0; k < 3; k++) {
+    int64_t mn = own[0][k], mx = own[0][k];
+#pragma unroll
+    for (int i = 1; i < 4; i++) {
+      mn = min(mn, own[i][k]);
+      mx = max(mx, own[i][k]);
+    }
+    // ceil(mn / 1024) and floor(mx / 1024), clipped to the grid
+    const int64_t c = mn >= 0 ? (mn + 1023) / 1024 : -((-mn) / 1024);
+    const int64_t f = mx >= 0 ? mx / 1024 : -((-mx + 1023) / 1024);
+    lo[k] = static_cast<int>(max<int64_t>(c, 0));
+    ext[k] = static_cast<int>(min<int64_t>(f, dims[k] - 1)) - lo[k] + 1;
+  }
+  if (ext[0] <= 0 || ext[1] <= 0 || ext[2] <= 0) return;
+  const size_t V = static_cast<size_t>(P.nx) * P.ny * P.nz;
+  const int64_t box = static_cast<int64_t>(ext[0]) * ext[1] * ext[2];
+  for (int64_t q = lane; q < box; q += 64) {
+    const int xv = lo[0] + static_cast<int>(q % ext[0]);
+    const int yv = lo[1] + static_cast<int>((q / ext[0]) % ext[1]);
+    const int zv = lo[2] + static_cast<int>(q / (static_cast<int64_t>(ext[0]) * ext[1]));
+    const int64_t p[3] = {static_cast<int64_t>(xv) * 1024, static_cast<int64_t>(yv) * 1024,
+                          static_cast<int64_t>(zv) * 1024};
+    i128 val[4];
+    if (!inside(own, sgn, p, val)) continue;
+    const size_t v = (static_cast<size_t>(zv) * P.ny + yv) * P.nx + xv;
+    if (!WRITE) {
+      atomicMin(&owner[d * V + v], t);
+      atomicAdd(&cover[d * V + v], 1u);
+    } else if (owner[d * V + v] == t) {
+      float* out = (d == 0 ? fwd : inv) + 3 * v;
+      const int pv[3] = {xv, yv, zv};
+#pragma unroll
+      for (int a = 0; a < 3; a++) {
+        double qa = static_cast<double>(oth[0][a]);
+#pragma unroll
+        for (int i = 1; i < 4; i++)
+          qa += static_cast<double>(val[i]) * inv_absD * static_cast<double>(oth[i][a] - oth[0][a]);
+        out[a] = static_cast<float>(qa * (1.0 / 1024.0) - pv[a]);
+      }
+    }
+  }
+}
+
+}  // namespace dvf
+}  // namespace morea
+
+using namespace morea;
+
+extern "C" morea_status morea_rasterize_dvf(morea_problem* p, const float* cand, float* fwd, float* inv,
+                                            uint32_t* cover, int32_t* work, void* stream) {
+  if (!p || !cand || !fwd || !inv || !cover || !work) {
+    set_error("NULL argument");
+    return MOREA_EINVAL;
+  }
+  {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+      set_error(hipGetErrorString(e));
+      return MOREA_EDEVICE;
+    }
+  }
+  const ProblemView& P = p->view;
+  const size_t V = static_cast<size_t>(P.nx) * P.ny * P.nz;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int items = 2 * P.n_tets;
+  hipLaunchKernelGGL(dvf::k_dvf_clear, dim3(static_cast<unsigned>((2 * V + 255) / 256)), dim3(256), 0, s, V, work,
+                     cover, fwd, inv);
+  hipLaunchKernelGGL(dvf::k_dvf_pass<false>, dim3((items + 3) / 4), dim3(256), 0, s, P, cand, work, cover, fwd, inv);
+  hipLaunchKernelGGL(dvf::k_dvf_pass<true>, dim3((items + 3) / 4), dim3(256), 0, s, P, cand, work, cover, fwd, inv);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    char buf[256];
+    snprintf(buf, sizeof(buf), "DVF rasterization: %s", hipGetErrorString(e));
+    set_error(buf);
+    return MOREA_EDEVICE;
+  }
+  return MOREA_OK;
+}
