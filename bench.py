@@ -11,7 +11,7 @@ Prints one JSON line: the plain full evaluation's throughput, its roofline
 (VALU-bound; HBM traffic from the committed counter summary), the oracle's
 CPU rate on a bounded sample, and the other forms (partial evaluation,
 reduced-precision storage, surrogate pre-screen, Sobol-sampled estimator,
-fold repair).
+fold repair, DVF rasterization).
 --gpus above 1 is refused: evaluation here runs on one GPU.
 """
 import argparse
@@ -87,9 +87,9 @@ def parse():
     ap.add_argument("--parity-samples", type=int, default=3)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this size first (counter calibration)")
-    ap.add_argument("--forms", default="partial,reduced,surrogate,sobol,repair",
+    ap.add_argument("--forms", default="partial,reduced,surrogate,sobol,repair,dvf",
                     help="comma list of the other forms to measure after the main timing "
-                         "(partial, reduced, surrogate, sobol, repair) or 'none'")
+                         "(partial, reduced, surrogate, sobol, repair, dvf) or 'none'")
     return ap.parse_args()
 
 
@@ -216,6 +216,26 @@ def form_repair(p, pop_np, steps):
             "moves": int(inf[:, 0].sum()),
             "outcomes": {str(k): int((inf[:, 1] == k).sum()) for k in range(5)},
             "parity": {"candidates": idx, "bit_exact": exact}}
+
+
+def form_dvf(p, pop_np, steps):
+    """Config 2: forward and inverse DVF of one candidate (both 128x128x96
+    grids), rasterized from its two meshes."""
+    import torch
+
+    import oracle
+    import paper_2303_04873_amd as morea
+    prob = morea.Problem.from_synth(p, max_population=1)
+    cand = torch.from_numpy(np.ascontiguousarray(pop_np[1])).cuda()
+    out = prob.rasterize_dvf(cand)
+    ms = timed(lambda: prob.rasterize_dvf(cand, out=out), steps, 2)
+    fwd, inv, cover = oracle.Problem.from_synth(p).dvf(pop_np[1])
+    err = max(float(np.max(np.abs(out["fwd"].cpu().numpy() - fwd))), float(np.max(np.abs(out["inv"].cpu().numpy() - inv))))
+    V = int(np.prod(p.dims))
+    return {"workload": f"candidate 1, {p.n_tets} tets per mesh, two {p.dims[0]}x{p.dims[1]}x{p.dims[2]} fields",
+            "ms_per_candidate": ms, "voxels_per_s": 2 * V / (ms * 1e-3),
+            "parity": {"cover_exact": bool(np.array_equal(out["cover"].cpu().numpy(), cover)),
+                       "max_abs_err_voxels": err}}
 
 
 def form_reduced(steps):
@@ -409,6 +429,8 @@ def main():
             forms["sobol_sampling_config2"] = form_sobol(p, pop_np, ms_per_step, max(3, args.steps // 4))
         elif name == "repair":
             forms["fold_repair_config2"] = form_repair(p, pop_np, max(3, args.steps // 4))
+        elif name == "dvf":
+            forms["dvf_config2"] = form_dvf(p, pop_np, max(3, args.steps // 4))
         print(f"# form {name} done in {time.time() - t_form:.1f}s", file=sys.stderr, flush=True)
 
     achieved_ops = samples * SAMPLE_OPS / (launch_ms * 1e-3)

@@ -72,6 +72,8 @@ def lib():
         L.oracle_sobol_points.restype = ctypes.c_int64
         L.oracle_dvf.argtypes = [P, P, P, P, P]
         L.oracle_dvf.restype = ctypes.c_int
+        L.oracle_point_guidance.argtypes = [P, P, P, P, ctypes.c_int, P, P]
+        L.oracle_point_guidance.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -165,6 +167,24 @@ class Problem:
         if records:
             out["records"] = rec
         return out
+
+    def point_guidance(self, pts):
+        """Point-based guidance error of candidates pts [pop][2][3][n_points]
+        (the prior work's form that Sec. 4.1.3 replaces): mean over all points c
+        of C_s of the squared distance from T(c) to the closest point of the
+        set's C_t.  Returns (f [pop] FP64, unmapped [pop] points in no tet)."""
+        pts = np.ascontiguousarray(pts, dtype=np.float32)
+        pop = pts.shape[0]
+        assert pts.shape[1:] == (2, 3, self.n_points), pts.shape
+        cs = np.ascontiguousarray(np.concatenate(self.sets_src) if self.sets_src else np.zeros((1, 3)),
+                                  dtype=np.float32)
+        ct = np.ascontiguousarray(np.concatenate(self.sets_tgt) if self.sets_tgt else np.zeros((1, 3)),
+                                  dtype=np.float32)
+        f = np.empty(pop, np.float64)
+        unmapped = np.empty(pop, np.int32)
+        lib().oracle_point_guidance(ctypes.byref(self._c), _ptr(cs), _ptr(ct), _ptr(pts), pop, _ptr(f),
+                                    _ptr(unmapped))
+        return f, unmapped
 
     def dvf(self, cand):
         """Forward and inverse deformation vector fields of one candidate

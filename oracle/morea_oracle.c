@@ -845,3 +845,70 @@ int oracle_dvf(const oracle_problem *P, const float *cand, double *fwd, double *
   free(owner);
   return 0;
 }
+
+/* ----------------------------------------------------- point-based guidance
+ *
+ * The guidance error of the paper's prior work, which Sec. 4.1.3 replaces by
+ * the continuous form: every point c of C_s is located in the source mesh,
+ * mapped to the target mesh through its barycentric coordinates, and its
+ * distance to the closest point of the set's C_t taken.  Readings: points are
+ * snapped like mesh coordinates; a point belongs to the tet that holds it
+ * under the tie rule of the evaluation (the smallest index if several, a
+ * folded mesh); the value is the mean of the squared distances over all
+ * points of all sets (each set weighted by |C_i| / |G| as in the continuous
+ * form); points in no tet are left out and counted.  pts_s and pts_t are the
+ * concatenated sets (CSR offsets of the problem). */
+int oracle_point_guidance(const oracle_problem *P, const float *set_pts_s, const float *set_pts_t,
+                          const float *pts, int pop, double *f, int32_t *unmapped) {
+  const int NP = P->n_points, NT = P->n_tets;
+  const int G = P->n_sets > 0 ? P->set_off_s[P->n_sets] : 0;
+  for (int c = 0; c < pop; c++) {
+    const float *cand = pts + (size_t)c * 6 * NP;
+    f[c] = NAN;
+    unmapped[c] = 0;
+    if (!candidate_valid(cand, NP)) continue;
+    double total = 0.0;
+    int n = 0;
+    for (int s = 0; s < P->n_sets; s++)
+      for (int j = P->set_off_s[s]; j < P->set_off_s[s + 1]; j++) {
+        const int64_t cp[3] = {snap(set_pts_s[3 * j]), snap(set_pts_s[3 * j + 1]), snap(set_pts_s[3 * j + 2])};
+        int found = 0;
+        double q[3] = {0, 0, 0};
+        for (int t = 0; t < NT && !found; t++) {
+          int64_t S[4][3], T[4][3];
+          for (int i = 0; i < 4; i++)
+            for (int k = 0; k < 3; k++) {
+              S[i][k] = snap(cand[k * NP + P->tets[4 * t + i]]);
+              T[i][k] = snap(cand[(3 + k) * NP + P->tets[4 * t + i]]);
+            }
+          const i128 D = orient(S);
+          if (D == 0) continue;
+          i128 lam[4];
+          if (!inside_tie(S, D, cp, lam)) continue;
+          int64_t kq[3];
+          double fq[3];
+          int ex[3];
+          map_point(lam, D < 0 ? -D : D, T, kq, fq, ex, q);
+          found = 1;
+        }
+        if (!found) {
+          unmapped[c] += 1;
+          continue;
+        }
+        double best = INFINITY;
+        for (int k = P->set_off_t[s]; k < P->set_off_t[s + 1]; k++) {
+          double d2 = 0.0;
+          for (int a = 0; a < 3; a++) {
+            const double diff = q[a] - (double)snap(set_pts_t[3 * k + a]) / (double)FIX_ONE;
+            d2 += diff * diff;
+          }
+          if (d2 < best) best = d2;
+        }
+        total += best;
+        n += 1;
+      }
+    (void)G;
+    f[c] = n > 0 ? total / n : NAN;
+  }
+  return 0;
+}
