@@ -198,6 +198,23 @@ morea_status morea_repair_folds(morea_problem *p, float *pts, int32_t pop, const
 morea_status morea_rasterize_dvf(morea_problem *p, const float *cand, float *fwd, float *inv, uint32_t *cover,
                                  int32_t *work, void *stream);
 
+/* Point-based guidance error of `pop` candidates: the guidance measure of
+ * the paper's prior work, which Sec. 4.1.3 replaces by the continuous form.
+ * Every point c of the problem's C_s sets is located in the candidate's
+ * source mesh (the tet that holds it under the tie rule of the evaluation,
+ * the smallest index if several), mapped to the target mesh through its
+ * barycentric coordinates, and its squared distance (voxel^2) to the nearest
+ * point of the set's C_t taken; f[c] is the mean over all points of all sets
+ * (each set weighted |C_i| / |G|), NaN for an invalid candidate or when no
+ * point is located; unmapped[c] counts the points in no tet.
+ *   pts       [pop][2][3][n_points] FP32 (layout of morea_eval_full)
+ *   f         [pop] FP32
+ *   unmapped  [pop] int32
+ * n_points <= 6144 (a candidate is held in LDS).  Asynchronous on `stream`;
+ * no allocation.  Errors: MOREA_EINVAL, MOREA_ERANGE, MOREA_EDEVICE. */
+morea_status morea_point_guidance(morea_problem *p, const float *pts, int32_t pop, float *f, int32_t *unmapped,
+                                  void *stream);
+
 /* Register the family of subsets: n_groups point groups in CSR form (host
  * pointers).  For every group the library builds the list of dependent
  * tetrahedra, those with at least one vertex in the group (Sec. 4.2.1), and

@@ -21,7 +21,7 @@ MOREA_OK, MOREA_EINVAL, MOREA_ENOMEM, MOREA_EDEVICE, MOREA_ERANGE, MOREA_ESTATE 
 STORE = {"f32": 0, "bf16": 1, "f16": 2}
 
 EXPORTS = ["morea_problem_create", "morea_problem_destroy", "morea_cache_bytes", "morea_eval_full",
-           "morea_eval_sobol", "morea_repair_folds", "morea_rasterize_dvf",
+           "morea_eval_sobol", "morea_repair_folds", "morea_rasterize_dvf", "morea_point_guidance",
            "morea_set_groups", "morea_reserve_partial", "morea_eval_partial",
            "morea_debug_distance_map", "morea_tune_partial", "morea_partial_shape",
            "morea_surrogate_num_params", "morea_surrogate_num_features", "morea_surrogate_create",
@@ -77,6 +77,8 @@ def load_library():
     L.morea_repair_folds.restype = I32
     L.morea_rasterize_dvf.argtypes = [P, P, P, P, P, P, P]
     L.morea_rasterize_dvf.restype = I32
+    L.morea_point_guidance.argtypes = [P, P, I32, P, P, P]
+    L.morea_point_guidance.restype = I32
     L.morea_set_groups.argtypes = [P, I32, P, P]
     L.morea_set_groups.restype = I32
     L.morea_reserve_partial.argtypes = [P, I32]
@@ -348,6 +350,19 @@ class Problem:
                                                   _dev_ptr(out["inv"]), _dev_ptr(out["cover"]),
                                                   _dev_ptr(out["work"]), _stream_ptr(stream)))
         return out
+
+    def point_guidance(self, pts, stream=None):
+        """Point-based guidance error of candidates pts float32 CUDA
+        [pop][2][3][n_points]: (f [pop] float32, unmapped [pop] int32)."""
+        import torch
+        assert pts.is_cuda and pts.dtype == torch.float32 and pts.is_contiguous()
+        pop = pts.shape[0]
+        assert tuple(pts.shape[1:]) == (2, 3, self.n_points)
+        f = torch.empty(pop, dtype=torch.float32, device="cuda")
+        un = torch.empty(pop, dtype=torch.int32, device="cuda")
+        _check(load_library().morea_point_guidance(self.handle, _dev_ptr(pts), pop, _dev_ptr(f), _dev_ptr(un),
+                                                   _stream_ptr(stream)))
+        return f, un
 
     def set_groups(self, grp_off, grp_pts):
         morea_set_groups(self.handle, grp_off, grp_pts)

@@ -235,6 +235,8 @@ morea_status morea_problem_create(const morea_problem_desc* d, morea_problem** o
       if (st != MOREA_OK) break;
       e = launch_distance_maps(nx, ny, nz, d->n_sets, doff, dpts, radius, dm, band, nullptr);
       if (e != hipSuccess) guard(hip_fail(e, "distance map kernel"));
+      p->d_set_off[m] = doff;
+      p->d_set_fix[m] = dpts;
     } else {
       e = hipMemset(band, 0, PV);
       if (e != hipSuccess) guard(hip_fail(e, "hipMemset"));

@@ -13,6 +13,14 @@
 // atomic minimum of the tet index and counts the covering tets, the second
 // lets the owner write the displacement (FP64 barycentric image, rounded once
 // to FP32).
+//
+// The same exact point location gives the point-based guidance error of the
+// paper's prior work, which Sec. 4.1.3 replaces by the continuous form: every
+// point c of C_s is located in the source mesh (smallest tet index if
+// several), mapped to the target mesh through its barycentric coordinates,
+// and its squared distance to the nearest point of the set's C_t taken; the
+// value is the mean over all points of all sets (sets weighted |C_i| / |G|);
+// points in no tet are left out and counted.
 #include <math.h>
 #include <stdio.h>
 
@@ -156,6 +164,128 @@ __global__ __launch_bounds__(256) void k_dvf_pass(ProblemView P, const float* ca
   }
 }
 
+// Point-based guidance: one block of 4 waves per candidate; wave w takes the
+// source guidance points w, w + 4, ... in order and sums their squared
+// distances in FP64; the 4 sums are added in wave order.
+__global__ __launch_bounds__(256) void k_point_guidance(ProblemView P, const float* pts, const int* off_s,
+                                                      const int* fix_s, const int* off_t, const int* fix_t,
+                                                      float* f, int* unmapped) {
+  extern __shared__ int X[];                 // [2][n][3] snapped coordinates
+  __shared__ double wsum[4];
+  __shared__ int wcnt[4], wun[4], bad;
+  const int n = P.n_points, c = blockIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6)), lane = lane_id();
+  const float* cp = pts + static_cast<size_t>(c) * 6 * n;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < 6 * n; i += blockDim.x) {
+    const int m = i / (3 * n), a = (i / n) % 3, v = i % n;
+    const float x = cp[i];
+    if (!(fabsf(x) < kCoordLimit)) bad = 1;
+    X[(m * n + v) * 3 + a] = fabsf(x) < kCoordLimit ? static_cast<int>(rintf(x * kFixOne)) : 0;
+  }
+  __syncthreads();
+  if (bad) {
+    if (threadIdx.x == 0) {
+      f[c] = __builtin_nanf("");
+      unmapped[c] = 0;
+    }
+    return;
+  }
+  const int G = P.n_sets > 0 ? off_s[P.n_sets] : 0;
+  double sum = 0.0;
+  int cnt = 0, un = 0;
+  for (int g = wave; g < G; g += 4) {
+    int s = 0;
+    while (off_s[s + 1] <= g) s++;
+    const int64_t cpt[3] = {fix_s[3 * g], fix_s[3 * g + 1], fix_s[3 * g + 2]};
+    // the smallest tet of the source mesh that holds the point
+    int hit_t = -1;
+    for (int base = 0; base < P.n_tets && hit_t < 0; base += 64) {
+      const int t = base + lane;
+      bool hit = false;
+      if (t < P.n_tets) {
+        const int4 tv = P.tets[t];
+        const int vi[4] = {tv.x, tv.y, tv.z, tv.w};
+        int64_t own[4][3];
+        bool in_box = true;
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+          int64_t mn = INT64_MAX, mx = INT64_MIN;
+#pragma unroll
+          for (int i = 0; i < 4; i++) {
+            own[i][k] = X[3 * vi[i] + k];
+            mn = min(mn, own[i][k]);
+            mx = max(mx, own[i][k]);
+          }
+          in_box = in_box && cpt[k] >= mn && cpt[k] <= mx;
+        }
+        if (in_box) {
+          const i128 D = vol6(own[0], own[1], own[2], own[3]);
+          i128 val[4];
+          hit = D != 0 && inside(own, D > 0 ? 1 : -1, cpt, val);
+        }
+      }
+      const uint64_t m = __ballot(hit);
+      if (m != 0ull) hit_t = base + __builtin_ctzll(m);
+    }
+    if (hit_t < 0) {
+      un += 1;
+      continue;
+    }
+    // its image in the target mesh (every lane, the same tet)
+    const int4 tv = P.tets[hit_t];
+    const int vi[4] = {tv.x, tv.y, tv.z, tv.w};
+    int64_t own[4][3], oth[4][3];
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+      for (int k = 0; k < 3; k++) {
+        own[i][k] = X[3 * vi[i] + k];
+        oth[i][k] = X[3 * (n + vi[i]) + k];
+      }
+    const i128 D = vol6(own[0], own[1], own[2], own[3]);
+    i128 val[4];
+    (void)inside(own, D > 0 ? 1 : -1, cpt, val);
+    const double inv_absD = 1.0 / static_cast<double>(D > 0 ? D : -D);
+    double q[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+      double qa = static_cast<double>(oth[0][a]);
+#pragma unroll
+      for (int i = 1; i < 4; i++)
+        qa += static_cast<double>(val[i]) * inv_absD * static_cast<double>(oth[i][a] - oth[0][a]);
+      q[a] = qa * (1.0 / 1024.0);
+    }
+    // nearest point of the set's C_t
+    double best = INFINITY;
+    for (int k = off_t[s] + lane; k < off_t[s + 1]; k += 64) {
+      double d2 = 0.0;
+#pragma unroll
+      for (int a = 0; a < 3; a++) {
+        const double diff = q[a] - static_cast<double>(fix_t[3 * k + a]) * (1.0 / 1024.0);
+        d2 = fma(diff, diff, d2);
+      }
+      best = fmin(best, d2);
+    }
+    for (int dd = 32; dd >= 1; dd >>= 1) best = fmin(best, __shfl_xor(best, dd, 64));
+    sum += best;
+    cnt += 1;
+  }
+  if (lane == 0) {
+    wsum[wave] = sum;
+    wcnt[wave] = cnt;
+    wun[wave] = un;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double total = ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3];
+    const int nn = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+    f[c] = nn > 0 ? static_cast<float>(total / nn) : __builtin_nanf("");
+    unmapped[c] = wun[0] + wun[1] + wun[2] + wun[3];
+  }
+}
+
 }  // namespace dvf
 }  // namespace morea
 
@@ -186,6 +316,46 @@ extern "C" morea_status morea_rasterize_dvf(morea_problem* p, const float* cand,
   if (e != hipSuccess) {
     char buf[256];
     snprintf(buf, sizeof(buf), "DVF rasterization: %s", hipGetErrorString(e));
+    set_error(buf);
+    return MOREA_EDEVICE;
+  }
+  return MOREA_OK;
+}
+
+extern "C" morea_status morea_point_guidance(morea_problem* p, const float* pts, int32_t pop, float* f,
+                                             int32_t* unmapped, void* stream) {
+  if (!p || pop < 0) {
+    set_error("bad argument");
+    return MOREA_EINVAL;
+  }
+  if (pop == 0) return MOREA_OK;
+  if (!pts || !f || !unmapped) {
+    set_error("NULL argument");
+    return MOREA_EINVAL;
+  }
+  const ProblemView& P = p->view;
+  if (P.n_points > 6144) {
+    set_error("point-based guidance keeps a candidate in LDS: at most 6144 points per mesh");
+    return MOREA_ERANGE;
+  }
+  {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+      set_error(hipGetErrorString(e));
+      return MOREA_EDEVICE;
+    }
+  }
+  const size_t lds = sizeof(int) * 6 * static_cast<size_t>(P.n_points);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(dvf::k_point_guidance),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(dvf::k_point_guidance, dim3(pop), dim3(256), lds, static_cast<hipStream_t>(stream), P, pts,
+                       p->d_set_off[0], p->d_set_fix[0], p->d_set_off[1], p->d_set_fix[1], f, unmapped);
+    e = hipGetLastError();
+  }
+  if (e != hipSuccess) {
+    char buf[256];
+    snprintf(buf, sizeof(buf), "point-based guidance: %s", hipGetErrorString(e));
     set_error(buf);
     return MOREA_EDEVICE;
   }

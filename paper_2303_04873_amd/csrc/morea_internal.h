@@ -127,6 +127,9 @@ struct morea_problem {
   int* d_pinc = nullptr;
   int* d_nb_off = nullptr;
   int* d_nb = nullptr;
+  // guidance sets per image: CSR offsets [n_sets + 1] and snapped points [*][3]
+  int* d_set_off[2] = {nullptr, nullptr};
+  int* d_set_fix[2] = {nullptr, nullptr};
   morea::Totals* work_totals = nullptr;    // [max_population]
   // family of subsets
   int n_groups = 0;
