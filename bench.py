@@ -220,7 +220,8 @@ def form_repair(p, pop_np, steps):
 
 def form_dvf(p, pop_np, steps):
     """Config 2: forward and inverse DVF of one candidate (both 128x128x96
-    grids), rasterized from its two meshes."""
+    grids), rasterized from its two meshes; the point-based guidance error of
+    the 512 candidates."""
     import torch
 
     import oracle
@@ -232,10 +233,24 @@ def form_dvf(p, pop_np, steps):
     fwd, inv, cover = oracle.Problem.from_synth(p).dvf(pop_np[1])
     err = max(float(np.max(np.abs(out["fwd"].cpu().numpy() - fwd))), float(np.max(np.abs(out["inv"].cpu().numpy() - inv))))
     V = int(np.prod(p.dims))
+    # the point-based guidance error of the whole population
+    prob_all = morea.Problem.from_synth(p, max_population=pop_np.shape[0])
+    pts = torch.from_numpy(pop_np).cuda()
+    ms_pg = timed(lambda: prob_all.point_guidance(pts), steps, 2)
+    fg, un = prob_all.point_guidance(pts)
+    idx = [0, pop_np.shape[0] - 1]
+    fo, uno = oracle.Problem.from_synth(p).point_guidance(pop_np[idx])
+    rel = float(np.max(np.abs(fg.cpu().numpy()[idx] - fo) / np.abs(fo)))
     return {"workload": f"candidate 1, {p.n_tets} tets per mesh, two {p.dims[0]}x{p.dims[1]}x{p.dims[2]} fields",
             "ms_per_candidate": ms, "voxels_per_s": 2 * V / (ms * 1e-3),
             "parity": {"cover_exact": bool(np.array_equal(out["cover"].cpu().numpy(), cover)),
-                       "max_abs_err_voxels": err}}
+                       "max_abs_err_voxels": err},
+            "point_guidance": {"workload": f"{pop_np.shape[0]} candidates x {sum(len(s) for s in p.sets_src)} "
+                                           f"guidance points located among {p.n_tets} tets",
+                               "ms_per_population": ms_pg,
+                               "unmapped_points": int(un.cpu().numpy().sum()),
+                               "parity": {"candidates": idx, "max_rel_err": rel,
+                                          "unmapped_exact": bool(np.array_equal(un.cpu().numpy()[idx], uno))}}}
 
 
 def form_reduced(steps):
