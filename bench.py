@@ -11,7 +11,8 @@ Prints one JSON line: the plain full evaluation's throughput, its roofline
 (VALU-bound; HBM traffic from the committed counter summary), the oracle's
 CPU rate on a bounded sample, and the other forms (partial evaluation,
 reduced-precision storage, surrogate pre-screen, Sobol-sampled estimator,
-fold repair, DVF rasterization).
+fold repair, DVF rasterization, one generation's colour-batched partial
+evaluations).
 --gpus above 1 is refused: evaluation here runs on one GPU.
 """
 import argparse
@@ -87,9 +88,9 @@ def parse():
     ap.add_argument("--parity-samples", type=int, default=3)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this size first (counter calibration)")
-    ap.add_argument("--forms", default="partial,reduced,surrogate,sobol,repair,dvf",
+    ap.add_argument("--forms", default="partial,reduced,surrogate,sobol,repair,dvf,generation",
                     help="comma list of the other forms to measure after the main timing "
-                         "(partial, reduced, surrogate, sobol, repair, dvf) or 'none'")
+                         "(partial, reduced, surrogate, sobol, repair, dvf, generation) or 'none'")
     return ap.parse_args()
 
 
@@ -251,6 +252,68 @@ def form_dvf(p, pop_np, steps):
                                "unmapped_points": int(un.cpu().numpy().sum()),
                                "parity": {"candidates": idx, "max_rel_err": rel,
                                           "unmapped_exact": bool(np.array_equal(un.cpu().numpy()[idx], uno))}}}
+
+
+def form_generation(p, pop_np, prob_full_ms, steps):
+    """Config 2: the evaluation work of one optimizer generation (Sec. 4.2.1):
+    the mesh's FOS elements (set-cover edges) in DSATUR colours, and for each
+    colour one batched partial evaluation of every (solution, element of the
+    colour) child of the 512 solutions, the element's two points moved by
+    N(0, 0.5) (a stand-in for sampling the element's distribution)."""
+    import torch
+
+    import oracle
+    import paper_2303_04873_amd as morea
+    t0 = time.perf_counter()
+    elements, colors, n_colors = morea.build_fos(p.n_points, p.tets)
+    fos_ms = (time.perf_counter() - t0) * 1e3
+    npop = pop_np.shape[0]
+    prob = morea.Problem.from_synth(p, max_population=npop)
+    off = np.arange(0, 2 * len(elements) + 1, 2, dtype=np.int32)
+    prob.set_groups(off, elements.reshape(-1))
+    per_colour = [np.flatnonzero(colors == c).astype(np.int32) for c in range(n_colors)]
+    prob.reserve_partial(npop * max(len(g) for g in per_colour))
+    par = torch.from_numpy(pop_np).cuda()
+    cache = prob.new_cache(npop)
+    prob.eval_full(par, cache=cache)
+    rs = np.random.default_rng(9)
+    fixed = p.fixed_axes
+    batches = []
+    for g in per_colour:
+        ep = np.repeat(np.arange(npop, dtype=np.int32), len(g))
+        eg = np.tile(g, npop)
+        pts = elements[eg]                                        # [n][2] point indices
+        new = pop_np[ep[:, None, None, None], np.arange(2)[None, None, :, None], np.arange(3)[None, None, None, :],
+                     pts[:, :, None, None]].astype(np.float64)    # [n][2 points][2 meshes][3]
+        step = rs.normal(0, 0.5, new.shape) * ~fixed[pts][:, :, None, :]
+        new = (new + step).astype(np.float32).reshape(-1, 2, 3)
+        batches.append((torch.from_numpy(ep).cuda(), torch.from_numpy(eg).cuda(), torch.from_numpy(new).cuda(),
+                        prob.outputs(len(ep)), ep, eg, new))
+
+    def sweep():
+        for dep, deg, dnew, out, *_ in batches:
+            prob.eval_partial(par, cache, dep, deg, dnew, out=out)
+
+    ms = timed(sweep, steps, 2)
+    n_evals = sum(len(b[4]) for b in batches)
+    # parity: two children of the first colour against the oracle's full evaluation
+    dep, deg, dnew, out, ep, eg, new = batches[0]
+    g = {k: v.cpu().numpy() for k, v in out.items()}
+    idx = [0, len(ep) - 1]
+    kids = []
+    for e in idx:
+        child = pop_np[ep[e]].copy()
+        child[:, :, elements[eg[e]]] = new[2 * e:2 * e + 2].transpose(1, 2, 0)
+        kids.append(child)
+    o = oracle.Problem.from_synth(p).evaluate(np.stack(kids))
+    rel = np.abs(g["obj"][idx] - o["obj"]) / np.maximum(np.abs(o["obj"]), 1e-30)
+    exact = bool((g["counts"][idx] == o["counts"]).all() and (g["flags"][idx] == o["flags"]).all())
+    return {"workload": f"{len(elements)} FOS elements (set-cover edges) in {n_colors} colours, {npop} solutions: "
+                        f"{n_evals} partial evaluations per generation in {n_colors} launches",
+            "fos_build_ms_host": fos_ms, "ms_per_generation": ms, "partial_evals_per_s": n_evals / (ms * 1e-3),
+            "vs_plain_full_evals_per_s": n_evals / (ms * 1e-3) / (npop / (prob_full_ms * 1e-3)),
+            "parity": {"evals": idx, "counts_flags_exact": exact,
+                       "max_rel_err": [float(x) for x in rel.max(axis=0)]}}
 
 
 def form_reduced(steps):
@@ -446,6 +509,8 @@ def main():
             forms["fold_repair_config2"] = form_repair(p, pop_np, max(3, args.steps // 4))
         elif name == "dvf":
             forms["dvf_config2"] = form_dvf(p, pop_np, max(3, args.steps // 4))
+        elif name == "generation":
+            forms["generation_config2"] = form_generation(p, pop_np, ms_per_step, max(3, args.steps // 4))
         print(f"# form {name} done in {time.time() - t_form:.1f}s", file=sys.stderr, flush=True)
 
     achieved_ops = samples * SAMPLE_OPS / (launch_ms * 1e-3)

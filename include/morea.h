@@ -215,6 +215,25 @@ morea_status morea_rasterize_dvf(morea_problem *p, const float *cand, float *fwd
 morea_status morea_point_guidance(morea_problem *p, const float *pts, int32_t pop, float *f, int32_t *unmapped,
                                   void *stream);
 
+/* Linkage model of the optimizer's parallel variation (Sec. 4.2.1): the mesh
+ * edges are the FOS elements; a greedy set cover (the edge covering the most
+ * uncovered points, ties to the lexicographically smallest (a, b), a < b)
+ * keeps edges until every point of a tet is covered; two elements interact
+ * when their dependent tets (those holding one of their points) overlap;
+ * DSATUR colours the interaction graph (largest saturation, then degree, then
+ * smaller index; smallest free colour), so the elements of one colour can be
+ * varied and evaluated in parallel -- e.g. registered with morea_set_groups
+ * and evaluated for every (solution, element of the colour) pair in one
+ * morea_eval_partial call.  Host code; all pointers are HOST pointers.
+ *   tets       [n_tets][4] point indices in [0, n_points)
+ *   elem_pts   [capacity][2] receives the elements (a < b), in cover order
+ *   color      [capacity] receives each element's colour
+ *   n_elements, n_colors  receive the counts
+ * Errors: MOREA_EINVAL, MOREA_ERANGE (more elements than capacity; at most
+ * n_points are needed). */
+morea_status morea_build_fos(int32_t n_points, int32_t n_tets, const int32_t *tets, int32_t capacity,
+                             int32_t *elem_pts, int32_t *color, int32_t *n_elements, int32_t *n_colors);
+
 /* Register the family of subsets: n_groups point groups in CSR form (host
  * pointers).  For every group the library builds the list of dependent
  * tetrahedra, those with at least one vertex in the group (Sec. 4.2.1), and

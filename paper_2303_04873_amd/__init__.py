@@ -22,6 +22,7 @@ STORE = {"f32": 0, "bf16": 1, "f16": 2}
 
 EXPORTS = ["morea_problem_create", "morea_problem_destroy", "morea_cache_bytes", "morea_eval_full",
            "morea_eval_sobol", "morea_repair_folds", "morea_rasterize_dvf", "morea_point_guidance",
+           "morea_build_fos",
            "morea_set_groups", "morea_reserve_partial", "morea_eval_partial",
            "morea_debug_distance_map", "morea_tune_partial", "morea_partial_shape",
            "morea_surrogate_num_params", "morea_surrogate_num_features", "morea_surrogate_create",
@@ -79,6 +80,8 @@ def load_library():
     L.morea_rasterize_dvf.restype = I32
     L.morea_point_guidance.argtypes = [P, P, I32, P, P, P]
     L.morea_point_guidance.restype = I32
+    L.morea_build_fos.argtypes = [I32, I32, P, I32, P, P, P, P]
+    L.morea_build_fos.restype = I32
     L.morea_set_groups.argtypes = [P, I32, P, P]
     L.morea_set_groups.restype = I32
     L.morea_reserve_partial.argtypes = [P, I32]
@@ -168,6 +171,19 @@ def morea_eval_sobol(handle, pts, pop, rate, seed, obj, flags, severity, counts,
     _check(load_library().morea_eval_sobol(handle, _dev_ptr(pts), pop, float(rate), int(seed), _dev_ptr(obj),
                                            _dev_ptr(flags), _dev_ptr(severity), _dev_ptr(counts),
                                            _stream_ptr(stream)))
+
+
+def build_fos(n_points, tets):
+    """Linkage model (Sec. 4.2.1) of a mesh: (elements int32 [n][2], colours
+    int32 [n], number of colours) -- host arrays, computed by the library."""
+    t = np.ascontiguousarray(tets, dtype=np.int32)
+    ep = np.empty((n_points, 2), np.int32)
+    col = np.empty(n_points, np.int32)
+    ne, nc = ctypes.c_int32(), ctypes.c_int32()
+    _check(load_library().morea_build_fos(n_points, len(t), t.ctypes.data_as(ctypes.c_void_p), n_points,
+                                          ep.ctypes.data_as(ctypes.c_void_p), col.ctypes.data_as(ctypes.c_void_p),
+                                          ctypes.byref(ne), ctypes.byref(nc)))
+    return ep[:ne.value].copy(), col[:ne.value].copy(), nc.value
 
 
 def morea_set_groups(handle, grp_off, grp_pts):
