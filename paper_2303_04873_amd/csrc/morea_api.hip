@@ -249,6 +249,12 @@ morea_status morea_problem_create(const morea_problem_desc* d, morea_problem** o
     e = launch_band_cells(P, band, cells, nullptr);
     if (e != hipSuccess) guard(hip_fail(e, "band cell kernel"));
     p->band_cell[m] = cells;
+    uint8_t* fgc = nullptr;
+    guard(upload(p, &fgc, nullptr, PV));
+    if (st != MOREA_OK) break;
+    e = launch_fg_cells(P, d->storage, P.img[m], fgc, nullptr);
+    if (e != hipSuccess) guard(hip_fail(e, "foreground cell kernel"));
+    p->fg_cell[m] = fgc;
   }
   if (st == MOREA_OK) {
     const size_t nrec = static_cast<size_t>(d->max_population) * d->n_tets * 2;

@@ -121,6 +121,10 @@ struct morea_problem {
   // per image: at padded element i (the lower corner of a grid cell), the OR
   // of the band bits of the cell's 8 corners i + {0, 1} + {0, px} + {0, pxy}
   uint8_t* band_cell[2] = {nullptr, nullptr};
+  // per image: at padded element i (the lower corner of a cell, i + {0, 1} +
+  // {0, px} + {0, pxy}, for every cell of the padded volume), bit 0 set when
+  // a corner holds a value > 0, bit 1 when all eight do
+  uint8_t* fg_cell[2] = {nullptr, nullptr};
   // point -> incident tets (entries tet << 2 | slot) and point -> neighbours
   // (the other vertices of its incident tets, each once, ascending), CSR
   int* d_pinc_off = nullptr;
@@ -173,6 +177,7 @@ hipError_t launch_finalize(const ProblemView& P, const float* pts, int pop, cons
                            Totals* totals, hipStream_t s);
 int partial_blocks_per_cu(int storage);
 hipError_t launch_band_cells(const ProblemView& P, const uint8_t* band, uint8_t* cells, hipStream_t s);
+hipError_t launch_fg_cells(const ProblemView& P, int storage, const void* img, uint8_t* cells, hipStream_t s);
 void set_error(const char* msg);   // message returned by morea_last_error() on this thread
 hipError_t launch_partial(const ProblemView& P, int storage, const PartialItems& I, int n_parents,
                           int n_groups, const Record* parent_rec, const Totals* parent_tot,

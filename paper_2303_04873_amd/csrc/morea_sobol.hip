@@ -123,8 +123,8 @@ __device__ __forceinline__ float ld(const void* base, int idx) {
 // Trilinear value and exact-support foreground of an image (zero padding) at
 // an FP32 point in grid coordinates.
 template <int ST>
-__device__ __forceinline__ float image_at(const ProblemView& P, const void* img, float x, float y, float z,
-                                          bool& fg) {
+__device__ __forceinline__ float image_at(const ProblemView& P, const void* img, const uint8_t* fgc, float x,
+                                          float y, float z, bool& fg) {
   const float kx = floorf(x), ky = floorf(y), kz = floorf(z);
   const float fx = x - kx, fy = y - ky, fz = z - kz;
   const int ix = static_cast<int>(kx), iy = static_cast<int>(ky), iz = static_cast<int>(kz);
@@ -132,16 +132,23 @@ __device__ __forceinline__ float image_at(const ProblemView& P, const void* img,
   // both corners of an axis lie outside the grid when k <= -2 or k >= n
   if (kx < -1.f || ky < -1.f || kz < -1.f || ix > P.nx - 1 || iy > P.ny - 1 || iz > P.nz - 1) return 0.f;
   const int i0 = (iz + 1) * P.pxy + (iy + 1) * P.px + ix + 1;
+  // a cell without a positive corner is background whatever the support
+  const unsigned code = fgc[i0];
+  if (!(code & 1u)) return 0.f;
   const int i1 = i0 + P.pxy;
   const float c000 = ld<ST>(img, i0), c100 = ld<ST>(img, i0 + 1);
   const float c010 = ld<ST>(img, i0 + P.px), c110 = ld<ST>(img, i0 + P.px + 1);
   const float c001 = ld<ST>(img, i1), c101 = ld<ST>(img, i1 + 1);
   const float c011 = ld<ST>(img, i1 + P.px), c111 = ld<ST>(img, i1 + P.px + 1);
-  const bool ux = fx > 0.f, uy = fy > 0.f, uz = fz > 0.f;
-  const bool f0 = c000 > 0.f || (ux && c100 > 0.f) || (uy && c010 > 0.f) || (ux && uy && c110 > 0.f);
-  const bool f1 = c001 > 0.f || (ux && c101 > 0.f) || (uy && c011 > 0.f) || (ux && uy && c111 > 0.f);
-  fg = f0 || (uz && f1);
-  if (!fg) return 0.f;
+  if (code & 2u) {
+    fg = true;    // every corner is positive, so is every supported one
+  } else {
+    const bool ux = fx > 0.f, uy = fy > 0.f, uz = fz > 0.f;
+    const bool f0 = c000 > 0.f || (ux && c100 > 0.f) || (uy && c010 > 0.f) || (ux && uy && c110 > 0.f);
+    const bool f1 = c001 > 0.f || (ux && c101 > 0.f) || (uy && c011 > 0.f) || (ux && uy && c111 > 0.f);
+    fg = f0 || (uz && f1);
+    if (!fg) return 0.f;
+  }
   const float x00 = fmaf(fx, c100 - c000, c000), x10 = fmaf(fx, c110 - c010, c010);
   const float x01 = fmaf(fx, c101 - c001, c001), x11 = fmaf(fx, c111 - c011, c011);
   const float y0 = fmaf(fy, x10 - x00, x00), y1 = fmaf(fy, x11 - x01, x01);
@@ -196,7 +203,8 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 template <int ST>
 __global__ __launch_bounds__(256) void k_eval_sobol(ProblemView P, const float* pts, int pop, double inv_pop,
                                                   double count_scale, uint64_t seed, const uint8_t* cells0,
-                                                  const uint8_t* cells1, Record* rec, int n_items) {
+                                                  const uint8_t* cells1, const uint8_t* fgc0, const uint8_t* fgc1,
+                                                  Record* rec, int n_items) {
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
   const int item = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
   if (item >= n_items) return;
@@ -329,6 +337,8 @@ __global__ __launch_bounds__(256) void k_eval_sobol(ProblemView P, const float* 
       const void* img_own = d == 0 ? P.img[0] : P.img[1];
       const void* img_oth = d == 0 ? P.img[1] : P.img[0];
       const uint8_t* cells = d == 0 ? cells0 : cells1;
+      const uint8_t* fgc_own = d == 0 ? fgc0 : fgc1;
+      const uint8_t* fgc_oth = d == 0 ? fgc1 : fgc0;
       const float* map_own = d == 0 ? P.dmap[0] : P.dmap[1];
       const float* map_oth = d == 0 ? P.dmap[1] : P.dmap[0];
       const float* set_w = d == 0 ? P.set_w[0] : P.set_w[1];
@@ -359,8 +369,8 @@ __global__ __launch_bounds__(256) void k_eval_sobol(ProblemView P, const float* 
           }
         }
         bool fa, fb;
-        const float a = image_at<ST>(P, img_own, p[0], p[1], p[2], fa);
-        const float b = image_at<ST>(P, img_oth, q[0], q[1], q[2], fb);
+        const float a = image_at<ST>(P, img_own, fgc_own, p[0], p[1], p[2], fa);
+        const float b = image_at<ST>(P, img_oth, fgc_oth, q[0], q[1], q[2], fb);
         h += (fa && fb) ? (a - b) * (a - b) : (fa == fb ? 0.f : 1.f);
         if (P.n_sets > 0) {
           const MapCell cp = map_cell(P, p[0], p[1], p[2]);
@@ -416,7 +426,40 @@ morea_status device_fail(hipError_t e, const char* what) {
   return MOREA_EDEVICE;
 }
 
+// Foreground code per cell (lower corner at padded element i): bit 0 when a
+// corner of the cell holds a value > 0, bit 1 when all eight do.
+template <int ST>
+__global__ void k_fg_cells(ProblemView P, const void* img, uint8_t* cells) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= static_cast<int>(P.pvox)) return;
+  const int x = i % P.px, y = (i / P.px) % (P.ny + 2), z = i / P.pxy;
+  uint8_t v = 0;
+  if (x + 1 < P.px && y + 1 < P.ny + 2 && z + 1 < P.nz + 2) {
+    const int j = i + P.pxy;
+    const int idx[8] = {i, i + 1, i + P.px, i + P.px + 1, j, j + 1, j + P.px, j + P.px + 1};
+    bool any = false, all = true;
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+      const bool pos = ld<ST>(img, idx[k]) > 0.f;
+      any = any || pos;
+      all = all && pos;
+    }
+    v = static_cast<uint8_t>((any ? 1 : 0) | (all ? 2 : 0));
+  }
+  cells[i] = v;
+}
+
 }  // namespace sobol
+
+hipError_t launch_fg_cells(const ProblemView& P, int storage, const void* img, uint8_t* cells, hipStream_t s) {
+  const dim3 grid((P.pvox + 255) / 256);
+  switch (storage) {
+    case kF32: hipLaunchKernelGGL(sobol::k_fg_cells<kF32>, grid, dim3(256), 0, s, P, img, cells); break;
+    case kBF16: hipLaunchKernelGGL(sobol::k_fg_cells<kBF16>, grid, dim3(256), 0, s, P, img, cells); break;
+    default: hipLaunchKernelGGL(sobol::k_fg_cells<kF16>, grid, dim3(256), 0, s, P, img, cells); break;
+  }
+  return hipGetLastError();
+}
 
 hipError_t launch_band_cells(const ProblemView& P, const uint8_t* band, uint8_t* cells, hipStream_t s) {
   hipLaunchKernelGGL(sobol::k_band_cells, dim3((P.pvox + 255) / 256), dim3(256), 0, s, P, band, cells);
@@ -450,17 +493,20 @@ extern "C" morea_status morea_eval_sobol(morea_problem* p, const float* pts, int
     switch (p->storage) {
       case kF32:
         hipLaunchKernelGGL(sobol::k_eval_sobol<kF32>, dim3(blocks), dim3(256), 0, s, P, pts, pop, inv_pop,
-                           count_scale, seed, p->band_cell[0], p->band_cell[1], p->work_records,
+                           count_scale, seed, p->band_cell[0], p->band_cell[1], p->fg_cell[0], p->fg_cell[1],
+                           p->work_records,
                            static_cast<int>(n_items));
         break;
       case kBF16:
         hipLaunchKernelGGL(sobol::k_eval_sobol<kBF16>, dim3(blocks), dim3(256), 0, s, P, pts, pop, inv_pop,
-                           count_scale, seed, p->band_cell[0], p->band_cell[1], p->work_records,
+                           count_scale, seed, p->band_cell[0], p->band_cell[1], p->fg_cell[0], p->fg_cell[1],
+                           p->work_records,
                            static_cast<int>(n_items));
         break;
       default:
         hipLaunchKernelGGL(sobol::k_eval_sobol<kF16>, dim3(blocks), dim3(256), 0, s, P, pts, pop, inv_pop,
-                           count_scale, seed, p->band_cell[0], p->band_cell[1], p->work_records,
+                           count_scale, seed, p->band_cell[0], p->band_cell[1], p->fg_cell[0], p->fg_cell[1],
+                           p->work_records,
                            static_cast<int>(n_items));
         break;
     }
