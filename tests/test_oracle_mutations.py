@@ -1,7 +1,9 @@
 """Each plausible mistake planted in the oracle (on the CPU, in a copy of its
-C source) must make at least one pin fail: the pins constrain every part of
-the definition, not only the code paths they happen to call."""
+C source, or of its Python references for fold repair and the linkage model)
+must make at least one pin fail: the pins constrain every part of the
+definition, not only the code paths they happen to call."""
 import os
+import shutil
 import subprocess
 import sys
 
@@ -11,6 +13,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "morea_oracle.c")
 PINS = os.path.join(ROOT, "tests", "test_oracle_pins.py")
 SOBOL = os.path.join(ROOT, "tests", "test_oracle_sobol.py")
+DVF = os.path.join(ROOT, "tests", "test_oracle_dvf.py")
+POINTS = os.path.join(ROOT, "tests", "test_oracle_point_guidance.py")
 
 MUTATIONS = [
     ("directions swapped in the target->source pass",
@@ -72,6 +76,38 @@ MUTATIONS = [
     ("Sobol: own image read at the mapped point",
      "const double a = fa ? trilinear(img_own, P->nx, P->ny, P->nz, kp, fp, 0) : 0.0;",
      "const double a = fa ? trilinear(img_own, P->nx, P->ny, P->nz, kq, fq, 0) : 0.0;", SOBOL),
+    # deformation vector fields and the point-based guidance error
+    ("DVF: displacement p - q instead of q - p",
+     "out[3 * v + a] = (double)(kq[a] - pv[a]) + fq[a];", "out[3 * v + a] = (double)(pv[a] - kq[a]) - fq[a];", DVF),
+    ("DVF: the last covering tet owns a centre",
+     "if (owner[v] >= 0) continue;", "if (owner[v] > t) continue;", DVF),
+    ("point guidance: distance instead of squared distance",
+     "        total += best;", "        total += sqrt(best);", POINTS),
+    ("point guidance: every tet's bounding box taken as containing the point",
+     "if (!inside_tie(S, D, cp, lam)) continue;", "(void)inside_tie(S, D, cp, lam);", POINTS),
+]
+
+# mistakes planted in copies of the Python references, each run against its pins
+REPAIR = os.path.join(ROOT, "tests", "test_oracle_repair.py")
+FOS = os.path.join(ROOT, "tests", "test_oracle_fos.py")
+PY_MUTATIONS = [
+    ("repair: step twice the rounded-down distance", "repair.py",
+     "while j < SIGMA_MAX_LOG2 and (4 ** (j + 1)) * n * n <= d2:",
+     "while j < SIGMA_MAX_LOG2 and (4 ** j) * n * n <= d2:", REPAIR, []),
+    ("repair: a tie aborts the candidate", "repair.py",
+     "elif best is not None and best[0] == c0:", "elif False:", REPAIR, []),
+    ("repair: pinned axes move", "repair.py",
+     "if not (fixed is not None and (int(fixed[v]) >> a) & 1):", "if True:", REPAIR, []),
+    ("repair: constraint without the folded volume", "repair.py", "sev += abs(D)", "sev += 0", REPAIR, []),
+    ("repair: points visited in descending order", "repair.py",
+     "todo += [(m, v) for v in sorted(pts)]", "todo += [(m, v) for v in sorted(pts, reverse=True)]", REPAIR, []),
+    ("fos: DSATUR ties to the smaller degree", "fos.py",
+     "return (sat, len(adj[v]), -v)", "return (sat, -len(adj[v]), -v)", FOS, ["-k", "not 2"]),
+    ("fos: interaction only between elements sharing a point", "fos.py",
+     "deps = [holding.get(a, set()) | holding.get(b, set()) for a, b in elements]",
+     "deps = [{-1 - a, -1 - b} for a, b in elements]", FOS, ["-k", "not 2"]),
+    ("fos: set cover prefers the last of equally good edges", "fos.py",
+     "if g > gain:", "if g >= gain and g > 0:", FOS, ["-k", "not 2"]),
 ]
 
 
@@ -89,4 +125,17 @@ def test_planted_mistake_is_caught(name, old, new, pins, tmp_path):
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         pins],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, f"no pin caught: {name}\n{r.stdout[-2000:]}"
+
+
+@pytest.mark.parametrize("name,fname,old,new,pins,args", PY_MUTATIONS, ids=[m[0] for m in PY_MUTATIONS])
+def test_planted_python_mistake_is_caught(name, fname, old, new, pins, args, tmp_path):
+    pkg = tmp_path / "oracle"
+    shutil.copytree(os.path.join(ROOT, "oracle"), pkg, ignore=shutil.ignore_patterns("__pycache__"))
+    src = (pkg / fname).read_text()
+    assert src.count(old) == 1, name
+    (pkg / fname).write_text(src.replace(old, new))
+    env = dict(os.environ, PYTHONPATH=os.pathsep.join([str(tmp_path), ROOT]), OMP_NUM_THREADS="4")
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", pins] + args,
+                       cwd=str(tmp_path), env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"no pin caught: {name}\n{r.stdout[-2000:]}"
