@@ -90,6 +90,7 @@ MUTATIONS = [
 # mistakes planted in copies of the Python references, each run against its pins
 REPAIR = os.path.join(ROOT, "tests", "test_oracle_repair.py")
 FOS = os.path.join(ROOT, "tests", "test_oracle_fos.py")
+ACCEPT = os.path.join(ROOT, "tests", "test_oracle_accept.py")
 PY_MUTATIONS = [
     ("repair: step twice the rounded-down distance", "repair.py",
      "while j < SIGMA_MAX_LOG2 and (4 ** (j + 1)) * n * n <= d2:",
@@ -108,6 +109,22 @@ PY_MUTATIONS = [
      "deps = [{-1 - a, -1 - b} for a, b in elements]", FOS, ["-k", "not 2"]),
     ("fos: set cover prefers the last of equally good edges", "fos.py",
      "if g > gain:", "if g >= gain and g > 0:", FOS, ["-k", "not 2"]),
+    ("accept: weak Pareto domination", "accept.py",
+     "and any(x < y for x, y in zip(a, b))", "", ACCEPT, []),
+    ("accept: infeasible preferred over feasible", "accept.py", "        return fa\n", "        return fb\n",
+     ACCEPT, []),
+    ("accept: equal violations dominate", "accept.py", "return va < vb", "return va <= vb", ACCEPT, []),
+    ("accept: archive test reversed", "accept.py",
+     "pareto_dominates(m, child[0]) for m in archive", "pareto_dominates(child[0], m) for m in archive", ACCEPT, []),
+    ("accept: infeasible children through the archive", "accept.py",
+     "return feasible and not any(", "return not any(", ACCEPT, []),
+    ("accept: NaN objectives count as feasible", "accept.py",
+     "if int(flags) & INVALID or any(math.isnan(v) for v in values):", "if int(flags) & INVALID:", ACCEPT, []),
+    ("accept: rows owned by accepted evaluations only", "accept.py",
+     "            out[int(eval_parent[e])][:, :, idx] = new_coords[row:row + len(idx)].transpose(1, 2, 0)\n"
+     "        row += len(idx)",
+     "            out[int(eval_parent[e])][:, :, idx] = new_coords[row:row + len(idx)].transpose(1, 2, 0)\n"
+     "            row += len(idx)", ACCEPT, []),
 ]
 
 
