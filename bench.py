@@ -12,7 +12,7 @@ Prints one JSON line: the plain full evaluation's throughput, its roofline
 CPU rate on a bounded sample, and the other forms (partial evaluation,
 reduced-precision storage, surrogate pre-screen, Sobol-sampled estimator,
 fold repair, DVF rasterization, one generation's colour-batched partial
-evaluations).
+evaluations and acceptances).
 --gpus above 1 is refused: evaluation here runs on one GPU.
 """
 import argparse
@@ -255,11 +255,14 @@ def form_dvf(p, pop_np, steps):
 
 
 def form_generation(p, pop_np, prob_full_ms, steps):
-    """Config 2: the evaluation work of one optimizer generation (Sec. 4.2.1):
-    the mesh's FOS elements (set-cover edges) in DSATUR colours, and for each
-    colour one batched partial evaluation of every (solution, element of the
-    colour) child of the 512 solutions, the element's two points moved by
-    N(0, 0.5) (a stand-in for sampling the element's distribution)."""
+    """Config 2: the evaluation work of one optimizer generation (Sec. 4.2.1,
+    Sec. 3): the mesh's FOS elements (set-cover edges) in DSATUR colours; for
+    each colour one batched partial evaluation of every (solution, element of
+    the colour) child of the 512 solutions, the element's two points moved by
+    N(0, 0.5) (a stand-in for sampling the element's distribution), then the
+    acceptance of the children against their parents and an elitist archive
+    (the non-dominated feasible parents of the start), written back into the
+    parents, their caches and their evaluations."""
     import torch
 
     import oracle
@@ -275,7 +278,12 @@ def form_generation(p, pop_np, prob_full_ms, steps):
     prob.reserve_partial(npop * max(len(g) for g in per_colour))
     par = torch.from_numpy(pop_np).cuda()
     cache = prob.new_cache(npop)
-    prob.eval_full(par, cache=cache)
+    par_out = prob.eval_full(par, cache=cache)
+    start = {k: v.cpu().numpy() for k, v in par_out.items()}
+    feas = np.flatnonzero(start["flags"] == 0)
+    fo = start["obj"][feas]
+    front = [i for i in range(len(fo)) if not np.any(np.all(fo <= fo[i], axis=1) & np.any(fo < fo[i], axis=1))]
+    archive = torch.from_numpy(np.ascontiguousarray(fo[front], dtype=np.float32)).cuda()
     rs = np.random.default_rng(9)
     fixed = p.fixed_axes
     batches = []
@@ -288,16 +296,22 @@ def form_generation(p, pop_np, prob_full_ms, steps):
         step = rs.normal(0, 0.5, new.shape) * ~fixed[pts][:, :, None, :]
         new = (new + step).astype(np.float32).reshape(-1, 2, 3)
         batches.append((torch.from_numpy(ep).cuda(), torch.from_numpy(eg).cuda(), torch.from_numpy(new).cuda(),
-                        prob.outputs(len(ep)), ep, eg, new))
+                        prob.outputs(len(ep)), torch.empty(len(ep), dtype=torch.uint8, device="cuda"), ep, eg, new))
 
-    def sweep():
-        for dep, deg, dnew, out, *_ in batches:
+    def evaluate_only():
+        for dep, deg, dnew, out, _, *_ in batches:
             prob.eval_partial(par, cache, dep, deg, dnew, out=out)
 
-    ms = timed(sweep, steps, 2)
-    n_evals = sum(len(b[4]) for b in batches)
-    # parity: two children of the first colour against the oracle's full evaluation
-    dep, deg, dnew, out, ep, eg, new = batches[0]
+    def generation():
+        for dep, deg, dnew, out, acc, *_ in batches:
+            prob.eval_partial(par, cache, dep, deg, dnew, out=out)
+            prob.accept_partial(par, cache, dep, deg, dnew, out, par_out, archive=archive, accepted=acc)
+
+    # parity on the first generation: two children of the first colour against
+    # the oracle's full evaluation, then, after the whole generation, two
+    # updated parents against the oracle and all against a fresh evaluation
+    dep, deg, dnew, out, acc, ep, eg, new = batches[0]
+    prob.eval_partial(par, cache, dep, deg, dnew, out=out)
     g = {k: v.cpu().numpy() for k, v in out.items()}
     idx = [0, len(ep) - 1]
     kids = []
@@ -305,15 +319,38 @@ def form_generation(p, pop_np, prob_full_ms, steps):
         child = pop_np[ep[e]].copy()
         child[:, :, elements[eg[e]]] = new[2 * e:2 * e + 2].transpose(1, 2, 0)
         kids.append(child)
-    o = oracle.Problem.from_synth(p).evaluate(np.stack(kids))
+    op = oracle.Problem.from_synth(p)
+    o = op.evaluate(np.stack(kids))
     rel = np.abs(g["obj"][idx] - o["obj"]) / np.maximum(np.abs(o["obj"]), 1e-30)
     exact = bool((g["counts"][idx] == o["counts"]).all() and (g["flags"][idx] == o["flags"]).all())
+    generation()
+    torch.cuda.synchronize()
+    kept = sum(int(b[4].sum().item()) for b in batches)
+    upd = par.cpu().numpy()
+    mine = {k: v.cpu().numpy() for k, v in par_out.items()}
+    fresh = {k: v.cpu().numpy() for k, v in prob.eval_full(par.clone()).items()}
+    moved = np.flatnonzero(np.any(upd != pop_np, axis=(1, 2, 3)))
+    pick = [int(moved[0]), int(moved[-1])] if len(moved) else [0]
+    o2 = op.evaluate(upd[pick])
+    rel2 = np.abs(mine["obj"][pick] - o2["obj"]) / np.maximum(np.abs(o2["obj"]), 1e-30)
+    exact2 = bool((mine["counts"][pick] == o2["counts"]).all() and (mine["flags"][pick] == o2["flags"]).all())
+    same_as_fresh = bool((mine["flags"] == fresh["flags"]).all() and (mine["counts"] == fresh["counts"]).all()
+                         and np.allclose(mine["obj"], fresh["obj"], rtol=1e-6, equal_nan=True))
+    ms_eval = timed(evaluate_only, steps, 1)
+    ms = timed(generation, steps, 1)
+    n_evals = sum(len(b[5]) for b in batches)
     return {"workload": f"{len(elements)} FOS elements (set-cover edges) in {n_colors} colours, {npop} solutions: "
-                        f"{n_evals} partial evaluations per generation in {n_colors} launches",
-            "fos_build_ms_host": fos_ms, "ms_per_generation": ms, "partial_evals_per_s": n_evals / (ms * 1e-3),
+                        f"{n_evals} partial evaluations and acceptances per generation in {n_colors} launches each, "
+                        f"archive of {archive.shape[0]}",
+            "fos_build_ms_host": fos_ms, "ms_per_generation": ms, "ms_evaluations_only": ms_eval,
+            "ms_acceptance": ms - ms_eval, "partial_evals_per_s": n_evals / (ms * 1e-3),
+            "accepted_first_generation": kept, "parents_changed_first_generation": int(len(moved)),
             "vs_plain_full_evals_per_s": n_evals / (ms * 1e-3) / (npop / (prob_full_ms * 1e-3)),
             "parity": {"evals": idx, "counts_flags_exact": exact,
-                       "max_rel_err": [float(x) for x in rel.max(axis=0)]}}
+                       "max_rel_err": [float(x) for x in rel.max(axis=0)],
+                       "parents_after_acceptance": pick, "parents_counts_flags_exact": exact2,
+                       "parents_max_rel_err": [float(x) for x in rel2.max(axis=0)],
+                       "parents_match_fresh_full_evaluation": same_as_fresh}}
 
 
 def form_reduced(steps):

@@ -281,6 +281,48 @@ morea_status morea_eval_partial(morea_problem *p, const float *parent_pts, int32
                                 const float *new_coords, float *obj, uint8_t *flags,
                                 float *severity, uint32_t *counts, void *stream);
 
+/* Acceptance of the evaluated partial solutions (Sec. 3 optimal mixing): a
+ * child (parent with its group's points moved) is kept when it dominates its
+ * parent or is not dominated within the elitist archive; kept children are
+ * written into their parents.  All three objectives are minimised.
+ *   domination child vs parent: constraint domination -- a feasible solution
+ *     (flags & 7 == 0) beats an infeasible one; two infeasible ones compare
+ *     their violation (severity; +inf with flags bit 2 or a NaN objective or
+ *     severity), the strictly smaller wins; two feasible ones compare by
+ *     Pareto domination (no objective worse, one strictly better);
+ *   archive: feasible objective vectors; a feasible child is non-dominated
+ *     when no member Pareto-dominates it (a member equal to it does not);
+ *   an evaluation with an out-of-range parent or group is rejected.
+ * For every kept evaluation e the group's new coordinates are written into
+ * parent_pts[eval_parent[e]] and the partial evaluation's records of the
+ * group's dependent tets into the parent's cache; then the totals in the
+ * cache and the parents' obj / flags / severity / counts are recomputed from
+ * the cached records of every parent (as morea_eval_full reports them).
+ *   parent_pts, n_parents, parent_cache, n_evals, eval_parent, eval_group,
+ *   new_coords   exactly the arguments (and contents) of the preceding
+ *                morea_eval_partial on this problem, whose records are read
+ *                from the library's workspace (MOREA_ESTATE otherwise, or
+ *                after morea_tune_partial / morea_set_groups /
+ *                morea_reserve_partial); parent_cache 16-byte aligned
+ *   child_obj, child_flags, child_sev   [n_evals] decision inputs, normally
+ *                the outputs of that call (layout of morea_eval_full)
+ *   parent_obj, parent_flags, parent_sev, parent_counts   [n_parents] the
+ *                parents' evaluation: read for the decisions, rewritten
+ *   archive_obj  [n_archive][3] FP32 (NULL when n_archive == 0)
+ *   accepted     [n_evals] receives 1 (kept) or 0
+ * The kept evaluations of one parent must have pairwise disjoint dependent
+ * tets (e.g. the elements of one colour of morea_build_fos); otherwise which
+ * child's values a shared tet or point keeps is unspecified (every write
+ * still stays inside the parent's arrays).  All arrays are device pointers;
+ * asynchronous on `stream`; no allocation.  Errors: MOREA_EINVAL,
+ * MOREA_ESTATE, MOREA_EDEVICE. */
+morea_status morea_accept_partial(morea_problem *p, float *parent_pts, int32_t n_parents, void *parent_cache,
+                                  int32_t n_evals, const int32_t *eval_parent, const int32_t *eval_group,
+                                  const float *new_coords, const float *child_obj, const uint8_t *child_flags,
+                                  const float *child_sev, float *parent_obj, uint8_t *parent_flags,
+                                  float *parent_sev, uint32_t *parent_counts, const float *archive_obj,
+                                  int32_t n_archive, uint8_t *accepted, void *stream);
+
 /* Copy the distance map d(p, C) of guidance set `set` on image `image`
  * (0 = I_s grid with C_s, 1 = I_t grid with C_t) to host memory `host_out`
  * ([nz][ny][nx] FP32), and, when `band_out` is not NULL, the per-voxel band

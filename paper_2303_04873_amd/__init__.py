@@ -23,7 +23,7 @@ STORE = {"f32": 0, "bf16": 1, "f16": 2}
 EXPORTS = ["morea_problem_create", "morea_problem_destroy", "morea_cache_bytes", "morea_eval_full",
            "morea_eval_sobol", "morea_repair_folds", "morea_rasterize_dvf", "morea_point_guidance",
            "morea_build_fos",
-           "morea_set_groups", "morea_reserve_partial", "morea_eval_partial",
+           "morea_set_groups", "morea_reserve_partial", "morea_eval_partial", "morea_accept_partial",
            "morea_debug_distance_map", "morea_tune_partial", "morea_partial_shape",
            "morea_surrogate_num_params", "morea_surrogate_num_features", "morea_surrogate_create",
            "morea_surrogate_destroy", "morea_surrogate_features", "morea_surrogate_targets",
@@ -88,6 +88,8 @@ def load_library():
     L.morea_reserve_partial.restype = I32
     L.morea_eval_partial.argtypes = [P, P, I32, P, I32, P, P, P, P, P, P, P, P]
     L.morea_eval_partial.restype = I32
+    L.morea_accept_partial.argtypes = [P, P, I32, P, I32, P, P, P, P, P, P, P, P, P, P, P, I32, P, P]
+    L.morea_accept_partial.restype = I32
     L.morea_tune_partial.argtypes = [P, P, I32, P, I32, P, P, P, P, P, P, P, P, P]
     L.morea_tune_partial.restype = I32
     L.morea_partial_shape.argtypes = [P, P, P]
@@ -203,6 +205,17 @@ def morea_eval_partial(handle, parent_pts, n_parents, parent_cache, n_evals, eva
         handle, _dev_ptr(parent_pts), n_parents, _dev_ptr(parent_cache), n_evals,
         _dev_ptr(eval_parent), _dev_ptr(eval_group), _dev_ptr(new_coords), _dev_ptr(obj),
         _dev_ptr(flags), _dev_ptr(severity), _dev_ptr(counts), _stream_ptr(stream)))
+
+
+def morea_accept_partial(handle, parent_pts, n_parents, parent_cache, n_evals, eval_parent, eval_group,
+                         new_coords, child_obj, child_flags, child_sev, parent_obj, parent_flags, parent_sev,
+                         parent_counts, archive_obj, n_archive, accepted, stream):
+    _check(load_library().morea_accept_partial(
+        handle, _dev_ptr(parent_pts), n_parents, _dev_ptr(parent_cache), n_evals,
+        _dev_ptr(eval_parent), _dev_ptr(eval_group), _dev_ptr(new_coords), _dev_ptr(child_obj),
+        _dev_ptr(child_flags), _dev_ptr(child_sev), _dev_ptr(parent_obj), _dev_ptr(parent_flags),
+        _dev_ptr(parent_sev), _dev_ptr(parent_counts), _dev_ptr(archive_obj), n_archive, _dev_ptr(accepted),
+        _stream_ptr(stream)))
 
 
 def morea_tune_partial(handle, parent_pts, n_parents, parent_cache, n_evals, eval_parent, eval_group,
@@ -394,6 +407,26 @@ class Problem:
                            eval_parent, eval_group, new_coords, out["obj"], out["flags"],
                            out["severity"], out["counts"], stream)
         return out
+
+    def accept_partial(self, parent_pts, parent_cache, eval_parent, eval_group, new_coords, child, parent,
+                       archive=None, accepted=None, stream=None):
+        """Acceptance after eval_partial with the same first five arguments
+        (Sec. 3): `child` the decision inputs (the outputs of eval_partial),
+        `parent` the parents' outputs dict (rewritten with the evaluation of
+        the updated parents), `archive` FP32 CUDA [m][3] or None.  Updates
+        parent_pts and parent_cache in place; returns `accepted` (uint8)."""
+        import torch
+        n = eval_parent.shape[0]
+        if accepted is None:
+            accepted = torch.empty(n, dtype=torch.uint8, device="cuda")
+        m = 0 if archive is None else archive.shape[0]
+        if archive is not None:
+            assert archive.is_cuda and archive.dtype == torch.float32 and archive.is_contiguous()
+        morea_accept_partial(self.handle, parent_pts, parent_pts.shape[0], parent_cache, n, eval_parent, eval_group,
+                             new_coords, child["obj"], child["flags"], child["severity"], parent["obj"],
+                             parent["flags"], parent["severity"], parent["counts"], archive if m else None, m,
+                             accepted, stream)
+        return accepted
 
     def tune_partial(self, parent_pts, parent_cache, eval_parent, eval_group, new_coords, out=None,
                      stream=None):

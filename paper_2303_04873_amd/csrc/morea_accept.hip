@@ -1,0 +1,208 @@
+// Acceptance of partial solutions in optimal mixing (Sec. 3): a sampled
+// partial solution, inserted into its parent, is kept when the result
+// dominates the parent or is not dominated within the current elitist
+// archive.  Kept children are written into their parents: the group's new
+// coordinates into the parent's points, the dependent tets' records of the
+// partial evaluation into the parent's cache, and the parent's totals and
+// objectives recomputed from the cache.
+//
+// Definitions where the paper leaves the details to MO-RV-GOMEA's
+// literature (all three objectives are minimised):
+//   feasible: flags == 0 in the fold and invalid bits; violation = severity
+//     (summed |signed volume| of the violating tets) when a fold bit is set,
+//     +inf when the invalid bit is set or an objective or the severity is NaN;
+//   child vs parent: constraint domination -- feasible beats infeasible, two
+//     infeasible compare violations (strictly smaller wins), two feasible
+//     compare by Pareto domination (none worse, one strictly better);
+//   archive: feasible objective vectors; a feasible child is non-dominated
+//     when no member Pareto-dominates it (an equal member does not);
+//   an evaluation whose parent or group index is out of range is rejected.
+//
+// Three launches: the decisions (one thread per evaluation, the archive
+// staged through LDS in chunks shared by the block), the write-back (one
+// wave per evaluation: 48-byte record pairs as three 16-byte vectors, then
+// the group's coordinates), and the per-candidate reduction of the
+// evaluation over the parents' caches.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "morea_internal.h"
+
+namespace morea {
+namespace accept {
+
+constexpr int kBlock = 256;
+constexpr int kChunk = 512;   // archive members staged per pass (6 KB of LDS)
+
+__device__ __forceinline__ bool feasible_of(float o0, float o1, float o2, uint8_t f, float sev, float& viol) {
+  if ((f & 4u) || isnan(o0) || isnan(o1) || isnan(o2) || isnan(sev)) {
+    viol = INFINITY;
+    return false;
+  }
+  if (f & 3u) {
+    viol = sev;
+    return false;
+  }
+  viol = 0.f;
+  return true;
+}
+
+__device__ __forceinline__ bool pareto(float a0, float a1, float a2, float b0, float b1, float b2) {
+  return a0 <= b0 && a1 <= b1 && a2 <= b2 && (a0 < b0 || a1 < b1 || a2 < b2);
+}
+
+__global__ __launch_bounds__(kBlock) void k_decide(int n_evals, int n_parents, int n_groups,
+                                                   const int* __restrict__ eval_parent,
+                                                   const int* __restrict__ eval_group,
+                                                   const float* __restrict__ child_obj,
+                                                   const uint8_t* __restrict__ child_flags,
+                                                   const float* __restrict__ child_sev,
+                                                   const float* __restrict__ parent_obj,
+                                                   const uint8_t* __restrict__ parent_flags,
+                                                   const float* __restrict__ parent_sev,
+                                                   const float* __restrict__ archive, int n_archive,
+                                                   uint8_t* __restrict__ accepted) {
+  __shared__ float s_arc[kChunk * 3];
+  const int e = blockIdx.x * kBlock + threadIdx.x;
+  bool decided = true, ok = false;
+  float c0 = 0.f, c1 = 0.f, c2 = 0.f;
+  if (e < n_evals) {
+    const int par = eval_parent[e], g = eval_group[e];
+    if (par >= 0 && par < n_parents && g >= 0 && g < n_groups) {
+      c0 = child_obj[3 * e];
+      c1 = child_obj[3 * e + 1];
+      c2 = child_obj[3 * e + 2];
+      float vc, vp;
+      const bool fc = feasible_of(c0, c1, c2, child_flags[e], child_sev[e], vc);
+      const float p0 = parent_obj[3 * par], p1 = parent_obj[3 * par + 1], p2 = parent_obj[3 * par + 2];
+      const bool fp = feasible_of(p0, p1, p2, parent_flags[par], parent_sev[par], vp);
+      const bool dom = (fc && fp) ? pareto(c0, c1, c2, p0, p1, p2) : (fc != fp ? fc : vc < vp);
+      if (dom) {
+        ok = true;
+      } else if (fc) {
+        ok = true;          // until a member of the archive dominates it
+        decided = false;
+      }
+    }
+  }
+  for (int base = 0; base < n_archive; base += kChunk) {
+    if (!__syncthreads_or(decided ? 0 : 1)) break;
+    const int m = min(kChunk, n_archive - base);
+    for (int i = threadIdx.x; i < 3 * m; i += kBlock) s_arc[i] = archive[3 * static_cast<size_t>(base) + i];
+    __syncthreads();
+    if (!decided) {
+      for (int i = 0; i < m; i++)
+        if (pareto(s_arc[3 * i], s_arc[3 * i + 1], s_arc[3 * i + 2], c0, c1, c2)) {
+          ok = false;
+          decided = true;
+          break;
+        }
+    }
+  }
+  if (e < n_evals) accepted[e] = ok ? 1 : 0;
+}
+
+// One wave per evaluation: the accepted child's dependent-tet records (two
+// directions, 48 bytes) into the parent's cache, and its group's new
+// coordinates into the parent's points.
+__global__ __launch_bounds__(kBlock) void k_write_back(int n_evals, int n_parents, int n_groups, int n_points,
+                                                       int n_tets, const int* __restrict__ eval_parent,
+                                                       const int* __restrict__ eval_group,
+                                                       const uint8_t* __restrict__ accepted,
+                                                       const int* __restrict__ row_off,
+                                                       const int* __restrict__ item_off,
+                                                       const int* __restrict__ grp_off,
+                                                       const int* __restrict__ grp_pts,
+                                                       const int* __restrict__ dep_off,
+                                                       const int* __restrict__ dep_tet,
+                                                       const float* __restrict__ new_coords,
+                                                       const uint4* __restrict__ new_rec,
+                                                       float* __restrict__ parent_pts,
+                                                       uint4* __restrict__ parent_rec) {
+  const int e = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  if (e >= n_evals || !accepted[e]) return;
+  const int par = eval_parent[e], g = eval_group[e];
+  if (par < 0 || par >= n_parents || g < 0 || g >= n_groups) return;
+  const int d0 = dep_off[g], nd = dep_off[g + 1] - d0;
+  const size_t src = static_cast<size_t>(item_off[e]) * 3;
+  for (int i = lane; i < 3 * nd; i += kWave) {
+    const int j = i / 3, q = i - 3 * j;
+    const size_t dst = (static_cast<size_t>(par) * n_tets + dep_tet[d0 + j]) * 3;
+    parent_rec[dst + q] = new_rec[src + 3 * static_cast<size_t>(j) + q];
+  }
+  const int k0 = grp_off[g], nk = grp_off[g + 1] - k0;
+  const size_t row = static_cast<size_t>(row_off[e]);
+  for (int i = lane; i < 6 * nk; i += kWave) {
+    const int k = i / 6, r = i - 6 * k;   // r = mesh * 3 + axis
+    parent_pts[(static_cast<size_t>(par) * 6 + r) * n_points + grp_pts[k0 + k]] = new_coords[(row + k) * 6 + r];
+  }
+}
+
+}  // namespace accept
+}  // namespace morea
+
+using namespace morea;
+
+namespace {
+
+morea_status accept_fail(morea_status code, const char* msg) {
+  set_error(msg);
+  return code;
+}
+
+}  // namespace
+
+extern "C" morea_status morea_accept_partial(morea_problem* p, float* parent_pts, int32_t n_parents,
+                                             void* parent_cache, int32_t n_evals, const int32_t* eval_parent,
+                                             const int32_t* eval_group, const float* new_coords,
+                                             const float* child_obj, const uint8_t* child_flags,
+                                             const float* child_sev, float* parent_obj, uint8_t* parent_flags,
+                                             float* parent_sev, uint32_t* parent_counts, const float* archive_obj,
+                                             int32_t n_archive, uint8_t* accepted, void* stream) {
+  if (!p) return accept_fail(MOREA_EINVAL, "problem is NULL");
+  if (n_evals < 0 || n_parents < 1 || n_archive < 0)
+    return accept_fail(MOREA_EINVAL, "need n_evals >= 0, n_parents >= 1, n_archive >= 0");
+  if (n_evals == 0) return MOREA_OK;
+  if (!parent_pts || !parent_cache || !eval_parent || !eval_group || !new_coords || !child_obj || !child_flags ||
+      !child_sev || !parent_obj || !parent_flags || !parent_sev || !parent_counts || !accepted ||
+      (n_archive > 0 && !archive_obj))
+    return accept_fail(MOREA_EINVAL, "NULL argument");
+  if (reinterpret_cast<uintptr_t>(parent_cache) % 16 != 0)
+    return accept_fail(MOREA_EINVAL, "parent_cache must be 16-byte aligned");
+  // the records and offsets of the partial evaluation live in the library's
+  // workspace: they must be those of this evaluation list
+  const void* key[5] = {parent_pts, parent_cache, eval_parent, eval_group, new_coords};
+  if (!p->graph_exec || memcmp(key, p->graph_key, sizeof(key)) != 0 || p->graph_key_n[0] != n_parents ||
+      p->graph_key_n[1] != n_evals)
+    return accept_fail(MOREA_ESTATE, "acceptance must follow morea_eval_partial of the same evaluations");
+  {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return accept_fail(MOREA_EDEVICE, hipGetErrorString(e));
+  }
+  const ProblemView& P = p->view;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(accept::k_decide, dim3((n_evals + accept::kBlock - 1) / accept::kBlock), dim3(accept::kBlock),
+                     0, s, n_evals, n_parents, p->n_groups, eval_parent, eval_group, child_obj, child_flags,
+                     child_sev, parent_obj, parent_flags, parent_sev, archive_obj, n_archive, accepted);
+  Record* rec = static_cast<Record*>(parent_cache);
+  Totals* tot = reinterpret_cast<Totals*>(static_cast<char*>(parent_cache) +
+                                          static_cast<size_t>(n_parents) * P.n_tets * 2 * sizeof(Record));
+  constexpr int per_block = accept::kBlock / kWave;
+  hipLaunchKernelGGL(accept::k_write_back, dim3((n_evals + per_block - 1) / per_block), dim3(accept::kBlock), 0, s,
+                     n_evals, n_parents, p->n_groups, P.n_points, P.n_tets, eval_parent, eval_group, accepted,
+                     p->d_row_off, p->d_item_off, p->d_grp_off, p->d_grp_pts, p->d_dep_off, p->d_dep_tet,
+                     new_coords, reinterpret_cast<const uint4*>(p->d_partial_records), parent_pts,
+                     reinterpret_cast<uint4*>(rec));
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess)
+    e = launch_finalize(P, parent_pts, n_parents, rec, parent_obj, parent_flags, parent_sev, parent_counts, tot, s);
+  if (e != hipSuccess) {
+    char buf[256];
+    snprintf(buf, sizeof(buf), "acceptance kernels: %s", hipGetErrorString(e));
+    set_error(buf);
+    return MOREA_EDEVICE;
+  }
+  return MOREA_OK;
+}

@@ -111,4 +111,6 @@ def test_null_arguments_rejected():
     assert L.morea_repair_folds(None, None, 1, None, 1, None, None, None) == morea.MOREA_EINVAL
     assert L.morea_rasterize_dvf(None, None, None, None, None, None, None) == morea.MOREA_EINVAL
     assert L.morea_point_guidance(None, None, 1, None, None, None) == morea.MOREA_EINVAL
+    assert L.morea_accept_partial(None, None, 1, None, 1, None, None, None, None, None, None, None, None, None,
+                                  None, None, 0, None, None) == morea.MOREA_EINVAL
     L.morea_problem_destroy(None)   # accepted
