@@ -91,6 +91,7 @@ MUTATIONS = [
 REPAIR = os.path.join(ROOT, "tests", "test_oracle_repair.py")
 FOS = os.path.join(ROOT, "tests", "test_oracle_fos.py")
 ACCEPT = os.path.join(ROOT, "tests", "test_oracle_accept.py")
+MIXING = os.path.join(ROOT, "tests", "test_oracle_mixing.py")
 PY_MUTATIONS = [
     ("repair: step twice the rounded-down distance", "repair.py",
      "while j < SIGMA_MAX_LOG2 and (4 ** (j + 1)) * n * n <= d2:",
@@ -125,6 +126,19 @@ PY_MUTATIONS = [
      "        row += len(idx)",
      "            out[int(eval_parent[e])][:, :, idx] = new_coords[row:row + len(idx)].transpose(1, 2, 0)\n"
      "            row += len(idx)", ACCEPT, []),
+    ("mixing: unbiased covariance", "mixing.py", "cov[u][v] = cov[v][u] = s / m", "cov[u][v] = cov[v][u] = s / (m - 1)",
+     MIXING, []),
+    ("mixing: mean over m + 1", "mixing.py", "mean.append(s / m)", "mean.append(s / (m + 1))", MIXING, []),
+    ("mixing: factor row uses its own entries", "mixing.py", "s = s - L[i][k] * L[j][k]", "s = s - L[i][k] * L[i][k]",
+     MIXING, []),
+    ("mixing: multiplier scales the deviation", "mixing.py", "scale = math.sqrt(float(np.float32(mult)))",
+     "scale = float(np.float32(mult))", MIXING, []),
+    ("mixing: diagonal term left out of the sample", "mixing.py", "for k in range(u + 1):", "for k in range(u):",
+     MIXING, []),
+    ("mixing: fallback uses variances", "mixing.py", "L[i][i] = math.sqrt(cov[i][i])", "L[i][i] = cov[i][i]",
+     MIXING, []),
+    ("mixing: pinned axes sampled", "mixing.py", "if pinned is None or not (int(pinned[pt]) >> a) & 1:", "if True:",
+     MIXING, []),
 ]
 
 
