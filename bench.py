@@ -11,8 +11,8 @@ Prints one JSON line: the plain full evaluation's throughput, its roofline
 (VALU-bound; HBM traffic from the committed counter summary), the oracle's
 CPU rate on a bounded sample, and the other forms (partial evaluation,
 reduced-precision storage, surrogate pre-screen, Sobol-sampled estimator,
-fold repair, DVF rasterization, one generation's colour-batched partial
-evaluations and acceptances).
+fold repair, DVF rasterization, one optimizer generation: distributions,
+sampled children, colour-batched partial evaluations and acceptances).
 --gpus above 1 is refused: evaluation here runs on one GPU.
 """
 import argparse
@@ -255,28 +255,33 @@ def form_dvf(p, pop_np, steps):
 
 
 def form_generation(p, pop_np, prob_full_ms, steps):
-    """Config 2: the evaluation work of one optimizer generation (Sec. 4.2.1,
-    Sec. 3): the mesh's FOS elements (set-cover edges) in DSATUR colours; for
-    each colour one batched partial evaluation of every (solution, element of
-    the colour) child of the 512 solutions, the element's two points moved by
-    N(0, 0.5) (a stand-in for sampling the element's distribution), then the
-    acceptance of the children against their parents and an elitist archive
-    (the non-dominated feasible parents of the start), written back into the
-    parents, their caches and their evaluations."""
+    """Config 2: one optimizer generation on the device (Sec. 3, Sec. 4.2.1):
+    the mesh's FOS elements (set-cover edges) in DSATUR colours; a snapshot of
+    the 512 solutions split into 10 equal clusters by their first objective
+    (a stand-in for the selection and clustering); a normal distribution per
+    (cluster, element) estimated from the snapshot; then for each colour the
+    children of every (solution, element of the colour) pair sampled from the
+    solution's cluster, evaluated in one batched partial evaluation, and
+    accepted against their parents and an elitist archive (the non-dominated
+    feasible solutions of the start), written back into the parents, their
+    caches and their evaluations."""
     import torch
 
     import oracle
     import paper_2303_04873_amd as morea
+    from oracle import mixing as mx
     t0 = time.perf_counter()
     elements, colors, n_colors = morea.build_fos(p.n_points, p.tets)
     fos_ms = (time.perf_counter() - t0) * 1e3
     npop = pop_np.shape[0]
     prob = morea.Problem.from_synth(p, max_population=npop)
     off = np.arange(0, 2 * len(elements) + 1, 2, dtype=np.int32)
-    prob.set_groups(off, elements.reshape(-1))
+    gpts = elements.reshape(-1).astype(np.int32)
+    prob.set_groups(off, gpts)
     per_colour = [np.flatnonzero(colors == c).astype(np.int32) for c in range(n_colors)]
     prob.reserve_partial(npop * max(len(g) for g in per_colour))
     par = torch.from_numpy(pop_np).cuda()
+    snap = torch.empty_like(par)
     cache = prob.new_cache(npop)
     par_out = prob.eval_full(par, cache=cache)
     start = {k: v.cpu().numpy() for k, v in par_out.items()}
@@ -284,51 +289,97 @@ def form_generation(p, pop_np, prob_full_ms, steps):
     fo = start["obj"][feas]
     front = [i for i in range(len(fo)) if not np.any(np.all(fo <= fo[i], axis=1) & np.any(fo < fo[i], axis=1))]
     archive = torch.from_numpy(np.ascontiguousarray(fo[front], dtype=np.float32)).cuda()
-    rs = np.random.default_rng(9)
-    fixed = p.fixed_axes
+    fa = p.fixed_axes.astype(np.uint8)
+    pinned_np = (fa[:, 0] | (fa[:, 1] << 1) | (fa[:, 2] << 2)).astype(np.uint8)
+    pinned = torch.from_numpy(pinned_np).cuda()
+    k = 10
+    clu_off_np = np.linspace(0, npop, k + 1).astype(np.int32)
+    clu_off = torch.from_numpy(clu_off_np).cuda()
+    rank_cluster = torch.from_numpy(np.repeat(np.arange(k, dtype=np.int32), np.diff(clu_off_np))).cuda()
+    work = prob.mixing_workspace(k)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(9)
     batches = []
     for g in per_colour:
         ep = np.repeat(np.arange(npop, dtype=np.int32), len(g))
         eg = np.tile(g, npop)
-        pts = elements[eg]                                        # [n][2] point indices
-        new = pop_np[ep[:, None, None, None], np.arange(2)[None, None, :, None], np.arange(3)[None, None, None, :],
-                     pts[:, :, None, None]].astype(np.float64)    # [n][2 points][2 meshes][3]
-        step = rs.normal(0, 0.5, new.shape) * ~fixed[pts][:, :, None, :]
-        new = (new + step).astype(np.float32).reshape(-1, 2, 3)
-        batches.append((torch.from_numpy(ep).cuda(), torch.from_numpy(eg).cuda(), torch.from_numpy(new).cuda(),
-                        prob.outputs(len(ep)), torch.empty(len(ep), dtype=torch.uint8, device="cuda"), ep, eg, new))
+        dep = torch.from_numpy(ep).cuda()
+        batches.append(dict(dep=dep, dep_long=dep.long(), deg=torch.from_numpy(eg).cuda(),
+                            new=torch.empty((2 * len(ep), 2, 3), dtype=torch.float32, device="cuda"),
+                            z=torch.empty((2 * len(ep), 2, 3), dtype=torch.float32, device="cuda"),
+                            out=prob.outputs(len(ep)), acc=torch.empty(len(ep), dtype=torch.uint8, device="cuda"),
+                            ep=ep, eg=eg))
+    state = {}
 
-    def evaluate_only():
-        for dep, deg, dnew, out, _, *_ in batches:
-            prob.eval_partial(par, cache, dep, deg, dnew, out=out)
+    def estimate():
+        snap.copy_(par)
+        order = torch.argsort(par_out["obj"][:, 0]).to(torch.int32)
+        cluster = torch.empty(npop, dtype=torch.int32, device="cuda")
+        cluster[order.long()] = rank_cluster
+        prob.estimate_distributions(snap, clu_off, order, work, pinned=pinned)
+        state["order"], state["cluster"] = order, cluster
+
+    def sample(b):
+        b["z"].normal_(generator=gen)
+        ec = state["cluster"][b["dep_long"]]
+        prob.sample_partial(par, work, k, b["dep"], b["deg"], ec, b["z"], pinned=pinned, out=b["new"])
 
     def generation():
-        for dep, deg, dnew, out, acc, *_ in batches:
-            prob.eval_partial(par, cache, dep, deg, dnew, out=out)
-            prob.accept_partial(par, cache, dep, deg, dnew, out, par_out, archive=archive, accepted=acc)
+        estimate()
+        for b in batches:
+            sample(b)
+            prob.eval_partial(par, cache, b["dep"], b["deg"], b["new"], out=b["out"])
+            prob.accept_partial(par, cache, b["dep"], b["deg"], b["new"], b["out"], par_out, archive=archive,
+                                accepted=b["acc"])
 
-    # parity on the first generation: two children of the first colour against
-    # the oracle's full evaluation, then, after the whole generation, two
-    # updated parents against the oracle and all against a fresh evaluation
-    dep, deg, dnew, out, acc, ep, eg, new = batches[0]
-    prob.eval_partial(par, cache, dep, deg, dnew, out=out)
-    g = {k: v.cpu().numpy() for k, v in out.items()}
-    idx = [0, len(ep) - 1]
-    kids = []
+    def mixing_only():
+        estimate()
+        for b in batches:
+            sample(b)
+
+    def evaluate_only():
+        for b in batches:
+            prob.eval_partial(par, cache, b["dep"], b["deg"], b["new"], out=b["out"])
+
+    # parity on the first generation: two samples of the first colour bit for
+    # bit against the reference, those children against the oracle's full
+    # evaluation, and after the generation two updated parents against the
+    # oracle and all parents against a fresh full evaluation
+    estimate()
+    b = batches[0]
+    sample(b)
+    prob.eval_partial(par, cache, b["dep"], b["deg"], b["new"], out=b["out"])
+    g = {kk: v.cpu().numpy() for kk, v in b["out"].items()}
+    new, z = b["new"].cpu().numpy(), b["z"].cpu().numpy()
+    order, cluster = state["order"].cpu().numpy(), state["cluster"].cpu().numpy()
+    idx = [0, len(b["ep"]) - 1]
+    kids, bit_exact = [], True
     for e in idx:
-        child = pop_np[ep[e]].copy()
-        child[:, :, elements[eg[e]]] = new[2 * e:2 * e + 2].transpose(1, 2, 0)
+        pa, el = int(b["ep"][e]), int(b["eg"][e])
+        c = int(cluster[pa])
+        gp = [int(v) for v in elements[el]]
+        dist = mx.estimate(pop_np, [int(i) for i in order[clu_off_np[c]:clu_off_np[c + 1]]], gp, pinned_np)
+        want = mx.sample(dist, z[2 * e:2 * e + 2].reshape(-1), 1.0, [mx.values(pop_np, pa, gp, v) for v in range(12)])
+        bit_exact &= bool(np.array_equal(new[2 * e:2 * e + 2].reshape(-1), np.array(want, np.float32)))
+        child = pop_np[pa].copy()
+        child[:, :, elements[el]] = new[2 * e:2 * e + 2].transpose(1, 2, 0)
         kids.append(child)
     op = oracle.Problem.from_synth(p)
     o = op.evaluate(np.stack(kids))
     rel = np.abs(g["obj"][idx] - o["obj"]) / np.maximum(np.abs(o["obj"]), 1e-30)
     exact = bool((g["counts"][idx] == o["counts"]).all() and (g["flags"][idx] == o["flags"]).all())
-    generation()
+    prob.accept_partial(par, cache, b["dep"], b["deg"], b["new"], b["out"], par_out, archive=archive,
+                        accepted=b["acc"])
+    for b in batches[1:]:
+        sample(b)
+        prob.eval_partial(par, cache, b["dep"], b["deg"], b["new"], out=b["out"])
+        prob.accept_partial(par, cache, b["dep"], b["deg"], b["new"], b["out"], par_out, archive=archive,
+                            accepted=b["acc"])
     torch.cuda.synchronize()
-    kept = sum(int(b[4].sum().item()) for b in batches)
+    kept = sum(int(b["acc"].sum().item()) for b in batches)
     upd = par.cpu().numpy()
-    mine = {k: v.cpu().numpy() for k, v in par_out.items()}
-    fresh = {k: v.cpu().numpy() for k, v in prob.eval_full(par.clone()).items()}
+    mine = {kk: v.cpu().numpy() for kk, v in par_out.items()}
+    fresh = {kk: v.cpu().numpy() for kk, v in prob.eval_full(par.clone()).items()}
     moved = np.flatnonzero(np.any(upd != pop_np, axis=(1, 2, 3)))
     pick = [int(moved[0]), int(moved[-1])] if len(moved) else [0]
     o2 = op.evaluate(upd[pick])
@@ -336,17 +387,19 @@ def form_generation(p, pop_np, prob_full_ms, steps):
     exact2 = bool((mine["counts"][pick] == o2["counts"]).all() and (mine["flags"][pick] == o2["flags"]).all())
     same_as_fresh = bool((mine["flags"] == fresh["flags"]).all() and (mine["counts"] == fresh["counts"]).all()
                          and np.allclose(mine["obj"], fresh["obj"], rtol=1e-6, equal_nan=True))
+    ms_mix = timed(mixing_only, steps, 1)
     ms_eval = timed(evaluate_only, steps, 1)
     ms = timed(generation, steps, 1)
-    n_evals = sum(len(b[5]) for b in batches)
-    return {"workload": f"{len(elements)} FOS elements (set-cover edges) in {n_colors} colours, {npop} solutions: "
-                        f"{n_evals} partial evaluations and acceptances per generation in {n_colors} launches each, "
-                        f"archive of {archive.shape[0]}",
+    n_evals = sum(len(b["ep"]) for b in batches)
+    return {"workload": f"{len(elements)} FOS elements (set-cover edges) in {n_colors} colours, {npop} solutions in "
+                        f"{k} clusters: {n_evals} sampled children, partial evaluations and acceptances per "
+                        f"generation, archive of {archive.shape[0]}",
             "fos_build_ms_host": fos_ms, "ms_per_generation": ms, "ms_evaluations_only": ms_eval,
-            "ms_acceptance": ms - ms_eval, "partial_evals_per_s": n_evals / (ms * 1e-3),
+            "ms_estimate_and_sample": ms_mix, "ms_acceptance": ms - ms_eval - ms_mix,
+            "children_per_s": n_evals / (ms * 1e-3),
             "accepted_first_generation": kept, "parents_changed_first_generation": int(len(moved)),
             "vs_plain_full_evals_per_s": n_evals / (ms * 1e-3) / (npop / (prob_full_ms * 1e-3)),
-            "parity": {"evals": idx, "counts_flags_exact": exact,
+            "parity": {"evals": idx, "samples_bit_exact": bit_exact, "counts_flags_exact": exact,
                        "max_rel_err": [float(x) for x in rel.max(axis=0)],
                        "parents_after_acceptance": pick, "parents_counts_flags_exact": exact2,
                        "parents_max_rel_err": [float(x) for x in rel2.max(axis=0)],

@@ -323,6 +323,62 @@ morea_status morea_accept_partial(morea_problem *p, float *parent_pts, int32_t n
                                   float *parent_sev, uint32_t *parent_counts, const float *archive_obj,
                                   int32_t n_archive, uint8_t *accepted, void *stream);
 
+/* Bytes of the caller-owned workspace of the optimal-mixing distributions
+ * for n_clusters clusters of the registered groups (one record per
+ * (cluster, group) plus one int per reserved evaluation); 0 before
+ * morea_set_groups / morea_reserve_partial. */
+size_t morea_mixing_bytes(const morea_problem *p, int32_t n_clusters);
+
+/* Distributions of optimal mixing (Sec. 3): for every registered group g and
+ * cluster c, a normal distribution over the group's free variables estimated
+ * from the cluster's members.  Variable (2 k + m) 3 + a is axis a of mesh m
+ * of the group's k-th point (the row layout of morea_eval_partial's
+ * new_coords); an axis whose bit is set in pinned[point] is no variable.
+ * Mean and covariance are the maximum-likelihood estimates (sums over the
+ * members in the given order, divided by m), the factor is Cholesky (each
+ * entry's sum in ascending index order) in FP64; a pivot not above 1e-12
+ * times its diagonal entry makes the distribution fall back to the diagonal
+ * (standard deviations).  A cluster with no members, or with a member outside
+ * [0, n_pop) or offsets outside [0, n_members], has no distribution.
+ *   pts          [n_pop][2][3][n_points] FP32, the selection's snapshot
+ *   clu_off      [n_clusters + 1] CSR offsets into clu_members
+ *   clu_members  [n_members] indices into pts
+ *   pinned       [n_points] bit a: axis a fixed, or NULL
+ *   work         morea_mixing_bytes(p, n_clusters) bytes, 16-byte aligned;
+ *                receives the distributions, read by morea_sample_partial
+ * Groups of at most 4 points (MOREA_ERANGE otherwise).  All arrays are device
+ * pointers; asynchronous on `stream`; no allocation.  Errors: MOREA_EINVAL,
+ * MOREA_ESTATE, MOREA_ERANGE, MOREA_EDEVICE. */
+morea_status morea_estimate_distributions(morea_problem *p, const float *pts, int32_t n_pop, int32_t n_clusters,
+                                          const int32_t *clu_off, const int32_t *clu_members, int32_t n_members,
+                                          const uint8_t *pinned, void *work, size_t work_bytes, void *stream);
+
+/* New partial solutions sampled from the distributions of the preceding
+ * morea_estimate_distributions (Sec. 3): evaluation e draws the free
+ * variables of group eval_group[e] from cluster eval_cluster[e]'s
+ * distribution, x = mean + sqrt(mult[c][g]) (L z) in FP64, rounded once to
+ * FP32; pinned variables keep parent eval_parent[e]'s values.  Evaluations
+ * with a valid group own |group| rows of new_coords in evaluation order (the
+ * layout morea_eval_partial reads); an out-of-range parent or cluster, or a
+ * cluster without a distribution, gives NaN for the sampled rows.
+ *   pts          [n_pop][2][3][n_points] FP32, the parents
+ *   work         the workspace of morea_estimate_distributions (the same
+ *                n_clusters); its tail receives the evaluations' row offsets
+ *   mult         [n_clusters][n_groups] FP32 distribution multipliers, or
+ *                NULL (1)
+ *   eval_parent, eval_group, eval_cluster   [n_evals]
+ *   z            [rows][2][3] FP32 standard normal draws (row layout of
+ *                new_coords; entries of pinned variables are not read)
+ *   pinned       as for the estimation
+ *   new_coords   [rows][2][3] FP32 output
+ * n_evals <= the reservation of morea_reserve_partial.  All arrays are device
+ * pointers; asynchronous on `stream`; no allocation.  Errors: MOREA_EINVAL,
+ * MOREA_ESTATE, MOREA_ERANGE, MOREA_EDEVICE. */
+morea_status morea_sample_partial(morea_problem *p, const float *pts, int32_t n_pop, void *work, size_t work_bytes,
+                                  int32_t n_clusters, const float *mult, int32_t n_evals, const int32_t *eval_parent,
+                                  const int32_t *eval_group, const int32_t *eval_cluster, const float *z,
+                                  const uint8_t *pinned, float *new_coords, void *stream);
+
 /* Copy the distance map d(p, C) of guidance set `set` on image `image`
  * (0 = I_s grid with C_s, 1 = I_t grid with C_t) to host memory `host_out`
  * ([nz][ny][nx] FP32), and, when `band_out` is not NULL, the per-voxel band

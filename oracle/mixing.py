@@ -18,7 +18,8 @@ uses a normal distribution; the readings (listed in the design notes):
     deviations sqrt(cov[v][v]));
   * sample: x = mean + sqrt(c) (L z), z the caller's standard normal draws, c
     the distribution multiplier, in FP64, rounded once to FP32;
-  * a cluster without members gives no distribution: its samples are NaN.
+  * a cluster without members, or with a member index or offsets out of
+    range, gives no distribution: its samples are NaN.
 All arithmetic is FP64 on Python floats, one operation at a time, in the
 order stated, so that the result is fixed to the last bit.
 """
@@ -51,7 +52,7 @@ def estimate(pts, members, group_pts, pinned):
     1 diagonal fallback, 2 no members."""
     free = free_variables(group_pts, pinned)
     n = len(free)
-    if len(members) == 0:
+    if len(members) == 0 or any(not 0 <= i < pts.shape[0] for i in members):
         return free, [math.nan] * n, [[0.0] * n for _ in range(n)], 2
     x = [[values(pts, i, group_pts, v) for v in free] for i in members]
     m = len(members)
@@ -131,7 +132,9 @@ def sample_batch(pts, clu_off, clu_members, grp_off, grp_pts, pinned, mult, eval
             rows.extend(np.full((len(gp), 2, 3), np.nan, np.float32))
             continue
         if (c, g) not in cache:
-            cache[(c, g)] = estimate(pts, [int(i) for i in clu_members[clu_off[c]:clu_off[c + 1]]], gp, pinned)
+            lo, hi = int(clu_off[c]), int(clu_off[c + 1])
+            members = [int(i) for i in clu_members[lo:hi]] if 0 <= lo <= hi <= len(clu_members) else [-1]
+            cache[(c, g)] = estimate(pts, members, gp, pinned)
         par = [values(pts, p, gp, v) for v in range(6 * len(gp))]
         cm = 1.0 if mult is None else mult[c][g]
         new = sample(cache[(c, g)], zr, cm, par)

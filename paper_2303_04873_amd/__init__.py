@@ -24,6 +24,7 @@ EXPORTS = ["morea_problem_create", "morea_problem_destroy", "morea_cache_bytes",
            "morea_eval_sobol", "morea_repair_folds", "morea_rasterize_dvf", "morea_point_guidance",
            "morea_build_fos",
            "morea_set_groups", "morea_reserve_partial", "morea_eval_partial", "morea_accept_partial",
+           "morea_mixing_bytes", "morea_estimate_distributions", "morea_sample_partial",
            "morea_debug_distance_map", "morea_tune_partial", "morea_partial_shape",
            "morea_surrogate_num_params", "morea_surrogate_num_features", "morea_surrogate_create",
            "morea_surrogate_destroy", "morea_surrogate_features", "morea_surrogate_targets",
@@ -90,6 +91,12 @@ def load_library():
     L.morea_eval_partial.restype = I32
     L.morea_accept_partial.argtypes = [P, P, I32, P, I32, P, P, P, P, P, P, P, P, P, P, P, I32, P, P]
     L.morea_accept_partial.restype = I32
+    L.morea_mixing_bytes.argtypes = [P, I32]
+    L.morea_mixing_bytes.restype = ctypes.c_size_t
+    L.morea_estimate_distributions.argtypes = [P, P, I32, I32, P, P, I32, P, P, ctypes.c_size_t, P]
+    L.morea_estimate_distributions.restype = I32
+    L.morea_sample_partial.argtypes = [P, P, I32, P, ctypes.c_size_t, I32, P, I32, P, P, P, P, P, P, P]
+    L.morea_sample_partial.restype = I32
     L.morea_tune_partial.argtypes = [P, P, I32, P, I32, P, P, P, P, P, P, P, P, P]
     L.morea_tune_partial.restype = I32
     L.morea_partial_shape.argtypes = [P, P, P]
@@ -395,6 +402,39 @@ class Problem:
 
     def set_groups(self, grp_off, grp_pts):
         morea_set_groups(self.handle, grp_off, grp_pts)
+        self._group_sizes = np.diff(np.asarray(grp_off, dtype=np.int64))
+
+    def mixing_workspace(self, n_clusters):
+        """Device workspace of the optimal-mixing distributions (uint8 tensor)."""
+        import torch
+        n = load_library().morea_mixing_bytes(self.handle, int(n_clusters))
+        if n == 0:
+            raise MoreaError(MOREA_ESTATE, "call set_groups and reserve_partial first")
+        return torch.empty(n, dtype=torch.uint8, device="cuda")
+
+    def estimate_distributions(self, pts, clu_off, clu_members, work, pinned=None, stream=None):
+        """Distributions of every (cluster, group) from the clusters' members
+        (Sec. 3); clu_off int32 CUDA [k + 1], clu_members int32 CUDA."""
+        n_clusters = clu_off.shape[0] - 1
+        _check(load_library().morea_estimate_distributions(
+            self.handle, _dev_ptr(pts), pts.shape[0], n_clusters, _dev_ptr(clu_off), _dev_ptr(clu_members),
+            clu_members.shape[0], _dev_ptr(pinned), _dev_ptr(work), work.numel(), _stream_ptr(stream)))
+
+    def sample_partial(self, pts, work, n_clusters, eval_parent, eval_group, eval_cluster, z, pinned=None,
+                       mult=None, out=None, stream=None):
+        """New coordinates [rows][2][3] of every evaluation sampled from its
+        cluster's distribution of its group (Sec. 3)."""
+        import torch
+        if out is None:
+            eg = eval_group.cpu().numpy()
+            ok = (eg >= 0) & (eg < len(self._group_sizes))
+            rows = int(self._group_sizes[eg[ok]].sum())
+            out = torch.empty((rows, 2, 3), dtype=torch.float32, device="cuda")
+        _check(load_library().morea_sample_partial(
+            self.handle, _dev_ptr(pts), pts.shape[0], _dev_ptr(work), work.numel(), int(n_clusters), _dev_ptr(mult),
+            eval_parent.shape[0], _dev_ptr(eval_parent), _dev_ptr(eval_group), _dev_ptr(eval_cluster), _dev_ptr(z),
+            _dev_ptr(pinned), _dev_ptr(out), _stream_ptr(stream)))
+        return out
 
     def reserve_partial(self, max_evals):
         morea_reserve_partial(self.handle, max_evals)
