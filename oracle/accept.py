@@ -22,7 +22,12 @@ Readings where the paper leaves the details to MO-RV-GOMEA's literature
   * an evaluation whose parent or group index is out of range is never
     accepted;
   * all accepted children of one parent within one batch (elements of one
-    colour, whose dependent tets are disjoint) are applied to it.
+    colour, whose dependent tets are disjoint) are applied to it;
+  * adaptive steering (Sec. 4.3.2) makes a guidance value above the bound
+    (1.5 times the archive's best guidance value, chosen by the caller) a
+    hard constraint: such a solution is infeasible, and violations compare
+    lexicographically as (fold violation, guidance excess), the excess being
+    the FP32 difference guidance - bound.  An infinite bound switches it off.
 """
 import math
 
@@ -32,14 +37,17 @@ INVALID = 4
 FOLDS = 3
 
 
-def violation(obj, flags, severity):
-    """(feasible, total violation) of one evaluated solution."""
+def violation(obj, flags, severity, guidance_max=math.inf):
+    """(feasible, violation) of one evaluated solution; the violation is the
+    pair (fold violation, guidance excess), compared lexicographically."""
     values = [float(v) for v in obj] + [float(severity)]
     if int(flags) & INVALID or any(math.isnan(v) for v in values):
-        return False, math.inf
-    if int(flags) & FOLDS:
-        return False, float(severity)
-    return True, 0.0
+        return False, (math.inf, math.inf)
+    folded = bool(int(flags) & FOLDS)
+    fold = float(severity) if folded else 0.0
+    over = float(obj[2]) > guidance_max
+    excess = float(np.float32(np.float32(obj[2]) - np.float32(guidance_max))) if over else 0.0
+    return not folded and not over, (fold, excess)
 
 
 def pareto_dominates(a, b):
@@ -47,10 +55,10 @@ def pareto_dominates(a, b):
     return all(x <= y for x, y in zip(a, b)) and any(x < y for x, y in zip(a, b))
 
 
-def constraint_dominates(a, b):
+def constraint_dominates(a, b, guidance_max=math.inf):
     """a, b: (objectives, flags, severity)."""
-    fa, va = violation(*a)
-    fb, vb = violation(*b)
+    fa, va = violation(*a, guidance_max)
+    fb, vb = violation(*b, guidance_max)
     if fa and fb:
         return pareto_dominates(a[0], b[0])
     if fa != fb:
@@ -58,16 +66,16 @@ def constraint_dominates(a, b):
     return va < vb
 
 
-def accept(child, parent, archive):
+def accept(child, parent, archive, guidance_max=math.inf):
     """child, parent: (objectives, flags, severity); archive: objective vectors."""
-    if constraint_dominates(child, parent):
+    if constraint_dominates(child, parent, guidance_max):
         return True
-    feasible, _ = violation(*child)
+    feasible, _ = violation(*child, guidance_max)
     return feasible and not any(pareto_dominates(m, child[0]) for m in archive)
 
 
 def accept_batch(child_obj, child_flags, child_sev, eval_parent, eval_group, n_groups,
-                 parent_obj, parent_flags, parent_sev, archive):
+                 parent_obj, parent_flags, parent_sev, archive, guidance_max=math.inf):
     """Decision of every evaluation (uint8 0/1)."""
     n_parents = len(parent_flags)
     out = np.zeros(len(child_flags), np.uint8)
@@ -76,7 +84,7 @@ def accept_batch(child_obj, child_flags, child_sev, eval_parent, eval_group, n_g
         if not (0 <= p < n_parents and 0 <= g < n_groups):
             continue
         out[e] = accept((child_obj[e], child_flags[e], child_sev[e]),
-                        (parent_obj[p], parent_flags[p], parent_sev[p]), archive)
+                        (parent_obj[p], parent_flags[p], parent_sev[p]), archive, guidance_max)
     return out
 
 

@@ -4,8 +4,10 @@ The decision rule is pinned by hand-worked cases, by the order properties
 constraint domination must have (irreflexive, antisymmetric, transitive; it
 reduces to Pareto domination among feasible solutions and to the violation
 order among infeasible ones), and by a textbook 2-D skyline (sort and sweep)
-that decides non-domination within an archive by another route.  Applying
-the accepted children is pinned against building each child on its own."""
+that decides non-domination within an archive by another route.  The
+steering bound (Sec. 4.3.2) is pinned by hand-worked cases, by changing
+nothing when infinite and by keeping the order properties.  Applying the
+accepted children is pinned against building each child on its own."""
 import bisect
 import functools
 
@@ -146,3 +148,40 @@ def test_apply_matches_children_built_one_by_one():
         perm = rs.permutation(len(ep))
         rows = np.concatenate([np.arange(2 * e, 2 * e + 2) for e in perm])
         np.testing.assert_array_equal(acc.apply(parents, off, pts, ep[perm], eg[perm], new[rows], mask[perm]), got)
+
+
+def test_steering_bound():
+    inf = float("inf")
+    cd = acc.constraint_dominates
+    inside, outside = sol((5, 5, 1.0)), sol((0, 0, 2.0))
+    assert cd(inside, outside, 1.5) and not cd(outside, inside, 1.5)      # the bound is a hard constraint
+    assert cd(outside, inside, inf) is False and cd(outside, inside) is False
+    assert acc.pareto_dominates((0, 0, 1.0), (5, 5, 1.0))
+    # both above the bound: the smaller excess wins; a fold outranks any excess
+    assert cd(sol((9, 9, 1.6)), sol((0, 0, 1.9)), 1.5)
+    assert cd(sol((9, 9, 100.0)), sol((0, 0, 1.0), S, 0.5), 1.5)
+    assert not cd(sol((0, 0, 1.0), S, 0.5), sol((9, 9, 100.0)), 1.5)
+    assert cd(sol((9, 9, 1.9), S, 0.5), sol((0, 0, 1.6), S, 0.7), 1.5)
+    assert cd(sol((9, 9, 1.6), S, 0.5), sol((0, 0, 1.9), S, 0.5), 1.5)
+    # equal to the bound is inside; the archive path needs the bound too
+    assert acc.violation((0, 0, 1.5), F, 0.0, 1.5)[0]
+    assert not acc.accept(sol((0.5, 9, 1.7)), sol((1, 1, 1.0)), [], 1.5)
+    assert acc.accept(sol((0.5, 9, 1.4)), sol((1, 1, 1.0)), [], 1.5)
+    # the excess is the FP32 difference
+    assert acc.violation((0, 0, 1.5000001), F, 0.0, 1.5)[1] == (0.0, float(np.float32(1.5000001) - np.float32(1.5)))
+
+
+def test_infinite_bound_changes_nothing_and_order_holds():
+    rs = np.random.default_rng(6)
+    xs = random_solutions(rs, 50)
+    arch = [tuple(map(float, rs.integers(0, 3, 3))) for _ in range(6)]
+    for a in xs:
+        for b in xs:
+            assert acc.accept(a, b, arch, float("inf")) == acc.accept(a, b, arch)
+    rel = [[acc.constraint_dominates(a, b, 1.0) for b in xs] for a in xs]
+    for i in range(len(xs)):
+        assert not rel[i][i]
+        for j in range(len(xs)):
+            assert not (rel[i][j] and rel[j][i])
+            if rel[i][j]:
+                assert all(rel[i][k] for k in range(len(xs)) if rel[j][k])

@@ -126,6 +126,12 @@ PY_MUTATIONS = [
      "        row += len(idx)",
      "            out[int(eval_parent[e])][:, :, idx] = new_coords[row:row + len(idx)].transpose(1, 2, 0)\n"
      "            row += len(idx)", ACCEPT, []),
+    ("steering: excess outranks folds", "accept.py", "return not folded and not over, (fold, excess)",
+     "return not folded and not over, (excess, fold)", ACCEPT, []),
+    ("steering: bound ignored for feasibility", "accept.py", "return not folded and not over, (fold, excess)",
+     "return not folded, (fold, excess)", ACCEPT, []),
+    ("steering: bound itself outside", "accept.py", "over = float(obj[2]) > guidance_max",
+     "over = float(obj[2]) >= guidance_max", ACCEPT, []),
     ("mixing: unbiased covariance", "mixing.py", "cov[u][v] = cov[v][u] = s / m", "cov[u][v] = cov[v][u] = s / (m - 1)",
      MIXING, []),
     ("mixing: mean over m + 1", "mixing.py", "mean.append(s / m)", "mean.append(s / (m + 1))", MIXING, []),
