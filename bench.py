@@ -263,8 +263,9 @@ def form_generation(p, pop_np, prob_full_ms, steps):
     children of every (solution, element of the colour) pair sampled from the
     solution's cluster, evaluated in one batched partial evaluation, and
     accepted against their parents and an elitist archive (the non-dominated
-    feasible solutions of the start), written back into the parents, their
-    caches and their evaluations."""
+    feasible solutions of the start) under the adaptive-steering bound (1.5
+    times the archive's best guidance value, Sec. 4.3.2), written back into
+    the parents, their caches and their evaluations."""
     import torch
 
     import oracle
@@ -289,6 +290,9 @@ def form_generation(p, pop_np, prob_full_ms, steps):
     fo = start["obj"][feas]
     front = [i for i in range(len(fo)) if not np.any(np.all(fo <= fo[i], axis=1) & np.any(fo < fo[i], axis=1))]
     archive = torch.from_numpy(np.ascontiguousarray(fo[front], dtype=np.float32)).cuda()
+    # adaptive steering as after the exploration period: guidance at most 1.5
+    # times the archive's best
+    gmax = float(1.5 * fo[front][:, 2].min()) if len(front) else float("inf")
     fa = p.fixed_axes.astype(np.uint8)
     pinned_np = (fa[:, 0] | (fa[:, 1] << 1) | (fa[:, 2] << 2)).astype(np.uint8)
     pinned = torch.from_numpy(pinned_np).cuda()
@@ -330,7 +334,7 @@ def form_generation(p, pop_np, prob_full_ms, steps):
             sample(b)
             prob.eval_partial(par, cache, b["dep"], b["deg"], b["new"], out=b["out"])
             prob.accept_partial(par, cache, b["dep"], b["deg"], b["new"], b["out"], par_out, archive=archive,
-                                accepted=b["acc"])
+                                guidance_max=gmax, accepted=b["acc"])
 
     def mixing_only():
         estimate()
@@ -341,6 +345,12 @@ def form_generation(p, pop_np, prob_full_ms, steps):
         for b in batches:
             prob.eval_partial(par, cache, b["dep"], b["deg"], b["new"], out=b["out"])
 
+    # launch shape of the persistent partial evaluation, tuned on the first
+    # colour's children (sampled from the distributions of the start)
+    estimate()
+    sample(batches[0])
+    tune_ms, shape = prob.tune_partial(par, cache, batches[0]["dep"], batches[0]["deg"], batches[0]["new"],
+                                       out=batches[0]["out"])
     # parity on the first generation: two samples of the first colour bit for
     # bit against the reference, those children against the oracle's full
     # evaluation, and after the generation two updated parents against the
@@ -369,12 +379,12 @@ def form_generation(p, pop_np, prob_full_ms, steps):
     rel = np.abs(g["obj"][idx] - o["obj"]) / np.maximum(np.abs(o["obj"]), 1e-30)
     exact = bool((g["counts"][idx] == o["counts"]).all() and (g["flags"][idx] == o["flags"]).all())
     prob.accept_partial(par, cache, b["dep"], b["deg"], b["new"], b["out"], par_out, archive=archive,
-                        accepted=b["acc"])
+                        guidance_max=gmax, accepted=b["acc"])
     for b in batches[1:]:
         sample(b)
         prob.eval_partial(par, cache, b["dep"], b["deg"], b["new"], out=b["out"])
         prob.accept_partial(par, cache, b["dep"], b["deg"], b["new"], b["out"], par_out, archive=archive,
-                            accepted=b["acc"])
+                            guidance_max=gmax, accepted=b["acc"])
     torch.cuda.synchronize()
     kept = sum(int(b["acc"].sum().item()) for b in batches)
     upd = par.cpu().numpy()
@@ -394,10 +404,11 @@ def form_generation(p, pop_np, prob_full_ms, steps):
     return {"workload": f"{len(elements)} FOS elements (set-cover edges) in {n_colors} colours, {npop} solutions in "
                         f"{k} clusters: {n_evals} sampled children, partial evaluations and acceptances per "
                         f"generation, archive of {archive.shape[0]}",
-            "fos_build_ms_host": fos_ms, "ms_per_generation": ms, "ms_evaluations_only": ms_eval,
+            "fos_build_ms_host": fos_ms, "launch_shape": {"blocks": shape[0], "items_per_pop": shape[1]},
+            "ms_per_generation": ms, "ms_evaluations_only": ms_eval,
             "ms_estimate_and_sample": ms_mix, "ms_acceptance": ms - ms_eval - ms_mix,
             "children_per_s": n_evals / (ms * 1e-3),
-            "accepted_first_generation": kept, "parents_changed_first_generation": int(len(moved)),
+            "steering_guidance_max": gmax, "accepted_first_generation": kept, "parents_changed_first_generation": int(len(moved)),
             "vs_plain_full_evals_per_s": n_evals / (ms * 1e-3) / (npop / (prob_full_ms * 1e-3)),
             "parity": {"evals": idx, "samples_bit_exact": bit_exact, "counts_flags_exact": exact,
                        "max_rel_err": [float(x) for x in rel.max(axis=0)],

@@ -292,7 +292,12 @@ morea_status morea_eval_partial(morea_problem *p, const float *parent_pts, int32
  *     Pareto domination (no objective worse, one strictly better);
  *   archive: feasible objective vectors; a feasible child is non-dominated
  *     when no member Pareto-dominates it (a member equal to it does not);
- *   an evaluation with an out-of-range parent or group is rejected.
+ *   an evaluation with an out-of-range parent or group is rejected;
+ *   adaptive steering (Sec. 4.3.2): with a finite guidance_max (the caller
+ *     passes 1.5 times the best guidance value in the archive) a solution
+ *     whose guidance objective exceeds it is infeasible too, and violations
+ *     compare lexicographically as (severity of folds, FP32 excess
+ *     guidance - guidance_max); INFINITY switches steering off.
  * For every kept evaluation e the group's new coordinates are written into
  * parent_pts[eval_parent[e]] and the partial evaluation's records of the
  * group's dependent tets into the parent's cache; then the totals in the
@@ -309,6 +314,7 @@ morea_status morea_eval_partial(morea_problem *p, const float *parent_pts, int32
  *   parent_obj, parent_flags, parent_sev, parent_counts   [n_parents] the
  *                parents' evaluation: read for the decisions, rewritten
  *   archive_obj  [n_archive][3] FP32 (NULL when n_archive == 0)
+ *   guidance_max steering bound, or INFINITY (not NaN)
  *   accepted     [n_evals] receives 1 (kept) or 0
  * The kept evaluations of one parent must have pairwise disjoint dependent
  * tets (e.g. the elements of one colour of morea_build_fos); otherwise which
@@ -321,7 +327,7 @@ morea_status morea_accept_partial(morea_problem *p, float *parent_pts, int32_t n
                                   const float *new_coords, const float *child_obj, const uint8_t *child_flags,
                                   const float *child_sev, float *parent_obj, uint8_t *parent_flags,
                                   float *parent_sev, uint32_t *parent_counts, const float *archive_obj,
-                                  int32_t n_archive, uint8_t *accepted, void *stream);
+                                  int32_t n_archive, float guidance_max, uint8_t *accepted, void *stream);
 
 /* Bytes of the caller-owned workspace of the optimal-mixing distributions
  * for n_clusters clusters of the registered groups (one record per
@@ -392,8 +398,9 @@ morea_status morea_debug_distance_map(morea_problem *p, int32_t image, int32_t s
  * blocks per compute unit up to the occupancy limit x work items taken per
  * queue pop in {1, 2, 4, 8, 16}) on the given inputs with HIP events and keeps the
  * fastest for later morea_eval_partial calls.  Synchronous; overwrites the
- * output arrays.  *best_ms (may be NULL) receives the best time.  Errors as
- * morea_eval_partial. */
+ * output arrays.  *best_ms (may be NULL) receives the best time.  Untuned,
+ * the shape is 4 blocks per compute unit (at most the occupancy limit) and 8
+ * items per pop.  Errors as morea_eval_partial. */
 morea_status morea_tune_partial(morea_problem *p, const float *parent_pts, int32_t n_parents,
                                 const void *parent_cache, int32_t n_evals,
                                 const int32_t *eval_parent, const int32_t *eval_group,

@@ -89,7 +89,8 @@ def load_library():
     L.morea_reserve_partial.restype = I32
     L.morea_eval_partial.argtypes = [P, P, I32, P, I32, P, P, P, P, P, P, P, P]
     L.morea_eval_partial.restype = I32
-    L.morea_accept_partial.argtypes = [P, P, I32, P, I32, P, P, P, P, P, P, P, P, P, P, P, I32, P, P]
+    L.morea_accept_partial.argtypes = [P, P, I32, P, I32, P, P, P, P, P, P, P, P, P, P, P, I32, ctypes.c_float, P,
+                                       P]
     L.morea_accept_partial.restype = I32
     L.morea_mixing_bytes.argtypes = [P, I32]
     L.morea_mixing_bytes.restype = ctypes.c_size_t
@@ -216,13 +217,13 @@ def morea_eval_partial(handle, parent_pts, n_parents, parent_cache, n_evals, eva
 
 def morea_accept_partial(handle, parent_pts, n_parents, parent_cache, n_evals, eval_parent, eval_group,
                          new_coords, child_obj, child_flags, child_sev, parent_obj, parent_flags, parent_sev,
-                         parent_counts, archive_obj, n_archive, accepted, stream):
+                         parent_counts, archive_obj, n_archive, guidance_max, accepted, stream):
     _check(load_library().morea_accept_partial(
         handle, _dev_ptr(parent_pts), n_parents, _dev_ptr(parent_cache), n_evals,
         _dev_ptr(eval_parent), _dev_ptr(eval_group), _dev_ptr(new_coords), _dev_ptr(child_obj),
         _dev_ptr(child_flags), _dev_ptr(child_sev), _dev_ptr(parent_obj), _dev_ptr(parent_flags),
-        _dev_ptr(parent_sev), _dev_ptr(parent_counts), _dev_ptr(archive_obj), n_archive, _dev_ptr(accepted),
-        _stream_ptr(stream)))
+        _dev_ptr(parent_sev), _dev_ptr(parent_counts), _dev_ptr(archive_obj), n_archive, guidance_max,
+        _dev_ptr(accepted), _stream_ptr(stream)))
 
 
 def morea_tune_partial(handle, parent_pts, n_parents, parent_cache, n_evals, eval_parent, eval_group,
@@ -449,11 +450,12 @@ class Problem:
         return out
 
     def accept_partial(self, parent_pts, parent_cache, eval_parent, eval_group, new_coords, child, parent,
-                       archive=None, accepted=None, stream=None):
+                       archive=None, guidance_max=None, accepted=None, stream=None):
         """Acceptance after eval_partial with the same first five arguments
         (Sec. 3): `child` the decision inputs (the outputs of eval_partial),
         `parent` the parents' outputs dict (rewritten with the evaluation of
-        the updated parents), `archive` FP32 CUDA [m][3] or None.  Updates
+        the updated parents), `archive` FP32 CUDA [m][3] or None,
+        `guidance_max` the steering bound (None: off).  Updates
         parent_pts and parent_cache in place; returns `accepted` (uint8)."""
         import torch
         n = eval_parent.shape[0]
@@ -465,7 +467,7 @@ class Problem:
         morea_accept_partial(self.handle, parent_pts, parent_pts.shape[0], parent_cache, n, eval_parent, eval_group,
                              new_coords, child["obj"], child["flags"], child["severity"], parent["obj"],
                              parent["flags"], parent["severity"], parent["counts"], archive if m else None, m,
-                             accepted, stream)
+                             float("inf") if guidance_max is None else float(guidance_max), accepted, stream)
         return accepted
 
     def tune_partial(self, parent_pts, parent_cache, eval_parent, eval_group, new_coords, out=None,

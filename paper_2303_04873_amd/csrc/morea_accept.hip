@@ -16,7 +16,11 @@
 //     compare by Pareto domination (none worse, one strictly better);
 //   archive: feasible objective vectors; a feasible child is non-dominated
 //     when no member Pareto-dominates it (an equal member does not);
-//   an evaluation whose parent or group index is out of range is rejected.
+//   an evaluation whose parent or group index is out of range is rejected;
+//   adaptive steering (Sec. 4.3.2): a guidance value above the caller's bound
+//     (1.5 times the archive's best) is a hard constraint -- the solution is
+//     infeasible and violations compare lexicographically as (fold
+//     violation, FP32 excess guidance - bound); an infinite bound is off.
 //
 // Three launches: the decisions (one thread per evaluation, the archive
 // staged through LDS in chunks shared by the block), the write-back (one
@@ -35,17 +39,17 @@ namespace accept {
 constexpr int kBlock = 256;
 constexpr int kChunk = 512;   // archive members staged per pass (6 KB of LDS)
 
-__device__ __forceinline__ bool feasible_of(float o0, float o1, float o2, uint8_t f, float sev, float& viol) {
+// Feasibility and the violation pair (fold violation, guidance excess).
+__device__ __forceinline__ bool feasible_of(float o0, float o1, float o2, uint8_t f, float sev, float gmax,
+                                            float& fold, float& excess) {
   if ((f & 4u) || isnan(o0) || isnan(o1) || isnan(o2) || isnan(sev)) {
-    viol = INFINITY;
+    fold = excess = INFINITY;
     return false;
   }
-  if (f & 3u) {
-    viol = sev;
-    return false;
-  }
-  viol = 0.f;
-  return true;
+  const bool folded = (f & 3u) != 0, over = o2 > gmax;
+  fold = folded ? sev : 0.f;
+  excess = over ? o2 - gmax : 0.f;
+  return !folded && !over;
 }
 
 __device__ __forceinline__ bool pareto(float a0, float a1, float a2, float b0, float b1, float b2) {
@@ -61,7 +65,7 @@ __global__ __launch_bounds__(kBlock) void k_decide(int n_evals, int n_parents, i
                                                    const float* __restrict__ parent_obj,
                                                    const uint8_t* __restrict__ parent_flags,
                                                    const float* __restrict__ parent_sev,
-                                                   const float* __restrict__ archive, int n_archive,
+                                                   const float* __restrict__ archive, int n_archive, float gmax,
                                                    uint8_t* __restrict__ accepted) {
   __shared__ float s_arc[kChunk * 3];
   const int e = blockIdx.x * kBlock + threadIdx.x;
@@ -73,11 +77,12 @@ __global__ __launch_bounds__(kBlock) void k_decide(int n_evals, int n_parents, i
       c0 = child_obj[3 * e];
       c1 = child_obj[3 * e + 1];
       c2 = child_obj[3 * e + 2];
-      float vc, vp;
-      const bool fc = feasible_of(c0, c1, c2, child_flags[e], child_sev[e], vc);
+      float fc_fold, fc_exc, fp_fold, fp_exc;
+      const bool fc = feasible_of(c0, c1, c2, child_flags[e], child_sev[e], gmax, fc_fold, fc_exc);
       const float p0 = parent_obj[3 * par], p1 = parent_obj[3 * par + 1], p2 = parent_obj[3 * par + 2];
-      const bool fp = feasible_of(p0, p1, p2, parent_flags[par], parent_sev[par], vp);
-      const bool dom = (fc && fp) ? pareto(c0, c1, c2, p0, p1, p2) : (fc != fp ? fc : vc < vp);
+      const bool fp = feasible_of(p0, p1, p2, parent_flags[par], parent_sev[par], gmax, fp_fold, fp_exc);
+      const bool less = fc_fold < fp_fold || (fc_fold == fp_fold && fc_exc < fp_exc);
+      const bool dom = (fc && fp) ? pareto(c0, c1, c2, p0, p1, p2) : (fc != fp ? fc : less);
       if (dom) {
         ok = true;
       } else if (fc) {
@@ -160,10 +165,12 @@ extern "C" morea_status morea_accept_partial(morea_problem* p, float* parent_pts
                                              const float* child_obj, const uint8_t* child_flags,
                                              const float* child_sev, float* parent_obj, uint8_t* parent_flags,
                                              float* parent_sev, uint32_t* parent_counts, const float* archive_obj,
-                                             int32_t n_archive, uint8_t* accepted, void* stream) {
+                                             int32_t n_archive, float guidance_max, uint8_t* accepted,
+                                             void* stream) {
   if (!p) return accept_fail(MOREA_EINVAL, "problem is NULL");
   if (n_evals < 0 || n_parents < 1 || n_archive < 0)
     return accept_fail(MOREA_EINVAL, "need n_evals >= 0, n_parents >= 1, n_archive >= 0");
+  if (isnan(guidance_max)) return accept_fail(MOREA_EINVAL, "guidance_max is NaN");
   if (n_evals == 0) return MOREA_OK;
   if (!parent_pts || !parent_cache || !eval_parent || !eval_group || !new_coords || !child_obj || !child_flags ||
       !child_sev || !parent_obj || !parent_flags || !parent_sev || !parent_counts || !accepted ||
@@ -185,7 +192,7 @@ extern "C" morea_status morea_accept_partial(morea_problem* p, float* parent_pts
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipLaunchKernelGGL(accept::k_decide, dim3((n_evals + accept::kBlock - 1) / accept::kBlock), dim3(accept::kBlock),
                      0, s, n_evals, n_parents, p->n_groups, eval_parent, eval_group, child_obj, child_flags,
-                     child_sev, parent_obj, parent_flags, parent_sev, archive_obj, n_archive, accepted);
+                     child_sev, parent_obj, parent_flags, parent_sev, archive_obj, n_archive, guidance_max, accepted);
   Record* rec = static_cast<Record*>(parent_cache);
   Totals* tot = reinterpret_cast<Totals*>(static_cast<char*>(parent_cache) +
                                           static_cast<size_t>(n_parents) * P.n_tets * 2 * sizeof(Record));

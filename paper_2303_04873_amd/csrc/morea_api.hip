@@ -513,8 +513,10 @@ morea_status morea_reserve_partial(morea_problem* p, int32_t max_evals) {
     int cus = 0, per_cu = 0;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
     per_cu = partial_blocks_per_cu(p->storage);
-    p->partial_blocks = std::max(1, cus) * std::max(1, per_cu);
-    p->partial_chunk = 1;
+    // the tuner's choice on the 128x128x96 workloads: 4 blocks per compute
+    // unit (at most the occupancy limit), 8 items per queue pop
+    p->partial_blocks = std::max(1, cus) * std::max(1, std::min(4, per_cu));
+    p->partial_chunk = 8;
   }
   p->max_evals = max_evals;
   return MOREA_OK;

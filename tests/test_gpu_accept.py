@@ -96,6 +96,36 @@ def test_c1_decisions_application_and_cache():
     assert_parity(out, oracle_problem(1).evaluate(kids), what="partial evaluation after acceptance")
 
 
+def test_c1_steering_bound():
+    p = synth_problem(1)
+    parents = synth.make_population(p, pop=8, seed=23, perturb_source=True, fold_fraction=0.25)
+    prob, off, pts, ep, eg, new = colour_setup(p, parents, 2, seed=7)
+    d = dev(parents)
+    cache = prob.new_cache(len(parents))
+    prob.eval_full(d, cache=cache)
+    dep, deg, dnew = dev(ep), dev(eg), dev(new)
+    prob.eval_partial(d, cache, dep, deg, dnew)
+    rs = np.random.default_rng(79)
+    child, parent = synthetic_decisions(rs, len(ep), len(parents))
+    # guidance values 0, 0.5, ..., 2.5 against the bound 1.2: several excesses
+    child[0][:, 2] = (rs.integers(0, 6, len(ep)) * 0.5).astype(np.float32)
+    parent[0][:, 2] = (rs.integers(0, 6, len(parents)) * 0.5).astype(np.float32)
+    archive = (rs.integers(0, 3, (40, 3)) * 0.5 + 0.25).astype(np.float32)
+    gmax = 1.2
+    c = dict(obj=dev(child[0]), flags=dev(child[1]), severity=dev(child[2]))
+    par = dict(obj=dev(parent[0]), flags=dev(parent[1]), severity=dev(parent[2]),
+               counts=torch.empty((len(parents), 2), dtype=torch.int32, device="cuda"))
+    got = prob.accept_partial(d, cache, dep, deg, dnew, c, par, archive=dev(archive), guidance_max=gmax)
+    torch.cuda.synchronize()
+    got = got.cpu().numpy()
+    want = acc.accept_batch(*child, ep, eg, len(off) - 1, *parent, [tuple(m) for m in archive],
+                            guidance_max=float(np.float32(gmax)))
+    np.testing.assert_array_equal(got, want)
+    off_bound = acc.accept_batch(*child, ep, eg, len(off) - 1, *parent, [tuple(m) for m in archive])
+    assert np.any(want != off_bound)          # the bound changed some decisions
+    np.testing.assert_array_equal(d.cpu().numpy(), acc.apply(parents, off, pts, ep, eg, new, want))
+
+
 def test_c1_real_objectives_and_state_errors():
     p = synth_problem(1)
     parents = synth.make_population(p, pop=6, seed=22, perturb_source=True, fold_fraction=0.3)
