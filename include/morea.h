@@ -331,7 +331,7 @@ morea_status morea_accept_partial(morea_problem *p, float *parent_pts, int32_t n
 
 /* Bytes of the caller-owned workspace of the optimal-mixing distributions
  * for n_clusters clusters of the registered groups (one record per
- * (cluster, group) plus one int per reserved evaluation); 0 before
+ * (cluster, group) plus the row offsets of the reserved evaluations); 0 before
  * morea_set_groups / morea_reserve_partial. */
 size_t morea_mixing_bytes(const morea_problem *p, int32_t n_clusters);
 

@@ -493,8 +493,11 @@ morea_status morea_reserve_partial(morea_problem* p, int32_t max_evals) {
     st = upload_to(p->partial_allocs, &p->d_partial_records, nullptr,
                    sizeof(Record) * 2 * static_cast<size_t>(max_evals) * p->max_dep);
   if (st == MOREA_OK)
+    // at least room for the prefix kernels' block totals (two ints per 256
+    // evaluations), which use the head of this array before the items fill it
     st = upload_to(p->partial_allocs, &p->d_item_info, nullptr,
-                   sizeof(int4) * static_cast<size_t>(max_evals) * p->max_dep);
+                   sizeof(int4) * std::max(static_cast<size_t>(max_evals) * p->max_dep,
+                                           static_cast<size_t>(max_evals) / 128 + 2));
   if (st == MOREA_OK)
     st = upload_to(p->partial_allocs, &p->d_item_dest, nullptr,
                    sizeof(int) * static_cast<size_t>(max_evals) * p->max_dep);

@@ -1352,68 +1352,108 @@ hipError_t launch_finalize(const ProblemView& P, const float* pts, int pop, cons
 // ------------------------------------------------------- partial evaluation
 namespace morea {
 
-// Prefix sums of the evaluation list (one block, fixed order): first
-// new-coordinate row of each evaluation and first record (dependent tet).
-// An evaluation with an out-of-range group owns no new-coordinate rows; one
-// with an out-of-range parent or group gets no work items and is reported
-// invalid by the finalize kernel.  Then the evaluations are bucketed by
-// group (rank within the group; the ranks' order does not affect any
-// result) and each group's first processing position is the prefix of
-// evaluations x dependent tets over the groups.  Also resets the work queue.
-__global__ __launch_bounds__(1024) void k_partial_prep(PartialItems I, int n_parents, int n_groups,
-                                                        int* queue) {
-  __shared__ int s_rows[1024], s_items[1024];
-  const int tid = threadIdx.x;
-  const int n_evals = I.n_evals;
-  const int per = (n_evals + 1023) / 1024;
-  const int b = tid * per, e_end = min(n_evals, b + per);
-  int rows = 0, items = 0;
-  for (int e = b; e < e_end; e++) {
-    const int g = I.eval_group[e], par = I.eval_parent[e];
-    if (g >= 0 && g < n_groups) {
-      rows += I.grp_off[g + 1] - I.grp_off[g];
-      if (par >= 0 && par < n_parents) items += I.dep_off[g + 1] - I.dep_off[g];
-    }
+// Prefix sums of the evaluation list: first new-coordinate row of each
+// evaluation and first record (dependent tet).  An evaluation with an
+// out-of-range group owns no new-coordinate rows; one with an out-of-range
+// parent or group gets no work items and is reported invalid by the finalize
+// kernel.  Then the evaluations are bucketed by group (rank within the
+// group; the ranks' order does not affect any result) and each group's first
+// processing position is the prefix of evaluations x dependent tets over the
+// groups.  Four launches: per-block scans of 256 evaluations (block totals
+// into the head of the item-info array, which the item kernel fills only
+// afterwards), one block scanning the block totals (and clearing the group
+// counters and the work queue), the block offsets added back with the ranks
+// taken, and one block for the group bases.
+constexpr int kPrepBlock = 256;
+
+__device__ __forceinline__ void eval_sizes(const PartialItems& I, int e, int n_parents, int n_groups, int& rows,
+                                           int& items) {
+  rows = items = 0;
+  const int g = I.eval_group[e], par = I.eval_parent[e];
+  if (g >= 0 && g < n_groups) {
+    rows = I.grp_off[g + 1] - I.grp_off[g];
+    if (par >= 0 && par < n_parents) items = I.dep_off[g + 1] - I.dep_off[g];
   }
+}
+
+__global__ __launch_bounds__(kPrepBlock) void k_prep_local(PartialItems I, int n_parents, int n_groups) {
+  __shared__ int s_rows[kPrepBlock], s_items[kPrepBlock];
+  const int tid = threadIdx.x, e = blockIdx.x * kPrepBlock + tid;
+  int rows = 0, items = 0;
+  if (e < I.n_evals) eval_sizes(I, e, n_parents, n_groups, rows, items);
   s_rows[tid] = rows;
   s_items[tid] = items;
-  for (int g = tid; g < n_groups; g += 1024) I.grp_count[g] = 0;
   __syncthreads();
-  for (int d = 1; d < 1024; d <<= 1) {
-    int r = tid >= d ? s_rows[tid - d] : 0, it = tid >= d ? s_items[tid - d] : 0;
+  for (int d = 1; d < kPrepBlock; d <<= 1) {
+    const int r = tid >= d ? s_rows[tid - d] : 0, it = tid >= d ? s_items[tid - d] : 0;
     __syncthreads();
     s_rows[tid] += r;
     s_items[tid] += it;
     __syncthreads();
   }
-  rows = s_rows[tid] - rows;
-  items = s_items[tid] - items;
-  int* row_off = const_cast<int*>(I.row_off);
-  int* item_off = const_cast<int*>(I.item_off);
-  for (int e = b; e < e_end; e++) {
-    row_off[e] = rows;
-    item_off[e] = items;
-    const int g = I.eval_group[e], par = I.eval_parent[e];
-    if (g >= 0 && g < n_groups) {
-      rows += I.grp_off[g + 1] - I.grp_off[g];
-      if (par >= 0 && par < n_parents) {
-        items += I.dep_off[g + 1] - I.dep_off[g];
-        I.eval_rank[e] = atomicAdd(&I.grp_count[g], 1);
-      }
-    }
+  if (e < I.n_evals) {
+    const_cast<int*>(I.row_off)[e] = s_rows[tid] - rows;
+    const_cast<int*>(I.item_off)[e] = s_items[tid] - items;
   }
-  if (tid == 1023) item_off[n_evals] = s_items[1023];
-  if (tid == 0) *queue = 0;
-  __threadfence();
-  __syncthreads();
-  // group bases: exclusive prefix of count x dependent tets, 1024 groups per pass
+  if (tid == kPrepBlock - 1) {
+    int* bsum = reinterpret_cast<int*>(I.item_info);
+    bsum[2 * blockIdx.x] = s_rows[tid];
+    bsum[2 * blockIdx.x + 1] = s_items[tid];
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_prep_blocks(PartialItems I, int n_blocks, int n_groups, int* queue) {
+  __shared__ int s_rows[1024], s_items[1024];
+  const int tid = threadIdx.x;
+  int* bsum = reinterpret_cast<int*>(I.item_info);
+  int carry_r = 0, carry_i = 0;
+  for (int b0 = 0; b0 < n_blocks; b0 += 1024) {
+    const int b = b0 + tid;
+    const int r = b < n_blocks ? bsum[2 * b] : 0, it = b < n_blocks ? bsum[2 * b + 1] : 0;
+    s_rows[tid] = r;
+    s_items[tid] = it;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+      const int x = tid >= d ? s_rows[tid - d] : 0, y = tid >= d ? s_items[tid - d] : 0;
+      __syncthreads();
+      s_rows[tid] += x;
+      s_items[tid] += y;
+      __syncthreads();
+    }
+    if (b < n_blocks) {
+      bsum[2 * b] = carry_r + s_rows[tid] - r;
+      bsum[2 * b + 1] = carry_i + s_items[tid] - it;
+    }
+    carry_r += s_rows[1023];
+    carry_i += s_items[1023];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const_cast<int*>(I.item_off)[I.n_evals] = carry_i;
+    *queue = 0;
+  }
+  for (int g = tid; g < n_groups; g += 1024) I.grp_count[g] = 0;
+}
+
+__global__ __launch_bounds__(kPrepBlock) void k_prep_offsets(PartialItems I, int n_parents, int n_groups) {
+  const int e = blockIdx.x * kPrepBlock + threadIdx.x;
+  if (e >= I.n_evals) return;
+  const int* bsum = reinterpret_cast<const int*>(I.item_info);
+  const_cast<int*>(I.row_off)[e] += bsum[2 * blockIdx.x];
+  const_cast<int*>(I.item_off)[e] += bsum[2 * blockIdx.x + 1];
+  const int g = I.eval_group[e], par = I.eval_parent[e];
+  if (g >= 0 && g < n_groups && par >= 0 && par < n_parents) I.eval_rank[e] = atomicAdd(&I.grp_count[g], 1);
+}
+
+// Group bases: exclusive prefix of count x dependent tets, 1024 groups per pass.
+__global__ __launch_bounds__(1024) void k_prep_groups(PartialItems I, int n_groups) {
+  __shared__ int s_items[1024];
+  const int tid = threadIdx.x;
   int carry = 0;
   for (int g0 = 0; g0 < n_groups; g0 += 1024) {
     const int g = g0 + tid;
     int v = 0;
-    if (g < n_groups)
-      v = __hip_atomic_load(&I.grp_count[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) *
-          (I.dep_off[g + 1] - I.dep_off[g]);
+    if (g < n_groups) v = I.grp_count[g] * (I.dep_off[g + 1] - I.dep_off[g]);
     s_items[tid] = v;
     __syncthreads();
     for (int d = 1; d < 1024; d <<= 1) {
@@ -1596,7 +1636,11 @@ hipError_t launch_partial(const ProblemView& P, int storage, const PartialItems&
                           Record* new_rec, int* queue, int blocks, int chunk, float* obj,
                           uint8_t* flags, float* severity, uint32_t* counts, hipStream_t s) {
   if (I.n_evals == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_partial_prep, dim3(1), dim3(1024), 0, s, I, n_parents, n_groups, queue);
+  const int prep_blocks = (I.n_evals + kPrepBlock - 1) / kPrepBlock;
+  hipLaunchKernelGGL(k_prep_local, dim3(prep_blocks), dim3(kPrepBlock), 0, s, I, n_parents, n_groups);
+  hipLaunchKernelGGL(k_prep_blocks, dim3(1), dim3(1024), 0, s, I, prep_blocks, n_groups, queue);
+  hipLaunchKernelGGL(k_prep_offsets, dim3(prep_blocks), dim3(kPrepBlock), 0, s, I, n_parents, n_groups);
+  hipLaunchKernelGGL(k_prep_groups, dim3(1), dim3(1024), 0, s, I, n_groups);
   hipLaunchKernelGGL(k_partial_items, dim3((I.n_evals + 3) / 4), dim3(256), 0, s, I, n_parents, n_groups);
   switch (storage) {
     case kF32:

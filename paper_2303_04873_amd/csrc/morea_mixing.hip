@@ -25,8 +25,8 @@
 // Estimation: one wave per (cluster, element): free variables by ballot,
 // means on lanes, the lower triangle of the covariance on lanes, the factor
 // column by column (pivot on one lane, the column below it on all lanes).
-// Sampling: a one-block prefix over the evaluations (first new-coordinate
-// row of each), then one wave per evaluation, its variables on lanes.
+// Sampling: a prefix over the evaluations (first new-coordinate row of
+// each), then one wave per evaluation, its variables on lanes.
 #include <math.h>
 #include <stdio.h>
 
@@ -173,33 +173,60 @@ __global__ __launch_bounds__(kWave) void k_estimate(const float* __restrict__ pt
   if (lane == 0) D.mode = fail ? 1 : 0;
 }
 
-// First new-coordinate row of every evaluation (one block, fixed order):
-// evaluations with a valid group own |group| rows.
-__global__ __launch_bounds__(1024) void k_rows(int n_evals, int n_groups, const int* __restrict__ eval_group,
-                                               const int* __restrict__ grp_off, int* __restrict__ row_off) {
-  __shared__ int s_rows[1024];
-  const int tid = threadIdx.x;
-  const int per = (n_evals + 1023) / 1024;
-  const int b = tid * per, e_end = min(n_evals, b + per);
+// First new-coordinate row of every evaluation: evaluations with a valid
+// group own |group| rows.  Per-block scans of 256 evaluations (block totals
+// after the row offsets in the workspace), one block scanning the totals,
+// then the block offsets added back.
+constexpr int kRowBlock = 256;
+
+__global__ __launch_bounds__(kRowBlock) void k_rows_local(int n_evals, int n_groups,
+                                                          const int* __restrict__ eval_group,
+                                                          const int* __restrict__ grp_off, int* __restrict__ row_off,
+                                                          int* __restrict__ bsum) {
+  __shared__ int s_rows[kRowBlock];
+  const int tid = threadIdx.x, e = blockIdx.x * kRowBlock + tid;
   int rows = 0;
-  for (int e = b; e < e_end; e++) {
+  if (e < n_evals) {
     const int g = eval_group[e];
-    if (g >= 0 && g < n_groups) rows += grp_off[g + 1] - grp_off[g];
+    if (g >= 0 && g < n_groups) rows = grp_off[g + 1] - grp_off[g];
   }
   s_rows[tid] = rows;
   __syncthreads();
-  for (int d = 1; d < 1024; d <<= 1) {
+  for (int d = 1; d < kRowBlock; d <<= 1) {
     const int r = tid >= d ? s_rows[tid - d] : 0;
     __syncthreads();
     s_rows[tid] += r;
     __syncthreads();
   }
-  rows = s_rows[tid] - rows;
-  for (int e = b; e < e_end; e++) {
-    row_off[e] = rows;
-    const int g = eval_group[e];
-    if (g >= 0 && g < n_groups) rows += grp_off[g + 1] - grp_off[g];
+  if (e < n_evals) row_off[e] = s_rows[tid] - rows;
+  if (tid == kRowBlock - 1) bsum[blockIdx.x] = s_rows[tid];
+}
+
+__global__ __launch_bounds__(1024) void k_rows_blocks(int n_blocks, int* __restrict__ bsum) {
+  __shared__ int s_rows[1024];
+  const int tid = threadIdx.x;
+  int carry = 0;
+  for (int b0 = 0; b0 < n_blocks; b0 += 1024) {
+    const int b = b0 + tid;
+    const int r = b < n_blocks ? bsum[b] : 0;
+    s_rows[tid] = r;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+      const int x = tid >= d ? s_rows[tid - d] : 0;
+      __syncthreads();
+      s_rows[tid] += x;
+      __syncthreads();
+    }
+    if (b < n_blocks) bsum[b] = carry + s_rows[tid] - r;
+    carry += s_rows[1023];
+    __syncthreads();
   }
+}
+
+__global__ __launch_bounds__(kRowBlock) void k_rows_add(int n_evals, int* __restrict__ row_off,
+                                                        const int* __restrict__ bsum) {
+  const int e = blockIdx.x * kRowBlock + threadIdx.x;
+  if (e < n_evals) row_off[e] += bsum[blockIdx.x];
 }
 
 __global__ __launch_bounds__(256) void k_sample(const float* __restrict__ pts, int n_pop, int n_points,
@@ -283,7 +310,9 @@ morea_status mix_launch_status(const char* what) {
 
 extern "C" size_t morea_mixing_bytes(const morea_problem* p, int32_t n_clusters) {
   if (!p || n_clusters < 1 || p->n_groups == 0 || p->max_evals == 0) return 0;
-  return mixing::dist_bytes(p, n_clusters) + static_cast<size_t>(p->max_evals) * sizeof(int);
+  // distributions, row offsets, block totals of the row scan
+  return mixing::dist_bytes(p, n_clusters) +
+         (static_cast<size_t>(p->max_evals) + p->max_evals / mixing::kRowBlock + 1) * sizeof(int);
 }
 
 extern "C" morea_status morea_estimate_distributions(morea_problem* p, const float* pts, int32_t n_pop,
@@ -333,8 +362,12 @@ extern "C" morea_status morea_sample_partial(morea_problem* p, const float* pts,
   hipStream_t s = static_cast<hipStream_t>(stream);
   const mixing::Dist* dist = static_cast<const mixing::Dist*>(work);
   int* row_off = reinterpret_cast<int*>(static_cast<char*>(work) + mixing::dist_bytes(p, n_clusters));
-  hipLaunchKernelGGL(mixing::k_rows, dim3(1), dim3(1024), 0, s, n_evals, p->n_groups, eval_group, p->d_grp_off,
-                     row_off);
+  int* bsum = row_off + p->max_evals;
+  const int row_blocks = (n_evals + mixing::kRowBlock - 1) / mixing::kRowBlock;
+  hipLaunchKernelGGL(mixing::k_rows_local, dim3(row_blocks), dim3(mixing::kRowBlock), 0, s, n_evals, p->n_groups,
+                     eval_group, p->d_grp_off, row_off, bsum);
+  hipLaunchKernelGGL(mixing::k_rows_blocks, dim3(1), dim3(1024), 0, s, row_blocks, bsum);
+  hipLaunchKernelGGL(mixing::k_rows_add, dim3(row_blocks), dim3(mixing::kRowBlock), 0, s, n_evals, row_off, bsum);
   morea_status st = mix_launch_status("sampling rows");
   if (st != MOREA_OK) return st;
   constexpr int per_block = 256 / kWave;
