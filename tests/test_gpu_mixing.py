@@ -155,3 +155,69 @@ def test_c2_full_mesh_sampled():
         want = mx.sample(cache[(c, g)], z[2 * e:2 * e + 2].reshape(-1), 1.0, par)
         np.testing.assert_array_equal(got[2 * e:2 * e + 2].reshape(-1), np.array(want, np.float32))
     assert all(v[3] == 0 for v in cache.values())
+
+
+def test_c1_one_generation_end_to_end():
+    """Distributions from a snapshot, then per colour: children sampled (bit
+    for bit against the reference), evaluated (against the oracle's full
+    evaluation of each child), accepted with an empty archive (every feasible
+    child is kept, infeasible ones compare their violations with the
+    parent's), written back.  The reference follows its own decisions; they
+    must equal the library's, the parents' points after each colour must
+    equal the reference's, and the parents' evaluations kept in the caches
+    must equal a fresh full evaluation and the oracle's."""
+    import oracle
+    from oracle import accept as acc
+    from parity import assert_parity, to_host
+    p = synth_problem(1)
+    pop = synth.make_population(p, pop=12, seed=44, perturb_source=True, fold_fraction=0.25)
+    prob, off, gpts, colors = setup(p, len(pop))
+    n_colors = int(colors.max()) + 1
+    pinned = pinned_bits(p)
+    k = 3
+    clu_off = np.array([0, 4, 8, 12], np.int32)
+    members = np.arange(12, dtype=np.int32)
+    cluster_of = np.repeat(np.arange(k, dtype=np.int32), 4)
+    per_colour = [np.flatnonzero(colors == c).astype(np.int32) for c in range(n_colors)]
+    prob.reserve_partial(len(pop) * max(len(g) for g in per_colour))
+    ora = oracle.Problem.from_synth(p)
+    d = dev(pop)
+    cache = prob.new_cache(len(pop))
+    par_out = prob.eval_full(d, cache=cache)
+    snapshot = pop.copy()
+    work = prob.mixing_workspace(k)
+    prob.estimate_distributions(dev(snapshot), dev(clu_off), dev(members), work, pinned=dev(pinned))
+    rs = np.random.default_rng(15)
+    state = pop.copy()
+    kept_total = rejected = 0
+    for c, g in enumerate(per_colour):
+        ep = np.repeat(np.arange(len(pop), dtype=np.int32), len(g))
+        eg = np.tile(g, len(pop))
+        ec = cluster_of[ep]
+        z = rs.normal(size=(2 * len(ep), 2, 3)).astype(np.float32)
+        dep, deg = dev(ep), dev(eg)
+        new = prob.sample_partial(d, work, k, dep, deg, dev(ec), dev(z), pinned=dev(pinned))
+        out = prob.eval_partial(d, cache, dep, deg, new)
+        kept = prob.accept_partial(d, cache, dep, deg, new, out, par_out)
+        torch.cuda.synchronize()
+        new_ref = mx.sample_batch(snapshot, clu_off, members, off, gpts, pinned, None, ep, eg, ec, z)
+        np.testing.assert_array_equal(new.cpu().numpy(), new_ref)
+        po = ora.evaluate(state)
+        kids = np.stack([synth.apply_child(state, off, gpts, ep, eg, new_ref, e) for e in range(len(ep))])
+        ko = ora.evaluate(kids)
+        assert_parity(to_host(out), ko, what=f"colour {c} children")
+        want = acc.accept_batch(ko["obj"], ko["flags"], ko["severity"], ep, eg, len(off) - 1, po["obj"],
+                                po["flags"], po["severity"], [])
+        np.testing.assert_array_equal(kept.cpu().numpy(), want, err_msg=f"colour {c} decisions")
+        kept_total += int(want.sum())
+        rejected += int(len(want) - want.sum())
+        state = acc.apply(state, off, gpts, ep, eg, new_ref, want)
+        np.testing.assert_array_equal(d.cpu().numpy(), state, err_msg=f"colour {c} parents")
+    print("kept", kept_total, "rejected", rejected, flush=True)
+    assert kept_total > 0 and rejected > 0
+    fresh = to_host(morea.Problem.from_synth(p, max_population=len(pop)).eval_full(dev(state)))
+    mine = to_host(par_out)
+    np.testing.assert_array_equal(mine["flags"], fresh["flags"])
+    np.testing.assert_array_equal(mine["counts"], fresh["counts"])
+    np.testing.assert_allclose(mine["obj"], fresh["obj"], rtol=1e-6)
+    assert_parity(mine, ora.evaluate(state), what="parents after the generation")
