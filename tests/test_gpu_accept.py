@@ -206,3 +206,40 @@ def test_c2_full_size_one_colour():
     changed = np.unique(ep[got == 1])
     pick = [int(changed[0]), int(changed[-1])]
     assert_parity(par_out, oracle_problem(2).evaluate(updated[pick]), idx=pick, what="c2 parents")
+
+
+def test_c1_large_groups_one_per_parent():
+    """Groups of 4-40 points (write-back loops of many lane passes), one
+    evaluation per parent (disjoint by construction)."""
+    p = synth_problem(1)
+    parents = synth.make_population(p, pop=10, seed=24, perturb_source=True, fold_fraction=0.2)
+    off, pts = synth.make_groups(p, n_groups=10, sizes=(4, 40), seed=3)
+    ep = np.arange(10, dtype=np.int32)
+    eg = np.random.default_rng(4).permutation(10).astype(np.int32)
+    _, _, all_new = synth.make_children(p, parents, off, pts, seed=4)
+    # rows of evaluation (e, eg[e]) taken from the (parent, group) pair's rows of make_children
+    sizes = np.diff(off)
+    start = {}
+    r = 0
+    for pa in range(10):
+        for g in range(10):
+            start[(pa, g)] = r
+            r += sizes[g]
+    new = np.concatenate([all_new[start[(e, eg[e])]:start[(e, eg[e])] + sizes[eg[e]]] for e in range(10)])
+    prob = morea.Problem.from_synth(p, max_population=10)
+    prob.set_groups(off, pts)
+    prob.reserve_partial(10)
+    d = dev(parents)
+    cache = prob.new_cache(10)
+    prob.eval_full(d, cache=cache)
+    dep, deg, dnew = dev(ep), dev(eg), dev(new)
+    prob.eval_partial(d, cache, dep, deg, dnew)
+    rs = np.random.default_rng(80)
+    child, parent = synthetic_decisions(rs, 10, 10)
+    got, par_out = run_accept(prob, d, cache, dep, deg, dnew, child, parent, None)
+    want = acc.accept_batch(*child, ep, eg, 10, *parent, [])
+    np.testing.assert_array_equal(got, want)
+    assert want.sum() >= 3 and sizes[eg[want == 1]].max() > 10
+    updated = acc.apply(parents, off, pts, ep, eg, new, want)
+    np.testing.assert_array_equal(d.cpu().numpy(), updated)
+    assert_parity(par_out, oracle_problem(1).evaluate(updated), what="large groups")

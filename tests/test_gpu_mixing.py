@@ -221,3 +221,51 @@ def test_c1_one_generation_end_to_end():
     np.testing.assert_array_equal(mine["counts"], fresh["counts"])
     np.testing.assert_allclose(mine["obj"], fresh["obj"], rtol=1e-6)
     assert_parity(mine, ora.evaluate(state), what="parents after the generation")
+
+
+def test_c1_groups_of_three_and_four_points():
+    """Up to 24 variables per distribution (several passes of the
+    covariance lanes and a 24-column factor); groups of 5 points refused."""
+    p = synth_problem(1)
+    pop = synth.make_population(p, pop=40, seed=45, perturb_source=True)
+    off, gpts = synth.make_groups(p, n_groups=12, sizes=(3, 4), seed=5)
+    assert set(np.diff(off)) == {3, 4}
+    prob = morea.Problem.from_synth(p, max_population=len(pop))
+    prob.set_groups(off, gpts)
+    n_groups = len(off) - 1
+    pinned = pinned_bits(p)
+    clusters = [list(range(0, 40)), list(range(10, 30)), [1, 2, 3, 4, 5, 6]]
+    clu_off = np.concatenate([[0], np.cumsum([len(c) for c in clusters])]).astype(np.int32)
+    clu_members = np.array(sum(clusters, []), np.int32)
+    k = len(clusters)
+    rs = np.random.default_rng(16)
+    ep = np.repeat(np.arange(len(pop), dtype=np.int32), n_groups)
+    eg = np.tile(np.arange(n_groups, dtype=np.int32), len(pop))
+    ec = rs.integers(0, k, len(ep)).astype(np.int32)
+    prob.reserve_partial(len(ep))
+    rows = int(np.diff(off)[eg].sum())
+    z = rs.normal(size=(rows, 2, 3)).astype(np.float32)
+    mult = rs.uniform(0.5, 2.0, (k, n_groups)).astype(np.float32)
+    d = dev(pop)
+    work = prob.mixing_workspace(k)
+    prob.estimate_distributions(d, dev(clu_off), dev(clu_members), work, pinned=dev(pinned))
+    new = prob.sample_partial(d, work, k, dev(ep), dev(eg), dev(ec), dev(z), pinned=dev(pinned), mult=dev(mult))
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(new.cpu().numpy(), mx.sample_batch(pop, clu_off, clu_members, off, gpts, pinned,
+                                                                      mult, ep, eg, ec, z))
+    rec = records(work, k * n_groups)
+    modes = set()
+    for c in range(k):
+        for g in range(n_groups):
+            ref = mx.estimate(pop, clusters[c], [int(v) for v in gpts[off[g]:off[g + 1]]], pinned)
+            check_record(rec[c * n_groups + g], ref)
+            modes.add(ref[3])
+    assert 0 in modes and 1 in modes
+    assert max(int(r["n_free"]) for r in rec) > 12
+    # groups of five points are refused
+    off5, pts5 = synth.make_groups(p, n_groups=3, sizes=(5, 5), seed=6)
+    prob.set_groups(off5, pts5)
+    prob.reserve_partial(8)
+    with pytest.raises(morea.MoreaError) as err:
+        prob.estimate_distributions(d, dev(clu_off), dev(clu_members), prob.mixing_workspace(k))
+    assert err.value.status == morea.MOREA_ERANGE
