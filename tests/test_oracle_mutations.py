@@ -92,6 +92,7 @@ REPAIR = os.path.join(ROOT, "tests", "test_oracle_repair.py")
 FOS = os.path.join(ROOT, "tests", "test_oracle_fos.py")
 ACCEPT = os.path.join(ROOT, "tests", "test_oracle_accept.py")
 MIXING = os.path.join(ROOT, "tests", "test_oracle_mixing.py")
+SELECTION = os.path.join(ROOT, "tests", "test_oracle_selection.py")
 PY_MUTATIONS = [
     ("repair: step twice the rounded-down distance", "repair.py",
      "while j < SIGMA_MAX_LOG2 and (4 ** (j + 1)) * n * n <= d2:",
@@ -132,6 +133,22 @@ PY_MUTATIONS = [
      "return not folded, (fold, excess)", ACCEPT, []),
     ("steering: bound itself outside", "accept.py", "over = float(obj[2]) > guidance_max",
      "over = float(obj[2]) >= guidance_max", ACCEPT, []),
+    ("selection: last front cut from the highest index", "selection.py",
+     "chosen += [i for i in range(len(rank)) if rank[i] == r][:size - len(chosen)]",
+     "chosen += [i for i in range(len(rank)) if rank[i] == r][::-1][:size - len(chosen)]", SELECTION, []),
+    ("selection: objectives not normalised", "selection.py",
+     "return [((float(v[o]) - lo[o]) / (hi[o] - lo[o])) if hi[o] > lo[o] else 0.0 for o in range(3)]",
+     "return [(float(v[o]) - lo[o]) for o in range(3)]", SELECTION, []),
+    ("selection: first leader of largest first objective", "selection.py",
+     "first = min(sel, key=lambda i: (pts[i][0], i))", "first = max(sel, key=lambda i: (pts[i][0], -i))",
+     SELECTION, []),
+    ("selection: distance to the last leader only", "selection.py", "            if d < nearest[i]:",
+     "            if True:", SELECTION, []),
+    ("selection: clusters of |S| / k", "selection.py", "m = min(len(sel), -(-2 * len(sel) // k))",
+     "m = min(len(sel), -(-len(sel) // k))", SELECTION, []),
+    ("selection: ties to the higher cluster", "selection.py",
+     "key=lambda j: (dist(pts[i], pts[leaders[j]]), j)))", "key=lambda j: (dist(pts[i], pts[leaders[j]]), -j)))",
+     SELECTION, []),
     ("mixing: unbiased covariance", "mixing.py", "cov[u][v] = cov[v][u] = s / m", "cov[u][v] = cov[v][u] = s / (m - 1)",
      MIXING, []),
     ("mixing: mean over m + 1", "mixing.py", "mean.append(s / m)", "mean.append(s / (m + 1))", MIXING, []),
