@@ -329,6 +329,37 @@ morea_status morea_accept_partial(morea_problem *p, float *parent_pts, int32_t n
                                   float *parent_sev, uint32_t *parent_counts, const float *archive_obj,
                                   int32_t n_archive, float guidance_max, uint8_t *accepted, void *stream);
 
+/* Selection and clustering at the start of a generation (Sec. 3: a
+ * selection of non-dominated solutions of the population, clustered into k
+ * equally sized clusters).  Solutions are ordered by the constraint
+ * domination of morea_accept_partial (with the same steering bound); fronts
+ * by peeling; the selection takes whole fronts in order and the last one it
+ * needs in ascending index, up to `size` solutions (invalid ones never).
+ * Objectives are normalised over the selection ((v - lo) / (hi - lo), 0 where
+ * hi == lo) and compared by squared Euclidean distance in FP64.  Leaders: the
+ * selected solution with the smallest normalised first objective, then
+ * repeatedly the one farthest from the leaders so far (ties to the lower
+ * index), min(k, |S|) of them.  Cluster j holds the m = min(|S|,
+ * ceil(2 |S| / k)) selected solutions nearest to leader j (ties to the lower
+ * index) in ascending index; clusters without a leader are empty.  Every
+ * valid solution is assigned the cluster of its nearest leader (ties to the
+ * lower cluster), an invalid one -1.
+ *   obj, flags, severity   [n_pop] (layout of morea_eval_full)
+ *   selection    [n_pop] receives the selected indices, ascending
+ *   n_selected   [1] receives |S|
+ *   clu_off      [k + 1] receives CSR offsets into clu_members
+ *   clu_members  [members_cap] receives the clusters' members
+ *   cluster_of   [n_pop] receives each solution's cluster or -1
+ * The outputs feed morea_estimate_distributions (clu_off, clu_members with
+ * n_members = members_cap) and morea_sample_partial (cluster_of gathered per
+ * evaluation).  n_pop <= 1024 (one block); members_cap >= k * ceil(2 min(size,
+ * n_pop) / k).  All arrays are device pointers; asynchronous on `stream`; no
+ * allocation.  Errors: MOREA_EINVAL, MOREA_ERANGE, MOREA_EDEVICE. */
+morea_status morea_select_clusters(const float *obj, const uint8_t *flags, const float *severity, int32_t n_pop,
+                                   int32_t size, int32_t k, float guidance_max, int32_t *selection,
+                                   int32_t *n_selected, int32_t *clu_off, int32_t *clu_members, int32_t members_cap,
+                                   int32_t *cluster_of, void *stream);
+
 /* Bytes of the caller-owned workspace of the optimal-mixing distributions
  * for n_clusters clusters of the registered groups (one record per
  * (cluster, group) plus the row offsets of the reserved evaluations); 0 before

@@ -23,7 +23,7 @@ STORE = {"f32": 0, "bf16": 1, "f16": 2}
 EXPORTS = ["morea_problem_create", "morea_problem_destroy", "morea_cache_bytes", "morea_eval_full",
            "morea_eval_sobol", "morea_repair_folds", "morea_rasterize_dvf", "morea_point_guidance",
            "morea_build_fos",
-           "morea_set_groups", "morea_reserve_partial", "morea_eval_partial", "morea_accept_partial",
+           "morea_set_groups", "morea_reserve_partial", "morea_eval_partial", "morea_accept_partial", "morea_select_clusters",
            "morea_mixing_bytes", "morea_estimate_distributions", "morea_sample_partial",
            "morea_debug_distance_map", "morea_tune_partial", "morea_partial_shape",
            "morea_surrogate_num_params", "morea_surrogate_num_features", "morea_surrogate_create",
@@ -92,6 +92,8 @@ def load_library():
     L.morea_accept_partial.argtypes = [P, P, I32, P, I32, P, P, P, P, P, P, P, P, P, P, P, I32, ctypes.c_float, P,
                                        P]
     L.morea_accept_partial.restype = I32
+    L.morea_select_clusters.argtypes = [P, P, P, I32, I32, I32, ctypes.c_float, P, P, P, P, I32, P, P]
+    L.morea_select_clusters.restype = I32
     L.morea_mixing_bytes.argtypes = [P, I32]
     L.morea_mixing_bytes.restype = ctypes.c_size_t
     L.morea_estimate_distributions.argtypes = [P, P, I32, I32, P, P, I32, P, P, ctypes.c_size_t, P]
@@ -224,6 +226,29 @@ def morea_accept_partial(handle, parent_pts, n_parents, parent_cache, n_evals, e
         _dev_ptr(child_flags), _dev_ptr(child_sev), _dev_ptr(parent_obj), _dev_ptr(parent_flags),
         _dev_ptr(parent_sev), _dev_ptr(parent_counts), _dev_ptr(archive_obj), n_archive, guidance_max,
         _dev_ptr(accepted), _stream_ptr(stream)))
+
+
+def select_clusters(out, size, k, guidance_max=None, stream=None):
+    """Selection and clustering (Sec. 3) of a population from its evaluation
+    outputs `out` (obj, flags, severity CUDA tensors).  Returns a dict of CUDA
+    int32 tensors: selection, n_selected [1], clu_off [k + 1], clu_members,
+    cluster_of; clu_members is sized k * ceil(2 min(size, n) / k)."""
+    import torch
+    n = out["flags"].shape[0]
+    s = min(size, n)
+    cap = max(1, k * ((2 * s + k - 1) // k))
+    dev = out["flags"].device
+    res = dict(selection=torch.empty(n, dtype=torch.int32, device=dev),
+               n_selected=torch.empty(1, dtype=torch.int32, device=dev),
+               clu_off=torch.empty(k + 1, dtype=torch.int32, device=dev),
+               clu_members=torch.empty(cap, dtype=torch.int32, device=dev),
+               cluster_of=torch.empty(n, dtype=torch.int32, device=dev))
+    _check(load_library().morea_select_clusters(
+        _dev_ptr(out["obj"]), _dev_ptr(out["flags"]), _dev_ptr(out["severity"]), n, int(size), int(k),
+        float("inf") if guidance_max is None else float(guidance_max), _dev_ptr(res["selection"]),
+        _dev_ptr(res["n_selected"]), _dev_ptr(res["clu_off"]), _dev_ptr(res["clu_members"]), cap,
+        _dev_ptr(res["cluster_of"]), _stream_ptr(stream)))
+    return res
 
 
 def morea_tune_partial(handle, parent_pts, n_parents, parent_cache, n_evals, eval_parent, eval_group,

@@ -28,6 +28,8 @@
 // the group's coordinates), and the per-candidate reduction of the
 // evaluation over the parents' caches.
 #include <math.h>
+
+#include <algorithm>
 #include <stdio.h>
 #include <string.h>
 
@@ -145,6 +147,228 @@ __global__ __launch_bounds__(kBlock) void k_write_back(int n_evals, int n_parent
   }
 }
 
+// ---------------------------------------------------------------- selection
+// Selection and clustering at the start of a generation (Sec. 3: a selection
+// of non-dominated solutions of the population, clustered into k equally
+// sized clusters), one block of 1024 threads, one solution per thread.
+// Definitions where the paper leaves the details to MO-RV-GOMEA's literature:
+//   fronts by peeling under the constraint domination above; the selection
+//     takes whole fronts in order and the last one it needs in ascending
+//     index, up to `size` solutions; invalid solutions are never selected;
+//   objectives normalised over the selection, (v - lo) / (hi - lo), 0 where
+//     hi == lo; squared Euclidean distances in FP64, contraction off;
+//   leaders: the selected solution with the smallest normalised first
+//     objective, then repeatedly the one farthest from the leaders so far
+//     (ties to the lower index), min(k, |S|) of them;
+//   cluster j: the m = min(|S|, ceil(2 |S| / k)) selected solutions nearest
+//     to leader j (ties to the lower index), in ascending index;
+//   the cluster of a valid solution: its nearest leader (ties to the lower
+//     cluster); -1 for an invalid one.
+constexpr int kSelThreads = 1024;
+
+struct SelShared {
+  double key[kSelThreads];
+  int idx[kSelThreads];
+  int scan[kSelThreads];
+  int count;
+};
+
+// Block-wide minimum of (key, idx) (lexicographic); every thread returns it.
+__device__ void block_argmin(SelShared& S, double key, int idx, double& out_key, int& out_idx) {
+  const int t = threadIdx.x;
+  S.key[t] = key;
+  S.idx[t] = idx;
+  __syncthreads();
+  for (int d = kSelThreads / 2; d > 0; d >>= 1) {
+    if (t < d) {
+      const double k2 = S.key[t + d];
+      const int i2 = S.idx[t + d];
+      if (k2 < S.key[t] || (k2 == S.key[t] && i2 < S.idx[t])) {
+        S.key[t] = k2;
+        S.idx[t] = i2;
+      }
+    }
+    __syncthreads();
+  }
+  out_key = S.key[0];
+  out_idx = S.idx[0];
+  __syncthreads();
+}
+
+// Block-wide exclusive prefix sum of v; *total receives the sum.
+__device__ int block_scan(SelShared& S, int v, int* total) {
+  const int t = threadIdx.x;
+  S.scan[t] = v;
+  __syncthreads();
+  for (int d = 1; d < kSelThreads; d <<= 1) {
+    const int x = t >= d ? S.scan[t - d] : 0;
+    __syncthreads();
+    S.scan[t] += x;
+    __syncthreads();
+  }
+  const int incl = S.scan[t];
+  *total = S.scan[kSelThreads - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+__device__ __forceinline__ double dist3(const double* a, const double* b) {
+#pragma clang fp contract(off)
+  double s = 0.0;
+  for (int o = 0; o < 3; o++) {
+    const double d = a[o] - b[o];
+    const double p = d * d;
+    s = s + p;
+  }
+  return s;
+}
+
+__global__ __launch_bounds__(kSelThreads) void k_select(int n, int size, int k, float gmax,
+                                                        const float* __restrict__ obj,
+                                                        const uint8_t* __restrict__ flags,
+                                                        const float* __restrict__ sev, int* __restrict__ sel_out,
+                                                        int* __restrict__ n_sel_out, int* __restrict__ clu_off,
+                                                        int* __restrict__ clu_members,
+                                                        int* __restrict__ cluster_of) {
+#pragma clang fp contract(off)
+  __shared__ SelShared S;
+  __shared__ float s_o[3][kSelThreads];
+  __shared__ float s_fold[kSelThreads], s_exc[kSelThreads];
+  __shared__ uint8_t s_feas[kSelThreads], s_left[kSelThreads];
+  __shared__ double s_norm[3][kSelThreads];
+  __shared__ int s_leader[kSelThreads];
+  const int i = threadIdx.x;
+  const bool in = i < n;
+  float o0 = 0.f, o1 = 0.f, o2 = 0.f, fold = 0.f, exc = 0.f;
+  bool valid = false, feas = false;
+  if (in) {
+    o0 = obj[3 * i];
+    o1 = obj[3 * i + 1];
+    o2 = obj[3 * i + 2];
+    const uint8_t f = flags[i];
+    const float sv = sev[i];
+    valid = !((f & 4u) || isnan(o0) || isnan(o1) || isnan(o2) || isnan(sv));
+    feas = feasible_of(o0, o1, o2, f, sv, gmax, fold, exc);
+  }
+  s_o[0][i] = o0;
+  s_o[1][i] = o1;
+  s_o[2][i] = o2;
+  s_fold[i] = fold;
+  s_exc[i] = exc;
+  s_feas[i] = feas;
+  s_left[i] = valid;
+  __syncthreads();
+  // fronts by peeling until `size` solutions are covered
+  int rank = -1, covered = 0, r = 0;
+  while (covered < size) {
+    bool front = false;
+    if (s_left[i]) {
+      front = true;
+      for (int j = 0; j < n && front; j++) {
+        if (j == i || !s_left[j]) continue;
+        bool dom;
+        if (s_feas[j] && s_feas[i])
+          dom = pareto(s_o[0][j], s_o[1][j], s_o[2][j], s_o[0][i], s_o[1][i], s_o[2][i]);
+        else if (s_feas[j] != s_feas[i])
+          dom = s_feas[j];
+        else
+          dom = s_fold[j] < s_fold[i] || (s_fold[j] == s_fold[i] && s_exc[j] < s_exc[i]);
+        if (dom) front = false;
+      }
+    }
+    int n_front;
+    const int before = block_scan(S, front ? 1 : 0, &n_front);
+    if (n_front == 0) break;
+    if (front) {
+      s_left[i] = 0;
+      // the last front needed is cut in ascending index
+      if (covered + before < size) rank = r;
+    }
+    covered += n_front;
+    r++;
+    __syncthreads();
+  }
+  const bool chosen = rank >= 0;
+  int n_sel;
+  const int pos = block_scan(S, chosen ? 1 : 0, &n_sel);
+  if (chosen) sel_out[pos] = i;
+  if (i == 0) *n_sel_out = n_sel;
+  const int k_eff = min(k, n_sel);
+  const int m = n_sel == 0 ? 0 : min(n_sel, (2 * n_sel + k - 1) / k);
+  for (int j = i; j <= k; j += kSelThreads) clu_off[j] = min(j, k_eff) * m;
+  if (n_sel == 0) {
+    if (in) cluster_of[i] = -1;
+    return;
+  }
+  // normalisation over the selection (exact minima and maxima)
+  double lo[3], hi[3];
+  for (int o = 0; o < 3; o++) {
+    double mn, mx;
+    int dummy;
+    block_argmin(S, chosen ? static_cast<double>(s_o[o][i]) : INFINITY, i, mn, dummy);
+    block_argmin(S, chosen ? -static_cast<double>(s_o[o][i]) : INFINITY, i, mx, dummy);
+    lo[o] = mn;
+    hi[o] = -mx;
+  }
+  double me[3];
+  for (int o = 0; o < 3; o++) {
+    const double v = static_cast<double>(s_o[o][i]);
+    me[o] = hi[o] > lo[o] ? (v - lo[o]) / (hi[o] - lo[o]) : 0.0;
+    s_norm[o][i] = me[o];
+  }
+  __syncthreads();
+  // leaders: smallest first objective, then farthest points
+  double kk;
+  int first;
+  block_argmin(S, chosen ? me[0] : INFINITY, chosen ? i : 0x7fffffff, kk, first);
+  if (i == 0) s_leader[0] = first;
+  double lead[3] = {s_norm[0][first], s_norm[1][first], s_norm[2][first]};
+  double nearest = chosen ? dist3(me, lead) : 0.0;
+  for (int j = 1; j < k_eff; j++) {
+    int nxt;
+    block_argmin(S, chosen ? -nearest : INFINITY, chosen ? i : 0x7fffffff, kk, nxt);
+    if (i == 0) s_leader[j] = nxt;
+    const double ln[3] = {s_norm[0][nxt], s_norm[1][nxt], s_norm[2][nxt]};
+    const double d = dist3(me, ln);
+    if (chosen && d < nearest) nearest = d;
+  }
+  __syncthreads();
+  // members of each cluster: the m nearest selected solutions, ascending index
+  for (int j = 0; j < k_eff; j++) {
+    const int L = s_leader[j];
+    const double ln[3] = {s_norm[0][L], s_norm[1][L], s_norm[2][L]};
+    const double dme = dist3(me, ln);
+    S.key[i] = chosen ? dme : INFINITY;
+    __syncthreads();
+    int closer = 0;
+    if (chosen)
+      for (int q = 0; q < n; q++) {
+        const double dq = S.key[q];
+        closer += (dq < dme || (dq == dme && q < i)) ? 1 : 0;
+      }
+    const bool member = chosen && closer < m;
+    int cnt;
+    const int at = block_scan(S, member ? 1 : 0, &cnt);
+    if (member) clu_members[j * m + at] = i;
+  }
+  // cluster of every valid solution: the nearest leader
+  if (in) {
+    int best = -1;
+    double bd = INFINITY;
+    if (valid)
+      for (int j = 0; j < k_eff; j++) {
+        const int L = s_leader[j];
+        const double ln[3] = {s_norm[0][L], s_norm[1][L], s_norm[2][L]};
+        const double d = dist3(me, ln);
+        if (best < 0 || d < bd) {
+          bd = d;
+          best = j;
+        }
+      }
+    cluster_of[i] = best;
+  }
+}
+
 }  // namespace accept
 }  // namespace morea
 
@@ -158,6 +382,35 @@ morea_status accept_fail(morea_status code, const char* msg) {
 }
 
 }  // namespace
+
+extern "C" morea_status morea_select_clusters(const float* obj, const uint8_t* flags, const float* severity,
+                                              int32_t n_pop, int32_t size, int32_t k, float guidance_max,
+                                              int32_t* selection, int32_t* n_selected, int32_t* clu_off,
+                                              int32_t* clu_members, int32_t members_cap, int32_t* cluster_of,
+                                              void* stream) {
+  if (n_pop < 1 || n_pop > accept::kSelThreads || size < 0 || k < 1 || isnan(guidance_max))
+    return accept_fail(MOREA_EINVAL, "need 1 <= n_pop <= 1024, size >= 0, k >= 1, guidance_max not NaN");
+  if (!obj || !flags || !severity || !selection || !n_selected || !clu_off || !clu_members || !cluster_of)
+    return accept_fail(MOREA_EINVAL, "NULL argument");
+  const int64_t s = std::min<int64_t>(size, n_pop);
+  if (static_cast<int64_t>(members_cap) < k * ((2 * s + k - 1) / k))
+    return accept_fail(MOREA_ERANGE, "members_cap below k * ceil(2 min(size, n_pop) / k)");
+  {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return accept_fail(MOREA_EDEVICE, hipGetErrorString(e));
+  }
+  hipLaunchKernelGGL(accept::k_select, dim3(1), dim3(accept::kSelThreads), 0, static_cast<hipStream_t>(stream),
+                     n_pop, static_cast<int>(s), k, guidance_max, obj, flags, severity, selection, n_selected, clu_off,
+                     clu_members, cluster_of);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    char buf[256];
+    snprintf(buf, sizeof(buf), "selection kernel: %s", hipGetErrorString(e));
+    set_error(buf);
+    return MOREA_EDEVICE;
+  }
+  return MOREA_OK;
+}
 
 extern "C" morea_status morea_accept_partial(morea_problem* p, float* parent_pts, int32_t n_parents,
                                              void* parent_cache, int32_t n_evals, const int32_t* eval_parent,

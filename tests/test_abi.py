@@ -114,6 +114,8 @@ def test_null_arguments_rejected():
     assert L.morea_accept_partial(None, None, 1, None, 1, None, None, None, None, None, None, None, None, None,
                                   None, None, 0, float("inf"), None, None) == morea.MOREA_EINVAL
     assert L.morea_mixing_bytes(None, 1) == 0
+    assert L.morea_select_clusters(None, None, None, 4, 2, 2, float("inf"), None, None, None, None, 8, None,
+                                   None) == morea.MOREA_EINVAL
     assert L.morea_estimate_distributions(None, None, 1, 1, None, None, 0, None, None, 0, None) == morea.MOREA_EINVAL
     assert L.morea_sample_partial(None, None, 1, None, 0, 1, None, 1, None, None, None, None, None, None,
                                   None) == morea.MOREA_EINVAL
