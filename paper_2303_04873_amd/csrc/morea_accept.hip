@@ -258,14 +258,21 @@ __global__ __launch_bounds__(kSelThreads) void k_select(int n, int size, int k, 
   s_feas[i] = feas;
   s_left[i] = valid;
   __syncthreads();
-  // fronts by peeling until `size` solutions are covered
-  int rank = -1, covered = 0, r = 0;
-  while (covered < size) {
-    bool front = false;
-    if (s_left[i]) {
-      front = true;
-      for (int j = 0; j < n && front; j++) {
-        if (j == i || !s_left[j]) continue;
+  // dominators of each solution as a bit row (32 words of 32 solutions),
+  // then fronts by peeling until `size` solutions are covered: a solution
+  // joins the front when none of its dominators is left
+  __shared__ uint32_t s_left_bits[kSelThreads / 32];
+  if (i < kSelThreads / 32) s_left_bits[i] = 0u;
+  __syncthreads();
+  if (valid) atomicOr(&s_left_bits[i >> 5], 1u << (i & 31));
+  uint32_t dm[kSelThreads / 32];
+#pragma unroll
+  for (int w = 0; w < kSelThreads / 32; w++) {
+    uint32_t bits = 0u;
+    if (valid && w * 32 < n)
+      for (int b = 0; b < 32; b++) {
+        const int j = w * 32 + b;
+        if (j >= n || j == i || !s_left[j]) continue;
         bool dom;
         if (s_feas[j] && s_feas[i])
           dom = pareto(s_o[0][j], s_o[1][j], s_o[2][j], s_o[0][i], s_o[1][i], s_o[2][i]);
@@ -273,14 +280,24 @@ __global__ __launch_bounds__(kSelThreads) void k_select(int n, int size, int k, 
           dom = s_feas[j];
         else
           dom = s_fold[j] < s_fold[i] || (s_fold[j] == s_fold[i] && s_exc[j] < s_exc[i]);
-        if (dom) front = false;
+        bits |= dom ? (1u << b) : 0u;
       }
-    }
+    dm[w] = bits;
+  }
+  __syncthreads();
+  int rank = -1, covered = 0, r = 0;
+  bool left = valid;
+  while (covered < size) {
+    uint32_t hit = 0u;
+#pragma unroll
+    for (int w = 0; w < kSelThreads / 32; w++) hit |= dm[w] & s_left_bits[w];
+    const bool front = left && hit == 0u;
     int n_front;
     const int before = block_scan(S, front ? 1 : 0, &n_front);
     if (n_front == 0) break;
     if (front) {
-      s_left[i] = 0;
+      left = false;
+      atomicAnd(&s_left_bits[i >> 5], ~(1u << (i & 31)));
       // the last front needed is cut in ascending index
       if (covered + before < size) rank = r;
     }
