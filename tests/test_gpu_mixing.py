@@ -269,3 +269,25 @@ def test_c1_groups_of_three_and_four_points():
     with pytest.raises(morea.MoreaError) as err:
         prob.estimate_distributions(d, dev(clu_off), dev(clu_members), prob.mixing_workspace(k))
     assert err.value.status == morea.MOREA_ERANGE
+
+
+def test_sampling_and_estimation_argument_errors():
+    p = synth_problem(1)
+    pop = synth.make_population(p, pop=4, seed=46)
+    prob, off, gpts, colors = setup(p, len(pop))
+    with pytest.raises(morea.MoreaError) as err:
+        prob.mixing_workspace(2)                       # no reservation yet
+    assert err.value.status == morea.MOREA_ESTATE
+    prob.reserve_partial(8)
+    work = prob.mixing_workspace(2)
+    d = dev(pop)
+    ep = np.zeros(9, np.int32)
+    eg = np.zeros(9, np.int32)
+    z = np.zeros((18, 2, 3), np.float32)
+    with pytest.raises(morea.MoreaError) as err:        # more evaluations than reserved
+        prob.sample_partial(d, work, 2, dev(ep), dev(eg), dev(ep), dev(z))
+    assert err.value.status == morea.MOREA_ERANGE
+    with pytest.raises(morea.MoreaError) as err:        # workspace for fewer clusters
+        prob.sample_partial(d, work, 3, dev(ep[:8]), dev(eg[:8]), dev(ep[:8]), dev(z[:16]))
+    assert err.value.status == morea.MOREA_ERANGE
+    torch.cuda.synchronize()

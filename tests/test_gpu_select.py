@@ -83,3 +83,21 @@ def test_full_block():
     check(obj, fl, sv, 40, 4)
     with pytest.raises(morea.MoreaError):
         run(np.zeros((1025, 3), np.float32), np.zeros(1025, np.uint8), np.zeros(1025, np.float32), 10, 2)
+
+
+def test_argument_errors():
+    """Host-side validation of the selection, sampling and acceptance calls."""
+    import ctypes
+    L = morea.load_library()
+    dev_f = torch.zeros(12, dtype=torch.float32, device="cuda")
+    dev_u8 = torch.zeros(4, dtype=torch.uint8, device="cuda")
+    dev_i = torch.zeros(64, dtype=torch.int32, device="cuda")
+    P = ctypes.c_void_p
+    args = [P(dev_f.data_ptr()), P(dev_u8.data_ptr()), P(dev_f.data_ptr()), 4, 4, 2, float("inf"),
+            P(dev_i.data_ptr()), P(dev_i.data_ptr()), P(dev_i.data_ptr()), P(dev_i.data_ptr())]
+    # members_cap below k * ceil(2 min(size, n) / k) = 8
+    assert L.morea_select_clusters(*args, 7, P(dev_i.data_ptr()), None) == morea.MOREA_ERANGE
+    assert L.morea_select_clusters(*args[:6], float("nan"), *args[7:], 8, P(dev_i.data_ptr()), None) == \
+        morea.MOREA_EINVAL
+    assert L.morea_select_clusters(*args[:4], -1, *args[5:], 8, P(dev_i.data_ptr()), None) == morea.MOREA_EINVAL
+    torch.cuda.synchronize()
