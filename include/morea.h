@@ -267,9 +267,9 @@ morea_status morea_reserve_partial(morea_problem *p, int32_t max_evals);
  * All arrays are device pointers.  The three kernels of a call (list prefix
  * sums, one persistent launch that takes (evaluation, dependent tet,
  * direction) items from a device work queue, and the per-evaluation
- * reduction) are captured once into a HIP graph and replayed while the
- * pointer arguments and sizes stay the same; a call with new buffers
- * captures a new graph.  Out-of-range eval_parent / eval_group entries give
+ * reduction) are captured into a HIP graph and replayed while the pointer
+ * arguments and sizes match one of the last 8 argument sets (see
+ * morea_partial_graphs); other calls capture a new graph.  Out-of-range eval_parent / eval_group entries give
  * that evaluation flags bit 2 and NaN objectives.  The evaluation list is
  * staged through a library-owned device workspace, so calls on one problem
  * must not overlap (use one stream per problem).  Errors: MOREA_ESTATE (no groups or no
@@ -287,9 +287,10 @@ morea_status morea_eval_partial(morea_problem *p, const float *parent_pts, int32
  * written into their parents.  All three objectives are minimised.
  *   domination child vs parent: constraint domination -- a feasible solution
  *     (flags & 7 == 0) beats an infeasible one; two infeasible ones compare
- *     their violation (severity; +inf with flags bit 2 or a NaN objective or
- *     severity), the strictly smaller wins; two feasible ones compare by
- *     Pareto domination (no objective worse, one strictly better);
+ *     their violation (severity; +inf with flags bit 2 or an objective or
+ *     severity that is not finite), the strictly smaller wins; two feasible
+ *     ones compare by Pareto domination (no objective worse, one strictly
+ *     better);
  *   archive: feasible objective vectors; a feasible child is non-dominated
  *     when no member Pareto-dominates it (a member equal to it does not);
  *   an evaluation with an out-of-range parent or group is rejected;
@@ -334,7 +335,8 @@ morea_status morea_accept_partial(morea_problem *p, float *parent_pts, int32_t n
  * equally sized clusters).  Solutions are ordered by the constraint
  * domination of morea_accept_partial (with the same steering bound); fronts
  * by peeling; the selection takes whole fronts in order and the last one it
- * needs in ascending index, up to `size` solutions (invalid ones never).
+ * needs in ascending index, up to `size` solutions (invalid ones -- flags
+ * bit 2, or an objective or severity that is not finite -- never).
  * Objectives are normalised over the selection ((v - lo) / (hi - lo), 0 where
  * hi == lo) and compared by squared Euclidean distance in FP64.  Leaders: the
  * selected solution with the smallest normalised first objective, then
@@ -441,6 +443,13 @@ morea_status morea_tune_partial(morea_problem *p, const float *parent_pts, int32
 /* Current persistent launch shape of partial evaluation (blocks of 256
  * threads, items per queue pop).  Errors: MOREA_EINVAL. */
 morea_status morea_partial_shape(const morea_problem *p, int32_t *blocks, int32_t *chunk);
+
+/* Graph cache of morea_eval_partial: up to 8 captured graphs are kept, one
+ * per argument set (pointers, sizes, launch shape); a call that matches one
+ * replays it, any other captures a new graph in place of the least recently
+ * used.  *cached receives the graphs held, *captures the graphs captured
+ * since the problem was created.  Errors: MOREA_EINVAL. */
+morea_status morea_partial_graphs(const morea_problem *p, int32_t *cached, int64_t *captures);
 
 /* ------------------------------------------------------------------------
  * Learned pre-screen of offspring.  A per-tetrahedron multilayer perceptron

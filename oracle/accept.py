@@ -13,8 +13,9 @@ Readings where the paper leaves the details to MO-RV-GOMEA's literature
     (the summed |signed volume| of the violating tets, Sec. 4.1.4 and App. A.4)
     dominates; of two feasible ones Pareto domination decides (no objective
     worse, at least one strictly better);
-  * a solution with invalid coordinates, or with a NaN objective or severity,
-    has infinite violation, so it is never accepted;
+  * a solution with invalid coordinates, or with an objective or severity
+    that is not finite (NaN or an infinity), has infinite violation, so it is
+    never accepted;
   * the archive holds feasible solutions; a feasible child is non-dominated
     in it when no member Pareto-dominates it (a member with the same
     objective vector does not); an infeasible child is not accepted through
@@ -41,7 +42,7 @@ def violation(obj, flags, severity, guidance_max=math.inf):
     """(feasible, violation) of one evaluated solution; the violation is the
     pair (fold violation, guidance excess), compared lexicographically."""
     values = [float(v) for v in obj] + [float(severity)]
-    if int(flags) & INVALID or any(math.isnan(v) for v in values):
+    if int(flags) & INVALID or not all(math.isfinite(v) for v in values):
         return False, (math.inf, math.inf)
     folded = bool(int(flags) & FOLDS)
     fold = float(severity) if folded else 0.0

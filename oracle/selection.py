@@ -11,7 +11,8 @@ design notes):
     dominates, front r those no solution outside fronts 0..r-1 dominates;
     the selection takes whole fronts in order and the last one it needs in
     ascending index, until it holds `size` solutions; a solution with invalid
-    coordinates or a NaN objective is never selected;
+    coordinates or an objective or severity that is not finite (NaN or an
+    infinity) is never selected;
   * objectives are normalised over the selection, (v - lo) / (hi - lo), 0
     where hi == lo; distances are squared Euclidean, FP64, summed over the
     three objectives in order;
@@ -31,7 +32,7 @@ from oracle import accept as acc
 
 
 def valid(obj, flags, severity):
-    return not (int(flags) & acc.INVALID) and not any(math.isnan(float(v)) for v in list(obj) + [severity])
+    return not (int(flags) & acc.INVALID) and all(math.isfinite(float(v)) for v in list(obj) + [severity])
 
 
 def fronts(obj, flags, sev, guidance_max=math.inf):

@@ -25,7 +25,7 @@ EXPORTS = ["morea_problem_create", "morea_problem_destroy", "morea_cache_bytes",
            "morea_build_fos",
            "morea_set_groups", "morea_reserve_partial", "morea_eval_partial", "morea_accept_partial", "morea_select_clusters",
            "morea_mixing_bytes", "morea_estimate_distributions", "morea_sample_partial",
-           "morea_debug_distance_map", "morea_tune_partial", "morea_partial_shape",
+           "morea_debug_distance_map", "morea_tune_partial", "morea_partial_shape", "morea_partial_graphs",
            "morea_surrogate_num_params", "morea_surrogate_num_features", "morea_surrogate_create",
            "morea_surrogate_destroy", "morea_surrogate_features", "morea_surrogate_targets",
            "morea_surrogate_train_step",
@@ -104,6 +104,8 @@ def load_library():
     L.morea_tune_partial.restype = I32
     L.morea_partial_shape.argtypes = [P, P, P]
     L.morea_partial_shape.restype = I32
+    L.morea_partial_graphs.argtypes = [P, P, P]
+    L.morea_partial_graphs.restype = I32
     L.morea_debug_distance_map.argtypes = [P, I32, I32, P, P]
     L.morea_debug_distance_map.restype = I32
     L.morea_surrogate_num_params.argtypes = []
@@ -266,6 +268,13 @@ def morea_partial_shape(handle):
     b, c = ctypes.c_int32(), ctypes.c_int32()
     _check(load_library().morea_partial_shape(handle, ctypes.byref(b), ctypes.byref(c)))
     return b.value, c.value
+
+
+def morea_partial_graphs(handle):
+    """(graphs held by the partial-evaluation cache, graphs captured so far)."""
+    n, c = ctypes.c_int32(), ctypes.c_int64()
+    _check(load_library().morea_partial_graphs(handle, ctypes.byref(n), ctypes.byref(c)))
+    return n.value, c.value
 
 
 def morea_debug_distance_map(handle, image: int, set_index: int, shape):

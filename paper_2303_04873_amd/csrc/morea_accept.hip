@@ -10,7 +10,8 @@
 // literature (all three objectives are minimised):
 //   feasible: flags == 0 in the fold and invalid bits; violation = severity
 //     (summed |signed volume| of the violating tets) when a fold bit is set,
-//     +inf when the invalid bit is set or an objective or the severity is NaN;
+//     +inf when the invalid bit is set or an objective or the severity is not
+//     finite (NaN or an infinity);
 //   child vs parent: constraint domination -- feasible beats infeasible, two
 //     infeasible compare violations (strictly smaller wins), two feasible
 //     compare by Pareto domination (none worse, one strictly better);
@@ -44,7 +45,7 @@ constexpr int kChunk = 512;   // archive members staged per pass (6 KB of LDS)
 // Feasibility and the violation pair (fold violation, guidance excess).
 __device__ __forceinline__ bool feasible_of(float o0, float o1, float o2, uint8_t f, float sev, float gmax,
                                             float& fold, float& excess) {
-  if ((f & 4u) || isnan(o0) || isnan(o1) || isnan(o2) || isnan(sev)) {
+  if ((f & 4u) || !isfinite(o0) || !isfinite(o1) || !isfinite(o2) || !isfinite(sev)) {
     fold = excess = INFINITY;
     return false;
   }
@@ -247,7 +248,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select(int n, int size, int k, 
     o2 = obj[3 * i + 2];
     const uint8_t f = flags[i];
     const float sv = sev[i];
-    valid = !((f & 4u) || isnan(o0) || isnan(o1) || isnan(o2) || isnan(sv));
+    valid = !((f & 4u) || !isfinite(o0) || !isfinite(o1) || !isfinite(o2) || !isfinite(sv));
     feas = feasible_of(o0, o1, o2, f, sv, gmax, fold, exc);
   }
   s_o[0][i] = o0;
@@ -366,7 +367,9 @@ __global__ __launch_bounds__(kSelThreads) void k_select(int n, int size, int k, 
     const bool member = chosen && closer < m;
     int cnt;
     const int at = block_scan(S, member ? 1 : 0, &cnt);
-    if (member) clu_members[j * m + at] = i;
+    // exactly m members by the (distance, index) order; the bound keeps every
+    // write inside cluster j's m slots whatever the keys hold
+    if (member && at < m) clu_members[j * m + at] = i;
   }
   // cluster of every valid solution: the nearest leader
   if (in) {
@@ -451,8 +454,8 @@ extern "C" morea_status morea_accept_partial(morea_problem* p, float* parent_pts
   // the records and offsets of the partial evaluation live in the library's
   // workspace: they must be those of this evaluation list
   const void* key[5] = {parent_pts, parent_cache, eval_parent, eval_group, new_coords};
-  if (!p->graph_exec || memcmp(key, p->graph_key, sizeof(key)) != 0 || p->graph_key_n[0] != n_parents ||
-      p->graph_key_n[1] != n_evals)
+  if (!p->last_partial || memcmp(key, p->last_key, sizeof(key)) != 0 || p->last_n[0] != n_parents ||
+      p->last_n[1] != n_evals)
     return accept_fail(MOREA_ESTATE, "acceptance must follow morea_eval_partial of the same evaluations");
   {
     const hipError_t e = hipGetLastError();

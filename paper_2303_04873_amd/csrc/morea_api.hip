@@ -81,6 +81,17 @@ void free_all(morea_problem* p) {
 
 namespace morea {
 void set_error(const char* msg) { g_error = msg; }
+
+void ensure_partial_shape(morea_problem* p) {
+  if (p->partial_blocks != 0) return;
+  int cus = 0, per_cu = 0;
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
+  per_cu = partial_blocks_per_cu(p->storage);
+  // the tuner's choice on the 128x128x96 workloads: 4 blocks per compute
+  // unit (at most the occupancy limit), 8 items per queue pop
+  p->partial_blocks = std::max(1, cus) * std::max(1, std::min(4, per_cu));
+  p->partial_chunk = 8;
+}
 }  // namespace morea
 
 extern "C" {
@@ -307,7 +318,8 @@ morea_status morea_problem_create(const morea_problem_desc* d, morea_problem** o
 void morea_problem_destroy(morea_problem* p) {
   if (!p) return;
   (void)hipDeviceSynchronize();
-  if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+  for (auto& g : p->graphs)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
   if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
   for (void* a : p->partial_allocs) (void)hipFree(a);
   for (void* a : p->group_allocs) (void)hipFree(a);
@@ -393,8 +405,11 @@ morea_status upload_to(std::vector<void*>& list, T** dst, const void* src, size_
 }
 
 void drop_graph(morea_problem* p) {
-  if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
-  p->graph_exec = nullptr;
+  for (auto& g : p->graphs) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    g = morea_problem::GraphSlot{};
+  }
+  p->last_partial = false;
 }
 
 void drop_partial(morea_problem* p) {
@@ -512,15 +527,7 @@ morea_status morea_reserve_partial(morea_problem* p, int32_t max_evals) {
     hipError_t e = hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking);
     if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
   }
-  if (p->partial_blocks == 0) {
-    int cus = 0, per_cu = 0;
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
-    per_cu = partial_blocks_per_cu(p->storage);
-    // the tuner's choice on the 128x128x96 workloads: 4 blocks per compute
-    // unit (at most the occupancy limit), 8 items per queue pop
-    p->partial_blocks = std::max(1, cus) * std::max(1, std::min(4, per_cu));
-    p->partial_chunk = 8;
-  }
+  ensure_partial_shape(p);
   p->max_evals = max_evals;
   return MOREA_OK;
 }
@@ -588,10 +595,19 @@ morea_status morea_eval_partial(morea_problem* p, const float* parent_pts, int32
   const void* key[9] = {parent_pts, parent_cache, eval_parent, eval_group, new_coords, obj, flags,
                         severity, counts};
   const int key_n[4] = {n_parents, n_evals, p->partial_blocks, p->partial_chunk};
-  const bool same = p->graph_exec && memcmp(key, p->graph_key, sizeof(key)) == 0 &&
-                    memcmp(key_n, p->graph_key_n, sizeof(key_n)) == 0;
-  if (!same) {
-    drop_graph(p);
+  morea_problem::GraphSlot* slot = nullptr;
+  for (auto& g : p->graphs)
+    if (g.exec && memcmp(key, g.key, sizeof(key)) == 0 && memcmp(key_n, g.key_n, sizeof(key_n)) == 0) slot = &g;
+  if (!slot) {
+    // capture into the least recently used slot (an empty one first)
+    slot = &p->graphs[0];
+    for (auto& g : p->graphs)
+      if (!g.exec || (slot->exec && g.used < slot->used)) {
+        slot = &g;
+        if (!g.exec) break;
+      }
+    if (slot->exec) (void)hipGraphExecDestroy(slot->exec);
+    *slot = morea_problem::GraphSlot{};
     hipError_t e = hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
     hipError_t le = partial_launch(p, parent_pts, n_parents, parent_cache, n_evals, eval_parent,
@@ -604,17 +620,24 @@ morea_status morea_eval_partial(morea_problem* p, const float* parent_pts, int32
       return hip_fail(le, "partial kernels");
     }
     if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
-    e = hipGraphInstantiate(&p->graph_exec, g, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(&slot->exec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
-      p->graph_exec = nullptr;
+      slot->exec = nullptr;
       return hip_fail(e, "hipGraphInstantiate");
     }
-    memcpy(p->graph_key, key, sizeof(key));
-    memcpy(p->graph_key_n, key_n, sizeof(key_n));
+    memcpy(slot->key, key, sizeof(key));
+    memcpy(slot->key_n, key_n, sizeof(key_n));
+    p->graph_captures++;
   }
-  hipError_t e = hipGraphLaunch(p->graph_exec, s);
+  slot->used = ++p->graph_clock;
+  p->last_partial = false;
+  hipError_t e = hipGraphLaunch(slot->exec, s);
   if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  memcpy(p->last_key, key, sizeof(p->last_key));
+  p->last_n[0] = n_parents;
+  p->last_n[1] = n_evals;
+  p->last_partial = true;
   return MOREA_OK;
 }
 
@@ -673,6 +696,15 @@ morea_status morea_tune_partial(morea_problem* p, const float* parent_pts, int32
   p->partial_chunk = best_chunk;
   drop_graph(p);
   if (best_ms) *best_ms = best / 2.0f;
+  return MOREA_OK;
+}
+
+morea_status morea_partial_graphs(const morea_problem* p, int32_t* cached, int64_t* captures) {
+  if (!p || !cached || !captures) return fail(MOREA_EINVAL, "NULL argument");
+  int n = 0;
+  for (const auto& g : p->graphs) n += g.exec ? 1 : 0;
+  *cached = n;
+  *captures = static_cast<int64_t>(p->graph_captures);
   return MOREA_OK;
 }
 

@@ -159,10 +159,25 @@ struct morea_problem {
   // autotuned persistent launch shape
   int partial_blocks = 0;
   int partial_chunk = 1;
-  // the last captured partial-evaluation graph and the arguments it bakes in
-  hipGraphExec_t graph_exec = nullptr;
-  const void* graph_key[9] = {};
-  int graph_key_n[4] = {};
+  // captured partial-evaluation graphs, each with the arguments it bakes in;
+  // a call whose arguments match an entry replays it, otherwise the least
+  // recently used entry is replaced (a generation alternates one argument set
+  // per colour)
+  static constexpr int kGraphSlots = 8;
+  struct GraphSlot {
+    hipGraphExec_t exec = nullptr;
+    const void* key[9] = {};
+    int key_n[4] = {};
+    uint64_t used = 0;   // call counter at the last replay
+  };
+  GraphSlot graphs[kGraphSlots];
+  uint64_t graph_clock = 0;
+  uint64_t graph_captures = 0;   // graphs captured so far (for tests)
+  // arguments of the last launched partial evaluation, whose records and
+  // offsets the workspace holds (the acceptance reads them)
+  bool last_partial = false;
+  const void* last_key[5] = {};
+  int last_n[2] = {};
 };
 
 namespace morea {
@@ -179,6 +194,7 @@ int partial_blocks_per_cu(int storage);
 hipError_t launch_band_cells(const ProblemView& P, const uint8_t* band, uint8_t* cells, hipStream_t s);
 hipError_t launch_fg_cells(const ProblemView& P, int storage, const void* img, uint8_t* cells, hipStream_t s);
 void set_error(const char* msg);   // message returned by morea_last_error() on this thread
+void ensure_partial_shape(morea_problem* p);   // untuned persistent launch shape, once
 hipError_t launch_partial(const ProblemView& P, int storage, const PartialItems& I, int n_parents,
                           int n_groups, const Record* parent_rec, const Totals* parent_tot,
                           Record* new_rec, int* queue, int blocks, int chunk, float* obj,

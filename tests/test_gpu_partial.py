@@ -79,6 +79,50 @@ def test_partial_graph_replay_and_tuner():
         np.testing.assert_array_equal(g[k], ref[k])
 
 
+def test_partial_graph_cache_alternating_sets():
+    """Four argument sets alternated (one per colour of a generation) are
+    captured once each and then replayed; each replay equals the first
+    result of its set; a ninth set evicts the least recently used graph."""
+    p = synth_problem(1)
+    parents = synth.make_population(p, pop=6, seed=14)
+    prob, off, pts, ep, eg, new, dev, cache = setup(p, parents, 10, (4, 16), seed=4)
+    h = prob.handle
+    n0, c0 = morea.morea_partial_graphs(h)
+    assert n0 == 0 and c0 == 0
+    sets = []
+    for k in range(4):
+        sel = torch.arange(k, len(ep), 4, device="cuda")
+        rows = []
+        eg_h = eg
+        starts = np.concatenate([[0], np.cumsum(np.diff(off)[eg_h])])
+        for e in sel.cpu().numpy():
+            rows.append(np.arange(starts[e], starts[e + 1]))
+        new_k = torch.from_numpy(new[np.concatenate(rows)]).cuda()
+        sets.append((dev["ep"][sel].contiguous(), dev["eg"][sel].contiguous(), new_k, prob.outputs(len(sel))))
+    first = []
+    for rnd in range(3):
+        for k, (a, b, c, o) in enumerate(sets):
+            prob.eval_partial(dev["parents"], cache, a, b, c, out=o)
+            torch.cuda.synchronize()
+            g = to_host(o)
+            if rnd == 0:
+                first.append(g)
+            else:
+                for key in g:
+                    np.testing.assert_array_equal(g[key], first[k][key])
+            o["obj"].zero_()
+    assert morea.morea_partial_graphs(h) == (4, 4)
+    # more argument sets than slots: the oldest ones are replaced
+    extra = [prob.outputs(len(sets[0][0])) for _ in range(5)]
+    for o in extra:
+        prob.eval_partial(dev["parents"], cache, sets[0][0], sets[0][1], sets[0][2], out=o)
+    torch.cuda.synchronize()
+    assert morea.morea_partial_graphs(h) == (8, 9)
+    for o in extra:
+        for key in ("obj", "flags", "counts"):
+            np.testing.assert_array_equal(to_host(o)[key], first[0][key])
+
+
 def test_partial_invalid_inputs():
     p = synth_problem(1)
     parents = synth.make_population(p, pop=4, seed=13)

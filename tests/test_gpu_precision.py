@@ -52,12 +52,17 @@ def test_c4_full_size_sampled(storage):
     assert_parity(g, quantized_oracle(p, storage).evaluate(pop[idx]), idx=idx, what=storage)
 
 
-def test_c4_partial_bf16():
+@pytest.mark.parametrize("storage", ["bf16", "f16"])
+def test_c4_partial(storage):
+    """192x192x128, 16 parents x 8 groups of 4-48 points: the partial
+    evaluations equal a full evaluation of each child with the same storage
+    (counts and flags exact, objectives within 1e-5) and the oracle on the
+    quantized images for three children."""
     p = synth_problem(4)
     parents = synth.make_population(p, pop=16)
     off, pts = synth.make_groups(p, n_groups=8, sizes=(4, 48))
     ep, eg, new = synth.make_children(p, parents, off, pts)
-    prob = morea.Problem.from_synth(p, storage="bf16", max_population=16)
+    prob = morea.Problem.from_synth(p, storage=storage, max_population=16)
     prob.set_groups(off, pts)
     prob.reserve_partial(len(ep))
     dpar = torch.from_numpy(parents).cuda()
@@ -66,11 +71,11 @@ def test_c4_partial_bf16():
     g = to_host(prob.eval_partial(dpar, cache, torch.from_numpy(ep).cuda(), torch.from_numpy(eg).cuda(),
                                   torch.from_numpy(new).cuda()))
     kids = np.stack([synth.apply_child(parents, off, pts, ep, eg, new, e) for e in range(len(ep))])
-    full = to_host(morea.Problem.from_synth(p, storage="bf16", max_population=len(kids)).eval_full(
+    full = to_host(morea.Problem.from_synth(p, storage=storage, max_population=len(kids)).eval_full(
         torch.from_numpy(kids).cuda()))
     np.testing.assert_array_equal(full["counts"], g["counts"])
     np.testing.assert_array_equal(full["flags"], g["flags"])
     rel = np.abs(full["obj"].astype(np.float64) - g["obj"]) / np.abs(full["obj"])
     assert rel.max() < 1e-5
     few = [0, 37, 101]
-    assert_parity(g, quantized_oracle(p, "bf16").evaluate(kids[few]), idx=few, what="c4 partial")
+    assert_parity(g, quantized_oracle(p, storage).evaluate(kids[few]), idx=few, what=f"c4 partial {storage}")

@@ -74,6 +74,32 @@ def test_grid_ties_and_steering():
     check(obj, fl, sv, 105, 10, gmax=0.75)
 
 
+def test_infinite_objectives_are_invalid():
+    """Regression: an infinite objective once passed as valid, normalised to
+    NaN and let a solution join every cluster past its m slots.  Now such
+    solutions are invalid (never selected, cluster -1), on a case whose
+    clusters fill members_cap exactly."""
+    rs = np.random.default_rng(24)
+    n = 40
+    obj = rs.normal(size=(n, 3)).astype(np.float32)
+    fl = np.zeros(n, np.uint8)
+    sv = np.zeros(n, np.float32)
+    obj[3, 0] = np.inf
+    obj[7, 1] = -np.inf
+    obj[11, 2] = np.inf
+    sv[13] = np.inf
+    for size, k in ((20, 4), (36, 6), (40, 5)):
+        print("case", size, k, flush=True)
+        n_sel, _ = check(obj, fl, sv, size, k)
+        got = run(obj, fl, sv, size, k)
+        m = min(n_sel, -(-2 * n_sel // k))
+        assert got["clu_off"][k] == min(k, n_sel) * m <= len(got["clu_members"])
+        if size < 40:
+            assert got["clu_off"][k] == len(got["clu_members"])      # the clusters fill members_cap
+        for i in (3, 7, 11, 13):
+            assert got["cluster_of"][i] == -1 and i not in got["selection"][:n_sel]
+
+
 def test_full_block():
     rs = np.random.default_rng(23)
     n = 1024

@@ -38,6 +38,12 @@ def test_hand_worked_cases():
     assert not cd(sol((1, 1, 1), BAD), sol((9, 9, 9), BAD))             # invalid never wins
     assert cd(sol((9, 9, 9), S, 1e30), sol((0, 0, 0), BAD))
     assert cd(sol((1, 1, 1)), sol((1, float("nan"), 0)))                # NaN counts as invalid
+    inf = float("inf")
+    assert cd(sol((1, 1, 1)), sol((-inf, 0, 0)))                        # so does an infinity
+    assert cd(sol((9, 9, 9), S, 1e30), sol((0, inf, 0)))
+    assert not cd(sol((0, 0, inf)), sol((9, 9, 9), S, 1e30))
+    assert not acc.accept(sol((-inf, -inf, -inf)), sol((9, 9, 9)), [])  # never kept
+    assert acc.violation((0, 0, 0), F, inf) == (False, (inf, inf))      # an infinite severity too
     parent = sol((1, 2, 3))
     trade = sol((0.5, 2.5, 3))                                          # better in one, worse in one
     assert acc.accept(trade, parent, [])                                # vacuously non-dominated

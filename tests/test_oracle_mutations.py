@@ -93,7 +93,12 @@ FOS = os.path.join(ROOT, "tests", "test_oracle_fos.py")
 ACCEPT = os.path.join(ROOT, "tests", "test_oracle_accept.py")
 MIXING = os.path.join(ROOT, "tests", "test_oracle_mixing.py")
 SELECTION = os.path.join(ROOT, "tests", "test_oracle_selection.py")
+QUANT = os.path.join(ROOT, "tests", "test_oracle_quantize.py")
 PY_MUTATIONS = [
+    ("quantize: BF16 truncated", "__init__.py", "rounded = (u + 0x7FFF + ((u >> 16) & 1)) >> 16",
+     "rounded = u >> 16", QUANT, []),
+    ("quantize: BF16 ties away from zero", "__init__.py", "rounded = (u + 0x7FFF + ((u >> 16) & 1)) >> 16",
+     "rounded = (u + 0x8000) >> 16", QUANT, []),
     ("repair: step twice the rounded-down distance", "repair.py",
      "while j < SIGMA_MAX_LOG2 and (4 ** (j + 1)) * n * n <= d2:",
      "while j < SIGMA_MAX_LOG2 and (4 ** j) * n * n <= d2:", REPAIR, []),
@@ -121,7 +126,13 @@ PY_MUTATIONS = [
     ("accept: infeasible children through the archive", "accept.py",
      "return feasible and not any(", "return not any(", ACCEPT, []),
     ("accept: NaN objectives count as feasible", "accept.py",
-     "if int(flags) & INVALID or any(math.isnan(v) for v in values):", "if int(flags) & INVALID:", ACCEPT, []),
+     "if int(flags) & INVALID or not all(math.isfinite(v) for v in values):", "if int(flags) & INVALID:", ACCEPT, []),
+    ("accept: infinite objectives count as feasible", "accept.py",
+     "if int(flags) & INVALID or not all(math.isfinite(v) for v in values):",
+     "if int(flags) & INVALID or any(math.isnan(v) for v in values):", ACCEPT, []),
+    ("selection: infinite objectives selected", "selection.py",
+     "and all(math.isfinite(float(v)) for v in list(obj) + [severity])",
+     "and not any(math.isnan(float(v)) for v in list(obj) + [severity])", SELECTION, []),
     ("accept: rows owned by accepted evaluations only", "accept.py",
      "            out[int(eval_parent[e])][:, :, idx] = new_coords[row:row + len(idx)].transpose(1, 2, 0)\n"
      "        row += len(idx)",

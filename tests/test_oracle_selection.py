@@ -30,6 +30,15 @@ def test_hand_worked_fronts_and_selection():
     assert sl.select(obj, fl, sv, 10) == [0, 1, 2, 3]          # the invalid one never
     obj, fl, sv = arrays([(1, 0, 0), (0, 1, 0), (0, 0, 1), (2, 2, 2), (0, 0.5, 0.5)])
     assert sl.select(obj, fl, sv, 2) == [0, 1]                   # last front cut in index order
+    # an infinite objective or severity makes a solution invalid: never
+    # selected (it would otherwise dominate everything or normalise to NaN)
+    inf = float("inf")
+    obj, fl, sv = arrays([(-inf, 0, 0), (1, 1, 1), (0, inf, 0), (2, 0, 2), (0, 0, 0)], sev=[0, 0, 0, 0, inf])
+    assert sl.fronts(obj, fl, sv) == [None, 0, None, 0, None]
+    assert sl.select(obj, fl, sv, 5) == [1, 3]
+    sel, leaders, members, cluster_of = sl.clusters(obj, fl, sv, 5, 2)
+    assert cluster_of[0] == cluster_of[2] == cluster_of[4] == -1
+    assert sorted(map(len, members)) == [2, 2]
 
 
 def chain_rank(obj, flags, sev):
