@@ -107,7 +107,19 @@ void morea_problem_destroy(morea_problem *p);
 
 /* Bytes of a per-tetrahedron cache for `pop` candidates (App. A.2's partial
  * objective values per tet, kept so that partial evaluations can reuse
- * them, Sec. 4.2.1). */
+ * them, Sec. 4.2.1).  Layout: pop * n_tets * 2 records of 24 bytes,
+ * candidate-major, then tet, then direction (0: the source tet rasterized on
+ * I_s and mapped into I_t; 1: the target tet on I_t mapped into I_s), each
+ *   float h      sum of the intensity term h over the tet's samples
+ *   float g      set-weighted guidance sum (weights |C_i| / |G|)
+ *   uint32 n     samples (voxel centres, or points of the sampled estimator)
+ *   float mag    the tet's magnitude term c * sum (|e_S| - |e_T|)^2
+ *                (direction 0; 0 in direction 1)
+ *   float vol    |signed volume| (voxel^3) when the direction's tet violates
+ *                its reference orientation, else 0
+ *   uint32 bits  bit0 violation, bit2 a vertex of the tet has an invalid
+ *                coordinate
+ * followed by pop blocks of 64 bytes of per-candidate totals (internal). */
 size_t morea_cache_bytes(const morea_problem *p, int32_t pop);
 
 /* Full evaluation of `pop` candidates (Sec. 4.1).

@@ -151,8 +151,8 @@ class Problem:
         flags [pop] (bit0 source fold, bit1 target fold, bit2 invalid),
         severity [pop], counts [pop][2] (|P_s|, |P_t|) and, with
         ``records``, per-(candidate, tet, direction) records
-        [pop][n_tets][2][5] = (h sum, guidance sum, samples, magnitude,
-        violating volume)."""
+        [pop][n_tets][2][6] = (h sum, guidance sum, samples, magnitude,
+        violating volume, violation 1/0)."""
         pts = np.ascontiguousarray(pts, dtype=np.float32)
         pop = pts.shape[0]
         assert pts.shape[1:] == (2, 3, self.n_points), pts.shape
@@ -160,7 +160,7 @@ class Problem:
         flags = np.empty(pop, np.uint8)
         sev = np.empty(pop, np.float64)
         counts = np.empty((pop, 2), np.int64)
-        rec = np.empty((pop, self.n_tets, 2, 5), np.float64) if records else None
+        rec = np.empty((pop, self.n_tets, 2, 6), np.float64) if records else None
         lib().oracle_eval(ctypes.byref(self._c), _ptr(pts), pop, _ptr(obj), _ptr(flags), _ptr(sev),
                           _ptr(counts), _ptr(rec))
         out = dict(obj=obj, flags=flags, severity=sev, counts=counts)
@@ -212,7 +212,7 @@ class Problem:
         flags = np.empty(pop, np.uint8)
         sev = np.empty(pop, np.float64)
         counts = np.empty((pop, 2), np.int64)
-        rec = np.empty((pop, self.n_tets, 2, 5), np.float64) if records else None
+        rec = np.empty((pop, self.n_tets, 2, 6), np.float64) if records else None
         if lib().oracle_eval_sobol(ctypes.byref(self._c), _ptr(pts), pop, float(rate), int(seed), _ptr(obj),
                                    _ptr(flags), _ptr(sev), _ptr(counts), _ptr(rec)) != 0:
             raise ValueError("rate must be > 0")

@@ -36,36 +36,57 @@ def pack(p):
     return np.concatenate([np.asarray(p[name], np.float64).ravel() for name, _ in SHAPES])
 
 
-def forward(theta, X):
-    """Predictions y [n] for inputs X [n][23], and the activations."""
+def _keep(a):
+    return a
+
+
+def forward(theta, X, rnd=None):
+    """Predictions y [n] for inputs X [n][23], and the activations.
+
+    ``rnd`` (default: none) rounds at the points where a matrix-core
+    implementation stores operands in a narrow type: the inputs, W1, W2 and
+    the layer-1 activations h1; biases, z2, h2, w3 and the output stay
+    unrounded."""
+    r = _keep if rnd is None else rnd
     p = unpack(theta)
-    X = np.asarray(X, np.float64)
-    z1 = X @ p["W1"].T + p["b1"]
-    h1 = np.maximum(z1, 0.0)
-    z2 = h1 @ p["W2"].T + p["b2"]
+    X = r(np.asarray(X, np.float64))
+    z1 = X @ r(p["W1"]).T + p["b1"]
+    h1 = r(np.maximum(z1, 0.0))
+    z2 = h1 @ r(p["W2"]).T + p["b2"]
     h2 = np.maximum(z2, 0.0)
     y = h2 @ p["w3"] + p["b3"][0]
     return y, (X, z1, h1, z2, h2)
 
 
-def loss(theta, X, t):
-    y, _ = forward(theta, X)
+def loss(theta, X, t, rnd=None):
+    y, _ = forward(theta, X, rnd)
     return float(np.mean((y - np.asarray(t, np.float64)) ** 2))
 
 
-def gradient(theta, X, t):
-    """Exact gradient of the mean squared error with respect to theta."""
+def gradient(theta, X, t, rnd=None):
+    """Gradient of the mean squared error with respect to theta (exact
+    backpropagation when ``rnd`` is None).
+
+    With ``rnd``, the forward pass rounds as in ``forward`` and the backward
+    pass rounds the two back-propagated activations that a matrix-core
+    implementation feeds to its products, dz2 (before dh1 = dz2 W2 and
+    dW2 = dz2^T h1) and dz1 (before dW1 = dz1^T X); the bias and output-layer
+    gradients use the unrounded dz2 and dz1, and the ReLU derivative of layer
+    1 is taken from the rounded h1 (h1 > 0 exactly when z1 > 0 for any
+    rounding that keeps signs and zeros)."""
+    r = _keep if rnd is None else rnd
     p = unpack(theta)
-    y, (X, z1, h1, z2, h2) = forward(theta, X)
+    y, (X, z1, h1, z2, h2) = forward(theta, X, rnd)
     n = X.shape[0]
     dy = 2.0 * (y - np.asarray(t, np.float64)) / n
     g = {"w3": h2.T @ dy, "b3": np.array([dy.sum()])}
     dz2 = np.outer(dy, p["w3"]) * (z2 > 0)
-    g["W2"] = dz2.T @ h1
     g["b2"] = dz2.sum(axis=0)
-    dz1 = (dz2 @ p["W2"]) * (z1 > 0)
-    g["W1"] = dz1.T @ X
+    dz2 = r(dz2)
+    g["W2"] = dz2.T @ h1
+    dz1 = (dz2 @ r(p["W2"])) * (h1 > 0)
     g["b1"] = dz1.sum(axis=0)
+    g["W1"] = r(dz1).T @ X
     return pack(g)
 
 

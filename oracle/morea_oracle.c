@@ -537,7 +537,7 @@ static int candidate_valid(const float *cand, int n_points) {
 }
 
 /* Records per (candidate, tet, direction): h, g, n, magnitude (direction 0
- * only), violation volume (0 when no violation). */
+ * only), violation volume (0 when no violation), violation (1 or 0). */
 typedef struct {
   double rate;
   uint64_t seed;
@@ -608,12 +608,13 @@ static int eval_all(const oracle_problem *P, const float *pts, int pop, const so
           sev += r->vol;
         }
         if (tet_rec) {
-          double *o = tet_rec + (it * 2 + m) * 5;
+          double *o = tet_rec + (it * 2 + m) * 6;
           o[0] = r->h;
           o[1] = r->g;
           o[2] = (double)r->n;
           o[3] = m == 0 ? mags[it] : 0.0;
           o[4] = r->viol ? r->vol : 0.0;
+          o[5] = r->viol ? 1.0 : 0.0;
         }
       }
       M += mags[it];

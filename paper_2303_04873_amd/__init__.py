@@ -357,6 +357,16 @@ class Problem:
         import torch
         return torch.empty(self.cache_bytes(pop), dtype=torch.uint8, device="cuda")
 
+    def cache_records(self, cache, pop):
+        """The per-(candidate, tet, direction) records of a cache as a NumPy
+        structured array [pop][n_tets][2] (fields h, g, n, mag, vol, bits)."""
+        dt = np.dtype([("h", "<f4"), ("g", "<f4"), ("n", "<u4"), ("mag", "<f4"), ("vol", "<f4"),
+                       ("bits", "<u4")])
+        assert dt.itemsize == 24
+        nbytes = pop * self.n_tets * 2 * dt.itemsize
+        raw = cache[:nbytes].cpu().numpy()
+        return raw.view(dt).reshape(pop, self.n_tets, 2)
+
     def outputs(self, n):
         import torch
         dev = "cuda"

@@ -48,3 +48,22 @@ def test_bf16_rounding():
     assert r[0] == 1.0 and r[1] == 1.0 and r[2] == 1.0 + 2 ** -7
     assert r[3] == 1.0 + 2 ** -6   # tie to even
     assert abs(r[4] - (-2.5e-3)) < 2.5e-3 * 2 ** -8
+
+
+def test_rounded_gradient_is_the_exact_one_with_identity_rounding():
+    """The rounding points of the mixed-precision gradient are parameters of
+    the same backpropagation: with the identity it is the exact gradient
+    (pinned above by finite differences), and with BF16 rounding it stays
+    within the relative error that 8-bit significands allow."""
+    rs = np.random.default_rng(3)
+    theta = rs.normal(0, 0.2, mlp.N_PARAMS)
+    X = rs.normal(0, 1, (41, mlp.N_IN))
+    t = rs.normal(0, 1, 41)
+    g = mlp.gradient(theta, X, t)
+    np.testing.assert_array_equal(mlp.gradient(theta, X, t, rnd=lambda a: a), g)
+    gb = mlp.gradient(theta, X, t, rnd=mlp.bf16)
+    assert 0 < np.linalg.norm(gb - g) <= 0.1 * np.linalg.norm(g)      # errors compound over two layers
+    yb, _ = mlp.forward(theta, X, rnd=mlp.bf16)
+    y, _ = mlp.forward(theta, X)
+    assert 0 < np.abs(yb - y).max() <= 2.0 ** -6 * np.abs(y).max()
+    assert mlp.loss(theta, X, t, rnd=mlp.bf16) != mlp.loss(theta, X, t)
