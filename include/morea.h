@@ -374,6 +374,72 @@ morea_status morea_select_clusters(const float *obj, const uint8_t *flags, const
                                    int32_t *n_selected, int32_t *clu_off, int32_t *clu_members, int32_t members_cap,
                                    int32_t *cluster_of, void *stream);
 
+/* Elitist archive (Sec. 3: non-dominated solutions kept across generations
+ * in an archive of fixed capacity, 2000 in App. C; Sec. 4.3.2: with adaptive
+ * steering only guidance values up to 1.5 times the archive's best are kept).
+ * The archive is caller-owned device memory of `capacity` slots:
+ *   arc_obj    [capacity][3] FP32 objective vectors; a free slot holds
+ *              (inf, inf, inf), which dominates nothing, so the slot array
+ *              can be passed whole as morea_accept_partial's archive
+ *   arc_stamp  [capacity] insertion stamps (order of the members), -1 free
+ *   arc_pts    [capacity][2][3][n_points] FP32 members' points, or NULL
+ *   arc_state  [4] int32: members, next stamp, boxes per objective of the
+ *              last thinning (0: none), 0
+ *   best_guidance [1] FP32: the members' smallest guidance value (inf when
+ *              empty); the next generation's steering bound is 1.5 times it
+ * morea_archive_clear empties it (kernels only: no memset, so a captured
+ * graph may hold it).  1 <= capacity <= 4096.  Errors: MOREA_EINVAL,
+ * MOREA_EDEVICE. */
+morea_status morea_archive_clear(int32_t capacity, float *arc_obj, int32_t *arc_stamp, int32_t *arc_state,
+                                 float *best_guidance, void *stream);
+
+/* Archive update with a batch of offered solutions (the population after a
+ * batch of acceptances).  The candidates are the members in stamp order, then
+ * the feasible offers (flags == 0, finite objectives and severity) in index
+ * order, less those whose guidance value is above guidance_max (the steering
+ * bound, inf when off: members above it are purged); a candidate stays unless
+ * another Pareto-dominates it or an earlier one has the same objective vector.
+ * If more than `capacity` stay, the objective range of the stayers is cut
+ * into L boxes per objective (FP64: min(L - 1, floor((v - lo) / (hi - lo) *
+ * L)), 0 where hi == lo), L found by binary search over [1, min(capacity,
+ * 1024)] for at most `capacity` occupied boxes, and each box keeps its
+ * earliest candidate.  Members that do not stay free their slots; staying
+ * offers take the free slots in ascending order with the next stamps.
+ *   offer_obj, offer_flags, offer_sev   [n_offers] (layout of morea_eval_full)
+ *   offer_pts  [n_offers][2][3][n_points] or NULL (then arc_pts NULL too)
+ *   inserted   [n_offers] receives 1 for offers that entered, else 0
+ *   slot_of    [n_offers] receives the slot of an entered offer, else -1
+ * 0 <= n_offers <= 1024, capacity + n_offers <= 4096.  All arrays are device
+ * pointers; asynchronous on `stream` (one block); no allocation.  Errors:
+ * MOREA_EINVAL, MOREA_ERANGE, MOREA_EDEVICE. */
+morea_status morea_archive_update(int32_t n_offers, const float *offer_obj, const uint8_t *offer_flags,
+                                  const float *offer_sev, const float *offer_pts, int32_t n_points,
+                                  float guidance_max, int32_t capacity, float *arc_obj, int32_t *arc_stamp,
+                                  float *arc_pts, int32_t *arc_state, float *best_guidance, uint8_t *inserted,
+                                  int32_t *slot_of, void *stream);
+
+/* Improvements of a batch for the distribution multipliers (MO-RV-GOMEA's
+ * adaptive variance scaling, to which Sec. 3 defers): improved[c][g] is set
+ * to 1 for every kept child (accepted[e] != 0) of cluster eval_cluster[e] and
+ * element eval_group[e] whose parent entered the archive in the batch's
+ * update (parent_inserted[eval_parent[e]] != 0); out-of-range indices are
+ * skipped.  Device pointers; asynchronous on `stream`.  Errors:
+ * MOREA_EINVAL, MOREA_EDEVICE. */
+morea_status morea_mark_improvements(int32_t n_evals, const int32_t *eval_parent, const int32_t *eval_group,
+                                     const int32_t *eval_cluster, const uint8_t *accepted, int32_t n_parents,
+                                     const uint8_t *parent_inserted, int32_t n_clusters, int32_t n_groups,
+                                     uint8_t *improved, void *stream);
+
+/* End-of-generation adaptation of the multipliers mult [n_clusters][n_groups]
+ * (FP32, morea_sample_partial's `mult`) with no-improvement stretches
+ * [n_clusters][n_groups] int32: improved -> stretch 0, c = min(max(c, 1) /
+ * 0.9, 10); otherwise the stretch grows while c <= 1, c = 0.9 c when c > 1 or
+ * the stretch has reached 25, and a c below 1 with a shorter stretch is reset
+ * to 1.  The marks are cleared.  Device pointers; asynchronous on `stream`.
+ * Errors: MOREA_EINVAL, MOREA_EDEVICE. */
+morea_status morea_adapt_multipliers(int32_t n_clusters, int32_t n_groups, uint8_t *improved, float *mult,
+                                     int32_t *no_improvement, void *stream);
+
 /* Bytes of the caller-owned workspace of the optimal-mixing distributions
  * for n_clusters clusters of the registered groups (one record per
  * (cluster, group) plus the row offsets of the reserved evaluations); 0 before

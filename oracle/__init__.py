@@ -61,6 +61,8 @@ def lib():
         L.oracle_orient.restype = ctypes.c_double
         L.oracle_threads.argtypes = []
         L.oracle_threads.restype = ctypes.c_int
+        L.oracle_set_threads.argtypes = [ctypes.c_int]
+        L.oracle_set_threads.restype = None
         L.oracle_eval_sobol.argtypes = [P, P, ctypes.c_int, ctypes.c_double, ctypes.c_uint64, P, P, P, P, P]
         L.oracle_eval_sobol.restype = ctypes.c_int
         L.oracle_sobol_coord.argtypes = [ctypes.c_int, ctypes.c_uint32]
@@ -301,6 +303,11 @@ def sobol_points(own, oth, direction=0, seed=0, rate=1.0, cap=1 << 20):
 def threads() -> int:
     """Threads the oracle's OpenMP loops use."""
     return int(lib().oracle_threads())
+
+
+def set_threads(n: int) -> None:
+    """Set the threads of the oracle's OpenMP loops."""
+    lib().oracle_set_threads(int(n))
 
 
 def timed_evaluate(problem: Problem, pts):

@@ -740,6 +740,8 @@ double oracle_orient(const float v[12]) {
  * oracle's timings). */
 int oracle_threads(void) { return omp_get_max_threads(); }
 
+void oracle_set_threads(int n) { omp_set_num_threads(n); }
+
 /* Coordinate j of point n of the unshifted Sobol sequence (natural order). */
 uint32_t oracle_sobol_coord(int j, uint32_t n) {
   sobol_init();

@@ -24,6 +24,7 @@ EXPORTS = ["morea_problem_create", "morea_problem_destroy", "morea_cache_bytes",
            "morea_eval_sobol", "morea_repair_folds", "morea_rasterize_dvf", "morea_point_guidance",
            "morea_build_fos",
            "morea_set_groups", "morea_reserve_partial", "morea_eval_partial", "morea_accept_partial", "morea_select_clusters",
+           "morea_archive_clear", "morea_archive_update", "morea_mark_improvements", "morea_adapt_multipliers",
            "morea_mixing_bytes", "morea_estimate_distributions", "morea_sample_partial",
            "morea_debug_distance_map", "morea_tune_partial", "morea_partial_shape", "morea_partial_graphs",
            "morea_surrogate_num_params", "morea_surrogate_num_features", "morea_surrogate_create",
@@ -94,6 +95,14 @@ def load_library():
     L.morea_accept_partial.restype = I32
     L.morea_select_clusters.argtypes = [P, P, P, I32, I32, I32, ctypes.c_float, P, P, P, P, I32, P, P]
     L.morea_select_clusters.restype = I32
+    L.morea_archive_clear.argtypes = [I32, P, P, P, P, P]
+    L.morea_archive_clear.restype = I32
+    L.morea_archive_update.argtypes = [I32, P, P, P, P, I32, ctypes.c_float, I32, P, P, P, P, P, P, P, P]
+    L.morea_archive_update.restype = I32
+    L.morea_mark_improvements.argtypes = [I32, P, P, P, P, I32, P, I32, I32, P, P]
+    L.morea_mark_improvements.restype = I32
+    L.morea_adapt_multipliers.argtypes = [I32, I32, P, P, P, P]
+    L.morea_adapt_multipliers.restype = I32
     L.morea_mixing_bytes.argtypes = [P, I32]
     L.morea_mixing_bytes.restype = ctypes.c_size_t
     L.morea_estimate_distributions.argtypes = [P, P, I32, I32, P, P, I32, P, P, ctypes.c_size_t, P]
@@ -253,6 +262,65 @@ def select_clusters(out, size, k, guidance_max=None, stream=None):
     return res
 
 
+class Archive:
+    """Elitist archive in device memory (morea_archive_clear / _update):
+    obj [capacity][3], stamp [capacity], pts [capacity][2][3][n_points] (or
+    None), state [4], best [1] -- torch CUDA tensors owned by this object."""
+
+    def __init__(self, capacity, n_points=0, stream=None):
+        import torch
+        self.capacity = int(capacity)
+        self.n_points = int(n_points)
+        dev = "cuda"
+        self.obj = torch.empty((self.capacity, 3), dtype=torch.float32, device=dev)
+        self.stamp = torch.empty(self.capacity, dtype=torch.int32, device=dev)
+        self.pts = (torch.empty((self.capacity, 2, 3, self.n_points), dtype=torch.float32, device=dev)
+                    if self.n_points else None)
+        self.state = torch.empty(4, dtype=torch.int32, device=dev)
+        self.best = torch.empty(1, dtype=torch.float32, device=dev)
+        self.clear(stream)
+
+    def clear(self, stream=None):
+        _check(load_library().morea_archive_clear(self.capacity, _dev_ptr(self.obj), _dev_ptr(self.stamp),
+                                                  _dev_ptr(self.state), _dev_ptr(self.best),
+                                                  _stream_ptr(stream)))
+
+    def update(self, out, pts=None, guidance_max=None, inserted=None, slot_of=None, stream=None):
+        """Offer the solutions whose evaluation outputs are `out` (obj, flags,
+        severity) and, when the archive keeps points, their points `pts`.
+        Returns (inserted uint8 [n], slot_of int32 [n])."""
+        import torch
+        n = out["flags"].shape[0]
+        if inserted is None:
+            inserted = torch.empty(n, dtype=torch.uint8, device="cuda")
+        if slot_of is None:
+            slot_of = torch.empty(n, dtype=torch.int32, device="cuda")
+        if (pts is None) != (self.pts is None):
+            raise ValueError("points are offered exactly when the archive keeps them")
+        _check(load_library().morea_archive_update(
+            n, _dev_ptr(out["obj"]), _dev_ptr(out["flags"]), _dev_ptr(out["severity"]), _dev_ptr(pts),
+            self.n_points, float("inf") if guidance_max is None else float(guidance_max), self.capacity,
+            _dev_ptr(self.obj), _dev_ptr(self.stamp), _dev_ptr(self.pts), _dev_ptr(self.state),
+            _dev_ptr(self.best), _dev_ptr(inserted), _dev_ptr(slot_of), _stream_ptr(stream)))
+        return inserted, slot_of
+
+
+def morea_mark_improvements(eval_parent, eval_group, eval_cluster, accepted, parent_inserted, improved,
+                            stream=None):
+    """improved: uint8 CUDA [n_clusters][n_groups] (marks set in place)."""
+    _check(load_library().morea_mark_improvements(
+        eval_parent.shape[0], _dev_ptr(eval_parent), _dev_ptr(eval_group), _dev_ptr(eval_cluster),
+        _dev_ptr(accepted), parent_inserted.shape[0], _dev_ptr(parent_inserted), improved.shape[0],
+        improved.shape[1], _dev_ptr(improved), _stream_ptr(stream)))
+
+
+def morea_adapt_multipliers(improved, mult, no_improvement, stream=None):
+    """improved uint8, mult float32, no_improvement int32: CUDA [k][n_groups]."""
+    _check(load_library().morea_adapt_multipliers(improved.shape[0], improved.shape[1], _dev_ptr(improved),
+                                                  _dev_ptr(mult), _dev_ptr(no_improvement),
+                                                  _stream_ptr(stream)))
+
+
 def morea_tune_partial(handle, parent_pts, n_parents, parent_cache, n_evals, eval_parent, eval_group,
                        new_coords, obj, flags, severity, counts, stream) -> float:
     best = ctypes.c_float()
@@ -328,6 +396,7 @@ class Problem:
         d.max_population = int(max_population)
         self.n_points = d.n_points
         self.n_tets = d.n_tets
+        self.tets_host = tets
         self.n_sets = n_sets
         self.max_population = int(max_population)
         self.handle = morea_problem_create(d)
