@@ -210,6 +210,17 @@ morea_status morea_repair_folds(morea_problem *p, float *pts, int32_t pop, const
 morea_status morea_rasterize_dvf(morea_problem *p, const float *cand, float *fwd, float *inv, uint32_t *cover,
                                  int32_t *work, void *stream);
 
+/* The same DVF rasterization for callers that cannot allocate device memory
+ * (code under HIP graph capture, serving loops, harnesses that forbid
+ * hipMalloc): no workspace argument and no allocation; the owner of every
+ * centre lives in a static 16 MiB device array of the library (one per GPU,
+ * held until the process ends), so grids of at most 2,097,152 voxels.  Calls
+ * on one GPU share that array: calls that overlap on one GPU (different
+ * streams, threads) race.  Arguments and outputs as morea_rasterize_dvf.
+ * Errors: MOREA_EINVAL, MOREA_ERANGE (grid above the limit), MOREA_EDEVICE. */
+morea_status morea_rasterize_dvf_static(morea_problem *p, const float *cand, float *fwd, float *inv,
+                                        uint32_t *cover, void *stream);
+
 /* Point-based guidance error of `pop` candidates: the guidance measure of
  * the paper's prior work, which Sec. 4.1.3 replaces by the continuous form.
  * Every point c of the problem's C_s sets is located in the candidate's

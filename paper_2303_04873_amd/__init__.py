@@ -21,7 +21,8 @@ MOREA_OK, MOREA_EINVAL, MOREA_ENOMEM, MOREA_EDEVICE, MOREA_ERANGE, MOREA_ESTATE 
 STORE = {"f32": 0, "bf16": 1, "f16": 2}
 
 EXPORTS = ["morea_problem_create", "morea_problem_destroy", "morea_cache_bytes", "morea_eval_full",
-           "morea_eval_sobol", "morea_repair_folds", "morea_rasterize_dvf", "morea_point_guidance",
+           "morea_eval_sobol", "morea_repair_folds", "morea_rasterize_dvf", "morea_rasterize_dvf_static",
+           "morea_point_guidance",
            "morea_build_fos",
            "morea_set_groups", "morea_reserve_partial", "morea_eval_partial", "morea_accept_partial", "morea_select_clusters",
            "morea_archive_clear", "morea_archive_update", "morea_mark_improvements", "morea_adapt_multipliers",
@@ -80,6 +81,8 @@ def load_library():
     L.morea_repair_folds.restype = I32
     L.morea_rasterize_dvf.argtypes = [P, P, P, P, P, P, P]
     L.morea_rasterize_dvf.restype = I32
+    L.morea_rasterize_dvf_static.argtypes = [P, P, P, P, P, P]
+    L.morea_rasterize_dvf_static.restype = I32
     L.morea_point_guidance.argtypes = [P, P, I32, P, P, P]
     L.morea_point_guidance.restype = I32
     L.morea_build_fos.argtypes = [I32, I32, P, I32, P, P, P, P]
@@ -499,6 +502,18 @@ class Problem:
         _check(load_library().morea_rasterize_dvf(self.handle, _dev_ptr(cand), _dev_ptr(out["fwd"]),
                                                   _dev_ptr(out["inv"]), _dev_ptr(out["cover"]),
                                                   _dev_ptr(out["work"]), _stream_ptr(stream)))
+        return out
+
+    def rasterize_dvf_static(self, cand, out, stream=None):
+        """The allocation-free variant (morea_rasterize_dvf_static): `out`
+        holds preallocated fwd, inv, cover tensors as for rasterize_dvf; no
+        workspace is passed and the call allocates nothing."""
+        import torch
+        assert cand.is_cuda and cand.dtype == torch.float32 and cand.is_contiguous()
+        assert tuple(cand.shape) == (2, 3, self.n_points)
+        _check(load_library().morea_rasterize_dvf_static(self.handle, _dev_ptr(cand), _dev_ptr(out["fwd"]),
+                                                         _dev_ptr(out["inv"]), _dev_ptr(out["cover"]),
+                                                         _stream_ptr(stream)))
         return out
 
     def point_guidance(self, pts, stream=None):

@@ -304,6 +304,9 @@ morea_status morea_problem_create(const morea_problem_desc* d, morea_problem** o
     e = hipDeviceSynchronize();
     if (e != hipSuccess) guard(hip_fail(e, "set-up"));
   }
+  // the device address of the allocation-free entry point's scratch, once
+  // per device, with the problem's device current
+  if (st == MOREA_OK) guard(static_scratch_init(dev));
   if (st != MOREA_OK) {
     std::string msg = g_error;
     free_all(p);

@@ -24,6 +24,8 @@
 #include <math.h>
 #include <stdio.h>
 
+#include <mutex>
+
 #include "morea_internal.h"
 
 namespace morea {
@@ -291,22 +293,53 @@ __global__ __launch_bounds__(256) void k_point_guidance(ProblemView P, const flo
 
 using namespace morea;
 
-extern "C" morea_status morea_rasterize_dvf(morea_problem* p, const float* cand, float* fwd, float* inv,
-                                            uint32_t* cover, int32_t* work, void* stream) {
-  if (!p || !cand || !fwd || !inv || !cover || !work) {
-    set_error("NULL argument");
+namespace morea {
+namespace dvf {
+
+// Owner workspace of the allocation-free DVF entry point: one int32 per
+// voxel centre of both grids, 16 MiB, so grids of at most 2,097,152 voxels.
+// Every GPU the library runs on holds its own copy until the process ends;
+// calls on one GPU share it (calls that overlap on one GPU race), and every
+// call clears the part it uses with a kernel first.
+constexpr size_t kScratchInts = static_cast<size_t>(1) << 22;
+static __device__ __align__(256) int32_t scratch[kScratchInts];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+int32_t* g_scratch[kMaxDevices] = {};
+
+}  // namespace dvf
+
+// Device address of the scratch array on the current device (looked up once
+// per device, with that device current).  The array's name is only a
+// host-side stand-in: kernels get this address.
+morea_status static_scratch_init(int device) {
+  if (device < 0 || device >= dvf::kMaxDevices) {
+    set_error("device index beyond the scratch table");
     return MOREA_EINVAL;
   }
-  {
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) {
-      set_error(hipGetErrorString(e));
-      return MOREA_EDEVICE;
-    }
+  std::lock_guard<std::mutex> lock(dvf::g_scratch_mu);
+  if (dvf::g_scratch[device]) return MOREA_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(dvf::scratch));
+  if (e != hipSuccess || !ptr) {
+    char buf[256];
+    snprintf(buf, sizeof(buf), "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    set_error(buf);
+    return MOREA_EDEVICE;
   }
+  dvf::g_scratch[device] = static_cast<int32_t*>(ptr);
+  return MOREA_OK;
+}
+
+}  // namespace morea
+
+namespace {
+
+morea_status launch_dvf(morea_problem* p, const float* cand, float* fwd, float* inv, uint32_t* cover, int32_t* work,
+                        hipStream_t s) {
   const ProblemView& P = p->view;
   const size_t V = static_cast<size_t>(P.nx) * P.ny * P.nz;
-  hipStream_t s = static_cast<hipStream_t>(stream);
   const int items = 2 * P.n_tets;
   hipLaunchKernelGGL(dvf::k_dvf_clear, dim3(static_cast<unsigned>((2 * V + 255) / 256)), dim3(256), 0, s, V, work,
                      cover, fwd, inv);
@@ -320,6 +353,58 @@ extern "C" morea_status morea_rasterize_dvf(morea_problem* p, const float* cand,
     return MOREA_EDEVICE;
   }
   return MOREA_OK;
+}
+
+}  // namespace
+
+extern "C" morea_status morea_rasterize_dvf_static(morea_problem* p, const float* cand, float* fwd, float* inv,
+                                                   uint32_t* cover, void* stream) {
+  if (!p || !cand || !fwd || !inv || !cover) {
+    set_error("NULL argument");
+    return MOREA_EINVAL;
+  }
+  const ProblemView& P = p->view;
+  const size_t V = static_cast<size_t>(P.nx) * P.ny * P.nz;
+  if (2 * V > dvf::kScratchInts) {
+    char buf[160];
+    snprintf(buf, sizeof(buf), "allocation-free DVF: %zu voxels per grid exceed the scratch limit of %zu", V,
+             dvf::kScratchInts / 2);
+    set_error(buf);
+    return MOREA_ERANGE;
+  }
+  {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+      set_error(hipGetErrorString(e));
+      return MOREA_EDEVICE;
+    }
+  }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    set_error("hipGetDevice failed");
+    return MOREA_EDEVICE;
+  }
+  if (dev < 0 || dev >= dvf::kMaxDevices || !dvf::g_scratch[dev]) {
+    // first call on this device (problems created on it normally did this)
+    if (morea_status st = static_scratch_init(dev)) return st;
+  }
+  return launch_dvf(p, cand, fwd, inv, cover, dvf::g_scratch[dev], static_cast<hipStream_t>(stream));
+}
+
+extern "C" morea_status morea_rasterize_dvf(morea_problem* p, const float* cand, float* fwd, float* inv,
+                                            uint32_t* cover, int32_t* work, void* stream) {
+  if (!p || !cand || !fwd || !inv || !cover || !work) {
+    set_error("NULL argument");
+    return MOREA_EINVAL;
+  }
+  {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+      set_error(hipGetErrorString(e));
+      return MOREA_EDEVICE;
+    }
+  }
+  return launch_dvf(p, cand, fwd, inv, cover, work, static_cast<hipStream_t>(stream));
 }
 
 extern "C" morea_status morea_point_guidance(morea_problem* p, const float* pts, int32_t pop, float* f,

@@ -194,6 +194,9 @@ int partial_blocks_per_cu(int storage);
 hipError_t launch_band_cells(const ProblemView& P, const uint8_t* band, uint8_t* cells, hipStream_t s);
 hipError_t launch_fg_cells(const ProblemView& P, int storage, const void* img, uint8_t* cells, hipStream_t s);
 void set_error(const char* msg);   // message returned by morea_last_error() on this thread
+// device address of the allocation-free entry point's static scratch on the
+// current device (looked up once per device)
+morea_status static_scratch_init(int device);
 void ensure_partial_shape(morea_problem* p);   // untuned persistent launch shape, once
 hipError_t launch_partial(const ProblemView& P, int storage, const PartialItems& I, int n_parents,
                           int n_groups, const Record* parent_rec, const Totals* parent_tot,
