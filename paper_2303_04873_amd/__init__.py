@@ -15,7 +15,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libmorea.so")
+# MOREA_LIB names another build of the same library (e.g. one whose host code
+# carries sanitizers); by default the in-tree build is loaded
+LIB_PATH = os.environ.get("MOREA_LIB") or os.path.join(HERE, "libmorea.so")
 
 MOREA_OK, MOREA_EINVAL, MOREA_ENOMEM, MOREA_EDEVICE, MOREA_ERANGE, MOREA_ESTATE = 0, -1, -2, -3, -4, -5
 STORE = {"f32": 0, "bf16": 1, "f16": 2}
