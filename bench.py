@@ -88,25 +88,62 @@ def parse():
     ap.add_argument("--parity-samples", type=int, default=3)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this size first (counter calibration)")
-    ap.add_argument("--forms", default="partial,reduced,surrogate,sobol,repair,dvf,generation",
+    ap.add_argument("--forms", default="partial,reduced,surrogate,sobol,repair,dvf,generation,optimizer",
                     help="comma list of the other forms to measure after the main timing "
-                         "(partial, reduced, surrogate, sobol, repair, dvf, generation) or 'none'")
+                         "(partial, reduced, surrogate, sobol, repair, dvf, generation, optimizer) or 'none'")
+    ap.add_argument("--generations", type=int, default=200, help="generations of the optimizer form")
     return ap.parse_args()
 
 
+class Timing(float):
+    """Median milliseconds of a timed call, with its spread (p10, p90, mean)."""
+
+    def __new__(cls, samples):
+        a = np.asarray(samples, np.float64)
+        t = super().__new__(cls, float(np.median(a)))
+        t.p10, t.p90, t.mean, t.n = (float(np.percentile(a, 10)), float(np.percentile(a, 90)), float(a.mean()),
+                                     len(a))
+        return t
+
+    def spread(self):
+        return {"median": float(self), "p10": self.p10, "p90": self.p90, "mean": self.mean, "reps": self.n}
+
+
 def timed(fn, steps, warmup):
-    """Average milliseconds of fn() on the current stream (HIP events)."""
+    """Milliseconds of fn() on the current stream: HIP events around every
+    repetition, median (p10, p90 and mean kept) over `steps`."""
     import torch
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record()
-    for _ in range(steps):
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a, b in ev:
+        a.record()
         fn()
-    b.record()
+        b.record()
     torch.cuda.synchronize()
-    return a.elapsed_time(b) / steps
+    return Timing([a.elapsed_time(b) for a, b in ev])
+
+
+def resampled(p, rec_n, grp_off, grp_pts, ep, eg, child_counts, parent_counts):
+    """Samples a batch of partial evaluations re-evaluated: per evaluation the
+    child's samples on its group's dependent tets (the tets holding a group
+    point) = child total - parent total + the parent's samples on those tets.
+    rec_n [n_parents][n_tets] parent samples per tet (both directions)."""
+    dep_sum = np.zeros((rec_n.shape[0], len(grp_off) - 1), np.int64)
+    for g in range(len(grp_off) - 1):
+        dep = np.flatnonzero(np.isin(p.tets, grp_pts[grp_off[g]:grp_off[g + 1]]).any(axis=1))
+        dep_sum[:, g] = rec_n[:, dep].sum(axis=1)
+    child = child_counts.astype(np.int64).sum(axis=1)
+    parent = parent_counts.astype(np.int64).sum(axis=1)
+    return int((child - parent[ep] + dep_sum[ep, eg]).sum())
+
+
+def alu(samples, ms):
+    """Achieved definition lane-ops (60 per voxel sample) and their fraction
+    of the VALU peak."""
+    a = samples * SAMPLE_OPS / (ms * 1e-3)
+    return {"samples_per_s": samples / (ms * 1e-3), "achieved_T_lane_ops_per_s": a / 1e12, "frac": a / VALU_PEAK}
 
 
 def form_partial(p, pop_np, prob_full_ms, steps):
@@ -127,9 +164,15 @@ def form_partial(p, pop_np, prob_full_ms, steps):
     prob.eval_full(par, cache=cache)
     dep, deg, dnew = (torch.from_numpy(a).cuda() for a in (ep, eg, new))
     out = prob.outputs(len(ep))
+    par_out = prob.eval_full(par.clone())
     tune_ms, shape = prob.tune_partial(par, cache, dep, deg, dnew, out=out)
+    n_graphs0 = morea.morea_partial_graphs(prob.handle)[1]
     ms = timed(lambda: prob.eval_partial(par, cache, dep, deg, dnew, out=out), steps, 2)
+    captures = morea.morea_partial_graphs(prob.handle)[1] - n_graphs0
     g = {k: v.cpu().numpy() for k, v in out.items()}
+    rec = prob.cache_records(cache, pop_np.shape[0])
+    samples = resampled(p, rec["n"].astype(np.int64).sum(axis=2), off, pts, ep, eg, g["counts"],
+                        par_out["counts"].cpu().numpy())
     idx = [0, 12345, len(ep) - 1]
     kids = np.stack([synth.apply_child(pop_np, off, pts, ep, eg, new, e) for e in idx])
     o = oracle.Problem.from_synth(p).evaluate(kids)
@@ -138,7 +181,9 @@ def form_partial(p, pop_np, prob_full_ms, steps):
     evals_s = len(ep) / (ms * 1e-3)
     return {"workload": f"{pop_np.shape[0]} parents x {len(off) - 1} groups of 4-48 points "
                         f"({len(ep)} partial evaluations) per launch",
-            "ms_per_launch": ms, "partial_evals_per_s": evals_s,
+            "ms_per_launch": ms, "timing_ms": ms.spread(), "partial_evals_per_s": evals_s,
+            "samples_per_launch": samples, "alu": alu(samples, ms),
+            "graph_captures_while_timed": captures,
             "vs_plain_full_evals_per_s": evals_s / (pop_np.shape[0] / (prob_full_ms * 1e-3)),
             "launch_shape": {"blocks": shape[0], "items_per_pop": shape[1], "tuned_ms": tune_ms},
             "parity": {"evals": idx, "counts_flags_exact": exact,
@@ -165,8 +210,8 @@ def form_sobol(p, pop_np, prob_full_ms, steps):
     evals_s = pop_np.shape[0] / (ms * 1e-3)
     return {"workload": f"{pop_np.shape[0]} candidates, {p.n_tets} tets, rate 1 (N = round(volume) "
                         f"points per tet and direction), seed 1",
-            "ms_per_step": ms, "evals_per_s": evals_s, "samples_per_s": samples / (ms * 1e-3),
-            "samples_per_step": int(samples),
+            "ms_per_step": ms, "timing_ms": ms.spread(), "evals_per_s": evals_s,
+            "samples_per_s": samples / (ms * 1e-3), "samples_per_step": int(samples),
             "vs_plain_full_evals_per_s": evals_s / (pop_np.shape[0] / (prob_full_ms * 1e-3)),
             "alu": {"ops_per_sample": SOBOL_SAMPLE_OPS,
                     "achieved_T_lane_ops_per_s": samples * SOBOL_SAMPLE_OPS / (ms * 1e-3) / 1e12,
@@ -202,7 +247,7 @@ def form_repair(p, pop_np, steps):
         prob.repair_folds(work, draws, pinned, info=info)
         b.record()
     torch.cuda.synchronize()
-    ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    ms = Timing([a.elapsed_time(b) for a, b in ev])
     before = prob.eval_full(base)["flags"].cpu().numpy()
     after = prob.eval_full(work)["flags"].cpu().numpy()
     inf = info.cpu().numpy()
@@ -212,7 +257,7 @@ def form_repair(p, pop_np, steps):
     exact = bool(np.array_equal(work.cpu().numpy()[idx].view(np.uint32), o.view(np.uint32)) and
                  np.array_equal(inf[idx, 0], moves) and np.array_equal(inf[idx, 1], outcome))
     return {"workload": f"{pop_np.shape[0]} candidates ({len(folded)} folded), 16 draw blocks of 64 trials",
-            "ms_per_launch": ms, "folded_candidates_per_s": len(folded) / (ms * 1e-3),
+            "ms_per_launch": ms, "timing_ms": ms.spread(), "folded_candidates_per_s": len(folded) / (ms * 1e-3),
             "folded_before": int(len(folded)), "fold_free_after": int((after[folded] == 0).sum()),
             "moves": int(inf[:, 0].sum()),
             "outcomes": {str(k): int((inf[:, 1] == k).sum()) for k in range(5)},
@@ -243,12 +288,12 @@ def form_dvf(p, pop_np, steps):
     fo, uno = oracle.Problem.from_synth(p).point_guidance(pop_np[idx])
     rel = float(np.max(np.abs(fg.cpu().numpy()[idx] - fo) / np.abs(fo)))
     return {"workload": f"candidate 1, {p.n_tets} tets per mesh, two {p.dims[0]}x{p.dims[1]}x{p.dims[2]} fields",
-            "ms_per_candidate": ms, "voxels_per_s": 2 * V / (ms * 1e-3),
+            "ms_per_candidate": ms, "timing_ms": ms.spread(), "voxels_per_s": 2 * V / (ms * 1e-3),
             "parity": {"cover_exact": bool(np.array_equal(out["cover"].cpu().numpy(), cover)),
                        "max_abs_err_voxels": err},
             "point_guidance": {"workload": f"{pop_np.shape[0]} candidates x {sum(len(s) for s in p.sets_src)} "
                                            f"guidance points located among {p.n_tets} tets",
-                               "ms_per_population": ms_pg,
+                               "ms_per_population": ms_pg, "timing_ms": ms_pg.spread(),
                                "unmapped_points": int(un.cpu().numpy().sum()),
                                "parity": {"candidates": idx, "max_rel_err": rel,
                                           "unmapped_exact": bool(np.array_equal(un.cpu().numpy()[idx], uno))}}}
@@ -405,7 +450,7 @@ def form_generation(p, pop_np, prob_full_ms, steps):
                         f"selection of {sel_size} in {k} clusters: {n_evals} sampled children, partial evaluations "
                         f"and acceptances per generation, archive of {archive.shape[0]}",
             "fos_build_ms_host": fos_ms, "launch_shape": {"blocks": shape[0], "items_per_pop": shape[1]},
-            "ms_per_generation": ms, "ms_evaluations_only": ms_eval,
+            "ms_per_generation": ms, "timing_ms": ms.spread(), "ms_evaluations_only": ms_eval,
             "ms_select_estimate_and_sample": ms_mix, "selected_first_generation": int(sc["n_selected"][0]), "ms_acceptance": ms - ms_eval - ms_mix,
             "children_per_s": n_evals / (ms * 1e-3),
             "steering_guidance_max": gmax, "accepted_first_generation": kept, "parents_changed_first_generation": int(len(moved)),
@@ -417,9 +462,71 @@ def form_generation(p, pop_np, prob_full_ms, steps):
                        "parents_match_fresh_full_evaluation": same_as_fresh}}
 
 
+def form_optimizer(p, pop_np, prob_full_ms, generations):
+    """Config 2: the optimizer's loop over many generations (Sec. 3, Sec. 4.3):
+    selection and 10 clusters, distributions, per colour sampled children of
+    every (solution, element), one batched partial evaluation, acceptance
+    against parents and the elitist archive (capacity 2000, App. C), the
+    archive update with the population and the multipliers' improvement
+    marks; the multipliers adapted per generation; folded solutions repaired
+    and re-evaluated; adaptive steering from generation 100 (Sec. 4.3.2).
+    Timed per generation on the host clock around whole generations (each
+    ends with the loop's one small read-back)."""
+    import torch
+
+    import paper_2303_04873_amd as morea
+    from paper_2303_04873_amd.optimizer import Optimizer
+    npop = pop_np.shape[0]
+    prob = morea.Problem.from_synth(p, max_population=npop)
+    fa = p.fixed_axes.astype(np.uint8)
+    pinned = torch.from_numpy((fa[:, 0] | (fa[:, 1] << 1) | (fa[:, 2] << 2)).astype(np.uint8)).cuda()
+    pts = torch.from_numpy(pop_np.copy()).cuda()
+    t0 = time.perf_counter()
+    opt = Optimizer(prob, pts, pinned=pinned, n_clusters=10, selection_fraction=0.35, archive_capacity=2000,
+                    steering_at=100, seed=3)
+    setup_s = time.perf_counter() - t0
+    repaired_start = opt.repaired
+    n_evals = sum(len(b["ep"]) for b in opt.batches)
+    kept = torch.zeros(generations, dtype=torch.int64, device="cuda")
+    ms, trace = [], []
+    for gen in range(generations):
+        t = time.perf_counter()
+        opt.step()
+        ms.append((time.perf_counter() - t) * 1e3)      # the step ends with a synchronising read-back
+        if gen == 0:
+            # launch shape of the persistent partial evaluation, tuned on the
+            # last colour's children of the first generation (copies of the
+            # population and cache: tuning rewrites only outputs)
+            b = opt.batches[-1]
+            opt.prob.tune_partial(opt.pts.clone(), opt.cache.clone(), b["dep"], b["deg"], b["new"],
+                                  out=opt.prob.outputs(len(b["ep"])))
+        kept[gen] = sum(b["acc"].sum(dtype=torch.int64) for b in opt.batches)
+        if gen in (0, 1, 9, 49, 98, 99, 100, 101, 149, generations - 1):
+            st = opt.archive.state.cpu().numpy()
+            trace.append({"generation": gen + 1, "archive_members": int(st[0]), "box_levels": int(st[2]),
+                          "best_guidance": opt.s_g, "steering_bound": opt.bound,
+                          "mult_mean": float(opt.mult.mean().item()),
+                          "population_mean_obj": [float(x) for x in opt.out["obj"].mean(dim=0).cpu().numpy()]})
+    kept = kept.cpu().numpy()
+    tm = Timing(ms)
+    tm_late = Timing(ms[1:])
+    return {"workload": f"{npop} solutions, {len(opt.elements)} FOS elements in {len(opt.batches)} colours, "
+                        f"10 clusters, archive capacity 2000, {generations} generations, steering from "
+                        f"generation 100",
+            "setup_s": setup_s, "repaired_at_start": repaired_start, "repaired_total": opt.repaired,
+            "ms_per_generation": tm, "timing_ms": tm.spread(), "timing_ms_after_first": tm_late.spread(),
+            "generations_per_s": 1e3 / tm, "children_per_s": n_evals / (tm * 1e-3),
+            "vs_plain_full_evals_per_s": n_evals / (tm * 1e-3) / (npop / (prob_full_ms * 1e-3)),
+            "kept_fraction_first_generation": float(kept[0] / n_evals),
+            "kept_fraction_after_first": float(kept[1:].mean() / n_evals) if generations > 1 else None,
+            "kept_fraction_last_10": float(kept[-10:].mean() / n_evals),
+            "trace": trace}
+
+
 def form_reduced(steps):
     """Config 4: 192x192x128 images stored BF16 / FP16 (and FP32 for
-    reference), 9,126 tets, population 256, full evaluation."""
+    reference), 9,126 tets, population 256: full evaluation, and 256 parents x
+    64 groups of 4-48 points of partial evaluations in one launch."""
     import torch
 
     import oracle
@@ -427,25 +534,57 @@ def form_reduced(steps):
     import synth
     p = synth.make_problem(4)
     pop_np = synth.make_population(p)
+    npop = pop_np.shape[0]
     pts = torch.from_numpy(pop_np).cuda()
+    off, gpts = synth.make_groups(p)
+    ep, eg, new = synth.make_children(p, pop_np, off, gpts)
+    dep, deg, dnew = (torch.from_numpy(a).cuda() for a in (ep, eg, new))
     res = {"workload": f"{p.dims[0]}x{p.dims[1]}x{p.dims[2]}, {p.n_tets} tets, population "
-                       f"{pop_np.shape[0]}, full evaluation"}
+                       f"{npop}: full evaluation; {npop} parents x {len(off) - 1} groups of 4-48 points "
+                       f"({len(ep)} partial evaluations) per launch"}
     o32 = oracle.Problem.from_synth(p).evaluate(pop_np[:2])
+    kid_idx = [0, len(ep) // 2, len(ep) - 1]
+    kids = np.stack([synth.apply_child(pop_np, off, gpts, ep, eg, new, e) for e in kid_idx])
+    k32 = oracle.Problem.from_synth(p).evaluate(kids)
+
+    def rel(a, b):
+        return [float(x) for x in (np.abs(a - b) / np.maximum(np.abs(b), 1e-30)).max(axis=0)]
+
     for storage in ("f32", "bf16", "f16"):
-        prob = morea.Problem.from_synth(p, storage=storage, max_population=pop_np.shape[0])
-        out = prob.outputs(pop_np.shape[0])
+        prob = morea.Problem.from_synth(p, storage=storage, max_population=npop)
+        out = prob.outputs(npop)
         ms = timed(lambda: prob.eval_full(pts, out=out), steps, 2)
         g = {k: v.cpu().numpy() for k, v in out.items()}
-        oq = oracle.Problem.from_synth(p, image_src=oracle.quantize(p.image_src, storage),
-                                       image_tgt=oracle.quantize(p.image_tgt, storage)).evaluate(pop_np[:2])
-        rel = np.abs(g["obj"][:2] - oq["obj"]) / np.maximum(np.abs(oq["obj"]), 1e-30)
-        eff = np.abs(g["obj"][:2] - o32["obj"]) / np.maximum(np.abs(o32["obj"]), 1e-30)
-        res[storage] = {"ms_per_step": ms, "evals_per_s": pop_np.shape[0] / (ms * 1e-3),
+        oqp = oracle.Problem.from_synth(p, image_src=oracle.quantize(p.image_src, storage),
+                                        image_tgt=oracle.quantize(p.image_tgt, storage))
+        oq = oqp.evaluate(pop_np[:2])
+        # partial evaluations on the same storage
+        prob.set_groups(off, gpts)
+        prob.reserve_partial(len(ep))
+        cache = prob.new_cache(npop)
+        prob.eval_full(pts, cache=cache)
+        pout = prob.outputs(len(ep))
+        tune_ms, shape = prob.tune_partial(pts, cache, dep, deg, dnew, out=pout)
+        ms_p = timed(lambda: prob.eval_partial(pts, cache, dep, deg, dnew, out=pout), steps, 2)
+        gp = {k: v.cpu().numpy() for k, v in pout.items()}
+        samples_p = resampled(p, prob.cache_records(cache, npop)["n"].astype(np.int64).sum(axis=2), off, gpts,
+                              ep, eg, gp["counts"], g["counts"])
+        kq = oqp.evaluate(kids)
+        res[storage] = {"ms_per_step": ms, "timing_ms": ms.spread(), "evals_per_s": npop / (ms * 1e-3),
                         "samples_per_s": float(g["counts"].astype(np.int64).sum()) / (ms * 1e-3),
-                        "max_rel_err_vs_oracle_same_storage": [float(x) for x in rel.max(axis=0)],
-                        "storage_effect_vs_fp32_oracle": [float(x) for x in eff.max(axis=0)],
+                        "max_rel_err_vs_oracle_same_storage": rel(g["obj"][:2], oq["obj"]),
+                        "storage_effect_vs_fp32_oracle": rel(g["obj"][:2], o32["obj"]),
                         "counts_flags_exact": bool((g["counts"][:2] == oq["counts"]).all()
-                                                   and (g["flags"][:2] == oq["flags"]).all())}
+                                                   and (g["flags"][:2] == oq["flags"]).all()),
+                        "partial": {"ms_per_launch": ms_p, "timing_ms": ms_p.spread(),
+                                    "partial_evals_per_s": len(ep) / (ms_p * 1e-3),
+                                    "samples_per_launch": samples_p, "alu": alu(samples_p, ms_p),
+                                    "launch_shape": {"blocks": shape[0], "items_per_pop": shape[1]},
+                                    "evals_checked": kid_idx,
+                                    "max_rel_err_vs_oracle_same_storage": rel(gp["obj"][kid_idx], kq["obj"]),
+                                    "storage_effect_vs_fp32_oracle": rel(gp["obj"][kid_idx], k32["obj"]),
+                                    "counts_flags_exact": bool((gp["counts"][kid_idx] == kq["counts"]).all()
+                                                               and (gp["flags"][kid_idx] == kq["flags"]).all())}}
         prob.close()
     return res
 
@@ -504,8 +643,9 @@ def form_surrogate(full_evals_per_s, steps):
     per_tet = (sur.predict_rows(X[:200000]).cpu().numpy() - t[:200000].cpu().numpy())
     return {"workload": f"{len(off)} offspring of 512 parents, top 512 evaluated exactly",
             "train_rows": n, "train_seconds": train_s, "final_train_loss": loss.item(),
-            "prescreen_ms": ms_pre, "offspring_screened_per_s": len(off) / (ms_pre * 1e-3),
-            "screen_select_exact512_ms": ms_all,
+            "prescreen_ms": ms_pre, "prescreen_timing_ms": ms_pre.spread(),
+            "offspring_screened_per_s": len(off) / (ms_pre * 1e-3),
+            "screen_select_exact512_ms": ms_all, "screen_select_exact512_timing_ms": ms_all.spread(),
             "offspring_per_s_with_exact_top512": len(off) / (ms_all * 1e-3),
             "vs_plain_full_evals_per_s": len(off) / (ms_all * 1e-3) / full_evals_per_s,
             "mean_exact_f_int": {"surrogate_top512": float(f[idx].mean()),
@@ -561,7 +701,8 @@ def main():
     torch.cuda.synchronize()
     t_end = time.perf_counter()
     ms_per_step = (t_end - t_start) * 1e3 / args.steps
-    launch_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    launch = Timing([a.elapsed_time(b) for a, b in ev])
+    launch_ms = launch.mean
 
     g = {k: v.cpu().numpy() for k, v in out.items()}
     samples = int(g["counts"].astype(np.int64).sum())
@@ -589,10 +730,21 @@ def main():
                 n_done += chunk
                 t_cpu = time.perf_counter() - t1
             cores = oracle.threads()
+            # the same oracle on one core, on a smaller sample
+            oracle.set_threads(1)
+            n1, t1c = 0, 0.0
+            t1 = time.perf_counter()
+            while t1c < args.cpu_seconds / 2 and n1 < pop:
+                op.evaluate(pop_np[n1:n1 + 1])
+                n1 += 1
+                t1c = time.perf_counter() - t1
+            oracle.set_threads(cores)
             cpu = {"value": n_done / t_cpu, "unit": "candidate evals/s", "cores": cores,
                    "kind": "oracle",
                    "sample": f"first {n_done} of {pop} candidates of the same population "
-                             f"(FP64 C oracle, OpenMP), {t_cpu:.1f}s"}
+                             f"(FP64 C oracle, OpenMP), {t_cpu:.1f}s",
+                   "one_core": {"value": n1 / t1c, "cores": 1,
+                                "sample": f"first {n1} candidates, one thread, {t1c:.1f}s"}}
 
     forms = {}
     wanted = [] if args.forms == "none" else args.forms.split(",")
@@ -612,6 +764,8 @@ def main():
             forms["dvf_config2"] = form_dvf(p, pop_np, max(3, args.steps // 4))
         elif name == "generation":
             forms["generation_config2"] = form_generation(p, pop_np, ms_per_step, max(3, args.steps // 4))
+        elif name == "optimizer":
+            forms["optimizer_config2"] = form_optimizer(p, pop_np, ms_per_step, args.generations)
         print(f"# form {name} done in {time.time() - t_form:.1f}s", file=sys.stderr, flush=True)
 
     achieved_ops = samples * SAMPLE_OPS / (launch_ms * 1e-3)
@@ -633,7 +787,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved_ops / 1e12, "peak": VALU_PEAK / 1e12,
                      "unit": "T lane-ops/s", "frac": achieved_ops / VALU_PEAK, "traffic": profiled_traffic(),
                      "kernel": "k_eval_full (event-timed launch incl. k_finalize)",
-                     "launch_ms": launch_ms,
+                     "launch_ms": launch_ms, "launch_ms_spread": launch.spread(),
                      "hbm_algorithmic_frac": samples * SAMPLE_BYTES / (launch_ms * 1e-3) / HBM_PEAK},
         "parity": parity,
         "cpu_baseline": cpu,
