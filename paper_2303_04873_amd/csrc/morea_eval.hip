@@ -167,9 +167,17 @@ __device__ __forceinline__ double det_f64(const int v[4][3]) {
 
 constexpr int kDeferCap = 128;
 
-// LDS scratch of one wave.
-struct WaveLds {
+// Per-item constants in LDS: both directions and the snapped vertices.
+struct ItemLds {
   DirConst c[2];
+  int vert[24];            // snapped S (12), then T (12)
+};
+
+// LDS scratch of one wave: the constants of its two items (the set-up runs
+// for both at once, one per half-wave) and the row and sample tables of the
+// item being evaluated.
+struct WaveLds {
+  ItemLds it[2];
   int4 row[kWave];         // padded element of the first sample, the row's first unit in
                            // the unit stream, jx | jy << 10 | jz << 20 (box-relative), length
   double rowq[kWave][3];   // mapped point of each row's first sample
@@ -180,7 +188,6 @@ struct WaveLds {
   //   near-grid: (position, a, b, 0)
   //   in band:   (position, band bits, 0, 1)
   int4 defer[kDeferCap];
-  int vert[24];            // snapped S (12), then T (12)
 };
 
 // Exact support test of the trilinear stencil (rare path, taken only when
@@ -193,11 +200,11 @@ struct WaveLds {
 // in-grid corner is > 0.
 template <int ST>
 __device__ __forceinline__ bool exact_foreground(const ProblemView& P, const void* img,
-                                                 const WaveLds* L, int d, int jx, int jy, int jz,
+                                                 const ItemLds* I, int d, int jx, int jy, int jz,
                                                  const double q[3], int amb) {
   const int nx = P.nx, ny = P.ny, nz = P.nz;
-  const DirConst& c = L->c[d];
-  const int* oth = L->vert + (d == 0 ? 12 : 0);
+  const DirConst& c = I->c[d];
+  const int* oth = I->vert + (d == 0 ? 12 : 0);
   int64_t s[4];
 #pragma unroll
   for (int i = 0; i < 4; i++) {
@@ -643,15 +650,15 @@ __device__ __forceinline__ void sample_pair_inner(const ProblemView& P, const Sa
 // whose mapped points stay inside the padded volume): the guidance term is
 // added.
 template <int ST>
-__device__ __forceinline__ void flush_deferred(const ProblemView& P, const WaveLds* L, int count,
-                                               float& h_acc, float& g_acc) {
+__device__ __forceinline__ void flush_deferred(const ProblemView& P, const WaveLds* L, const ItemLds* I,
+                                               int count, float& h_acc, float& g_acc) {
   const int lane = lane_id();
   for (int base = 0; base < count; base += kWave) {
     const int e = base + lane;
     if (e >= count) continue;
     const int4 q4 = L->defer[e];
     const int jx = q4.x & 1023, jy = (q4.x >> 10) & 1023, jz = (q4.x >> 20) & 1023, d = (q4.x >> 30) & 1;
-    const DirConst& C = L->c[d];
+    const DirConst& C = I->c[d];
     double q[3];
 #pragma unroll
     for (int k = 0; k < 3; k++)
@@ -676,44 +683,53 @@ __device__ __forceinline__ void flush_deferred(const ProblemView& P, const WaveL
 #pragma unroll
     for (int k = 0; k < 3; k++)
       if (fabs(q[k] - floor(q[k]) - 0.5) >= C.gthr[k]) axes |= 1 << k;
-    const bool fg_b = exact_foreground<ST>(P, d ? P.img[0] : P.img[1], L, d, jx, jy, jz, q, axes);
+    const bool fg_b = exact_foreground<ST>(P, d ? P.img[0] : P.img[1], I, d, jx, jy, jz, q, axes);
     const bool fg_a = a > 0.f;
     const float dd = a - (fg_b ? b : 0.f);
     h_acc += (fg_a && fg_b) ? dd * dd : ((fg_a != fg_b) ? 1.f : 0.f);
   }
 }
 
-// Evaluate one tet of one candidate in both directions.  Lanes 0..11 hold
-// the source tet's coordinates (v0x v0y v0z v1x ...), lanes 12..23 the
-// target tet's (`coord`).  The wave writes out[0] (direction 0) and out[1].
+// Evaluate two items (a tet of a candidate each) in both directions.  The
+// set-up runs for both at once, item s on half-wave s (lanes 32 s .. 32 s +
+// 31); rows and samples then take one item after the other on the whole
+// wave.  Lanes 0..11 of a half hold the source tet's coordinates (v0x v0y
+// v0z v1x ...), lanes 12..23 the target tet's (`coord`).  Item s writes
+// out_s[0] (direction 0) and out_s[1]; item 1 exists only when has1.
 template <int ST>
-__device__ void eval_tet(const ProblemView& P, int tet, float coord, WaveLds* L, Record* out) {
+__device__ void eval_tet(const ProblemView& P, int tet0, int tet1, bool has1, float coord, WaveLds* L,
+                         Record* out0, Record* out1) {
   // the lane index is made opaque so that values derived from it are not
   // hoisted out of the persistent partial-evaluation loop (they would stay
   // live across every item and cost registers, i.e. occupancy)
   int lane = lane_id();
   asm volatile("" : "+v"(lane));
+  const int half = lane >> 5, hl = lane & 31;
+  ItemLds* I = &L->it[half];
+  const int tet = half ? tet1 : tet0;
   // ---- snap and validate (the loading lane snaps its own coordinate)
-  const bool in_range = lane >= 24 || fabsf(coord) < kCoordLimit;
-  const bool all_ok = __ballot(in_range) == ~0ull;
-  const int fix = (lane < 24 && in_range) ? static_cast<int>(rintf(coord * kFixOne)) : 0;
-  if (!all_ok) {
-    if (lane < 2) out[lane] = Record{0.f, 0.f, 0u, 0.f, 0.f, 4u};
-    return;
-  }
-  if (lane < 24) L->vert[lane] = fix;
+  const bool in_range = hl >= 24 || fabsf(coord) < kCoordLimit;
+  const uint64_t ok_mask = __ballot(in_range);
+  const bool ok0 = static_cast<uint32_t>(ok_mask) == 0xffffffffu;
+  const bool ok1 = has1 && static_cast<uint32_t>(ok_mask >> 32) == 0xffffffffu;
+  const int fix = (hl < 24 && in_range) ? static_cast<int>(rintf(coord * kFixOne)) : 0;
+  if (!ok0 && lane < 2) out0[lane] = Record{0.f, 0.f, 0u, 0.f, 0.f, 4u};
+  if (has1 && !ok1 && lane >= 32 && lane < 34) out1[lane - 32] = Record{0.f, 0.f, 0u, 0.f, 0.f, 4u};
+  if (!ok0 && !ok1) return;
+  if (hl < 24) I->vert[hl] = fix;
+  wave_sync();
   int V[2][4][3];
 #pragma unroll
   for (int m = 0; m < 2; m++)
 #pragma unroll
     for (int i = 0; i < 4; i++)
 #pragma unroll
-      for (int k = 0; k < 3; k++) V[m][i][k] = __builtin_amdgcn_readlane(fix, 12 * m + 3 * i + k);
-  wave_sync();
+      for (int k = 0; k < 3; k++) V[m][i][k] = I->vert[12 * m + 3 * i + k];
 
   // ---- per direction: box on its grid, fold check (App. A.4), interior
-  // flag.  The values are wave-uniform; they go to the wave's LDS block so
-  // that only the current direction's copy is live in the sample loop.
+  // flag.  The values are uniform within a half; they go to the item's LDS
+  // block so that only the current direction's copy is live in the sample
+  // loop.
   const int dims[3] = {P.nx, P.ny, P.nz};
   const int ref = P.ref_sign[tet];
   bool any_active = false;
@@ -741,8 +757,8 @@ __device__ void eval_tet(const ProblemView& P, int tet, float coord, WaveLds* L,
     const int64_t absD = D < 0 ? -D : D;
     const bool active = D != 0 && lo[0] <= hi[0] && lo[1] <= hi[1] && lo[2] <= hi[2];
     any_active = any_active || active;
-    if (lane == 0) {
-      DirConst& C = L->c[m];
+    if (hl == 0) {
+      DirConst& C = I->c[m];
       C.absD = absD;
       C.fast = fast ? 1 : 0;
       C.sigma = D > 0 ? 1 : -1;
@@ -755,7 +771,7 @@ __device__ void eval_tet(const ProblemView& P, int tet, float coord, WaveLds* L,
       C.NYb = hi[1] - lo[1] + 1;
       C.R = active ? C.NYb * (hi[2] - lo[2] + 1) : 0;
       C.active = active ? 1 : 0;
-      L->c[1 - m].inner = interior ? 1 : 0;
+      I->c[1 - m].inner = interior ? 1 : 0;
       C.h = 0.f;
       C.g = 0.f;
       C.samples = 0u;
@@ -764,34 +780,37 @@ __device__ void eval_tet(const ProblemView& P, int tet, float coord, WaveLds* L,
       C.bits = viol ? 1u : 0u;
     }
   }
+  // items with samples to visit (a half-wave value made wave-uniform)
+  const uint64_t act_mask = __ballot(any_active && (half ? ok1 : ok0));
+  const bool act0 = (act_mask & 1ull) != 0, act1 = ((act_mask >> 32) & 1ull) != 0;
 
   // ---- deformation magnitude (Sec. 4.1.1), one edge per lane:
   // |e_s| - |e_t| = (|e_s|^2 - |e_t|^2) / (|e_s| + |e_t|) with the squared
   // lengths exact in FP64 (components < 2^22, sums < 2^46).
   {
     float term = 0.f;
-    if (lane < 10) {
+    if (hl < 10) {
       double ls = 0.0, lt = 0.0;
       float scale;
-      if (lane < 6) {
-        const int i = lane < 3 ? 0 : (lane < 5 ? 1 : 2);
-        const int j = lane < 3 ? lane + 1 : (lane < 5 ? lane - 1 : 3);
+      if (hl < 6) {
+        const int i = hl < 3 ? 0 : (hl < 5 ? 1 : 2);
+        const int j = hl < 3 ? hl + 1 : (hl < 5 ? hl - 1 : 3);
 #pragma unroll
         for (int k = 0; k < 3; k++) {
-          const double ds = L->vert[3 * i + k] - L->vert[3 * j + k];
-          const double dt = L->vert[12 + 3 * i + k] - L->vert[12 + 3 * j + k];
+          const double ds = I->vert[3 * i + k] - I->vert[3 * j + k];
+          const double dt = I->vert[12 + 3 * i + k] - I->vert[12 + 3 * j + k];
           ls = fma(ds, ds, ls);
           lt = fma(dt, dt, lt);
         }
         scale = 1.0f / kFixOne;
       } else {
-        const int v = lane - 6;
+        const int v = hl - 6;
 #pragma unroll
         for (int k = 0; k < 3; k++) {
-          const int ss = L->vert[k] + L->vert[3 + k] + L->vert[6 + k] + L->vert[9 + k];
-          const int st = L->vert[12 + k] + L->vert[15 + k] + L->vert[18 + k] + L->vert[21 + k];
-          const double ds = 4 * L->vert[3 * v + k] - ss;
-          const double dt = 4 * L->vert[12 + 3 * v + k] - st;
+          const int ss = I->vert[k] + I->vert[3 + k] + I->vert[6 + k] + I->vert[9 + k];
+          const int st = I->vert[12 + k] + I->vert[15 + k] + I->vert[18 + k] + I->vert[21 + k];
+          const double ds = 4 * I->vert[3 * v + k] - ss;
+          const double dt = 4 * I->vert[12 + 3 * v + k] - st;
           ls = fma(ds, ds, ls);
           lt = fma(dt, dt, lt);
         }
@@ -802,25 +821,32 @@ __device__ void eval_tet(const ProblemView& P, int tet, float coord, WaveLds* L,
       const float dd = den > 0.f ? static_cast<float>(ls - lt) * __builtin_amdgcn_rcpf(den) * scale : 0.f;
       term = dd * dd;
     }
-    const float mag = P.elasticity[tet] * wave_sum(term);
-    if (lane == 0) L->c[0].mag = mag;
+    // the sum within each half-wave (butterfly over lane bits 0..4)
+#pragma unroll
+    for (int d = 16; d >= 1; d >>= 1) term += __shfl_xor(term, d, 64);
+    const float mag = P.elasticity[tet] * term;
+    if (hl == 0) I->c[0].mag = mag;
   }
   wave_sync();
-  if (!any_active) {
-    if (lane < 2) {
-      const DirConst& C = L->c[lane];
-      out[lane] = Record{0.f, 0.f, 0u, C.mag, C.vol, C.bits};
+  if (!act0 && !act1) {
+    if (ok0 && lane < 2) {
+      const DirConst& C = L->it[0].c[lane];
+      out0[lane] = Record{0.f, 0.f, 0u, C.mag, C.vol, C.bits};
+    }
+    if (ok1 && lane >= 32 && lane < 34) {
+      const DirConst& C = L->it[1].c[lane - 32];
+      out1[lane - 32] = Record{0.f, 0.f, 0u, C.mag, C.vol, C.bits};
     }
     return;
   }
 
-  // ---- set-up phase 1, lanes 0..7 (direction d = lane / 4, face i): face
-  // plane (gradient of D * lambda_i oriented inwards, its value at the box
-  // corner, the row-boundary estimate)
-  if (lane < 8) {
-    const int d = lane >> 2, i = lane & 3;
-    DirConst& C = L->c[d];
-    const int* own = L->vert + 12 * d;
+  // ---- set-up phase 1, lanes 0..7 of each half (direction d = hl / 4, face
+  // i): face plane (gradient of D * lambda_i oriented inwards, its value at
+  // the box corner, the row-boundary estimate)
+  if (hl < 8) {
+    const int d = hl >> 2, i = hl & 3;
+    DirConst& C = I->c[d];
+    const int* own = I->vert + 12 * d;
     const int sigma = C.sigma;
     const int b0 = i == 0 ? 1 : 0;                            // base vertex on the face
     const int u0 = i == 0 ? 2 : (i == 1 ? 2 : (i == 2 ? 3 : 1));
@@ -879,13 +905,13 @@ __device__ void eval_tet(const ProblemView& P, int tet, float coord, WaveLds* L,
     }
   }
   wave_sync();
-  // phase 2, lanes 0..17: map entry M[a][c] of direction d = lane / 9:
-  // sum_i b_i[a] adj_i[c] / D with b_i = oth_i - oth_0 and adj_i = sigma n_i
-  // (i = 1..3), the rows of adj(E)
-  if (lane < 18) {
-    const int d = lane / 9, a = (lane % 9) / 3, cc = lane % 3;
-    DirConst& C = L->c[d];
-    const int* oth = L->vert + 12 * (1 - d);
+  // phase 2, lanes 0..17 of each half: map entry M[a][c] of direction
+  // d = hl / 9: sum_i b_i[a] adj_i[c] / D with b_i = oth_i - oth_0 and
+  // adj_i = sigma n_i (i = 1..3), the rows of adj(E)
+  if (hl < 18) {
+    const int d = hl / 9, a = (hl % 9) / 3, cc = hl % 3;
+    DirConst& C = I->c[d];
+    const int* oth = I->vert + 12 * (1 - d);
     const double sigma = C.sigma;
     const double invD = sigma * rcp64(static_cast<double>(C.absD != 0 ? C.absD : 1));
     const double oth0 = oth[a];
@@ -901,13 +927,13 @@ __device__ void eval_tet(const ProblemView& P, int tet, float coord, WaveLds* L,
     C.Mabs[a][cc] = mag * fabs(invD);
   }
   wave_sync();
-  // phase 3, lanes 0..5: q at the box corner (padded coordinates: grid
-  // coordinate + 1) and the FP64 error bound of q
-  if (lane < 6) {
-    const int d = lane / 3, a = lane % 3;
-    DirConst& C = L->c[d];
-    const int* own = L->vert + 12 * d;
-    const int* oth = L->vert + 12 * (1 - d);
+  // phase 3, lanes 0..5 of each half: q at the box corner (padded
+  // coordinates: grid coordinate + 1) and the FP64 error bound of q
+  if (hl < 6) {
+    const int d = hl / 3, a = hl % 3;
+    DirConst& C = I->c[d];
+    const int* own = I->vert + 12 * d;
+    const int* oth = I->vert + 12 * (1 - d);
     double q = oth[a] * (1.0 / 1024.0) + 1.0;
     double bound = fabs(q) + 1.0;
 #pragma unroll
@@ -933,9 +959,12 @@ __device__ void eval_tet(const ProblemView& P, int tet, float coord, WaveLds* L,
   // chunk of rows to the next, so only the direction's last batch runs
   // part-empty.
   L->mark[lane] = 0;
-  int tag = 0;          // batch tags: unique within the item
+  int tag = 0;          // batch tags: unique within the wave's call
+  for (int s = 0; s < 2; s++) {
+  if (!(s ? act1 : act0)) continue;
+  ItemLds* IT = &L->it[s];
   for (int d = 0; d < 2; d++) {
-    const DirConst& Cd = L->c[d];
+    const DirConst& Cd = IT->c[d];
     if (!uniform_i(Cd.active)) continue;
     const int nyb = uniform_i(Cd.NYb), Wd = uniform_i(Cd.W);
     const int lox = uniform_i(Cd.lo[0]), loy = uniform_i(Cd.lo[1]), loz = uniform_i(Cd.lo[2]);
@@ -972,7 +1001,7 @@ __device__ void eval_tet(const ProblemView& P, int tet, float coord, WaveLds* L,
       if (amb_mask) {
         if (n_defer + __popcll(amb_mask) > kDeferCap) {
           wave_sync();
-          flush_deferred<ST>(P, L, n_defer, h, g);
+          flush_deferred<ST>(P, L, IT, n_defer, h, g);
           n_defer = 0;
           wave_sync();
         }
@@ -1022,7 +1051,7 @@ __device__ void eval_tet(const ProblemView& P, int tet, float coord, WaveLds* L,
               const int nn = __popcll(m_near), nb = __popcll(m_band);
               if (n_defer + nn + nb > kDeferCap) {
                 wave_sync();
-                flush_deferred<ST>(P, L, n_defer, h, g);
+                flush_deferred<ST>(P, L, IT, n_defer, h, g);
                 n_defer = 0;
                 wave_sync();
               }
@@ -1057,7 +1086,7 @@ __device__ void eval_tet(const ProblemView& P, int tet, float coord, WaveLds* L,
     // rows: slices in groups of 64 (one per lane), the rows of the non-empty
     // slices of a group enumerated 64 at a time
     const int nzb = uniform_i(Cd.hi[2]) - loz + 1;
-    const int* own_v = L->vert + 12 * d;
+    const int* own_v = IT->vert + 12 * d;
     for (int zb = 0; zb < nzb; zb += kWave) {
       int y0 = 0, cnt = 0;
       if (zb + lane < nzb) slice_rows(own_v, loz + zb + lane, loy, loy + nyb - 1, y0, cnt);
@@ -1125,21 +1154,26 @@ __device__ void eval_tet(const ProblemView& P, int tet, float coord, WaveLds* L,
     if (tab_end > cons) run_batches(tab_end);
     if (n_defer > 0) {
       wave_sync();
-      flush_deferred<ST>(P, L, n_defer, h, g);
+      flush_deferred<ST>(P, L, IT, n_defer, h, g);
     }
     h = wave_sum(h);
     g = wave_sum(g);
     n = wave_sum_i(n);
     if (lane == 0) {
-      L->c[d].h = h;
-      L->c[d].g = g;
-      L->c[d].samples = static_cast<uint32_t>(n);
+      IT->c[d].h = h;
+      IT->c[d].g = g;
+      IT->c[d].samples = static_cast<uint32_t>(n);
     }
   }
+  }
   wave_sync();
-  if (lane < 2) {
-    const DirConst& C = L->c[lane];
-    out[lane] = Record{C.h, C.g, C.samples, C.mag, C.vol, C.bits};
+  if (ok0 && lane < 2) {
+    const DirConst& C = L->it[0].c[lane];
+    out0[lane] = Record{C.h, C.g, C.samples, C.mag, C.vol, C.bits};
+  }
+  if (ok1 && lane >= 32 && lane < 34) {
+    const DirConst& C = L->it[1].c[lane - 32];
+    out1[lane - 32] = Record{C.h, C.g, C.samples, C.mag, C.vol, C.bits};
   }
 }
 
@@ -1154,18 +1188,13 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 
 // ------------------------------------------------------------------ kernels
 
-// Full evaluation: one wave per (candidate, tet), item = tet * pop + candidate,
-// so the 4 waves of a block are 4 candidates of one tet.
-template <int ST>
-__global__ __launch_bounds__(256, 4) void k_eval_full(ProblemView P, FullItems F, Record* rec,
-                                                    int n_items) {
-  __shared__ WaveLds lds[4];
-  const int wave = uniform_i(static_cast<int>(threadIdx.x >> 6));
-  const int item = xcd_block(blockIdx.x, gridDim.x) * 4 + wave;
-  if (item >= n_items) return;
+// Full evaluation: one wave per two (candidate, tet) items, item = tet * pop
+// + candidate, so the 4 waves of a block take 8 consecutive candidates of one
+// tet (fewer at a tet boundary).
+__device__ __forceinline__ void split_item(const FullItems& F, int item, int& tet, int& cand) {
   // item = tet * pop + cand, split with the reciprocal (wave-uniform values)
-  int tet = static_cast<int>(static_cast<double>(item) * F.inv_pop);
-  int cand = item - tet * F.pop;
+  tet = static_cast<int>(static_cast<double>(item) * F.inv_pop);
+  cand = item - tet * F.pop;
   if (cand < 0) {
     tet -= 1;
     cand += F.pop;
@@ -1175,16 +1204,32 @@ __global__ __launch_bounds__(256, 4) void k_eval_full(ProblemView P, FullItems F
   }
   tet = uniform_i(tet);
   cand = uniform_i(cand);
+}
+
+template <int ST>
+__global__ __launch_bounds__(256, 4) void k_eval_full(ProblemView P, FullItems F, Record* rec,
+                                                    int n_items) {
+  __shared__ WaveLds lds[4];
+  const int wave = uniform_i(static_cast<int>(threadIdx.x >> 6));
+  const int item0 = 2 * (xcd_block(blockIdx.x, gridDim.x) * 4 + wave);
+  if (item0 >= n_items) return;
+  const bool has1 = item0 + 1 < n_items;
+  int tet0, cand0, tet1 = 0, cand1 = 0;
+  split_item(F, item0, tet0, cand0);
+  if (has1) split_item(F, item0 + 1, tet1, cand1);
   const int lane = lane_id();
+  const int half = lane >> 5, hl = lane & 31;
   float coord = 0.f;
-  if (lane < 24) {
+  if (hl < 24 && (half == 0 || has1)) {
+    const int tet = half ? tet1 : tet0, cand = half ? cand1 : cand0;
     const int4 tv = P.tets[tet];
-    const int i = (lane % 12) / 3, k = lane % 3;
+    const int i = (hl % 12) / 3, k = hl % 3;
     const int v = i == 0 ? tv.x : (i == 1 ? tv.y : (i == 2 ? tv.z : tv.w));
-    const int mesh = lane < 12 ? 0 : 1;
+    const int mesh = hl < 12 ? 0 : 1;
     coord = F.pts[((static_cast<size_t>(cand) * 2 + mesh) * 3 + k) * P.n_points + v];
   }
-  eval_tet<ST>(P, tet, coord, &lds[wave], &rec[(static_cast<size_t>(cand) * P.n_tets + tet) * 2]);
+  eval_tet<ST>(P, tet0, tet1, has1, coord, &lds[wave], &rec[(static_cast<size_t>(cand0) * P.n_tets + tet0) * 2],
+               &rec[(static_cast<size_t>(cand1) * P.n_tets + tet1) * 2]);
 }
 
 template __global__ void k_eval_full<kF32>(ProblemView, FullItems, Record*, int);
@@ -1322,7 +1367,7 @@ hipError_t launch_eval_full(const ProblemView& P, int storage, const float* pts,
                             Record* rec, hipStream_t s) {
   const size_t n_items = static_cast<size_t>(pop) * P.n_tets;
   if (n_items == 0) return hipSuccess;
-  const int blocks = static_cast<int>((n_items + 3) / 4);
+  const int blocks = static_cast<int>((n_items + 7) / 8);
   FullItems F{pts, pop, 1.0 / pop};
   switch (storage) {
     case kF32:
@@ -1507,13 +1552,18 @@ __global__ __launch_bounds__(256, 4) void k_eval_partial(ProblemView P, PartialI
     base = __shfl(base, 0, 64);
     if (base >= total) break;
     const int end = min(total, base + chunk);
-    for (int idx = base; idx < end; idx++) {
-      const int4 it = I.item_info[idx];
-      const int slot = uniform_i(it.x), tet = uniform_i(it.y), par = uniform_i(it.z), row = uniform_i(it.w);
+    for (int idx = base; idx < end; idx += 2) {
+      const bool has1 = idx + 1 < end;
+      const int4 it0 = I.item_info[idx];
+      const int4 it1 = has1 ? I.item_info[idx + 1] : it0;
+      const int tet0 = uniform_i(it0.y), tet1 = uniform_i(it1.y);
+      const int half = lane >> 5, hl = lane & 31;
+      const int4 it = half ? it1 : it0;
       float coord = 0.f;
-      if (lane < 24) {
-        const int i = (lane % 12) / 3, k = lane % 3;
-        const int mesh = lane < 12 ? 0 : 1;
+      if (hl < 24 && (half == 0 || has1)) {
+        const int slot = it.x, tet = it.y, par = it.z, row = it.w;
+        const int i = (hl % 12) / 3, k = hl % 3;
+        const int mesh = hl < 12 ? 0 : 1;
         const int loc = I.dep_local[4 * slot + i];
         if (loc >= 0) {
           coord = I.new_coords[((static_cast<size_t>(row) + loc) * 2 + mesh) * 3 + k];
@@ -1523,8 +1573,10 @@ __global__ __launch_bounds__(256, 4) void k_eval_partial(ProblemView P, PartialI
           coord = I.parent_pts[((static_cast<size_t>(par) * 2 + mesh) * 3 + k) * P.n_points + v];
         }
       }
-      const int dest = uniform_i(I.item_dest[idx]);
-      eval_tet<ST>(P, tet, coord, &lds[wave], &out[static_cast<size_t>(dest) * 2]);
+      const int dest0 = uniform_i(I.item_dest[idx]);
+      const int dest1 = has1 ? uniform_i(I.item_dest[idx + 1]) : dest0;
+      eval_tet<ST>(P, tet0, tet1, has1, coord, &lds[wave], &out[static_cast<size_t>(dest0) * 2],
+                   &out[static_cast<size_t>(dest1) * 2]);
     }
   }
 }
