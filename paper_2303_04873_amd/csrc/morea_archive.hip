@@ -32,8 +32,11 @@
 //     under 25 is reset to 1.
 //
 // The update is one block of 1,024 threads holding up to 4,096 candidates
-// in LDS; domination and duplicates are O(n^2) comparisons against LDS
-// (broadcast reads), the thinning's box counts the same per resolution.
+// in LDS: the members ordered by a bitonic sort of their stamps, domination
+// and duplicates by comparisons against LDS (broadcast reads; members only
+// against the offers, since they are mutually non-dominated and distinct),
+// and each resolution of the thinning's search by a bitonic sort of the
+// stayers' (box key, candidate) pairs.
 #include <math.h>
 #include <stdio.h>
 
@@ -55,12 +58,39 @@ __device__ __forceinline__ bool pareto(float a0, float a1, float a2, float b0, f
 struct Shared {
   float o[3][kMax];      // candidate objective vectors, in candidate order
   int src[kMax];         // slot of a member, -1 - index of an offer
-  uint32_t key[kMax];    // stamps, then box keys, then slot occupancy
-  int freelist[kMax];    // free slots in ascending order
+  // sort keys: (stamp, slot) of the members, then (box key, candidate) of
+  // the stayers; afterwards the occupancy of the slots (low words)
+  uint64_t sortbuf[kMax];
+  int flag[kMax];        // first candidate of its box; then the free slots in ascending order
   int wsum[kThreads / 64];
   float wmin[kThreads / 64];
   float wmax[kThreads / 64];
 };
+
+// Ascending bitonic sort of a[0 .. n2) (n2 a power of two, at most kMax) by
+// the whole block; ends with a barrier.
+__device__ void bitonic_sort(uint64_t* a, int n2) {
+  for (int k = 2; k <= n2; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < n2; i += kThreads) {
+        const int l = i ^ j;
+        if (l > i) {
+          const uint64_t x = a[i], y = a[l];
+          if ((x > y) == ((i & k) == 0)) {
+            a[i] = y;
+            a[l] = x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+}
+
+__device__ __forceinline__ int pow2_at_least(int n) {
+  int p = 1;
+  while (p < n) p <<= 1;
+  return p;
+}
 
 // Exclusive prefix over the block of one value per thread; *total gets the sum.
 __device__ int block_excl(Shared& S, int v, int* total) {
@@ -123,29 +153,23 @@ __global__ __launch_bounds__(kThreads) void k_update(int n_off, const float* __r
                                                      uint8_t* __restrict__ inserted, int* __restrict__ slot_of) {
   __shared__ Shared S;
   const int t = threadIdx.x;
-  // ---- members in stamp order
-  int stamp[kPer];
+  // ---- members in stamp order: sort (stamp, slot) of the occupied slots
+  const int ncap = pow2_at_least(cap);
   int n_occ_mine = 0;
-#pragma unroll
-  for (int j = 0; j < kPer; j++) {
-    const int s = t + j * kThreads;
-    stamp[j] = s < cap ? arc_stamp[s] : -1;
-    if (s < cap) S.key[s] = stamp[j] >= 0 ? static_cast<uint32_t>(stamp[j]) : kNoKey;
-    n_occ_mine += stamp[j] >= 0 ? 1 : 0;
+  for (int s = t; s < ncap; s += kThreads) {
+    const int st = s < cap ? arc_stamp[s] : -1;
+    S.sortbuf[s] = st >= 0 ? (static_cast<uint64_t>(st) << 32 | static_cast<uint32_t>(s)) : ~0ull;
+    n_occ_mine += st >= 0 ? 1 : 0;
   }
   int nm;
-  block_excl(S, n_occ_mine, &nm);     // includes a barrier: the stamps are in LDS
-#pragma unroll
-  for (int j = 0; j < kPer; j++) {
-    const int s = t + j * kThreads;
-    if (s >= cap || stamp[j] < 0) continue;
-    const uint32_t me = static_cast<uint32_t>(stamp[j]);
-    int rank = 0;
-    for (int q = 0; q < cap; q++) rank += S.key[q] < me ? 1 : 0;
-    S.o[0][rank] = arc_obj[3 * s];
-    S.o[1][rank] = arc_obj[3 * s + 1];
-    S.o[2][rank] = arc_obj[3 * s + 2];
-    S.src[rank] = s;
+  block_excl(S, n_occ_mine, &nm);     // its barriers publish the keys
+  bitonic_sort(S.sortbuf, ncap);
+  for (int r = t; r < nm; r += kThreads) {
+    const int s = static_cast<int>(S.sortbuf[r] & 0xffffffffu);
+    S.o[0][r] = arc_obj[3 * s];
+    S.o[1][r] = arc_obj[3 * s + 1];
+    S.o[2][r] = arc_obj[3 * s + 2];
+    S.src[r] = s;
   }
   // ---- feasible offers after them, in index order
   bool feas = false;
@@ -167,7 +191,10 @@ __global__ __launch_bounds__(kThreads) void k_update(int n_off, const float* __r
   }
   const int N = nm + n_feas;
   __syncthreads();
-  // ---- stayers: inside the steering window, not dominated, first of equals
+  // ---- stayers: inside the steering window, not dominated, first of equals.
+  // The members are mutually non-dominated and distinct (every update leaves
+  // them so), so a member can only be dominated by an offer and is never the
+  // later of two equal vectors; an offer is tested against every candidate.
   bool stay[kPer];
   int n_stay_mine = 0;
 #pragma unroll
@@ -176,7 +203,7 @@ __global__ __launch_bounds__(kThreads) void k_update(int n_off, const float* __r
     bool ok = x < N && !(S.o[2][x] > gmax);
     if (ok) {
       const float a0 = S.o[0][x], a1 = S.o[1][x], a2 = S.o[2][x];
-      for (int y = 0; y < N; y++) {
+      for (int y = x < nm ? nm : 0; y < N; y++) {
         const float b0 = S.o[0][y], b1 = S.o[1][y], b2 = S.o[2][y];
         if (y == x || b2 > gmax) continue;
         if (pareto(b0, b1, b2, a0, a1, a2) || (y < x && b0 == a0 && b1 == a1 && b2 == a2)) {
@@ -190,7 +217,9 @@ __global__ __launch_bounds__(kThreads) void k_update(int n_off, const float* __r
   }
   int n_stay;
   block_excl(S, n_stay_mine, &n_stay);
-  // ---- thinning by boxes above capacity
+  // ---- thinning by boxes above capacity: per resolution, the stayers'
+  // (box key, candidate) sorted; the first entry of each key is its box's
+  // earliest candidate
   int levels = 0;
   if (n_stay > cap) {
     double lo[3], hi[3];
@@ -207,36 +236,30 @@ __global__ __launch_bounds__(kThreads) void k_update(int n_off, const float* __r
       lo[o] = block_min(S, mn);
       hi[o] = block_max(S, mx);
     }
-    bool first[kPer];
+    const int n2 = pow2_at_least(N);
     int a = 1, b = cap < kMaxLevels ? cap : kMaxLevels;
-    // the last pass (a == b) recomputes the keys at the chosen resolution
+    // the last pass (a == b) sorts at the chosen resolution
     for (;;) {
       const int L = a < b ? (a + b + 1) / 2 : a;
+      for (int x = t; x < n2; x += kThreads) S.sortbuf[x] = ~0ull;
+      __syncthreads();
 #pragma unroll
       for (int j = 0; j < kPer; j++) {
         const int x = t + j * kThreads;
-        if (x >= N) continue;
-        S.key[x] = stay[j] ? static_cast<uint32_t>(box_of(S.o[0][x], lo[0], hi[0], L)) |
-                                 static_cast<uint32_t>(box_of(S.o[1][x], lo[1], hi[1], L)) << 10 |
-                                 static_cast<uint32_t>(box_of(S.o[2][x], lo[2], hi[2], L)) << 20
-                           : kNoKey;
+        if (x < N && stay[j]) {
+          const uint32_t key = static_cast<uint32_t>(box_of(S.o[0][x], lo[0], hi[0], L)) |
+                               static_cast<uint32_t>(box_of(S.o[1][x], lo[1], hi[1], L)) << 10 |
+                               static_cast<uint32_t>(box_of(S.o[2][x], lo[2], hi[2], L)) << 20;
+          S.sortbuf[x] = static_cast<uint64_t>(key) << 32 | static_cast<uint32_t>(x);
+        }
       }
       __syncthreads();
+      bitonic_sort(S.sortbuf, n2);
       int n_first_mine = 0;
-#pragma unroll
-      for (int j = 0; j < kPer; j++) {
-        const int x = t + j * kThreads;
-        bool f = stay[j];
-        if (f) {
-          const uint32_t k = S.key[x];
-          for (int y = 0; y < x; y++)
-            if (S.key[y] == k) {
-              f = false;
-              break;
-            }
-        }
-        first[j] = f;
-        n_first_mine += f ? 1 : 0;
+      for (int i = t; i < n2; i += kThreads) {
+        const uint64_t v = S.sortbuf[i];
+        const bool first = v != ~0ull && (i == 0 || (S.sortbuf[i - 1] >> 32) != (v >> 32));
+        n_first_mine += first ? 1 : 0;
       }
       int cnt;
       block_excl(S, n_first_mine, &cnt);    // its barriers also end the key reads
@@ -245,20 +268,27 @@ __global__ __launch_bounds__(kThreads) void k_update(int n_off, const float* __r
       else b = L - 1;
     }
     levels = a;
+    // keep the first candidate of each box
+    for (int x = t; x < N; x += kThreads) S.flag[x] = 0;
+    __syncthreads();
+    for (int i = t; i < n2; i += kThreads) {
+      const uint64_t v = S.sortbuf[i];
+      if (v != ~0ull && (i == 0 || (S.sortbuf[i - 1] >> 32) != (v >> 32)))
+        S.flag[static_cast<uint32_t>(v)] = 1;
+    }
+    __syncthreads();
     n_stay_mine = 0;
 #pragma unroll
     for (int j = 0; j < kPer; j++) {
-      stay[j] = first[j];
+      const int x = t + j * kThreads;
+      stay[j] = stay[j] && S.flag[x] != 0;
       n_stay_mine += stay[j] ? 1 : 0;
     }
     block_excl(S, n_stay_mine, &n_stay);
   }
-  // ---- slots: occupancy after the update
-#pragma unroll
-  for (int j = 0; j < kPer; j++) {
-    const int s = t + j * kThreads;
-    if (s < cap) S.key[s] = 0u;
-  }
+  // ---- slots: occupancy after the update (low words of sortbuf)
+  uint32_t* occ = reinterpret_cast<uint32_t*>(S.sortbuf);
+  for (int s = t; s < cap; s += kThreads) occ[s] = 0u;
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < kPer; j++) {
@@ -267,7 +297,7 @@ __global__ __launch_bounds__(kThreads) void k_update(int n_off, const float* __r
     const int src = S.src[x];
     if (src >= 0) {
       if (stay[j]) {
-        S.key[src] = 1u;
+        occ[src] = 1u;
       } else {
         arc_stamp[src] = -1;
         arc_obj[3 * src] = INFINITY;
@@ -283,14 +313,14 @@ __global__ __launch_bounds__(kThreads) void k_update(int n_off, const float* __r
 #pragma unroll
     for (int j = 0; j < kPer; j++) {
       const int s = kPer * t + j;
-      fr[j] = (s < cap && S.key[s] == 0u) ? 1 : 0;
+      fr[j] = (s < cap && occ[s] == 0u) ? 1 : 0;
       nf += fr[j];
     }
     int total;
     int pos = block_excl(S, nf, &total);
 #pragma unroll
     for (int j = 0; j < kPer; j++)
-      if (fr[j]) S.freelist[pos++] = kPer * t + j;
+      if (fr[j]) S.flag[pos++] = kPer * t + j;
   }
   // staying offers take the free slots in candidate order (x = t + j * 1024,
   // so one pass per j, each ranked by a block prefix)
@@ -308,7 +338,7 @@ __global__ __launch_bounds__(kThreads) void k_update(int n_off, const float* __r
     int cnt;
     const int r = base + block_excl(S, nw ? 1 : 0, &cnt);
     if (nw) {
-      const int s = S.freelist[r];
+      const int s = S.flag[r];
       const int i = -1 - S.src[x];
       arc_obj[3 * s] = S.o[0][x];
       arc_obj[3 * s + 1] = S.o[1][x];
