@@ -951,6 +951,40 @@ __device__ void eval_tet(const ProblemView& P, int tet0, int tet1, bool has1, fl
   }
   wave_sync();
 
+  // ---- the slices of all four (item, direction) units at once when each
+  // has at most 16: unit u = 2 s + d on lanes 16 u .. 16 u + 15, one slice z
+  // per lane; unit u's non-empty slices go to slice[16 u ..] in ascending z
+  // (with their first row index, an exclusive scan within the 16 lanes).
+  // Otherwise every unit takes its slices in groups of 64 as it goes.
+  int pre_rows[4] = {0, 0, 0, 0}, pre_ns[4] = {0, 0, 0, 0};
+  bool pre = false;
+  {
+    const int u = lane >> 4, zl = lane & 15;
+    const ItemLds* IU = &L->it[u >> 1];
+    const DirConst& CU = IU->c[u & 1];
+    const bool uact = ((u >> 1) ? act1 : act0) && CU.active != 0;
+    const int unzb = CU.hi[2] - CU.lo[2] + 1;
+    pre = __ballot(uact && unzb > 16) == 0ull;
+    if (pre) {
+      int y0 = 0, cnt = 0;
+      if (uact && zl < unzb) slice_rows(IU->vert + 12 * (u & 1), CU.lo[2] + zl, CU.lo[1], CU.lo[1] + CU.NYb - 1, y0, cnt);
+      const uint64_t ne = __ballot(cnt > 0);
+      const uint64_t seg = 0xffffull << (16 * u);
+      int x = cnt;   // inclusive scan within each row of 16 lanes
+      x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);   // row_shr:1
+      x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);   // row_shr:2
+      x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);   // row_shr:4
+      x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);   // row_shr:8
+      if (cnt > 0) L->slice[16 * u + bits_below(ne & seg)] = make_int4(zl, y0, x - cnt, cnt);
+#pragma unroll
+      for (int v = 0; v < 4; v++) {
+        pre_rows[v] = __builtin_amdgcn_readlane(x, 16 * v + 15);
+        pre_ns[v] = __popcll(ne & (0xffffull << (16 * v)));
+      }
+    }
+  }
+  wave_sync();
+
   // ---- rows and samples, one direction at a time (wave-uniform d).  Rows
   // are solved 64 at a time; non-empty rows enter a table of up to 64 rows.
   // Each row is cut into units of two consecutive samples (the last unit of
@@ -1087,16 +1121,24 @@ __device__ void eval_tet(const ProblemView& P, int tet0, int tet1, bool has1, fl
     // slices of a group enumerated 64 at a time
     const int nzb = uniform_i(Cd.hi[2]) - loz + 1;
     const int* own_v = IT->vert + 12 * d;
-    for (int zb = 0; zb < nzb; zb += kWave) {
-      int y0 = 0, cnt = 0;
-      if (zb + lane < nzb) slice_rows(own_v, loz + zb + lane, loy, loy + nyb - 1, y0, cnt);
-      const uint64_t ne = __ballot(cnt > 0);
-      const int ns = __popcll(ne);
-      const int sexcl = wave_excl_scan(cnt);
-      const int Rg = __builtin_amdgcn_readlane(sexcl + cnt, 63);
-      if (cnt > 0) L->slice[bits_below(ne)] = make_int4(zb + lane, y0, sexcl, cnt);
-      wave_sync();
-      const int my_soff = lane < ns ? L->slice[lane].z : 0x7fffffff;
+    const int unit = 2 * s + d;
+    const int sbase = pre ? 16 * unit : 0;
+    for (int zb = 0; zb < (pre ? 1 : nzb); zb += kWave) {
+      int ns, Rg;
+      if (pre) {
+        ns = pre_ns[unit];
+        Rg = pre_rows[unit];
+      } else {
+        int y0 = 0, cnt = 0;
+        if (zb + lane < nzb) slice_rows(own_v, loz + zb + lane, loy, loy + nyb - 1, y0, cnt);
+        const uint64_t ne = __ballot(cnt > 0);
+        ns = __popcll(ne);
+        const int sexcl = wave_excl_scan(cnt);
+        Rg = __builtin_amdgcn_readlane(sexcl + cnt, 63);
+        if (cnt > 0) L->slice[bits_below(ne)] = make_int4(zb + lane, y0, sexcl, cnt);
+        wave_sync();
+      }
+      const int my_soff = lane < ns ? L->slice[sbase + lane].z : 0x7fffffff;
       for (int rb = 0; rb < Rg; rb += kWave) {
         const int rr = rb + lane;
         // slice of each lane's row: the mark trick over the slices' first rows
@@ -1109,7 +1151,7 @@ __device__ void eval_tet(const ProblemView& P, int tet0, int tet1, bool has1, fl
         const int si = sfirst + bits_below(sst) + static_cast<int>((sst >> lane) & 1ull);
         int js = 1, je = 0, yr = 0, zr = 0;
         if (rr < Rg) {
-          const int4 sl = L->slice[si];
+          const int4 sl = L->slice[sbase + si];
           zr = sl.x;
           yr = sl.y + (rr - sl.z);
           if (fast)
