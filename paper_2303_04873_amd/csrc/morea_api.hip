@@ -197,7 +197,6 @@ morea_status morea_problem_create(const morea_problem_desc* d, morea_problem** o
   // inputs >= 2^-39 stay >= 2^-40 after BF16 rounding; FP16 keeps positive
   // values >= 2^-24 or rounds them to 0
   P.fg_from_b = min_pos >= 0x1p-39f ? 1 : 0;
-  memcpy(P.set_w, set_w, sizeof(set_w));
 
   morea_status st = MOREA_OK;
   auto guard = [&](morea_status s) {
@@ -223,6 +222,9 @@ morea_status morea_problem_create(const morea_problem_desc* d, morea_problem** o
     }
     P.img[m] = dst;
   }
+  float* sw = nullptr;
+  if (st == MOREA_OK) guard(upload(p, &sw, set_w, sizeof(set_w)));
+  P.set_w = sw;
   int4* tets = nullptr;
   int8_t* rs = nullptr;
   float* el = nullptr;

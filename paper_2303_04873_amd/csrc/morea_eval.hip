@@ -23,6 +23,8 @@
 // lane).  Samples whose mapped point lies within its error bound of a grid
 // plane, and samples inside a guidance band, are queued and resolved a full
 // wave at a time.
+#include <type_traits>
+
 #include "morea_internal.h"
 
 namespace morea {
@@ -188,6 +190,7 @@ struct WaveLds {
   //   near-grid: (position, a, b, 0)
   //   in band:   (position, band bits, 0, 1)
   int4 defer[kDeferCap];
+  int pre_rows[4], pre_ns[4];   // per (item, direction) unit: rows and non-empty slices of its table
 };
 
 // Exact support test of the trilinear stencil (rare path, taken only when
@@ -426,7 +429,6 @@ __device__ __forceinline__ float uniform_f(float v) {
 struct SampleConst {
   double m0, m1, m2;    // M[:, 0]: step of the mapped point per voxel along x
   float thr;            // near-grid threshold on max_a |frac(q_a) - 1/2|
-  int sy, sz;           // padded strides in bytes of the sampled image: row, slice
 };
 
 // One voxel sample of direction d whose mapped points may leave the padded
@@ -511,7 +513,7 @@ __device__ __forceinline__ bool sample_one(const ProblemView& P, const SampleCon
         const float u0 = fmaf(f[1], u01 - u00, u00), u1 = fmaf(f[1], u11 - u10, u10);
         const float d2 = fmaf(f[2], u1 - u0, u0);
         const float diff = dist - d2;
-        g_acc += P.set_w[d][sidx] * ((r - dist) * inv_r) * diff * diff;
+        g_acc += P.set_w[d * kMaxSets + sidx] * ((r - dist) * inv_r) * diff * diff;
       }
     }
   }
@@ -549,7 +551,7 @@ __device__ __forceinline__ void guidance(const ProblemView& P, int d, unsigned b
     const float u0 = fmaf(f[1], u01 - u00, u00), u1 = fmaf(f[1], u11 - u10, u10);
     const float d2 = fmaf(f[2], u1 - u0, u0);
     const float diff = dist - d2;
-    g_acc += P.set_w[d][sidx] * ((r - dist) * inv_r) * diff * diff;
+    g_acc += P.set_w[d * kMaxSets + sidx] * ((r - dist) * inv_r) * diff * diff;
   }
 }
 
@@ -587,14 +589,16 @@ __device__ __forceinline__ void sample_pair_inner(const ProblemView& P, const Sa
   // loads: own voxels (one pair), the 2 x 4 corner pairs, the two band bytes
   float v[2][8];
   bool fg8[2];
+  constexpr int esize = ST == kF32 ? 4 : 2;
+  const int sy = P.px * esize, sz = P.pxy * esize;   // row and slice offsets in bytes
   if constexpr (ST == kF32) {
     const F2 own = ld_pair(r_own, e0, 0);
     a[0] = own.a;
     a[1] = own.b;
 #pragma unroll
     for (int s = 0; s < 2; s++) {
-      const F2 p00 = ld_pair(r_oth, base[s], 0), p01 = ld_pair(r_oth, base[s], U.sy);
-      const F2 p10 = ld_pair(r_oth, base[s], U.sz), p11 = ld_pair(r_oth, base[s], U.sy + U.sz);
+      const F2 p00 = ld_pair(r_oth, base[s], 0), p01 = ld_pair(r_oth, base[s], sy);
+      const F2 p10 = ld_pair(r_oth, base[s], sz), p11 = ld_pair(r_oth, base[s], sy + sz);
       v[s][0] = p00.a; v[s][1] = p00.b; v[s][2] = p01.a; v[s][3] = p01.b;
       v[s][4] = p10.a; v[s][5] = p10.b; v[s][6] = p11.a; v[s][7] = p11.b;
     }
@@ -605,19 +609,16 @@ __device__ __forceinline__ void sample_pair_inner(const ProblemView& P, const Sa
 #pragma unroll
     for (int s = 0; s < 2; s++) {
       const uint32_t sh = static_cast<uint32_t>(base[s] & 1) << 4;
-      const uint32_t w00 = ld_pair16(r_oth, base[s], 0, sh), w01 = ld_pair16(r_oth, base[s], U.sy, sh);
-      const uint32_t w10 = ld_pair16(r_oth, base[s], U.sz, sh), w11 = ld_pair16(r_oth, base[s], U.sy + U.sz, sh);
+      const uint32_t w00 = ld_pair16(r_oth, base[s], 0, sh), w01 = ld_pair16(r_oth, base[s], sy, sh);
+      const uint32_t w10 = ld_pair16(r_oth, base[s], sz, sh), w11 = ld_pair16(r_oth, base[s], sy + sz, sh);
       v[s][0] = lo16<ST>(w00); v[s][1] = hi16<ST>(w00); v[s][2] = lo16<ST>(w01); v[s][3] = hi16<ST>(w01);
       v[s][4] = lo16<ST>(w10); v[s][5] = hi16<ST>(w10); v[s][6] = lo16<ST>(w11); v[s][7] = hi16<ST>(w11);
       if (!P.fg_from_b) fg8[s] = ((w00 | w01 | w10 | w11) & 0x7fff7fffu) != 0u;
     }
   }
-  band[0] = 0u;
-  band[1] = 0u;
-  if (P.n_sets > 0) {
-    band[0] = __builtin_amdgcn_raw_buffer_load_b8(r_band, static_cast<unsigned>(e0), 0, 0);
-    band[1] = __builtin_amdgcn_raw_buffer_load_b8(r_band, static_cast<unsigned>(e0) + 1u, 0, 0);
-  }
+  // the band mask is all zero when the problem has no guidance sets
+  band[0] = __builtin_amdgcn_raw_buffer_load_b8(r_band, static_cast<unsigned>(e0), 0, 0);
+  band[1] = __builtin_amdgcn_raw_buffer_load_b8(r_band, static_cast<unsigned>(e0) + 1u, 0, 0);
 #pragma unroll
   for (int s = 0; s < 2; s++) {
     const float* w = v[s];
@@ -956,7 +957,6 @@ __device__ void eval_tet(const ProblemView& P, int tet0, int tet1, bool has1, fl
   // per lane; unit u's non-empty slices go to slice[16 u ..] in ascending z
   // (with their first row index, an exclusive scan within the 16 lanes).
   // Otherwise every unit takes its slices in groups of 64 as it goes.
-  int pre_rows[4] = {0, 0, 0, 0}, pre_ns[4] = {0, 0, 0, 0};
   bool pre = false;
   {
     const int u = lane >> 4, zl = lane & 15;
@@ -976,10 +976,9 @@ __device__ void eval_tet(const ProblemView& P, int tet0, int tet1, bool has1, fl
       x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);   // row_shr:4
       x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);   // row_shr:8
       if (cnt > 0) L->slice[16 * u + bits_below(ne & seg)] = make_int4(zl, y0, x - cnt, cnt);
-#pragma unroll
-      for (int v = 0; v < 4; v++) {
-        pre_rows[v] = __builtin_amdgcn_readlane(x, 16 * v + 15);
-        pre_ns[v] = __popcll(ne & (0xffffull << (16 * v)));
+      if (zl == 15) {
+        L->pre_rows[u] = x;
+        L->pre_ns[u] = __popcll(ne & seg);
       }
     }
   }
@@ -1009,9 +1008,6 @@ __device__ void eval_tet(const ProblemView& P, int tet0, int tet1, bool has1, fl
     U.m1 = uniform_d(Cd.M[1][0]);
     U.m2 = uniform_d(Cd.M[2][0]);
     U.thr = uniform_f(fminf(fminf(Cd.thr_f[0], Cd.thr_f[1]), Cd.thr_f[2]));
-    constexpr int esize = ST == kF32 ? 4 : 2;
-    U.sy = P.px * esize;
-    U.sz = P.pxy * esize;
     const __amdgpu_buffer_rsrc_t r_own = image_rsrc<ST>(P.img[d], P.pvox);
     const __amdgpu_buffer_rsrc_t r_oth = image_rsrc<ST>(P.img[1 - d], P.pvox);
     const __amdgpu_buffer_rsrc_t r_band = byte_rsrc(P.band[d], P.pvox);
@@ -1049,7 +1045,8 @@ __device__ void eval_tet(const ProblemView& P, int tet0, int tet1, bool has1, fl
 
     // consume units [cons, limit) in batches of 64 (one unit per lane), then
     // drop the rows that end by `limit` (a prefix of the ring)
-    auto run_batches = [&](int limit) {
+    auto run_batches_t = [&](auto inner_tag, int limit) {
+      constexpr bool kInner = decltype(inner_tag)::value;
       const bool valid = ((lane - head) & (kWave - 1)) < n_tab;
       const int my_off = valid ? L->row[lane].y : 0x7fffffff;
       for (int sb = cons; sb < limit; sb += kWave) {
@@ -1069,7 +1066,7 @@ __device__ void eval_tet(const ProblemView& P, int tet0, int tet1, bool has1, fl
         const double qr[3] = {L->rowq[slot][0], L->rowq[slot][1], L->rowq[slot][2]};
         const int k = 2 * (u - rw.y);
         const bool ok2 = ok && k + 1 < rw.w;
-        if (inner) {
+        if constexpr (kInner) {
           bool amb[2];
           float a[2], b[2];
           unsigned band[2];
@@ -1116,6 +1113,14 @@ __device__ void eval_tet(const ProblemView& P, int tet0, int tet1, bool has1, fl
       n_tab -= done;
       cons = limit;
     };
+    // the mapped points stay inside the padded volume (no clamps) or not:
+    // one specialised batch loop each
+    auto run_batches = [&](int limit) {
+      if (inner)
+        run_batches_t(std::true_type{}, limit);
+      else
+        run_batches_t(std::false_type{}, limit);
+    };
 
     // rows: slices in groups of 64 (one per lane), the rows of the non-empty
     // slices of a group enumerated 64 at a time
@@ -1126,8 +1131,8 @@ __device__ void eval_tet(const ProblemView& P, int tet0, int tet1, bool has1, fl
     for (int zb = 0; zb < (pre ? 1 : nzb); zb += kWave) {
       int ns, Rg;
       if (pre) {
-        ns = pre_ns[unit];
-        Rg = pre_rows[unit];
+        ns = uniform_i(L->pre_ns[unit]);
+        Rg = uniform_i(L->pre_rows[unit]);
       } else {
         int y0 = 0, cnt = 0;
         if (zb + lane < nzb) slice_rows(own_v, loz + zb + lane, loy, loy + nyb - 1, y0, cnt);

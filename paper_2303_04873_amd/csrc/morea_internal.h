@@ -68,7 +68,7 @@ struct ProblemView {
   const void* img[2];            // [0] = I_s, [1] = I_t, storage type, padded
   const float* dmap[2];          // [n_sets][pvox] distance maps on each image grid, padded
   const uint8_t* band[2];        // [pvox] bit s set where dmap[s] < radius
-  float set_w[2][kMaxSets];      // |C_i| / |G| per direction
+  const float* set_w;            // [2][kMaxSets] |C_i| / |G| per direction (device memory)
   const int4* tets;
   const int8_t* ref_sign;
   const float* elasticity;

@@ -341,7 +341,7 @@ __global__ __launch_bounds__(256) void k_eval_sobol(ProblemView P, const float* 
       const uint8_t* fgc_oth = d == 0 ? fgc1 : fgc0;
       const float* map_own = d == 0 ? P.dmap[0] : P.dmap[1];
       const float* map_oth = d == 0 ? P.dmap[1] : P.dmap[0];
-      const float* set_w = d == 0 ? P.set_w[0] : P.set_w[1];
+      const float* set_w = P.set_w + d * kMaxSets;
       for (int base = 0; base < N; base += kWave) {
         // Sobol integers of 64 k (wave-uniform)
         uint32_t xk[4] = {0u, 0u, 0u, 0u};
