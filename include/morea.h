@@ -542,19 +542,34 @@ morea_status morea_partial_graphs(const morea_problem *p, int32_t *cached, int64
 
 /* ------------------------------------------------------------------------
  * Learned pre-screen of offspring.  A per-tetrahedron multilayer perceptron
- * 23 -> 128 -> 128 -> 1 (ReLU) predicts each tet's mean intensity term, the
- * sum of h (Sec. 4.1.2) over the tet's samples in both directions divided by
- * their number.  Inputs per (candidate, tet): the deformation of the tet's 4
- * target-mesh vertices, (T_v - ref_v) / 4 voxels (12 values); 8 statistics
- * of the tet's region in the reference mesh (mean, std and foreground
- * fraction of I_s and of I_t over its voxels, their mean squared difference,
- * its voxel count over the mean count); and 3 samples of I_t around the
- * deformed tet: at the centroid c of its 4 target-mesh vertices, the mean
- * over those 4 vertices, and max - min over the 5 points (each sample the
- * trilinear interpolant at the point clamped into [0, n - 1] per axis, in
- * the cell below it capped at n - 2).  A candidate's score is
- * the voxel-count-weighted mean of its tets' predictions (a predicted
- * f_intensity); the best-scoring offspring are then evaluated exactly.  Dense
+ * 23 -> 128 -> 128 -> 1 (ReLU) predicts the change of a tet's mean intensity
+ * term (the sum of h, Sec. 4.1.2, over the tet's samples in both directions
+ * divided by their number) from an offspring's parent, whose exact
+ * evaluation is known, to the offspring, in units of h_scale, the mean of
+ * (I_s - I_t)^2 over the grid's voxels (1 when that is 0).  Inputs per
+ * (offspring, tet), in order:
+ *   0..11  the moves of the tet's 4 target-mesh vertices from the parent's,
+ *          (T_v - T_parent,v) / 0.5 voxel, vertex-major;
+ *   12..14 three cheap estimates of the change: the mean of
+ *          h = (I_s(x) - I_t(y))^2 over a fixed point set of the tet (x, y
+ *          at the same barycentric coordinates in the source and target
+ *          tets) in the offspring minus that in the parent, over the 4
+ *          vertices, the 6 edge midpoints, and 16 interior points (Halton
+ *          points j = 1..16 in bases 2, 3, 5, each sorted into a <= b <= c
+ *          and taken as barycentric coordinates (a, b - a, c - b, 1 - c));
+ *          divided by h_scale;
+ *   15..21 statistics of the tet's region in the reference mesh: mean, std
+ *          and foreground fraction of I_s and of I_t over its voxels, and
+ *          their mean squared difference divided by h_scale;
+ *   22     the parent's exact mean term of the tet, (h_S + h_T) / (n_S + n_T)
+ *          from its cache records (0 without samples), divided by h_scale.
+ * Image values are trilinear interpolants at the point clamped into
+ * [0, n - 1] per axis, in the cell below it capped at n - 2.  An offspring's
+ * score is sum_tet w_tet (parent term + h_scale prediction) / sum_tet w_tet
+ * with w_tet the offspring's |volume| of the tet's source plus that of its
+ * target (voxel^3: the samples the tet contributes in the two directions), a
+ * predicted f_intensity; the best-scoring offspring are then evaluated
+ * exactly.  Dense
  * layers run on the matrix cores with BF16 operands and FP32 accumulation;
  * master weights, gradients and Adam state are FP32.  The surrogate is an
  * addition of this library; the paper has no counterpart.  Parameters are
@@ -569,21 +584,32 @@ int32_t morea_surrogate_num_features(void);   /* 23 inputs per row */
 
 /* Create a surrogate for problem p (which must outlive it): He-normal
  * weights from `seed`, zero Adam state, the per-tet statistics of the
- * reference mesh, a padded FP32 copy of I_t (whatever the problem's image
- * storage), and a training workspace for batches of up to max_rows rows.
+ * reference mesh, h_scale, padded FP32 copies of I_s and I_t (whatever the
+ * problem's image storage), and a training workspace for batches of up to max_rows rows.
  * Synchronous.  Errors: MOREA_EINVAL, MOREA_ENOMEM, MOREA_EDEVICE. */
 morea_status morea_surrogate_create(morea_problem *p, int32_t max_rows, uint64_t seed,
                                     morea_surrogate **out);
 void morea_surrogate_destroy(morea_surrogate *s);
 
-/* Input rows of every (candidate, tet): feats [pop][n_tets][23] FP32. */
-morea_status morea_surrogate_features(morea_surrogate *s, const float *pts, int32_t pop,
+/* Input rows of every (offspring, tet): feats [pop][n_tets][23] FP32.
+ *   pts           [pop][2][3][n_points] the offspring
+ *   parent_pts    [n_parents][2][3][n_points] their parents
+ *   parent_cache  the parents' cache (morea_eval_full of parent_pts)
+ *   parent_of     [pop] int32 parent of each offspring; an index outside
+ *                 [0, n_parents) gives a row of NaN */
+morea_status morea_surrogate_features(morea_surrogate *s, const float *pts, int32_t pop, const float *parent_pts,
+                                      int32_t n_parents, const void *parent_cache, const int32_t *parent_of,
                                       float *feats, void *stream);
 
-/* Training targets from a cache written by morea_eval_full for `pop`
- * candidates: targets [pop][n_tets] FP32 (0 for a tet without samples). */
-morea_status morea_surrogate_targets(morea_surrogate *s, const void *cache, int32_t pop,
-                                     float *targets, void *stream);
+/* Training targets of `pop` offspring: targets [pop][n_tets] FP32, the
+ * offspring's mean term of each tet minus its parent's (a term is 0 for a tet
+ * without samples), divided by h_scale; NaN for an offspring whose parent_of
+ * is outside [0, n_parents).
+ *   cache         the offspring's cache (morea_eval_full)
+ *   parent_cache  the parents' cache (morea_eval_full), n_parents of them
+ *   parent_of     [pop] int32 */
+morea_status morea_surrogate_targets(morea_surrogate *s, const void *cache, int32_t pop, const void *parent_cache,
+                                     int32_t n_parents, const int32_t *parent_of, float *targets, void *stream);
 
 /* One Adam step (beta 0.9 / 0.999, eps 1e-8) on the mean squared error of
  * n_rows <= max_rows rows; *loss_out (device, may be NULL) receives the loss
@@ -601,9 +627,11 @@ morea_status morea_surrogate_gradients(morea_surrogate *s, const float *feats,
 morea_status morea_surrogate_predict_rows(morea_surrogate *s, const float *feats, int32_t n_rows,
                                           float *pred, void *stream);
 
-/* Pre-screen: score [pop] of candidates pts [pop][2][3][n_points]
- * (features built on the fly; one launch). */
-morea_status morea_surrogate_prescreen(morea_surrogate *s, const float *pts, int32_t pop,
+/* Pre-screen: score [pop] of offspring pts [pop][2][3][n_points] with their
+ * parents as for morea_surrogate_features (features built on the fly; one
+ * launch); an offspring without a valid parent scores +inf. */
+morea_status morea_surrogate_prescreen(morea_surrogate *s, const float *pts, int32_t pop, const float *parent_pts,
+                                       int32_t n_parents, const void *parent_cache, const int32_t *parent_of,
                                        float *score, void *stream);
 
 /* Indices of the k lowest scores (ties: lower index first) into idx_out [k],
@@ -617,6 +645,9 @@ morea_status morea_surrogate_select(const float *score, int32_t n, int32_t k, co
  * checkpoints).  Synchronous. */
 morea_status morea_surrogate_get_params(morea_surrogate *s, float *host_params);
 morea_status morea_surrogate_set_params(morea_surrogate *s, const float *host_params);
+
+/* h_scale of the surrogate's problem into *h_scale (host). */
+morea_status morea_surrogate_scale(const morea_surrogate *s, float *h_scale);
 
 /* The per-tet statistics host_stats [n_tets][8] and reference voxel counts
  * host_counts [n_tets] (may be NULL).  Synchronous. */

@@ -34,7 +34,7 @@ EXPORTS = ["morea_problem_create", "morea_problem_destroy", "morea_cache_bytes",
            "morea_surrogate_destroy", "morea_surrogate_features", "morea_surrogate_targets",
            "morea_surrogate_train_step",
            "morea_surrogate_gradients", "morea_surrogate_predict_rows", "morea_surrogate_prescreen",
-           "morea_surrogate_select", "morea_surrogate_get_params", "morea_surrogate_set_params",
+           "morea_surrogate_scale", "morea_surrogate_select", "morea_surrogate_get_params", "morea_surrogate_set_params",
            "morea_surrogate_stats", "morea_last_error"]
 
 
@@ -130,9 +130,15 @@ def load_library():
     L.morea_surrogate_create.restype = I32
     L.morea_surrogate_destroy.argtypes = [P]
     L.morea_surrogate_destroy.restype = None
-    for name, n in [("features", 5), ("targets", 5), ("predict_rows", 5), ("prescreen", 5)]:
+    L.morea_surrogate_predict_rows.argtypes = [P, P, I32, P, P]
+    L.morea_surrogate_predict_rows.restype = I32
+    L.morea_surrogate_targets.argtypes = [P, P, I32, P, I32, P, P, P]
+    L.morea_surrogate_targets.restype = I32
+    L.morea_surrogate_scale.argtypes = [P, P]
+    L.morea_surrogate_scale.restype = I32
+    for name in ["features", "prescreen"]:
         f = getattr(L, "morea_surrogate_" + name)
-        f.argtypes = [P, P, I32, P, P]
+        f.argtypes = [P, P, I32, P, I32, P, P, P, P]
         f.restype = I32
     L.morea_surrogate_train_step.argtypes = [P, P, P, I32, ctypes.c_float, P, P]
     L.morea_surrogate_train_step.restype = I32
@@ -637,18 +643,34 @@ class Surrogate:
         except Exception:
             pass
 
-    def features(self, pts, stream=None):
+    def features(self, pts, parent_pts, parent_cache, parent_of, stream=None):
+        """Input rows [pop][n_tets][23] of offspring `pts` whose parents are
+        `parent_pts` (evaluated into `parent_cache`); parent_of int32 CUDA
+        [pop]."""
         import torch
         out = torch.empty((pts.shape[0], self.problem.n_tets, self.n_features), dtype=torch.float32,
                           device="cuda")
         _check(load_library().morea_surrogate_features(self.handle, _dev_ptr(pts), pts.shape[0],
+                                                       _dev_ptr(parent_pts), parent_pts.shape[0],
+                                                       _dev_ptr(parent_cache), _dev_ptr(parent_of),
                                                        _dev_ptr(out), _stream_ptr(stream)))
         return out
 
-    def targets(self, cache, pop, stream=None):
+    @property
+    def h_scale(self):
+        """The mean of (I_s - I_t)^2 over the grid (1 when 0): the unit of
+        the h-valued features, the targets and the predictions."""
+        v = ctypes.c_float()
+        _check(load_library().morea_surrogate_scale(self.handle, ctypes.byref(v)))
+        return v.value
+
+    def targets(self, cache, pop, parent_cache, n_parents, parent_of, stream=None):
+        """Targets [pop][n_tets]: each offspring's per-tet mean term (from
+        `cache`) minus its parent's (from `parent_cache`), over h_scale."""
         import torch
         out = torch.empty((pop, self.problem.n_tets), dtype=torch.float32, device="cuda")
-        _check(load_library().morea_surrogate_targets(self.handle, _dev_ptr(cache), pop, _dev_ptr(out),
+        _check(load_library().morea_surrogate_targets(self.handle, _dev_ptr(cache), pop, _dev_ptr(parent_cache),
+                                                      n_parents, _dev_ptr(parent_of), _dev_ptr(out),
                                                       _stream_ptr(stream)))
         return out
 
@@ -675,10 +697,13 @@ class Surrogate:
                                                            _stream_ptr(stream)))
         return y
 
-    def prescreen(self, pts, score=None, stream=None):
+    def prescreen(self, pts, parent_pts, parent_cache, parent_of, score=None, stream=None):
+        """Scores [pop] of offspring `pts` (parents as for `features`)."""
         import torch
         score = torch.empty(pts.shape[0], dtype=torch.float32, device="cuda") if score is None else score
         _check(load_library().morea_surrogate_prescreen(self.handle, _dev_ptr(pts), pts.shape[0],
+                                                        _dev_ptr(parent_pts), parent_pts.shape[0],
+                                                        _dev_ptr(parent_cache), _dev_ptr(parent_of),
                                                         _dev_ptr(score), _stream_ptr(stream)))
         return score
 

@@ -1,10 +1,14 @@
 // Learned pre-screen of offspring: a per-tetrahedron multilayer perceptron
-// 23 -> 128 -> 128 -> 1 (ReLU) that predicts each tet's mean intensity term
-// (the sum of h over the tet's samples in both directions divided by their
-// number, Sec. 4.1.2), trained on records produced by the exact evaluator and
-// used to rank a batch of offspring before only the best are evaluated
-// exactly.  The surrogate has no counterpart in the paper; it sits in front of
-// the exact evaluation, which stays the judge of every selected candidate.
+// 23 -> 128 -> 128 -> 1 (ReLU) that predicts how an offspring's mean
+// intensity term of a tet (the sum of h over the tet's samples in both
+// directions divided by their number, Sec. 4.1.2) differs from its parent's,
+// from how the tet's vertices moved away from the parent's, the tet's region
+// statistics, the parent's exact term and samples of the target image.
+// Trained on records produced by the exact evaluator for offspring and
+// parents; a batch of offspring is ranked by the parent's exact terms plus
+// the predicted changes before only the best are evaluated exactly.  The
+// surrogate has no counterpart in the paper; it sits in front of the exact
+// evaluation, which stays the judge of every selected candidate.
 //
 // Dense layers run on the matrix cores: v_mfma_f32_32x32x8_bf16 with BF16
 // operands and FP32 accumulation, one 64-lane wave per tile of 32 rows.
@@ -16,6 +20,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <random>
 #include <string>
 #include <vector>
@@ -135,24 +140,46 @@ __device__ void tile_forward(const NetLds* N, TileLds* T, RedTile& red, f16v z2[
 
 // ------------------------------------------------------------- features
 
-// Features of (candidate, tet): the deformation of the tet's 4 target-mesh
-// vertices, (T_v - ref_v) / 4 voxels (12 values: the deformed vertex
-// coordinates relative to the reference mesh, at a scale where a fraction of
-// a voxel stays well resolved in BF16), the tet's 8 source-region
-// statistics, then 3 samples of the target image around the deformed tet:
-// I_t at the centroid c of the 4 deformed vertices, the mean of I_t over the
-// 4 deformed vertices, and max - min of I_t over those 5 points.  Each sample
-// is the trilinear interpolant at the point clamped into the image box, so
-// all three are continuous in the vertex positions.
-constexpr float kDispScale = 0.25f;
-constexpr int kImgFeat = 20;   // index of the first image feature
+// Features of (offspring, tet), relative to the offspring's parent (whose
+// exact evaluation is known: its per-tet records are in its cache):
+//   0..11  the move of the tet's 4 target-mesh vertices from the parent's,
+//          (T_v - T_parent,v) / 0.5 voxel (the scale of the offspring's
+//          perturbation, well resolved in BF16);
+//   12..14 estimates of the change of the tet's mean intensity term, each
+//          the mean of h = (I_s(x) - I_t(y))^2 over a fixed set of points of
+//          the tet, x and y at the same barycentric coordinates in the
+//          offspring's source and target tets, minus the same mean for the
+//          parent: over the 4 vertices, the 6 edge midpoints, and 16
+//          interior points (Halton points in barycentric form); divided by
+//          h_scale;
+//   15..21 the first 7 of the tet's 8 source-region statistics, the 7th
+//          (the mean of (I_s - I_t)^2) divided by h_scale;
+//   22     the parent's exact mean intensity term of the tet, (h_S + h_T) /
+//          (n_S + n_T) from its records (0 without samples), divided by
+//          h_scale.
+// h_scale is the mean of (I_s - I_t)^2 over the grid's voxels (1 when that is
+// 0), so that the h-valued features and the targets are of order 1.  Image
+// values are trilinear interpolants at the point clamped into the image box,
+// so every feature is continuous in the vertex positions.
+constexpr float kRelScale = 2.0f;
+constexpr int kHalton = 16;
 
-// Trilinear I_t at (x, y, z) clamped into [0, n - 1] on each axis, from the
-// padded FP32 copy `img` (voxel (i, j, k) at (k + 1) pxy + (j + 1) px + i + 1).
-// The cell is the one below the point, capped at n - 2, so the upper corner
-// always lies in the volume or, for an axis of size 1, on its zero border
-// with weight 0.
-__device__ __forceinline__ float it_clamped(const ProblemView& P, const float* img, float x, float y, float z) {
+// The parents of a batch of offspring: points [n][2][3][n_points], per-tet
+// records of their full evaluation [n][n_tets][2], the parent of each
+// offspring.
+struct Parents {
+  const float* pts;
+  const Record* rec;
+  const int* of;
+  int n;
+};
+
+// Trilinear interpolant of a padded FP32 image copy `img` (voxel (i, j, k)
+// at (k + 1) pxy + (j + 1) px + i + 1) at (x, y, z) clamped into [0, n - 1]
+// on each axis.  The cell is the one below the point, capped at n - 2, so the
+// upper corner always lies in the volume or, for an axis of size 1, on its
+// zero border with weight 0.
+__device__ __forceinline__ float sample_clamped(const ProblemView& P, const float* img, float x, float y, float z) {
   const float q[3] = {fminf(fmaxf(x, 0.f), static_cast<float>(P.nx - 1)),
                       fminf(fmaxf(y, 0.f), static_cast<float>(P.ny - 1)),
                       fminf(fmaxf(z, 0.f), static_cast<float>(P.nz - 1))};
@@ -172,65 +199,109 @@ __device__ __forceinline__ float it_clamped(const ProblemView& P, const float* i
   return fmaf(f[2], y1 - y0, y0);
 }
 
-// The deformed vertices' target-mesh coordinates d[v][a] of a tet.
-__device__ __forceinline__ void deformed_vertices(const ProblemView& P, const float* cand, int tet, float d[4][3]) {
+// A tet's vertices in one candidate: mesh 0 (source) or 1 (target).
+__device__ __forceinline__ void tet_vertices(const ProblemView& P, const float* cand, int tet, int mesh,
+                                             float d[4][3]) {
   const int4 tv = P.tets[tet];
   const int vs[4] = {tv.x, tv.y, tv.z, tv.w};
 #pragma unroll
   for (int v = 0; v < 4; v++)
 #pragma unroll
-    for (int a = 0; a < 3; a++) d[v][a] = cand[(3 + a) * P.n_points + vs[v]];
+    for (int a = 0; a < 3; a++) d[v][a] = cand[(3 * mesh + a) * P.n_points + vs[v]];
 }
 
-__device__ __forceinline__ void centroid(const float d[4][3], float c[3]) {
+// h at barycentric coordinates l of the tet: (I_s(S l) - I_t(T l))^2.
+__device__ __forceinline__ float h_at(const ProblemView& P, const float* img_s, const float* img_t,
+                                      const float S[4][3], const float T[4][3], const float l[4]) {
+  float x[3], y[3];
 #pragma unroll
-  for (int a = 0; a < 3; a++) c[a] = ((d[0][a] + d[1][a]) + (d[2][a] + d[3][a])) * 0.25f;
-}
-
-// Row features 0..11 (kh = 0), 12..19 (kh = 1) or 20..22 (kh = 2) into out.
-__device__ __forceinline__ void row_features(const ProblemView& P, const float* cand, const float* ref,
-                                             const float* img, int tet, const float* stats, int kh, float* out) {
-  const int4 tv = P.tets[tet];
-  const int vs[4] = {tv.x, tv.y, tv.z, tv.w};
-  if (kh == 0) {
-#pragma unroll
-    for (int v = 0; v < 4; v++)
-#pragma unroll
-      for (int a = 0; a < 3; a++)
-        out[3 * v + a] = (cand[(3 + a) * P.n_points + vs[v]] - ref[3 * vs[v] + a]) * kDispScale;
-  } else if (kh == 1) {
-#pragma unroll
-    for (int f = 0; f < 8; f++) out[f] = stats[8 * tet + f];
-  } else {
-    float d[4][3], c[3];
-    deformed_vertices(P, cand, tet, d);
-    centroid(d, c);
-    const float ic = it_clamped(P, img, c[0], c[1], c[2]);
-    float sum = 0.f, mn = ic, mx = ic;
-#pragma unroll
-    for (int v = 0; v < 4; v++) {
-      const float iv = it_clamped(P, img, d[v][0], d[v][1], d[v][2]);
-      sum += iv;
-      mn = fminf(mn, iv);
-      mx = fmaxf(mx, iv);
-    }
-    out[0] = ic;
-    out[1] = sum * 0.25f;
-    out[2] = mx - mn;
+  for (int a = 0; a < 3; a++) {
+    x[a] = fmaf(l[0], S[0][a], fmaf(l[1], S[1][a], fmaf(l[2], S[2][a], l[3] * S[3][a])));
+    y[a] = fmaf(l[0], T[0][a], fmaf(l[1], T[1][a], fmaf(l[2], T[2][a], l[3] * T[3][a])));
   }
+  const float d = sample_clamped(P, img_s, x[0], x[1], x[2]) - sample_clamped(P, img_t, y[0], y[1], y[2]);
+  return d * d;
 }
 
-// Padded FP32 copy of the target image (any storage), read by the features.
+// Means of h over the tet's point sets in one candidate: m[0] the 4
+// vertices, m[1] the 6 edge midpoints, m[2] the 16 interior points `bary`.
+__device__ __forceinline__ void point_means(const ProblemView& P, const float* img_s, const float* img_t,
+                                            const float* cand, int tet, const float4* bary, float m[3]) {
+  float S[4][3], T[4][3];
+  tet_vertices(P, cand, tet, 0, S);
+  tet_vertices(P, cand, tet, 1, T);
+  // one point at a time (the same point in every lane): 4 vertices, the
+  // edges (0,1) (0,2) (0,3) (1,2) (1,3) (2,3), then the interior points
+  float sv = 0.f, se = 0.f, sr = 0.f;
+#pragma unroll 1
+  for (int j = 0; j < 10 + kHalton; j++) {
+    float l[4] = {0.f, 0.f, 0.f, 0.f};
+    if (j < 4) {
+      l[0] = j == 0 ? 1.f : 0.f;
+      l[1] = j == 1 ? 1.f : 0.f;
+      l[2] = j == 2 ? 1.f : 0.f;
+      l[3] = j == 3 ? 1.f : 0.f;
+    } else if (j < 10) {
+      const int e = j - 4, a = e < 3 ? 0 : (e < 5 ? 1 : 2), b = e < 3 ? e + 1 : (e < 5 ? e - 1 : 3);
+#pragma unroll
+      for (int v = 0; v < 4; v++) l[v] = (v == a || v == b) ? .5f : 0.f;
+    } else {
+      const float4 q = bary[j - 10];
+      l[0] = q.x;
+      l[1] = q.y;
+      l[2] = q.z;
+      l[3] = q.w;
+    }
+    const float hv = h_at(P, img_s, img_t, S, T, l);
+    if (j < 4) sv += hv;
+    else if (j < 10) se += hv;
+    else sr += hv;
+  }
+  m[0] = sv * 0.25f;
+  m[1] = se * (1.f / 6.f);
+  m[2] = sr * (1.f / kHalton);
+}
+
+// |signed volume| of a tet's source and target (voxel^3): the expected
+// samples of the tet in both directions.
+__device__ __forceinline__ float tet_weight(const ProblemView& P, const float* cand, int tet) {
+  float w = 0.f;
+#pragma unroll
+  for (int mesh = 0; mesh < 2; mesh++) {
+    float d[4][3];
+    tet_vertices(P, cand, tet, mesh, d);
+    float e[3][3];
+#pragma unroll
+    for (int k = 0; k < 3; k++)
+#pragma unroll
+      for (int a = 0; a < 3; a++) e[k][a] = d[k + 1][a] - d[0][a];
+    const float det = e[0][0] * (e[1][1] * e[2][2] - e[1][2] * e[2][1]) -
+                      e[0][1] * (e[1][0] * e[2][2] - e[1][2] * e[2][0]) +
+                      e[0][2] * (e[1][0] * e[2][1] - e[1][1] * e[2][0]);
+    w += fabsf(det) * (1.f / 6.f);
+  }
+  return w;
+}
+
+// Mean intensity term per sample of a tet over both directions, from its
+// two records.
+__device__ __forceinline__ float tet_mean_h(const Record* rec, int tet) {
+  const Record a = rec[2 * static_cast<size_t>(tet)], b = rec[2 * static_cast<size_t>(tet) + 1];
+  const uint32_t n = a.n + b.n;
+  return n ? (a.h + b.h) / static_cast<float>(n) : 0.f;
+}
+
+// Padded FP32 copy of image `which` (0 source, 1 target; any storage).
 template <int ST>
-__global__ void k_target_f32(ProblemView P, float* out) {
+__global__ void k_image_f32(ProblemView P, int which, float* out) {
   const size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= P.pvox) return;
   if constexpr (ST == kF32) {
-    out[i] = static_cast<const float*>(P.img[1])[i];
+    out[i] = static_cast<const float*>(P.img[which])[i];
   } else if constexpr (ST == kBF16) {
-    out[i] = bf2f(static_cast<const bf16*>(P.img[1])[i]);
+    out[i] = bf2f(static_cast<const bf16*>(P.img[which])[i]);
   } else {
-    out[i] = static_cast<float>(static_cast<const _Float16*>(P.img[1])[i]);
+    out[i] = static_cast<float>(static_cast<const _Float16*>(P.img[which])[i]);
   }
 }
 
@@ -331,30 +402,61 @@ __global__ void k_tet_stats(ProblemView P, const float* ref, float* stats, int* 
   }
 }
 
-__global__ void k_features(ProblemView P, const float* pts, const float* ref, const float* img, int pop,
-                           const float* stats, float* feats) {
-  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = lane_id();
-  if (row >= pop * P.n_tets || lane >= 3) return;
-  const int cand = row / P.n_tets, tet = row % P.n_tets;
-  float f[12];
-  row_features(P, pts + static_cast<size_t>(cand) * 6 * P.n_points, ref, img, tet, stats, lane, f);
+// Images and constants the features read.
+struct FeatureInputs {
+  const float* img_s;   // padded FP32 copies of the two images
+  const float* img_t;
+  const float4* bary;   // [16] interior points, barycentric
+  const float* stats;   // [n_tets][8]
+  float h_scale;
+  float inv_h;          // 1 / h_scale
+};
+
+// One thread per (offspring, tet) row: the 23 features in order.
+__global__ void k_features(ProblemView P, const float* pts, Parents Q, FeatureInputs F, int pop, float* feats) {
+  const long long row = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (row >= static_cast<long long>(pop) * P.n_tets) return;
+  const int cand = static_cast<int>(row / P.n_tets), tet = static_cast<int>(row % P.n_tets);
   float* o = feats + static_cast<size_t>(row) * kIn;
-  if (lane == 0)
-    for (int k = 0; k < 12; k++) o[k] = f[k];
-  else if (lane == 1)
-    for (int k = 0; k < 8; k++) o[12 + k] = f[k];
-  else
-    for (int k = 0; k < 3; k++) o[kImgFeat + k] = f[k];
+  const int par = Q.of[cand];
+  if (par < 0 || par >= Q.n) {   // no parent: the row has no features
+    for (int k = 0; k < kIn; k++) o[k] = __builtin_nanf("");
+    return;
+  }
+  const float* cp = pts + static_cast<size_t>(cand) * 6 * P.n_points;
+  const float* pp = Q.pts + static_cast<size_t>(par) * 6 * P.n_points;
+  float d[4][3], dp[4][3];
+  tet_vertices(P, cp, tet, 1, d);
+  tet_vertices(P, pp, tet, 1, dp);
+#pragma unroll
+  for (int v = 0; v < 4; v++)
+#pragma unroll
+    for (int a = 0; a < 3; a++) o[3 * v + a] = (d[v][a] - dp[v][a]) * kRelScale;
+  float mc[3], mp[3];
+  point_means(P, F.img_s, F.img_t, cp, tet, F.bary, mc);
+  point_means(P, F.img_s, F.img_t, pp, tet, F.bary, mp);
+#pragma unroll
+  for (int k = 0; k < 3; k++) o[12 + k] = (mc[k] - mp[k]) * F.inv_h;
+#pragma unroll
+  for (int k = 0; k < 6; k++) o[15 + k] = F.stats[8 * tet + k];
+  o[21] = F.stats[8 * tet + 6] * F.inv_h;
+  o[22] = tet_mean_h(Q.rec + static_cast<size_t>(par) * P.n_tets * 2, tet) * F.inv_h;
 }
 
-// Per-tet target: mean h per sample over both directions, from a cache.
-__global__ void k_targets(const Record* rec, int rows, float* t) {
+// Target of (offspring, tet): its mean intensity term minus its parent's
+// (both from their caches' records), divided by h_scale; NaN without a valid
+// parent.
+__global__ void k_targets(const Record* rec, int n_tets, int rows, Parents Q, float inv_h, float* t) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= rows) return;
-  const Record a = rec[2 * static_cast<size_t>(r)], b = rec[2 * static_cast<size_t>(r) + 1];
-  const uint32_t n = a.n + b.n;
-  t[r] = n ? (a.h + b.h) / static_cast<float>(n) : 0.f;
+  const int cand = r / n_tets, tet = r - cand * n_tets;
+  const int par = Q.of[cand];
+  if (par < 0 || par >= Q.n) {
+    t[r] = __builtin_nanf("");
+    return;
+  }
+  t[r] = (tet_mean_h(rec + static_cast<size_t>(cand) * n_tets * 2, tet) -
+          tet_mean_h(Q.rec + static_cast<size_t>(par) * n_tets * 2, tet)) * inv_h;
 }
 
 // ------------------------------------------------------------ prescreen
@@ -401,12 +503,14 @@ __device__ __forceinline__ bf8 pack8(const float v[8]) {
   return __builtin_bit_cast(bf8, w);
 }
 
-// Score of each candidate: the predicted intensity objective,
-// sum_tet pred_tet * n_tet / sum_tet n_tet with n_tet the reference voxel
-// counts.  Blocks of 4 waves loop over candidates; each wave takes tiles of
+// Score of each offspring: the predicted intensity objective,
+// sum_tet (parent_tet + h_scale pred_tet) w_tet / sum_tet w_tet with
+// parent_tet the parent's exact mean term (FP32, from its records), pred_tet
+// the network's predicted change (in units of h_scale) and w_tet the
+// offspring's |volume| of the tet's source plus that of its target (voxel^3,
+// the samples the tet contributes in the two directions).  Blocks of 4 waves loop over candidates; each wave takes tiles of
 // 32 tets; fixed-order reductions.
-__global__ __launch_bounds__(256, 3) void k_prescreen(ProblemView P, const float* pts, const float* ref,
-                                                    const float* img, const float* stats, const int* counts,
+__global__ __launch_bounds__(256, 3) void k_prescreen(ProblemView P, const float* pts, Parents Q, FeatureInputs F,
                                                     const float* params, int pop, float* score) {
   __shared__ PreLds N;
   __shared__ float wsum[4], wcnt[4];
@@ -436,63 +540,63 @@ __global__ __launch_bounds__(256, 3) void k_prescreen(ProblemView P, const float
   const int wave = threadIdx.x >> 6, lane = lane_id(), i = lane & 31, h = lane >> 5;
   const int n_tiles = (P.n_tets + kRowTile - 1) / kRowTile;
   for (int cand = blockIdx.x; cand < pop; cand += gridDim.x) {
+    const int par = Q.of[cand];
+    if (par < 0 || par >= Q.n) {   // no parent: never preferred
+      if (threadIdx.x == 0) score[cand] = INFINITY;
+      continue;
+    }
     const float* cp = pts + static_cast<size_t>(cand) * 6 * P.n_points;
+    const float* pp = Q.pts + static_cast<size_t>(par) * 6 * P.n_points;
+    const Record* prec = Q.rec + static_cast<size_t>(par) * P.n_tets * 2;
     float acc_s = 0.f, cnt = 0.f;
     for (int tile = wave; tile < n_tiles; tile += 4) {
       const int tet = tile * kRowTile + i;
-      // this lane's half of the tet's features (natural order: 12 deformation
-      // values, 8 statistics, 3 image samples, three constant 1s, zeros);
-      // the 5 image samples are split over the halves (h = 0: centroid and
-      // vertices 0, 1; h = 1: vertices 2, 3) and combined across them
+      // this lane's half of the tet's features (natural order: 12 vertex
+      // moves, 3 estimated changes, 7 statistics, the parent's mean term,
+      // three constant 1s, zeros): h = 0 holds features 0..7 and 16..23,
+      // h = 1 features 8..15 and 24..31.  The point means behind the
+      // estimated changes are split over the halves (h = 0 the offspring's,
+      // h = 1 the parent's) and combined in the upper half.
       float f0[8], f1[8];
 #pragma unroll
       for (int k = 0; k < 8; k++) f0[k] = f1[k] = 0.f;
-      float ic = 0.f, isum = 0.f, imn = 0.f, imx = 0.f;
+      float m[3] = {0.f, 0.f, 0.f};
+      float pterm = 0.f, wt = 0.f;
       if (tet < P.n_tets) {
-        const int4 tv = P.tets[tet];
-        const int vs[4] = {tv.x, tv.y, tv.z, tv.w};
-        float d[4][3];
-        deformed_vertices(P, cp, tet, d);
-        if (h == 0) {   // features 0..7, 16..23
+        point_means(P, F.img_s, F.img_t, h == 0 ? cp : pp, tet, F.bary, m);
+        float d[4][3], dp[4][3];
+        tet_vertices(P, cp, tet, 1, d);
+        tet_vertices(P, pp, tet, 1, dp);
+        if (h == 0) {
 #pragma unroll
           for (int k = 0; k < 8; k++) {
             const int v = k / 3, a = k % 3;
-            f0[k] = (d[v][a] - ref[3 * vs[v] + a]) * kDispScale;
+            f0[k] = (d[v][a] - dp[v][a]) * kRelScale;
           }
 #pragma unroll
-          for (int k = 0; k < 4; k++) f1[k] = stats[8 * tet + 4 + k];
+          for (int k = 0; k < 5; k++) f1[k] = F.stats[8 * tet + 1 + k];
+          f1[5] = F.stats[8 * tet + 6] * F.inv_h;
+          pterm = tet_mean_h(prec, tet);
+          f1[6] = pterm * F.inv_h;
           f1[7] = 1.f;   // the first term of b1
-          float c[3];
-          centroid(d, c);
-          ic = it_clamped(P, img, c[0], c[1], c[2]);
-          const float i0 = it_clamped(P, img, d[0][0], d[0][1], d[0][2]);
-          const float i1 = it_clamped(P, img, d[1][0], d[1][1], d[1][2]);
-          isum = i0 + i1;
-          imn = fminf(ic, fminf(i0, i1));
-          imx = fmaxf(ic, fmaxf(i0, i1));
-        } else {        // features 8..15, 24..31
+          wt = tet_weight(P, cp, tet);
+        } else {
 #pragma unroll
           for (int k = 0; k < 4; k++) {
             const int fk = 8 + k, v = fk / 3, a = fk % 3;
-            f0[k] = (d[v][a] - ref[3 * vs[v] + a]) * kDispScale;
+            f0[k] = (d[v][a] - dp[v][a]) * kRelScale;
           }
-#pragma unroll
-          for (int k = 0; k < 4; k++) f0[4 + k] = stats[8 * tet + k];
+          f0[7] = F.stats[8 * tet];
           f1[0] = f1[1] = 1.f;   // the other two terms of b1
-          const float i2 = it_clamped(P, img, d[2][0], d[2][1], d[2][2]);
-          const float i3 = it_clamped(P, img, d[3][0], d[3][1], d[3][2]);
-          isum = i2 + i3;
-          imn = fminf(i2, i3);
-          imx = fmaxf(i2, i3);
         }
       }
       {
-        const float osum = __shfl_xor(isum, 32, 64), omn = __shfl_xor(imn, 32, 64),
-                    omx = __shfl_xor(imx, 32, 64);
-        if (h == 0) {
-          f1[4] = ic;
-          f1[5] = (isum + osum) * 0.25f;
-          f1[6] = fmaxf(imx, omx) - fminf(imn, omn);
+        float mo[3];
+#pragma unroll
+        for (int k = 0; k < 3; k++) mo[k] = __shfl_xor(m[k], 32, 64);
+        if (h == 1) {
+#pragma unroll
+          for (int k = 0; k < 3; k++) f0[4 + k] = (mo[k] - m[k]) * F.inv_h;
         }
       }
       const bf8 xb0 = pack8(f0), xb1 = pack8(f1);
@@ -529,9 +633,10 @@ __global__ __launch_bounds__(256, 3) void k_prescreen(ProblemView P, const float
       }
       const float y = part + __shfl_xor(part, 32, 64) + b3;   // the two halves hold different units
       if (h == 0 && tet < P.n_tets) {
-        const float c = static_cast<float>(counts[tet]);
-        acc_s = fmaf(y, c, acc_s);
-        cnt += c;
+        // the parent's exact term plus the predicted change, weighted by the
+        // offspring's expected samples of the tet
+        acc_s = fmaf(wt, fmaf(y, F.h_scale, pterm), acc_s);
+        cnt += wt;
       }
     }
     for (int d = 32; d >= 1; d >>= 1) {
@@ -835,7 +940,10 @@ struct morea_surrogate {
   float* stats = nullptr;
   int* counts = nullptr;
   float* ref = nullptr;
-  float* img_t = nullptr;   // padded FP32 copy of the target image
+  float* img_s = nullptr;   // padded FP32 copies of the source and target images
+  float* img_t = nullptr;
+  float4* bary = nullptr;   // [16] interior sample points of a tet, barycentric
+  float h_scale = 1.f;      // mean of (I_s - I_t)^2 over the grid (1 when 0)
   TrainBuf tb{};
   int steps = 0;
   std::vector<void*> allocs;
@@ -880,15 +988,44 @@ hipError_t launch_stats(morea_surrogate* s, const float* ref_dev) {
   return hipGetLastError();
 }
 
-hipError_t launch_target_copy(morea_surrogate* s) {
+hipError_t launch_image_copies(morea_surrogate* s) {
   const ProblemView& P = s->p->view;
   const dim3 grid((P.pvox + 255) / 256);
-  switch (s->p->storage) {
-    case kF32: hipLaunchKernelGGL(k_target_f32<kF32>, grid, dim3(256), 0, 0, P, s->img_t); break;
-    case kBF16: hipLaunchKernelGGL(k_target_f32<kBF16>, grid, dim3(256), 0, 0, P, s->img_t); break;
-    default: hipLaunchKernelGGL(k_target_f32<kF16>, grid, dim3(256), 0, 0, P, s->img_t); break;
+  for (int which = 0; which < 2; which++) {
+    float* out = which ? s->img_t : s->img_s;
+    switch (s->p->storage) {
+      case kF32: hipLaunchKernelGGL(k_image_f32<kF32>, grid, dim3(256), 0, 0, P, which, out); break;
+      case kBF16: hipLaunchKernelGGL(k_image_f32<kBF16>, grid, dim3(256), 0, 0, P, which, out); break;
+      default: hipLaunchKernelGGL(k_image_f32<kF16>, grid, dim3(256), 0, 0, P, which, out); break;
+    }
   }
   return hipGetLastError();
+}
+
+// Radical inverse of j in base b (van der Corput).
+double radical_inverse(int j, int b) {
+  double r = 0.0, f = 1.0 / b;
+  for (; j > 0; j /= b, f /= b) r += f * (j % b);
+  return r;
+}
+
+// The interior sample points: Halton points j = 1..16 in bases 2, 3, 5,
+// each (u1, u2, u3) sorted into a <= b <= c and mapped to the barycentric
+// coordinates (a, b - a, c - b, 1 - c) (the spacings of sorted uniforms,
+// uniform on the simplex).
+std::vector<float4> interior_points() {
+  std::vector<float4> out;
+  for (int j = 1; j <= kHalton; j++) {
+    double u[3] = {radical_inverse(j, 2), radical_inverse(j, 3), radical_inverse(j, 5)};
+    std::sort(u, u + 3);
+    out.push_back(make_float4(static_cast<float>(u[0]), static_cast<float>(u[1] - u[0]),
+                              static_cast<float>(u[2] - u[1]), static_cast<float>(1.0 - u[2])));
+  }
+  return out;
+}
+
+FeatureInputs feature_inputs(const morea_surrogate* s) {
+  return FeatureInputs{s->img_s, s->img_t, s->bary, s->stats, s->h_scale, 1.f / s->h_scale};
 }
 
 morea_status train_launch(morea_surrogate* s, const float* X, const float* t, int n, float lr,
@@ -947,7 +1084,9 @@ morea_status morea_surrogate_create(morea_problem* p, int32_t max_rows, uint64_t
   ok(salloc(s, &s->tb.wpart, sizeof(float) * kWavePart * static_cast<size_t>(bmax / kRowTile + 4)));
   ok(salloc(s, &s->tb.gpart, sizeof(float) * kSplitK * kGradTiles * 1024));
   ok(salloc(s, &s->ref, sizeof(float) * 3 * p->view.n_points));
+  ok(salloc(s, &s->img_s, sizeof(float) * static_cast<size_t>(p->view.pvox)));
   ok(salloc(s, &s->img_t, sizeof(float) * static_cast<size_t>(p->view.pvox)));
+  ok(salloc(s, &s->bary, sizeof(float4) * kHalton));
   float* ref_dev = s->ref;
   if (st == MOREA_OK) {
     // He-normal initial weights, zero biases, from the given seed
@@ -967,8 +1106,25 @@ morea_status morea_surrogate_create(morea_problem* p, int32_t max_rows, uint64_t
     hipLaunchKernelGGL(k_refresh_bf16, dim3((kHid * kHid + 255) / 256), dim3(256), 0, 0, s->params, s->w1b, s->w2b);
     ok(sdev(hipGetLastError(), "refresh"));
     ok(sdev(launch_stats(s, ref_dev), "tet statistics"));
-    ok(sdev(launch_target_copy(s), "target image copy"));
+    ok(sdev(launch_image_copies(s), "image copies"));
+    const std::vector<float4> bary = interior_points();
+    ok(sdev(hipMemcpy(s->bary, bary.data(), sizeof(float4) * kHalton, hipMemcpyHostToDevice), "upload"));
     ok(sdev(hipDeviceSynchronize(), "surrogate set-up"));
+  }
+  if (st == MOREA_OK) {
+    // h_scale: the count-weighted mean of the tets' mean (I_s - I_t)^2 (the
+    // reference mesh tiles the grid, so this is the mean over its voxels)
+    std::vector<float> hs(8 * static_cast<size_t>(NT));
+    std::vector<int> hc(NT);
+    ok(sdev(hipMemcpy(hs.data(), s->stats, sizeof(float) * hs.size(), hipMemcpyDeviceToHost), "copy"));
+    ok(sdev(hipMemcpy(hc.data(), s->counts, sizeof(int) * hc.size(), hipMemcpyDeviceToHost), "copy"));
+    double num = 0.0, den = 0.0;
+    for (int t = 0; t < NT; t++) {
+      num += static_cast<double>(hc[t]) * hs[8 * static_cast<size_t>(t) + 6];
+      den += hc[t];
+    }
+    const double hsc = den > 0.0 ? num / den : 0.0;
+    s->h_scale = hsc > 0.0 && std::isfinite(hsc) ? static_cast<float>(hsc) : 1.f;
   }
   if (st != MOREA_OK) {
     for (void* a : s->allocs) (void)hipFree(a);
@@ -986,24 +1142,33 @@ void morea_surrogate_destroy(morea_surrogate* s) {
   delete s;
 }
 
-morea_status morea_surrogate_features(morea_surrogate* s, const float* pts, int32_t pop, float* feats,
-                                      void* stream) {
-  if (!s || !pts || !feats || pop < 0) return sfail(MOREA_EINVAL, "bad argument");
+morea_status morea_surrogate_features(morea_surrogate* s, const float* pts, int32_t pop, const float* parent_pts,
+                                      int32_t n_parents, const void* parent_cache, const int32_t* parent_of,
+                                      float* feats, void* stream) {
+  if (!s || pop < 0 || n_parents < 0) return sfail(MOREA_EINVAL, "bad argument");
   const long long rows = static_cast<long long>(pop) * s->p->view.n_tets;
   if (rows == 0) return MOREA_OK;
+  if (!pts || !feats || !parent_of || (n_parents > 0 && (!parent_pts || !parent_cache)))
+    return sfail(MOREA_EINVAL, "NULL argument");
   if (rows > (1LL << 31) / 4) return sfail(MOREA_ERANGE, "too many rows");
-  hipLaunchKernelGGL(k_features, dim3(static_cast<unsigned>((rows + 3) / 4)), dim3(256), 0,
-                     static_cast<hipStream_t>(stream), s->p->view, pts, s->ref, s->img_t, pop, s->stats, feats);
+  const Parents Q{parent_pts, static_cast<const Record*>(parent_cache), parent_of, n_parents};
+  hipLaunchKernelGGL(k_features, dim3(static_cast<unsigned>((rows + 255) / 256)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), s->p->view, pts, Q, feature_inputs(s), pop, feats);
   return sdev(hipGetLastError(), "features");
 }
 
-morea_status morea_surrogate_targets(morea_surrogate* s, const void* cache, int32_t pop, float* targets,
-                                     void* stream) {
-  if (!s || !cache || !targets || pop < 0) return sfail(MOREA_EINVAL, "bad argument");
-  const int rows = pop * s->p->view.n_tets;
+morea_status morea_surrogate_targets(morea_surrogate* s, const void* cache, int32_t pop, const void* parent_cache,
+                                     int32_t n_parents, const int32_t* parent_of, float* targets, void* stream) {
+  if (!s || pop < 0 || n_parents < 0) return sfail(MOREA_EINVAL, "bad argument");
+  const long long rows = static_cast<long long>(pop) * s->p->view.n_tets;
   if (rows == 0) return MOREA_OK;
-  hipLaunchKernelGGL(k_targets, dim3((rows + 255) / 256), dim3(256), 0, static_cast<hipStream_t>(stream),
-                     static_cast<const Record*>(cache), rows, targets);
+  if (!cache || !targets || !parent_of || (n_parents > 0 && !parent_cache))
+    return sfail(MOREA_EINVAL, "NULL argument");
+  if (rows > (1LL << 31) - 256) return sfail(MOREA_ERANGE, "too many rows");
+  const Parents Q{nullptr, static_cast<const Record*>(parent_cache), parent_of, n_parents};
+  hipLaunchKernelGGL(k_targets, dim3(static_cast<unsigned>((rows + 255) / 256)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), static_cast<const Record*>(cache), s->p->view.n_tets,
+                     static_cast<int>(rows), Q, 1.f / s->h_scale, targets);
   return sdev(hipGetLastError(), "targets");
 }
 
@@ -1028,13 +1193,17 @@ morea_status morea_surrogate_predict_rows(morea_surrogate* s, const float* feats
   return sdev(hipGetLastError(), "predict");
 }
 
-morea_status morea_surrogate_prescreen(morea_surrogate* s, const float* pts, int32_t pop, float* score,
-                                       void* stream) {
-  if (!s || !pts || !score || pop < 0) return sfail(MOREA_EINVAL, "bad argument");
+morea_status morea_surrogate_prescreen(morea_surrogate* s, const float* pts, int32_t pop, const float* parent_pts,
+                                       int32_t n_parents, const void* parent_cache, const int32_t* parent_of,
+                                       float* score, void* stream) {
+  if (!s || pop < 0 || n_parents < 0) return sfail(MOREA_EINVAL, "bad argument");
   if (pop == 0) return MOREA_OK;
+  if (!pts || !score || !parent_of || (n_parents > 0 && (!parent_pts || !parent_cache)))
+    return sfail(MOREA_EINVAL, "NULL argument");
+  const Parents Q{parent_pts, static_cast<const Record*>(parent_cache), parent_of, n_parents};
   const int blocks = std::min<int>(pop, 1024);
   hipLaunchKernelGGL(k_prescreen, dim3(blocks), dim3(256), 0, static_cast<hipStream_t>(stream), s->p->view,
-                     pts, s->ref, s->img_t, s->stats, s->counts, s->params, pop, score);
+                     pts, Q, feature_inputs(s), s->params, pop, score);
   return sdev(hipGetLastError(), "prescreen");
 }
 
@@ -1064,6 +1233,12 @@ morea_status morea_surrogate_set_params(morea_surrogate* s, const float* host_pa
   st = sdev(hipGetLastError(), "refresh");
   if (st == MOREA_OK) st = sdev(hipDeviceSynchronize(), "set params");
   return st;
+}
+
+morea_status morea_surrogate_scale(const morea_surrogate* s, float* h_scale) {
+  if (!s || !h_scale) return sfail(MOREA_EINVAL, "bad argument");
+  *h_scale = s->h_scale;
+  return MOREA_OK;
 }
 
 morea_status morea_surrogate_stats(morea_surrogate* s, float* host_stats, int32_t* host_counts) {

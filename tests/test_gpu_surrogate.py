@@ -134,14 +134,25 @@ def test_gradients_finite_differences_on_gpu(c1_surrogate):
     s.set_params(theta)
 
 
+def family(p, prob, n_parents=2, per_parent=8, seed=None):
+    """Parents and offspring (synth.make_offspring), both evaluated in full:
+    (parents, offspring, parent_of, parent cache, offspring cache) on the
+    GPU."""
+    par, off = synth.make_offspring(p, n_parents=n_parents, per_parent=per_parent, seed=seed)
+    dp, do = torch.from_numpy(par).cuda(), torch.from_numpy(off).cuda()
+    of = torch.arange(n_parents, dtype=torch.int32, device="cuda").repeat_interleave(per_parent)
+    pc, oc = prob.new_cache(len(par)), prob.new_cache(len(off))
+    prob.eval_full(dp, cache=pc)
+    prob.eval_full(do, cache=oc)
+    return dp, do, of, pc, oc
+
+
 def test_training_reduces_loss(c1_surrogate):
     p, prob, s = c1_surrogate
     s.set_params(random_theta(7, scale=0.5))
-    pop = torch.from_numpy(synth.make_population(p)).cuda()
-    cache = prob.new_cache(16)
-    prob.eval_full(pop, cache=cache)
-    X = s.features(pop).reshape(-1, s.n_features).contiguous()
-    t = s.targets(cache, 16).reshape(-1).contiguous()
+    dp, do, of, pc, oc = family(p, prob)
+    X = s.features(do, dp, pc, of).reshape(-1, s.n_features).contiguous()
+    t = s.targets(oc, len(do), pc, len(dp), of).reshape(-1).contiguous()
     loss = torch.empty(1, device="cuda")
     losses = []
     for step in range(300):
@@ -152,38 +163,43 @@ def test_training_reduces_loss(c1_surrogate):
 
 
 def test_features_and_stats(c1_surrogate):
+    """Every input row against the FP64 reference (oracle surrogate_inputs),
+    one offspring moved far outside the image box (clamped samples): the
+    moves within FP32 subtraction, the estimated changes within FP32
+    arithmetic on h values of at most the image range squared (1e-5 of it,
+    over h_scale, plus 1e-4 relative), the parent's terms within the records'
+    parity bar; h_scale to FP32 summation; the statistics are the library's
+    own, checked against the reference by check_stats."""
     p, prob, s = c1_surrogate
     assert s.n_features == mlp.N_IN == 23
-    pop = synth.make_population(p)
-    F = s.features(torch.from_numpy(pop).cuda()).cpu().numpy()
+    dp, do, of, pc, oc = family(p, prob, seed=41)
+    off = do.cpu().numpy()
+    off[0, 1] += np.float32(3.0 * max(p.dims))
+    F = s.features(torch.from_numpy(off).cuda(), dp, pc, of).cpu().numpy().astype(np.float64)
     st, cnt = s.stats()
-    T = pop[:, 1].transpose(0, 2, 1)                      # [pop][P][3]
-    verts = T[:, p.tets]                                  # [pop][tets][4][3] float32
-    coords = (verts - p.ref_points[p.tets]) * 0.25
-    np.testing.assert_allclose(F[..., :12], coords.reshape(len(pop), -1, 12), rtol=1e-6, atol=1e-6)
-    np.testing.assert_array_equal(F[..., 12:20], np.broadcast_to(st, F[..., 12:20].shape))
-    # image samples: the oracle's edge-replicating trilinear is the
-    # interpolant at the point clamped into the box
-    c = ((verts[:, :, 0] + verts[:, :, 1]) + (verts[:, :, 2] + verts[:, :, 3])) * np.float32(0.25)
-    img = p.image_tgt
-    want = np.empty((len(pop), p.n_tets, 3))
-    for k in range(len(pop)):
-        for j in range(p.n_tets):
-            ic = oracle.trilinear(img, c[k, j], clamp=True)
-            iv = [oracle.trilinear(img, verts[k, j, v], clamp=True) for v in range(4)]
-            want[k, j] = [ic, np.mean(iv), max(iv + [ic]) - min(iv + [ic])]
-    scale = float(np.abs(img).max())
-    np.testing.assert_allclose(F[..., 20:], want, rtol=1e-5, atol=1e-5 * scale)
-    # a tet pushed outside the box samples the clamped edge value
-    out = pop[:1].copy()
-    out[0, 1] += np.float32(3.0 * max(p.dims))
-    Fo = s.features(torch.from_numpy(out).cuda()).cpu().numpy()[0]
-    corner = float(img[-1, -1, -1])
-    np.testing.assert_allclose(Fo[:, 20:22], corner, rtol=1e-6, atol=1e-6 * scale)
-    np.testing.assert_allclose(Fo[:, 22], 0.0, atol=1e-6 * scale)
+    op = oracle_problem(1)
+    hs = surrogate_inputs.h_scale(op)
+    np.testing.assert_allclose(s.h_scale, hs, rtol=1e-5)
+    ref_st, _ = surrogate_inputs.region_stats(op)
+    par = dp.cpu().numpy()
+    prec = op.evaluate(par, records=True)["records"]
+    want = surrogate_inputs.features(op, ref_st, off, par, prec, of.cpu().numpy())
+    scale2 = float(np.abs(p.image_tgt).max()) ** 2
+    np.testing.assert_allclose(F[..., :12], want[..., :12], rtol=0, atol=1e-5)
+    np.testing.assert_allclose(F[..., 12:15], want[..., 12:15], rtol=1e-4, atol=1e-5 * scale2 / hs)
+    np.testing.assert_array_equal(F[..., 15:21], np.broadcast_to(st[:, :6], F[..., 15:21].shape))
+    np.testing.assert_allclose(F[..., 21], np.broadcast_to(st[:, 6] / s.h_scale, F[..., 21].shape), rtol=1e-6)
+    np.testing.assert_allclose(F[..., 22], want[..., 22], rtol=1e-5, atol=2e-6 * scale2 / hs)
+    assert np.isfinite(F).all()
+    # an offspring whose parent index is out of range gets a row of NaN
+    bad_of = torch.tensor([0, len(par)], dtype=torch.int32, device="cuda")
+    Fo = s.features(do[:2].contiguous(), dp, pc, bad_of).cpu().numpy()
+    Fg = s.features(do[:2].contiguous(), dp, pc, of[:2].contiguous()).cpu().numpy()
+    np.testing.assert_array_equal(Fo[0], Fg[0])
+    assert np.all(np.isnan(Fo[1]))
     V = int(np.prod(p.dims))
     assert cnt.sum() == V            # the reference mesh tiles the grid exactly
-    check_stats(st, cnt, oracle_problem(1))
+    check_stats(st, cnt, op)
 
 
 def check_stats(st, cnt, op):
@@ -218,19 +234,25 @@ def test_stats_quantized_storage():
 
 
 def test_targets_match_oracle_records(c1_surrogate):
-    """Training targets, (h_S + h_T) / (n_S + n_T) per (candidate, tet), from
-    the full evaluation's cache against the oracle's per-tet records: the
-    records' bound (1e-6 per sample plus 2e-6 relative) divided by the
-    samples."""
+    """Training targets, the offspring's (h_S + h_T) / (n_S + n_T) per tet
+    minus its parent's over h_scale, from the full evaluations' caches against
+    the oracle's per-tet records: twice the records' bound (1e-6 per sample
+    plus 2e-6 relative) divided by the samples, over h_scale; NaN rows for a
+    parent index out of range."""
     p, prob, s = c1_surrogate
-    pop = synth.make_population(p, pop=16, seed=31, perturb_source=True, fold_fraction=0.25)
-    d = torch.from_numpy(pop).cuda()
-    cache = prob.new_cache(16)
-    prob.eval_full(d, cache=cache)
-    t = s.targets(cache, 16).cpu().numpy().reshape(16, p.n_tets).astype(np.float64)
-    want = surrogate_inputs.targets(oracle_problem(1).evaluate(pop, records=True)["records"])
-    np.testing.assert_allclose(t, want, rtol=3e-6, atol=1.5e-6)
-    assert (want > 0).mean() > 0.3
+    dp, do, of, pc, oc = family(p, prob, seed=31)
+    t = s.targets(oc, len(do), pc, len(dp), of).cpu().numpy().astype(np.float64)
+    op = oracle_problem(1)
+    hs = surrogate_inputs.h_scale(op)
+    want = surrogate_inputs.targets(op.evaluate(do.cpu().numpy(), records=True)["records"],
+                                    op.evaluate(dp.cpu().numpy(), records=True)["records"], of.cpu().numpy(), hs)
+    np.testing.assert_allclose(t, want, rtol=6e-6, atol=3e-6 / hs)
+    assert (np.abs(want) > 0).mean() > 0.3
+    bad = of.clone()
+    bad[3] = -1
+    t2 = s.targets(oc, len(do), pc, len(dp), bad).cpu().numpy()
+    assert np.all(np.isnan(t2[3]))
+    np.testing.assert_array_equal(np.delete(t2, 3, axis=0), np.delete(t.astype(np.float32), 3, axis=0))
 
 
 def test_select_and_gather():
@@ -245,14 +267,26 @@ def test_select_and_gather():
 
 
 def test_prescreen_equals_weighted_row_predictions(c1_surrogate):
+    """The fused pre-screen's score is sum_tet w_tet (parent term + h_scale
+    row prediction) / sum_tet w_tet over the same rows built explicitly, w_tet
+    the offspring's source plus target |volume| of the tet (the reference's
+    score form); an offspring without a valid parent scores +inf."""
     p, prob, s = c1_surrogate
     s.set_params(random_theta(9, scale=0.5))
-    pop = torch.from_numpy(synth.make_population(p)).cuda()
-    score = s.prescreen(pop).cpu().numpy()
-    y = s.predict_rows(s.features(pop).reshape(-1, s.n_features).contiguous()).cpu().numpy().reshape(16, -1)
-    _, cnt = s.stats()
-    want = (y * cnt).sum(axis=1) / cnt.sum()
+    dp, do, of, pc, oc = family(p, prob, seed=43)
+    score = s.prescreen(do, dp, pc, of).cpu().numpy()
+    F = s.features(do, dp, pc, of)
+    y = s.predict_rows(F.reshape(-1, s.n_features).contiguous()).cpu().numpy().astype(np.float64)
+    y = y.reshape(len(do), -1)
+    op = oracle_problem(1)
+    prec = op.evaluate(dp.cpu().numpy(), records=True)["records"]
+    want = surrogate_inputs.score(op, do.cpu().numpy(), prec, of.cpu().numpy(), y * s.h_scale / surrogate_inputs.h_scale(op))
     np.testing.assert_allclose(score, want, rtol=1e-4, atol=1e-6)
+    bad = of.clone()
+    bad[5] = len(dp)
+    score2 = s.prescreen(do, dp, pc, bad).cpu().numpy()
+    assert score2[5] == np.inf
+    np.testing.assert_array_equal(np.delete(score2, 5), np.delete(score, 5))
 
 
 def spearman(a, b):
@@ -262,19 +296,19 @@ def spearman(a, b):
 
 
 def test_surrogate_gain_config5():
-    """4,096 offspring of 512 parents (source fixed), exact budget 512.
-    Trained on ~1 M exact per-tet targets of other candidates, the surrogate's
-    selection must beat a random selection of the same size."""
+    """Offspring of 512 parents, 8 each (source fixed, the parents evaluated
+    exactly), exact budget 512 of the 4,096.  Trained on ~1 M exact per-tet
+    changes of 37 other families, the surrogate's ranking, on three batches
+    drawn with different seeds, must correlate with the exact f_int (Spearman
+    rho >= 0.5), its 512 must close at least half of the gap between the
+    batch mean (the expected value of a random 512) and the true best 512, and
+    it must beat ranking by the parent's exact f_int alone."""
     p = synth_problem(5)
     prob = morea.Problem.from_synth(p, max_population=4096)
     s = morea.Surrogate(prob, max_rows=8192, seed=11)
-    # training data: 296 candidates drawn like the offspring, other seeds
-    _, train = synth.make_offspring(p, n_parents=37, per_parent=8, seed=105)
-    tr = torch.from_numpy(train).cuda()
-    cache = prob.new_cache(len(train))
-    prob.eval_full(tr, cache=cache)
-    X = s.features(tr).reshape(-1, s.n_features).contiguous()
-    t = s.targets(cache, len(train)).reshape(-1).contiguous()
+    dp, do, of, pc, oc = family(p, prob, n_parents=37, per_parent=8, seed=105)
+    X = s.features(do, dp, pc, of).reshape(-1, s.n_features).contiguous()
+    t = s.targets(oc, len(do), pc, len(dp), of).reshape(-1).contiguous()
     n = t.numel()
     assert n > 1_000_000
     g = torch.Generator(device="cpu").manual_seed(0)
@@ -283,21 +317,24 @@ def test_surrogate_gain_config5():
         for b in range(0, n - 8191, 8192):
             sel = perm[b:b + 8192]
             s.train_step(X[sel].contiguous(), t[sel].contiguous(), 2e-3 if epoch < 6 else 5e-4)
-    # the offspring batch
-    _, off = synth.make_offspring(p)
-    offs = torch.from_numpy(off).cuda()
-    exact = prob.eval_full(offs)
-    f = exact["obj"][:, 0].cpu().numpy().astype(np.float64)
-    score = s.prescreen(offs)
-    idx, chosen = morea.morea_surrogate_select(score, 512, offs)
-    idx = idx.cpu().numpy()
-    f_sel = morea.Problem.from_synth(p, max_population=512).eval_full(chosen)["obj"][:, 0].cpu().numpy()
-    np.testing.assert_allclose(f_sel, f[idx], rtol=1e-6)
-    rnd = np.random.default_rng(0).choice(len(f), 512, replace=False)
-    best = np.argsort(f)[:512]
-    m_sur, m_rnd, m_best = f[idx].mean(), f[rnd].mean(), f[best].mean()
-    rho = spearman(score.cpu().numpy(), f)
-    overlap = len(set(idx.tolist()) & set(best.tolist())) / 512
-    print(f"surrogate {m_sur:.6f} random {m_rnd:.6f} best {m_best:.6f} rho {rho:.3f} overlap {overlap:.3f}")
-    assert rho > 0.2
-    assert m_rnd - m_sur > 0.2 * (m_rnd - m_best)
+    del X, t, oc
+    prob512 = morea.Problem.from_synth(p, max_population=512)
+    for seed in (5, 205, 305):
+        dp, do, of, pc, _ = family(p, prob, n_parents=512, per_parent=8, seed=seed)
+        f = prob.eval_full(do)["obj"][:, 0].cpu().numpy().astype(np.float64)
+        fp = prob.eval_full(dp)["obj"][:, 0].cpu().numpy().astype(np.float64)
+        score = s.prescreen(do, dp, pc, of)
+        idx, chosen = morea.morea_surrogate_select(score, 512, do)
+        idx = idx.cpu().numpy()
+        f_sel = prob512.eval_full(chosen)["obj"][:, 0].cpu().numpy()
+        np.testing.assert_allclose(f_sel, f[idx], rtol=1e-6)
+        best = np.argsort(f)[:512]
+        by_parent = np.argsort(fp[of.cpu().numpy()], kind="stable")[:512]
+        m_sur, m_all, m_best, m_par = f[idx].mean(), f.mean(), f[best].mean(), f[by_parent].mean()
+        rho = spearman(score.cpu().numpy(), f)
+        gap = (m_all - m_sur) / (m_all - m_best)
+        print(f"seed {seed}: surrogate {m_sur:.6f} batch mean {m_all:.6f} best {m_best:.6f} "
+              f"parent-only {m_par:.6f} rho {rho:.3f} gap closed {gap:.3f}", flush=True)
+        assert rho >= 0.5
+        assert gap >= 0.5
+        assert m_sur < m_par
