@@ -584,8 +584,9 @@ int32_t morea_surrogate_num_features(void);   /* 23 inputs per row */
 
 /* Create a surrogate for problem p (which must outlive it): He-normal
  * weights from `seed`, zero Adam state, the per-tet statistics of the
- * reference mesh, h_scale, padded FP32 copies of I_s and I_t (whatever the
- * problem's image storage), and a training workspace for batches of up to max_rows rows.
+ * reference mesh, h_scale, FP32 copies of I_s and I_t (whatever the
+ * problem's image storage; 16 bytes per padded voxel, the four voxels of a
+ * cell face read by one aligned load), and a training workspace for batches of up to max_rows rows.
  * Synchronous.  Errors: MOREA_EINVAL, MOREA_ENOMEM, MOREA_EDEVICE. */
 morea_status morea_surrogate_create(morea_problem *p, int32_t max_rows, uint64_t seed,
                                     morea_surrogate **out);
@@ -628,8 +629,13 @@ morea_status morea_surrogate_predict_rows(morea_surrogate *s, const float *feats
                                           float *pred, void *stream);
 
 /* Pre-screen: score [pop] of offspring pts [pop][2][3][n_points] with their
- * parents as for morea_surrogate_features (features built on the fly; one
- * launch); an offspring without a valid parent scores +inf. */
+ * parents as for morea_surrogate_features (features built on the fly: one
+ * launch for the parents' point means, one for the offspring); an offspring
+ * without a valid parent scores +inf.  The parents' point means go to a
+ * workspace of the surrogate (16 bytes per (parent, tet)), allocated again
+ * (hipMalloc, after waiting for the device) when a call needs more than
+ * every earlier one; calls on one surrogate that overlap on different
+ * streams race on it. */
 morea_status morea_surrogate_prescreen(morea_surrogate *s, const float *pts, int32_t pop, const float *parent_pts,
                                        int32_t n_parents, const void *parent_cache, const int32_t *parent_of,
                                        float *score, void *stream);

@@ -174,13 +174,15 @@ struct Parents {
   int n;
 };
 
-// Trilinear interpolant of a padded FP32 image copy `img` (voxel (i, j, k)
-// at (k + 1) pxy + (j + 1) px + i + 1) at (x, y, z) clamped into [0, n - 1]
-// on each axis.  The cell is the one below the point, capped at n - 2, so the
-// upper corner always lies in the volume or, for an axis of size 1, on its
-// zero border with weight 0.
-__device__ __forceinline__ float sample_clamped(const ProblemView& P, const float* img, float x, float y, float z) {
-  const float q[3] = {fminf(fmaxf(x, 0.f), static_cast<float>(P.nx - 1)),
+// Trilinear interpolant at (x, y, z) clamped into [0, n - 1] on each axis,
+// from a quad copy `q` of a padded image (entry e holds the FP32 voxels e,
+// e + 1, e + px, e + px + 1 of the padded volume, voxel (i, j, k) at
+// (k + 1) pxy + (j + 1) px + i + 1), so a sample reads two aligned 16-byte
+// entries instead of eight scattered values.  The cell is the one below the
+// point, capped at n - 2, so the upper corner always lies in the volume or,
+// for an axis of size 1, on its zero border with weight 0.
+__device__ __forceinline__ float sample_clamped(const ProblemView& P, const float4* q, float x, float y, float z) {
+  const float p[3] = {fminf(fmaxf(x, 0.f), static_cast<float>(P.nx - 1)),
                       fminf(fmaxf(y, 0.f), static_cast<float>(P.ny - 1)),
                       fminf(fmaxf(z, 0.f), static_cast<float>(P.nz - 1))};
   const int n[3] = {P.nx, P.ny, P.nz};
@@ -188,13 +190,13 @@ __device__ __forceinline__ float sample_clamped(const ProblemView& P, const floa
   float f[3];
 #pragma unroll
   for (int a = 0; a < 3; a++) {
-    c[a] = max(min(static_cast<int>(floorf(q[a])), n[a] - 2), 0);
-    f[a] = q[a] - static_cast<float>(c[a]);
+    c[a] = max(min(static_cast<int>(floorf(p[a])), n[a] - 2), 0);
+    f[a] = p[a] - static_cast<float>(c[a]);
   }
-  const float* b = img + static_cast<size_t>(c[2] + 1) * P.pxy + static_cast<size_t>(c[1] + 1) * P.px + c[0] + 1;
-  const float* b1 = b + P.pxy;
-  const float x00 = fmaf(f[0], b[1] - b[0], b[0]), x10 = fmaf(f[0], b[P.px + 1] - b[P.px], b[P.px]);
-  const float x01 = fmaf(f[0], b1[1] - b1[0], b1[0]), x11 = fmaf(f[0], b1[P.px + 1] - b1[P.px], b1[P.px]);
+  const size_t e = static_cast<size_t>(c[2] + 1) * P.pxy + static_cast<size_t>(c[1] + 1) * P.px + c[0] + 1;
+  const float4 b = q[e], b1 = q[e + P.pxy];
+  const float x00 = fmaf(f[0], b.y - b.x, b.x), x10 = fmaf(f[0], b.w - b.z, b.z);
+  const float x01 = fmaf(f[0], b1.y - b1.x, b1.x), x11 = fmaf(f[0], b1.w - b1.z, b1.z);
   const float y0 = fmaf(f[1], x10 - x00, x00), y1 = fmaf(f[1], x11 - x01, x01);
   return fmaf(f[2], y1 - y0, y0);
 }
@@ -211,7 +213,7 @@ __device__ __forceinline__ void tet_vertices(const ProblemView& P, const float* 
 }
 
 // h at barycentric coordinates l of the tet: (I_s(S l) - I_t(T l))^2.
-__device__ __forceinline__ float h_at(const ProblemView& P, const float* img_s, const float* img_t,
+__device__ __forceinline__ float h_at(const ProblemView& P, const float4* img_s, const float4* img_t,
                                       const float S[4][3], const float T[4][3], const float l[4]) {
   float x[3], y[3];
 #pragma unroll
@@ -223,18 +225,16 @@ __device__ __forceinline__ float h_at(const ProblemView& P, const float* img_s, 
   return d * d;
 }
 
-// Means of h over the tet's point sets in one candidate: m[0] the 4
-// vertices, m[1] the 6 edge midpoints, m[2] the 16 interior points `bary`.
-__device__ __forceinline__ void point_means(const ProblemView& P, const float* img_s, const float* img_t,
-                                            const float* cand, int tet, const float4* bary, float m[3]) {
-  float S[4][3], T[4][3];
-  tet_vertices(P, cand, tet, 0, S);
-  tet_vertices(P, cand, tet, 1, T);
-  // one point at a time (the same point in every lane): 4 vertices, the
-  // edges (0,1) (0,2) (0,3) (1,2) (1,3) (2,3), then the interior points
-  float sv = 0.f, se = 0.f, sr = 0.f;
+// Sums of h over points [j0, j1) of a tet's 26 (the 4 vertices, the edge
+// midpoints (0,1) (0,2) (0,3) (1,2) (1,3) (2,3), then the 16 interior points
+// `bary`) into acc: [0] vertices, [1] edges, [2] interior.  One point at a
+// time.
+__device__ __forceinline__ void point_sums(const ProblemView& P, const float4* img_s, const float4* img_t,
+                                           const float S[4][3], const float T[4][3], const float4* bary, int j0,
+                                           int j1, float acc[3]) {
+  acc[0] = acc[1] = acc[2] = 0.f;
 #pragma unroll 1
-  for (int j = 0; j < 10 + kHalton; j++) {
+  for (int j = j0; j < j1; j++) {
     float l[4] = {0.f, 0.f, 0.f, 0.f};
     if (j < 4) {
       l[0] = j == 0 ? 1.f : 0.f;
@@ -253,13 +253,32 @@ __device__ __forceinline__ void point_means(const ProblemView& P, const float* i
       l[3] = q.w;
     }
     const float hv = h_at(P, img_s, img_t, S, T, l);
-    if (j < 4) sv += hv;
-    else if (j < 10) se += hv;
-    else sr += hv;
+    acc[j < 4 ? 0 : (j < 10 ? 1 : 2)] += hv;
   }
-  m[0] = sv * 0.25f;
-  m[1] = se * (1.f / 6.f);
-  m[2] = sr * (1.f / kHalton);
+}
+
+// The points are summed in two parts, [0, 13) and [13, 26), added at the end:
+// the pre-screen splits them over two lane halves in the same way, so both
+// paths give the same values.
+constexpr int kPointSplit = 13, kPoints = 10 + kHalton;
+
+__device__ __forceinline__ void combine_means(const float a[3], const float b[3], float m[3]) {
+  m[0] = (a[0] + b[0]) * 0.25f;
+  m[1] = (a[1] + b[1]) * (1.f / 6.f);
+  m[2] = (a[2] + b[2]) * (1.f / kHalton);
+}
+
+// Means of h over the tet's point sets in one candidate: m[0] the 4
+// vertices, m[1] the 6 edge midpoints, m[2] the 16 interior points.
+__device__ __forceinline__ void point_means(const ProblemView& P, const float4* img_s, const float4* img_t,
+                                            const float* cand, int tet, const float4* bary, float m[3]) {
+  float S[4][3], T[4][3];
+  tet_vertices(P, cand, tet, 0, S);
+  tet_vertices(P, cand, tet, 1, T);
+  float a[3], b[3];
+  point_sums(P, img_s, img_t, S, T, bary, 0, kPointSplit, a);
+  point_sums(P, img_s, img_t, S, T, bary, kPointSplit, kPoints, b);
+  combine_means(a, b, m);
 }
 
 // |signed volume| of a tet's source and target (voxel^3): the expected
@@ -291,18 +310,27 @@ __device__ __forceinline__ float tet_mean_h(const Record* rec, int tet) {
   return n ? (a.h + b.h) / static_cast<float>(n) : 0.f;
 }
 
-// Padded FP32 copy of image `which` (0 source, 1 target; any storage).
+// Value of stored voxel e of image `which` as FP32 (0 beyond the volume).
 template <int ST>
-__global__ void k_image_f32(ProblemView P, int which, float* out) {
-  const size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= P.pvox) return;
+__device__ __forceinline__ float stored_voxel(const ProblemView& P, int which, size_t e) {
+  if (e >= P.pvox) return 0.f;
   if constexpr (ST == kF32) {
-    out[i] = static_cast<const float*>(P.img[which])[i];
+    return static_cast<const float*>(P.img[which])[e];
   } else if constexpr (ST == kBF16) {
-    out[i] = bf2f(static_cast<const bf16*>(P.img[which])[i]);
+    return bf2f(static_cast<const bf16*>(P.img[which])[e]);
   } else {
-    out[i] = static_cast<float>(static_cast<const _Float16*>(P.img[which])[i]);
+    return static_cast<float>(static_cast<const _Float16*>(P.img[which])[e]);
   }
+}
+
+// Quad copy of image `which` (0 source, 1 target; any storage): entry e
+// holds the padded voxels e, e + 1, e + px, e + px + 1 as FP32.
+template <int ST>
+__global__ void k_image_quads(ProblemView P, int which, float4* out) {
+  const size_t e = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= P.pvox) return;
+  out[e] = make_float4(stored_voxel<ST>(P, which, e), stored_voxel<ST>(P, which, e + 1),
+                       stored_voxel<ST>(P, which, e + P.px), stored_voxel<ST>(P, which, e + P.px + 1));
 }
 
 template <int ST>
@@ -404,20 +432,22 @@ __global__ void k_tet_stats(ProblemView P, const float* ref, float* stats, int* 
 
 // Images and constants the features read.
 struct FeatureInputs {
-  const float* img_s;   // padded FP32 copies of the two images
-  const float* img_t;
+  const float4* img_s;  // quad copies of the two images
+  const float4* img_t;
   const float4* bary;   // [16] interior points, barycentric
   const float* stats;   // [n_tets][8]
   float h_scale;
   float inv_h;          // 1 / h_scale
 };
 
-// One thread per (offspring, tet) row: the 23 features in order.
+// One thread per (offspring, tet) row: the 23 features in order.  Threads in
+// tet-major order, so that the threads in flight read the same part of the
+// images.
 __global__ void k_features(ProblemView P, const float* pts, Parents Q, FeatureInputs F, int pop, float* feats) {
-  const long long row = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (row >= static_cast<long long>(pop) * P.n_tets) return;
-  const int cand = static_cast<int>(row / P.n_tets), tet = static_cast<int>(row % P.n_tets);
-  float* o = feats + static_cast<size_t>(row) * kIn;
+  const long long r = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= static_cast<long long>(pop) * P.n_tets) return;
+  const int tet = static_cast<int>(r / pop), cand = static_cast<int>(r % pop);
+  float* o = feats + (static_cast<size_t>(cand) * P.n_tets + tet) * kIn;
   const int par = Q.of[cand];
   if (par < 0 || par >= Q.n) {   // no parent: the row has no features
     for (int k = 0; k < kIn; k++) o[k] = __builtin_nanf("");
@@ -459,6 +489,18 @@ __global__ void k_targets(const Record* rec, int n_tets, int rows, Parents Q, fl
           tet_mean_h(Q.rec + static_cast<size_t>(par) * n_tets * 2, tet)) * inv_h;
 }
 
+// Point means of every (parent, tet): out [n][n_tets] (m0, m1, m2, 0).
+// Threads in tet-major order, so that the threads in flight read the same
+// part of the images.
+__global__ void k_parent_means(ProblemView P, const float* pts, int n, FeatureInputs F, float4* out) {
+  const long long r = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= static_cast<long long>(n) * P.n_tets) return;
+  const int tet = static_cast<int>(r / n), cand = static_cast<int>(r % n);
+  float m[3];
+  point_means(P, F.img_s, F.img_t, pts + static_cast<size_t>(cand) * 6 * P.n_points, tet, F.bary, m);
+  out[static_cast<size_t>(cand) * P.n_tets + tet] = make_float4(m[0], m[1], m[2], 0.f);
+}
+
 // ------------------------------------------------------------ prescreen
 // The pre-screen runs both dense layers transposed, Z^T = W X^T, on
 // v_mfma_f32_32x32x16_bf16 (BF16 operands, FP32 accumulation): the weights
@@ -477,6 +519,7 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef unsigned u4v __attribute__((ext_vector_type(4)));
 
 constexpr int kPreIn = 32;                 // features padded: 23 + three constant 1s + zeros
+constexpr int kTetRun = 8;                 // tets per pre-screen work item
 constexpr int kW1Row = kPreIn + 8;         // LDS row strides padded against bank conflicts
 constexpr int kW2Row = kHid + 8;
 
@@ -511,9 +554,9 @@ __device__ __forceinline__ bf8 pack8(const float v[8]) {
 // the samples the tet contributes in the two directions).  Blocks of 4 waves loop over candidates; each wave takes tiles of
 // 32 tets; fixed-order reductions.
 __global__ __launch_bounds__(256, 3) void k_prescreen(ProblemView P, const float* pts, Parents Q, FeatureInputs F,
-                                                    const float* params, int pop, float* score) {
+                                                    const float4* pmeans, const float* params, int pop,
+                                                    float2* partial) {
   __shared__ PreLds N;
-  __shared__ float wsum[4], wcnt[4];
   for (int e = threadIdx.x; e < kHid * kPreIn; e += blockDim.x) {
     const int j = e / kPreIn, k = e % kPreIn;
     if (k < kIn) {
@@ -538,35 +581,50 @@ __global__ __launch_bounds__(256, 3) void k_prescreen(ProblemView P, const float
   const float b3 = params[oB3];
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = lane_id(), i = lane & 31, h = lane >> 5;
-  const int n_tiles = (P.n_tets + kRowTile - 1) / kRowTile;
-  for (int cand = blockIdx.x; cand < pop; cand += gridDim.x) {
-    const int par = Q.of[cand];
-    if (par < 0 || par >= Q.n) {   // no parent: never preferred
-      if (threadIdx.x == 0) score[cand] = INFINITY;
-      continue;
-    }
-    const float* cp = pts + static_cast<size_t>(cand) * 6 * P.n_points;
-    const float* pp = Q.pts + static_cast<size_t>(par) * 6 * P.n_points;
-    const Record* prec = Q.rec + static_cast<size_t>(par) * P.n_tets * 2;
+  const int n_groups = (pop + kRowTile - 1) / kRowTile;
+  const int n_runs = (P.n_tets + kTetRun - 1) / kTetRun;
+  const long long n_items = static_cast<long long>(n_runs) * n_groups;
+  const long long n_waves = static_cast<long long>(gridDim.x) * 4;
+  // work items (run of kTetRun tets, group of 32 offspring), run-major, one
+  // per wave at a time: a tile of the network is one tet of 32 offspring, so
+  // the lanes of a wave read nearly the same image positions and the waves
+  // in flight share a few runs of tets
+  for (long long w = static_cast<long long>(blockIdx.x) * 4 + wave; w < n_items; w += n_waves) {
+    const int run = static_cast<int>(w / n_groups), grp = static_cast<int>(w % n_groups);
+    const int cand = grp * kRowTile + i;
+    const int par = cand < pop ? Q.of[cand] : -1;
+    const bool ok = par >= 0 && par < Q.n;   // no parent: scored by the reduction
+    const float* cp = pts + static_cast<size_t>(ok ? cand : 0) * 6 * P.n_points;
+    const float* pp = Q.pts + static_cast<size_t>(ok ? par : 0) * 6 * P.n_points;
+    const Record* prec = Q.rec + static_cast<size_t>(ok ? par : 0) * P.n_tets * 2;
+    const float4* pmr = pmeans + static_cast<size_t>(ok ? par : 0) * P.n_tets;
     float acc_s = 0.f, cnt = 0.f;
-    for (int tile = wave; tile < n_tiles; tile += 4) {
-      const int tet = tile * kRowTile + i;
+    const int t_end = min(P.n_tets, (run + 1) * kTetRun);
+    for (int tet = run * kTetRun; tet < t_end; tet++) {
       // this lane's half of the tet's features (natural order: 12 vertex
       // moves, 3 estimated changes, 7 statistics, the parent's mean term,
       // three constant 1s, zeros): h = 0 holds features 0..7 and 16..23,
-      // h = 1 features 8..15 and 24..31.  The point means behind the
-      // estimated changes are split over the halves (h = 0 the offspring's,
-      // h = 1 the parent's) and combined in the upper half.
+      // h = 1 features 8..15 and 24..31.  The offspring's 26 points behind
+      // the estimated changes are split over the halves (h = 0 points
+      // 0..12, h = 1 points 13..25) and combined in the upper half, which
+      // subtracts the parent's means computed beforehand.
       float f0[8], f1[8];
 #pragma unroll
       for (int k = 0; k < 8; k++) f0[k] = f1[k] = 0.f;
-      float m[3] = {0.f, 0.f, 0.f};
+      float acc[3] = {0.f, 0.f, 0.f};
       float pterm = 0.f, wt = 0.f;
-      if (tet < P.n_tets) {
-        point_means(P, F.img_s, F.img_t, h == 0 ? cp : pp, tet, F.bary, m);
+      float4 pm = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (ok) {
         float d[4][3], dp[4][3];
         tet_vertices(P, cp, tet, 1, d);
         tet_vertices(P, pp, tet, 1, dp);
+        {
+          float sv[4][3];
+          tet_vertices(P, cp, tet, 0, sv);
+          point_sums(P, F.img_s, F.img_t, sv, d, F.bary, h == 0 ? 0 : kPointSplit, h == 0 ? kPointSplit : kPoints,
+                     acc);
+        }
+        if (h == 1) pm = pmr[tet];
         if (h == 0) {
 #pragma unroll
           for (int k = 0; k < 8; k++) {
@@ -591,12 +649,14 @@ __global__ __launch_bounds__(256, 3) void k_prescreen(ProblemView P, const float
         }
       }
       {
-        float mo[3];
+        float lo[3], m[3];
 #pragma unroll
-        for (int k = 0; k < 3; k++) mo[k] = __shfl_xor(m[k], 32, 64);
+        for (int k = 0; k < 3; k++) lo[k] = __shfl_xor(acc[k], 32, 64);
         if (h == 1) {
-#pragma unroll
-          for (int k = 0; k < 3; k++) f0[4 + k] = (mo[k] - m[k]) * F.inv_h;
+          combine_means(lo, acc, m);
+          f0[4] = (m[0] - pm.x) * F.inv_h;
+          f0[5] = (m[1] - pm.y) * F.inv_h;
+          f0[6] = (m[2] - pm.z) * F.inv_h;
         }
       }
       const bf8 xb0 = pack8(f0), xb1 = pack8(f1);
@@ -632,28 +692,33 @@ __global__ __launch_bounds__(256, 3) void k_prescreen(ProblemView P, const float
           part = fmaf(fmaxf(z[r], 0.f), N.w3[32 * n + 8 * (r >> 2) + 4 * h + (r & 3)], part);
       }
       const float y = part + __shfl_xor(part, 32, 64) + b3;   // the two halves hold different units
-      if (h == 0 && tet < P.n_tets) {
+      if (h == 0 && ok) {
         // the parent's exact term plus the predicted change, weighted by the
         // offspring's expected samples of the tet
         acc_s = fmaf(wt, fmaf(y, F.h_scale, pterm), acc_s);
         cnt += wt;
       }
     }
-    for (int d = 32; d >= 1; d >>= 1) {
-      acc_s += __shfl_xor(acc_s, d, 64);
-      cnt += __shfl_xor(cnt, d, 64);
-    }
-    if (lane == 0) {
-      wsum[wave] = acc_s;
-      wcnt[wave] = cnt;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      const float c = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
-      score[cand] = c > 0.f ? (wsum[0] + wsum[1] + wsum[2] + wsum[3]) / c : 0.f;
-    }
-    __syncthreads();
+    if (h == 0 && cand < pop) partial[static_cast<size_t>(run) * pop + cand] = make_float2(acc_s, cnt);
   }
+}
+
+// Scores from the per-(run, offspring) partial sums, added in run order.
+__global__ void k_prescreen_reduce(const float2* partial, int n_runs, int pop, Parents Q, float* score) {
+  const int cand = blockIdx.x * blockDim.x + threadIdx.x;
+  if (cand >= pop) return;
+  const int par = Q.of[cand];
+  if (par < 0 || par >= Q.n) {   // no parent: never preferred
+    score[cand] = INFINITY;
+    return;
+  }
+  float a = 0.f, c = 0.f;
+  for (int t = 0; t < n_runs; t++) {
+    const float2 v = partial[static_cast<size_t>(t) * pop + cand];
+    a += v.x;
+    c += v.y;
+  }
+  score[cand] = c > 0.f ? a / c : 0.f;
 }
 
 // Predictions for explicit feature rows (one wave per 32 rows).
@@ -940,10 +1005,12 @@ struct morea_surrogate {
   float* stats = nullptr;
   int* counts = nullptr;
   float* ref = nullptr;
-  float* img_s = nullptr;   // padded FP32 copies of the source and target images
-  float* img_t = nullptr;
+  float4* img_s = nullptr;  // quad copies of the source and target images
+  float4* img_t = nullptr;
   float4* bary = nullptr;   // [16] interior sample points of a tet, barycentric
   float h_scale = 1.f;      // mean of (I_s - I_t)^2 over the grid (1 when 0)
+  void* work = nullptr;     // pre-screen workspace: the parents' point means,
+  size_t work_cap = 0;      // then the per-(tile, offspring) partial sums (bytes)
   TrainBuf tb{};
   int steps = 0;
   std::vector<void*> allocs;
@@ -992,11 +1059,11 @@ hipError_t launch_image_copies(morea_surrogate* s) {
   const ProblemView& P = s->p->view;
   const dim3 grid((P.pvox + 255) / 256);
   for (int which = 0; which < 2; which++) {
-    float* out = which ? s->img_t : s->img_s;
+    float4* out = which ? s->img_t : s->img_s;
     switch (s->p->storage) {
-      case kF32: hipLaunchKernelGGL(k_image_f32<kF32>, grid, dim3(256), 0, 0, P, which, out); break;
-      case kBF16: hipLaunchKernelGGL(k_image_f32<kBF16>, grid, dim3(256), 0, 0, P, which, out); break;
-      default: hipLaunchKernelGGL(k_image_f32<kF16>, grid, dim3(256), 0, 0, P, which, out); break;
+      case kF32: hipLaunchKernelGGL(k_image_quads<kF32>, grid, dim3(256), 0, 0, P, which, out); break;
+      case kBF16: hipLaunchKernelGGL(k_image_quads<kBF16>, grid, dim3(256), 0, 0, P, which, out); break;
+      default: hipLaunchKernelGGL(k_image_quads<kF16>, grid, dim3(256), 0, 0, P, which, out); break;
     }
   }
   return hipGetLastError();
@@ -1084,8 +1151,8 @@ morea_status morea_surrogate_create(morea_problem* p, int32_t max_rows, uint64_t
   ok(salloc(s, &s->tb.wpart, sizeof(float) * kWavePart * static_cast<size_t>(bmax / kRowTile + 4)));
   ok(salloc(s, &s->tb.gpart, sizeof(float) * kSplitK * kGradTiles * 1024));
   ok(salloc(s, &s->ref, sizeof(float) * 3 * p->view.n_points));
-  ok(salloc(s, &s->img_s, sizeof(float) * static_cast<size_t>(p->view.pvox)));
-  ok(salloc(s, &s->img_t, sizeof(float) * static_cast<size_t>(p->view.pvox)));
+  ok(salloc(s, &s->img_s, sizeof(float4) * static_cast<size_t>(p->view.pvox)));
+  ok(salloc(s, &s->img_t, sizeof(float4) * static_cast<size_t>(p->view.pvox)));
   ok(salloc(s, &s->bary, sizeof(float4) * kHalton));
   float* ref_dev = s->ref;
   if (st == MOREA_OK) {
@@ -1139,6 +1206,7 @@ void morea_surrogate_destroy(morea_surrogate* s) {
   if (!s) return;
   (void)hipDeviceSynchronize();
   for (void* a : s->allocs) (void)hipFree(a);
+  if (s->work) (void)hipFree(s->work);
   delete s;
 }
 
@@ -1200,10 +1268,33 @@ morea_status morea_surrogate_prescreen(morea_surrogate* s, const float* pts, int
   if (pop == 0) return MOREA_OK;
   if (!pts || !score || !parent_of || (n_parents > 0 && (!parent_pts || !parent_cache)))
     return sfail(MOREA_EINVAL, "NULL argument");
+  const ProblemView& P = s->p->view;
+  const int n_runs = (P.n_tets + kTetRun - 1) / kTetRun;
+  const size_t rows = static_cast<size_t>(n_parents) * P.n_tets;
+  const size_t pm_bytes = (sizeof(float4) * rows + 255) / 256 * 256;
+  const size_t need = pm_bytes + sizeof(float2) * static_cast<size_t>(n_runs) * pop;
+  if (need > s->work_cap) {   // grow the workspace (hipFree waits for the device)
+    if (s->work) (void)hipFree(s->work);
+    s->work = nullptr;
+    s->work_cap = 0;
+    void* d = nullptr;
+    const hipError_t e = hipMalloc(&d, need);
+    if (e != hipSuccess) return sfail(MOREA_ENOMEM, "hipMalloc(%zu): %s", need, hipGetErrorString(e));
+    s->work = d;
+    s->work_cap = need;
+  }
+  float4* pmeans = static_cast<float4*>(s->work);
+  float2* partial = reinterpret_cast<float2*>(static_cast<char*>(s->work) + pm_bytes);
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  const FeatureInputs F = feature_inputs(s);
+  if (rows > 0)
+    hipLaunchKernelGGL(k_parent_means, dim3(static_cast<unsigned>((rows + 255) / 256)), dim3(256), 0, st, P,
+                       parent_pts, n_parents, F, pmeans);
   const Parents Q{parent_pts, static_cast<const Record*>(parent_cache), parent_of, n_parents};
-  const int blocks = std::min<int>(pop, 1024);
-  hipLaunchKernelGGL(k_prescreen, dim3(blocks), dim3(256), 0, static_cast<hipStream_t>(stream), s->p->view,
-                     pts, Q, feature_inputs(s), s->params, pop, score);
+  const long long items = static_cast<long long>(n_runs) * ((pop + kRowTile - 1) / kRowTile);
+  const int blocks = static_cast<int>(std::min<long long>((items + 3) / 4, 768));
+  hipLaunchKernelGGL(k_prescreen, dim3(blocks), dim3(256), 0, st, P, pts, Q, F, pmeans, s->params, pop, partial);
+  hipLaunchKernelGGL(k_prescreen_reduce, dim3((pop + 255) / 256), dim3(256), 0, st, partial, n_runs, pop, Q, score);
   return sdev(hipGetLastError(), "prescreen");
 }
 
