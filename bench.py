@@ -446,6 +446,14 @@ def form_generation(p, pop_np, prob_full_ms, steps):
     ms_eval = timed(evaluate_only, steps, 1)
     ms = timed(generation, steps, 1)
     n_evals = sum(len(b["ep"]) for b in batches)
+    # samples re-evaluated by one generation's partial evaluations, counted on
+    # the current parents (evaluate_only leaves them unchanged)
+    evaluate_only()
+    rec = prob.cache_records(cache, npop)
+    rec_n = rec["n"].astype(np.int64).sum(axis=2)
+    parent_counts = par_out["counts"].cpu().numpy()
+    samples = sum(resampled(p, rec_n, off, gpts, b["ep"], b["eg"], b["out"]["counts"].cpu().numpy(), parent_counts)
+                  for b in batches)
     return {"workload": f"{len(elements)} FOS elements (set-cover edges) in {n_colors} colours, {npop} solutions, "
                         f"selection of {sel_size} in {k} clusters: {n_evals} sampled children, partial evaluations "
                         f"and acceptances per generation, archive of {archive.shape[0]}",
@@ -453,6 +461,7 @@ def form_generation(p, pop_np, prob_full_ms, steps):
             "ms_per_generation": ms, "timing_ms": ms.spread(), "ms_evaluations_only": ms_eval,
             "ms_select_estimate_and_sample": ms_mix, "selected_first_generation": int(sc["n_selected"][0]), "ms_acceptance": ms - ms_eval - ms_mix,
             "children_per_s": n_evals / (ms * 1e-3),
+            "samples_per_generation": samples, "alu_evaluations": alu(samples, ms_eval),
             "steering_guidance_max": gmax, "accepted_first_generation": kept, "parents_changed_first_generation": int(len(moved)),
             "vs_plain_full_evals_per_s": n_evals / (ms * 1e-3) / (npop / (prob_full_ms * 1e-3)),
             "parity": {"evals": idx, "samples_bit_exact": bit_exact, "counts_flags_exact": exact,
