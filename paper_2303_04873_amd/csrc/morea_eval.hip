@@ -128,9 +128,15 @@ __device__ __forceinline__ int64_t det_i64(const int v[4][3]) {
 //   s_i + lex_i = A_i j + PY_i yr + PZ_i zr + B0_i      (exact integers)
 // and the mapped point is q = qlo + M (p - lo).
 struct DirConst {
-  double A[4], PY[4], PZ[4], B0[4];            // exact in FP64 when the extent is <= 2^16
+  union {
+    struct {
+      double A[4], PY[4], PZ[4], B0[4];        // exact in FP64 when the extent is <= 2^16
+    };
+    struct {
+      long long Ai[4], PYi[4], PZi[4], B0i[4]; // int64 form for wider tets (fast == 0)
+    };
+  };
   double invA[4];
-  long long Ai[4], PYi[4], PZi[4], B0i[4];     // int64 copies for wider tets
   // x position of face i's plane on row (yr, zr): t_i = TA yr + TB zr + TG
   // (= -(PY yr + PZ zr + B0) / A); for a face with A = 0 the same three
   // numbers hold PY, PZ, B0 (so "t" is the face value itself).  TE bounds the
@@ -138,12 +144,9 @@ struct DirConst {
   double TA[4], TB[4], TG[4], TE[4];
   int kind[4];                                 // sign of A_i
   int lex[4];                                  // tie-break bit of face i
-  double n[4][3];                              // oriented face normals (set-up only)
   double M[3][3];
-  double Mabs[3][3];
   double qlo[3];
-  double guard[3];                             // FP64 error bound of q per axis (x1000 margin)
-  double gthr[3];                              // 0.5 - guard: near-grid iff |frac(q) - 0.5| >= gthr
+  double gthr[3];                              // 0.5 - FP64 error bound of q: near-grid iff |frac(q) - 0.5| >= gthr
   float thr_f[3];                              // the same test on the FP32 fraction (wider margin)
   int64_t absD;
   int fast;                                    // extent <= 2^16: FP64 plane arithmetic
@@ -167,7 +170,7 @@ __device__ __forceinline__ double det_f64(const int v[4][3]) {
   return a0 * (b1 * c2 - b2 * c1) - a1 * (b0 * c2 - b2 * c0) + a2 * (b0 * c1 - b1 * c0);
 }
 
-constexpr int kDeferCap = 128;
+constexpr int kDeferCap = 64;   // a wave's worth: every append adds at most 64
 
 // Per-item constants in LDS: both directions and the snapped vertices.
 struct ItemLds {
@@ -182,7 +185,13 @@ struct WaveLds {
   ItemLds it[2];
   int4 row[kWave];         // padded element of the first sample, the row's first unit in
                            // the unit stream, jx | jy << 10 | jz << 20 (box-relative), length
-  double rowq[kWave][3];   // mapped point of each row's first sample
+  union {
+    double rowq[kWave][3]; // mapped point of each row's first sample
+    struct {               // set-up only, per (half, direction): oriented face normals and
+      double n[2][2][4][3];        // the absolute map terms behind the error bound of q
+      double Mabs[2][2][3][3];
+    } su;
+  };
   int4 slice[kWave];       // non-empty slices of a group: z, first row y, first row index, rows
   int mark[kWave];         // row starts inside the current batch, tagged with the batch
   // samples left to the slow paths, resolved a wave at a time; the first
@@ -865,9 +874,9 @@ __device__ void eval_tet(const ProblemView& P, int tet0, int tet1, bool has1, fl
     const double nx_ = sg * (u[1] * w[2] - u[2] * w[1]);
     const double ny_ = sg * (u[2] * w[0] - u[0] * w[2]);
     const double nz_ = sg * (u[0] * w[1] - u[1] * w[0]);
-    C.n[i][0] = nx_;
-    C.n[i][1] = ny_;
-    C.n[i][2] = nz_;
+    L->su.n[half][d][i][0] = nx_;
+    L->su.n[half][d][i][1] = ny_;
+    L->su.n[half][d][i][2] = nz_;
     const int lex = (nx_ > 0 || (nx_ == 0 && (ny_ > 0 || (ny_ == 0 && nz_ > 0)))) ? 1 : 0;
     const double ox = 1024.0 * C.lo[0] - r[0], oy = 1024.0 * C.lo[1] - r[1], oz = 1024.0 * C.lo[2] - r[2];
     const double A = nx_ * 1024.0, PY = ny_ * 1024.0, PZ = nz_ * 1024.0;
@@ -920,12 +929,12 @@ __device__ void eval_tet(const ProblemView& P, int tet0, int tet1, bool has1, fl
 #pragma unroll
     for (int i = 0; i < 3; i++) {
       const double bi = static_cast<double>(oth[3 * (i + 1) + a]) - oth0;
-      const double t = bi * (sigma * C.n[i + 1][cc]);
+      const double t = bi * (sigma * L->su.n[half][d][i + 1][cc]);
       num += t;
       mag += fabs(t);
     }
     C.M[a][cc] = num * invD;
-    C.Mabs[a][cc] = mag * fabs(invD);
+    L->su.Mabs[half][d][a][cc] = mag * fabs(invD);
   }
   wave_sync();
   // phase 3, lanes 0..5 of each half: q at the box corner (padded
@@ -941,10 +950,9 @@ __device__ void eval_tet(const ProblemView& P, int tet0, int tet1, bool has1, fl
     for (int cc = 0; cc < 3; cc++) {
       const double off = C.lo[cc] - own[cc] * (1.0 / 1024.0);
       q += C.M[a][cc] * off;
-      bound += C.Mabs[a][cc] * (fabs(off) + (C.hi[cc] - C.lo[cc]));
+      bound += L->su.Mabs[half][d][a][cc] * (fabs(off) + (C.hi[cc] - C.lo[cc]));
     }
     C.qlo[a] = q;
-    C.guard[a] = bound * 0x1p-40;
     C.gthr[a] = 0.5 - bound * 0x1p-40;
     // FP32 fraction: rounding it and subtracting 1/2 moves the test value by
     // < 2^-24; the margin 2^-22 also covers rounding the threshold
@@ -1072,30 +1080,28 @@ __device__ void eval_tet(const ProblemView& P, int tet0, int tet1, bool has1, fl
           unsigned band[2];
           sample_pair_inner<ST>(P, U, r_own, r_oth, r_band, d, rw.x, qr, k, ok, ok2, h, amb, a, b, band);
           n += static_cast<int>(ok) + static_cast<int>(ok2);
-          // near-grid and in-band samples join the queue (a flush first when
-          // they would not fit)
+          // near-grid and in-band samples join the queue, at most one wave's
+          // worth (64, the queue's capacity) at a time, a flush first when
+          // they would not fit
 #pragma unroll
-          for (int s2 = 0; s2 < 2; s2++) {
-            const uint64_t m_near = __ballot(amb[s2]);
-            const uint64_t m_band = __ballot(band[s2] != 0u);
-            if (m_near | m_band) {
-              const int nn = __popcll(m_near), nb = __popcll(m_band);
-              if (n_defer + nn + nb > kDeferCap) {
+          for (int s2 = 0; s2 < 4; s2++) {
+            const bool want = (s2 & 1) ? band[s2 >> 1] != 0u : amb[s2 >> 1];
+            const uint64_t m = __ballot(want);
+            if (m) {
+              const int nq = __popcll(m);
+              if (n_defer + nq > kDeferCap) {
                 wave_sync();
                 flush_deferred<ST>(P, L, IT, n_defer, h, g);
                 n_defer = 0;
                 wave_sync();
               }
-              if (amb[s2]) {
-                const int slot2 = n_defer + bits_below(m_near);
-                L->defer[slot2] = make_int4((rw.z + k + s2) | (d << 30), __float_as_int(a[s2]),
-                                            __float_as_int(b[s2]), 0);
+              if (want) {
+                const int j = rw.z + k + (s2 >> 1);
+                L->defer[n_defer + bits_below(m)] =
+                    (s2 & 1) ? make_int4(j | (d << 30), static_cast<int>(band[s2 >> 1]), 0, 1)
+                             : make_int4(j | (d << 30), __float_as_int(a[s2 >> 1]), __float_as_int(b[s2 >> 1]), 0);
               }
-              if (band[s2] != 0u) {
-                const int slot2 = n_defer + nn + bits_below(m_band);
-                L->defer[slot2] = make_int4((rw.z + k + s2) | (d << 30), static_cast<int>(band[s2]), 0, 1);
-              }
-              n_defer += nn + nb;
+              n_defer += nq;
             }
           }
         } else {
@@ -1254,7 +1260,7 @@ __device__ __forceinline__ void split_item(const FullItems& F, int item, int& te
 }
 
 template <int ST>
-__global__ __launch_bounds__(256, 4) void k_eval_full(ProblemView P, FullItems F, Record* rec,
+__global__ __launch_bounds__(256, 5) void k_eval_full(ProblemView P, FullItems F, Record* rec,
                                                     int n_items) {
   __shared__ WaveLds lds[4];
   const int wave = uniform_i(static_cast<int>(threadIdx.x >> 6));
