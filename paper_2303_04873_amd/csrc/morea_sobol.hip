@@ -201,7 +201,7 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 }
 
 template <int ST>
-__global__ __launch_bounds__(256) void k_eval_sobol(ProblemView P, const float* pts, int pop, double inv_pop,
+__global__ __launch_bounds__(256, 6) void k_eval_sobol(ProblemView P, const float* pts, int pop, double inv_pop,
                                                   double count_scale, uint64_t seed, const uint8_t* cells0,
                                                   const uint8_t* cells1, const uint8_t* fgc0, const uint8_t* fgc1,
                                                   Record* rec, int n_items) {
