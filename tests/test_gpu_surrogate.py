@@ -289,6 +289,46 @@ def test_prescreen_equals_weighted_row_predictions(c1_surrogate):
     np.testing.assert_array_equal(np.delete(score2, 5), np.delete(score, 5))
 
 
+def test_prescreen_workspace_regrows_and_orders_do_not_matter(c1_surrogate):
+    """Two pre-screens in a row, the second with more parents (the workspace
+    grows) and the offspring in another order, and a third with fewer: each
+    score equals the offspring's score in a fresh single-family call."""
+    p, prob, s = c1_surrogate
+    s.set_params(random_theta(21, scale=0.5))
+    dp, do, of, pc, _ = family(p, prob, n_parents=2, per_parent=8, seed=51)
+    s1 = s.prescreen(do, dp, pc, of).cpu().numpy()
+    # four parents: the two above plus two more, offspring reversed
+    dp2, do2, of2, pc2, _ = family(p, prob, n_parents=2, per_parent=8, seed=52)
+    par4 = torch.cat([dp2, dp]).contiguous()
+    pc4 = prob.new_cache(4)
+    prob.eval_full(par4, cache=pc4)
+    rev = torch.arange(15, -1, -1, device="cuda")
+    s2 = s.prescreen(do[rev].contiguous(), par4, pc4, (of[rev] + 2).to(torch.int32).contiguous()).cpu().numpy()
+    np.testing.assert_allclose(s2, s1[::-1], rtol=1e-6, atol=1e-9)
+    s3 = s.prescreen(do[:3].contiguous(), dp, pc, of[:3].contiguous()).cpu().numpy()
+    np.testing.assert_allclose(s3, s1[:3], rtol=1e-6, atol=1e-9)
+
+
+def test_features_bf16_storage_read_the_stored_images():
+    """A BF16 problem's features sample the stored (rounded) images: against
+    the reference on the quantized images."""
+    p = synth_problem(1)
+    prob = morea.Problem.from_synth(p, storage="bf16", max_population=16)
+    s = morea.Surrogate(prob, max_rows=1024, seed=2)
+    dp, do, of, pc, _ = family(p, prob, n_parents=1, per_parent=4, seed=61)
+    F = s.features(do, dp, pc, of).cpu().numpy().astype(np.float64)
+    op = oracle.Problem.from_synth(p, image_src=oracle.quantize(p.image_src, "bf16"),
+                                   image_tgt=oracle.quantize(p.image_tgt, "bf16"))
+    st, _ = surrogate_inputs.region_stats(op)
+    hs = surrogate_inputs.h_scale(op)
+    np.testing.assert_allclose(s.h_scale, hs, rtol=1e-5)
+    prec = op.evaluate(dp.cpu().numpy(), records=True)["records"]
+    want = surrogate_inputs.features(op, st, do.cpu().numpy(), dp.cpu().numpy(), prec, of.cpu().numpy())
+    scale2 = float(np.abs(p.image_tgt).max()) ** 2
+    np.testing.assert_allclose(F[..., 12:15], want[..., 12:15], rtol=1e-4, atol=1e-5 * scale2 / hs)
+    np.testing.assert_allclose(F[..., 22], want[..., 22], rtol=1e-5, atol=2e-6 * scale2 / hs)
+
+
 def spearman(a, b):
     ra = np.argsort(np.argsort(a))
     rb = np.argsort(np.argsort(b))
