@@ -519,6 +519,22 @@ def form_optimizer(p, pop_np, prob_full_ms, generations):
     kept = kept.cpu().numpy()
     tm = Timing(ms)
     tm_late = Timing(ms[1:])
+    # the last generation's children re-evaluated against the final parents
+    # (no acceptance): the steady state's re-evaluated samples and their rate
+    torch.cuda.synchronize()
+    off = np.arange(0, 2 * len(opt.elements) + 1, 2, dtype=np.int32)
+    gpts = np.asarray(opt.elements).reshape(-1).astype(np.int32)
+    outs = [opt.prob.outputs(len(b["ep"])) for b in opt.batches]
+
+    def evaluate_only():
+        for b, o in zip(opt.batches, outs):
+            opt.prob.eval_partial(opt.pts, opt.cache, b["dep"], b["deg"], b["new"], out=o)
+
+    ms_eval = timed(evaluate_only, 5, 1)
+    rec_n = opt.prob.cache_records(opt.cache, npop)["n"].astype(np.int64).sum(axis=2)
+    parent_counts = opt.out["counts"].cpu().numpy()
+    samples = sum(resampled(p, rec_n, off, gpts, b["ep"], b["eg"], o["counts"].cpu().numpy(), parent_counts)
+                  for b, o in zip(opt.batches, outs))
     return {"workload": f"{npop} solutions, {len(opt.elements)} FOS elements in {len(opt.batches)} colours, "
                         f"10 clusters, archive capacity 2000, {generations} generations, steering from "
                         f"generation 100",
@@ -529,6 +545,8 @@ def form_optimizer(p, pop_np, prob_full_ms, generations):
             "kept_fraction_first_generation": float(kept[0] / n_evals),
             "kept_fraction_after_first": float(kept[1:].mean() / n_evals) if generations > 1 else None,
             "kept_fraction_last_10": float(kept[-10:].mean() / n_evals),
+            "last_generation_reevaluated": {"ms_evaluations_only": ms_eval, "timing_ms": ms_eval.spread(),
+                                            "samples": samples, "alu": alu(samples, ms_eval)},
             "trace": trace}
 
 
