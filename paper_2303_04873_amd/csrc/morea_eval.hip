@@ -728,29 +728,26 @@ __device__ void eval_tet(const ProblemView& P, int tet0, int tet1, bool has1, fl
   if (!ok0 && !ok1) return;
   if (hl < 24) I->vert[hl] = fix;
   wave_sync();
-  int V[2][4][3];
-#pragma unroll
-  for (int m = 0; m < 2; m++)
+  // ---- per direction: box on its grid, fold check (App. A.4), interior
+  // flag; lanes 0..15 of a half take mesh 0, lanes 16..31 mesh 1.  The
+  // values go to the item's LDS block so that only the current direction's
+  // copy is live in the sample loop.
+  const int dims[3] = {P.nx, P.ny, P.nz};
+  const int ref = P.ref_sign[tet];
+  bool active;
+  {
+    const int m = hl >> 4;
+    int V[4][3];
 #pragma unroll
     for (int i = 0; i < 4; i++)
 #pragma unroll
-      for (int k = 0; k < 3; k++) V[m][i][k] = I->vert[12 * m + 3 * i + k];
-
-  // ---- per direction: box on its grid, fold check (App. A.4), interior
-  // flag.  The values are uniform within a half; they go to the item's LDS
-  // block so that only the current direction's copy is live in the sample
-  // loop.
-  const int dims[3] = {P.nx, P.ny, P.nz};
-  const int ref = P.ref_sign[tet];
-  bool any_active = false;
-#pragma unroll
-  for (int m = 0; m < 2; m++) {
+      for (int k = 0; k < 3; k++) V[i][k] = I->vert[12 * m + 3 * i + k];
     int ext = 0, lo[3], hi[3];
     bool interior = true;
 #pragma unroll
     for (int k = 0; k < 3; k++) {
-      const int mn = min(min(V[m][0][k], V[m][1][k]), min(V[m][2][k], V[m][3][k]));
-      const int mx = max(max(V[m][0][k], V[m][1][k]), max(V[m][2][k], V[m][3][k]));
+      const int mn = min(min(V[0][k], V[1][k]), min(V[2][k], V[3][k]));
+      const int mx = max(max(V[0][k], V[1][k]), max(V[2][k], V[3][k]));
       ext = max(ext, mx - mn);
       lo[k] = max(0, -static_cast<int>(floor_div_pos(-static_cast<int64_t>(mn), 1024)));
       hi[k] = min(dims[k] - 1, static_cast<int>(floor_div_pos(mx, 1024)));
@@ -761,13 +758,12 @@ __device__ void eval_tet(const ProblemView& P, int tet0, int tet1, bool has1, fl
     }
     const bool fast = ext <= kFastExtent;
     // FP64 is exact for extents <= 2^16: |6V| <= 6 E^3 < 2^53
-    const int64_t D = fast ? static_cast<int64_t>(det_f64(V[m])) : det_i64(V[m]);
+    const int64_t D = fast ? static_cast<int64_t>(det_f64(V)) : det_i64(V);
     const int sg = (D > 0) - (D < 0);
     const bool viol = (sg == 0) || (sg != ref);
     const int64_t absD = D < 0 ? -D : D;
-    const bool active = D != 0 && lo[0] <= hi[0] && lo[1] <= hi[1] && lo[2] <= hi[2];
-    any_active = any_active || active;
-    if (hl == 0) {
+    active = D != 0 && lo[0] <= hi[0] && lo[1] <= hi[1] && lo[2] <= hi[2];
+    if ((hl & 15) == 0) {
       DirConst& C = I->c[m];
       C.absD = absD;
       C.fast = fast ? 1 : 0;
@@ -791,20 +787,25 @@ __device__ void eval_tet(const ProblemView& P, int tet0, int tet1, bool has1, fl
     }
   }
   // items with samples to visit (a half-wave value made wave-uniform)
-  const uint64_t act_mask = __ballot(any_active && (half ? ok1 : ok0));
-  const bool act0 = (act_mask & 1ull) != 0, act1 = ((act_mask >> 32) & 1ull) != 0;
+  const uint64_t act_mask = __ballot(active && (half ? ok1 : ok0));
+  const bool act0 = (act_mask & 0xffffffffull) != 0, act1 = (act_mask >> 32) != 0;
 
-  // ---- deformation magnitude (Sec. 4.1.1), one edge per lane:
+  wave_sync();   // the box constants are read below
+
+  // ---- one pass over lanes 0..17 of each half: set-up phase 1 on lanes
+  // 0..7 (below) and the deformation magnitude on lanes 8..17.
+  // Deformation magnitude (Sec. 4.1.1), one edge per lane:
   // |e_s| - |e_t| = (|e_s|^2 - |e_t|^2) / (|e_s| + |e_t|) with the squared
   // lengths exact in FP64 (components < 2^22, sums < 2^46).
   {
     float term = 0.f;
-    if (hl < 10) {
+    const int e = hl - 8;   // the magnitude's edge (lanes 8..17 of the half)
+    if (e >= 0 && e < 10) {
       double ls = 0.0, lt = 0.0;
       float scale;
-      if (hl < 6) {
-        const int i = hl < 3 ? 0 : (hl < 5 ? 1 : 2);
-        const int j = hl < 3 ? hl + 1 : (hl < 5 ? hl - 1 : 3);
+      if (e < 6) {
+        const int i = e < 3 ? 0 : (e < 5 ? 1 : 2);
+        const int j = e < 3 ? e + 1 : (e < 5 ? e - 1 : 3);
 #pragma unroll
         for (int k = 0; k < 3; k++) {
           const double ds = I->vert[3 * i + k] - I->vert[3 * j + k];
@@ -814,7 +815,7 @@ __device__ void eval_tet(const ProblemView& P, int tet0, int tet1, bool has1, fl
         }
         scale = 1.0f / kFixOne;
       } else {
-        const int v = hl - 6;
+        const int v = e - 6;
 #pragma unroll
         for (int k = 0; k < 3; k++) {
           const int ss = I->vert[k] + I->vert[3 + k] + I->vert[6 + k] + I->vert[9 + k];
@@ -837,20 +838,7 @@ __device__ void eval_tet(const ProblemView& P, int tet0, int tet1, bool has1, fl
     const float mag = P.elasticity[tet] * term;
     if (hl == 0) I->c[0].mag = mag;
   }
-  wave_sync();
-  if (!act0 && !act1) {
-    if (ok0 && lane < 2) {
-      const DirConst& C = L->it[0].c[lane];
-      out0[lane] = Record{0.f, 0.f, 0u, C.mag, C.vol, C.bits};
-    }
-    if (ok1 && lane >= 32 && lane < 34) {
-      const DirConst& C = L->it[1].c[lane - 32];
-      out1[lane - 32] = Record{0.f, 0.f, 0u, C.mag, C.vol, C.bits};
-    }
-    return;
-  }
-
-  // ---- set-up phase 1, lanes 0..7 of each half (direction d = hl / 4, face
+  // set-up phase 1, lanes 0..7 of each half (direction d = hl / 4, face
   // i): face plane (gradient of D * lambda_i oriented inwards, its value at
   // the box corner, the row-boundary estimate)
   if (hl < 8) {
@@ -915,6 +903,17 @@ __device__ void eval_tet(const ProblemView& P, int tet0, int tet1, bool has1, fl
     }
   }
   wave_sync();
+  if (!act0 && !act1) {
+    if (ok0 && lane < 2) {
+      const DirConst& C = L->it[0].c[lane];
+      out0[lane] = Record{0.f, 0.f, 0u, C.mag, C.vol, C.bits};
+    }
+    if (ok1 && lane >= 32 && lane < 34) {
+      const DirConst& C = L->it[1].c[lane - 32];
+      out1[lane - 32] = Record{0.f, 0.f, 0u, C.mag, C.vol, C.bits};
+    }
+    return;
+  }
   // phase 2, lanes 0..17 of each half: map entry M[a][c] of direction
   // d = hl / 9: sum_i b_i[a] adj_i[c] / D with b_i = oth_i - oth_0 and
   // adj_i = sigma n_i (i = 1..3), the rows of adj(E)
