@@ -166,6 +166,11 @@ def form_partial(p, pop_np, prob_full_ms, steps):
     out = prob.outputs(len(ep))
     par_out = prob.eval_full(par.clone())
     tune_ms, shape = prob.tune_partial(par, cache, dep, deg, dnew, out=out)
+    # the other launch form, timed for comparison, then the tuned shape back
+    other = (0, 0) if shape != (0, 0) else (1024, 8)
+    prob.set_partial_shape(*other)
+    ms_other = timed(lambda: prob.eval_partial(par, cache, dep, deg, dnew, out=out), steps, 2)
+    prob.set_partial_shape(*shape)
     n_graphs0 = morea.morea_partial_graphs(prob.handle)[1]
     ms = timed(lambda: prob.eval_partial(par, cache, dep, deg, dnew, out=out), steps, 2)
     captures = morea.morea_partial_graphs(prob.handle)[1] - n_graphs0
@@ -185,7 +190,10 @@ def form_partial(p, pop_np, prob_full_ms, steps):
             "samples_per_launch": samples, "alu": alu(samples, ms),
             "graph_captures_while_timed": captures,
             "vs_plain_full_evals_per_s": evals_s / (pop_np.shape[0] / (prob_full_ms * 1e-3)),
-            "launch_shape": {"blocks": shape[0], "items_per_pop": shape[1], "tuned_ms": tune_ms},
+            "launch_shape": {"blocks": shape[0], "items_per_pop": shape[1], "tuned_ms": tune_ms,
+                             "form": "grid" if shape == (0, 0) else "persistent"},
+            "other_form_ms": {"shape": list(other), "median": float(ms_other), "p10": ms_other.p10,
+                              "p90": ms_other.p90},
             "parity": {"evals": idx, "counts_flags_exact": exact,
                        "max_rel_err": [float(x) for x in rel.max(axis=0)]}}
 

@@ -515,23 +515,32 @@ morea_status morea_sample_partial(morea_problem *p, const float *pts, int32_t n_
 morea_status morea_debug_distance_map(morea_problem *p, int32_t image, int32_t set, float *host_out,
                                       uint8_t *band_out);
 
-/* Autotuner of the persistent partial-evaluation launch: with the same
- * arguments as morea_eval_partial, times every launch shape (persistent
- * blocks per compute unit up to the occupancy limit x work items taken per
- * queue pop in {1, 2, 4, 8, 16}) on the given inputs with HIP events and keeps the
- * fastest for later morea_eval_partial calls.  Synchronous; overwrites the
- * output arrays.  *best_ms (may be NULL) receives the best time.  Untuned,
- * the shape is 4 blocks per compute unit (at most the occupancy limit) and 8
- * items per pop.  Errors as morea_eval_partial. */
+/* Autotuner of the partial-evaluation launch: with the same arguments as
+ * morea_eval_partial, times every launch shape (persistent blocks per compute
+ * unit up to the occupancy limit x work items taken per queue pop in
+ * {1, 2, 4, 8, 16}, and the grid form: one wave per two items over a grid
+ * that covers n_evals x the largest dependent-tet count of a group, the
+ * waves beyond the actual item count returning at once) on the given inputs
+ * with HIP events and keeps the fastest for later morea_eval_partial calls.
+ * Synchronous; overwrites the output arrays.  *best_ms (may be NULL) receives
+ * the best time.  Untuned, the shape is 4 persistent blocks per compute unit
+ * (at most the occupancy limit) and 8 items per pop.  Errors as
+ * morea_eval_partial. */
 morea_status morea_tune_partial(morea_problem *p, const float *parent_pts, int32_t n_parents,
                                 const void *parent_cache, int32_t n_evals,
                                 const int32_t *eval_parent, const int32_t *eval_group,
                                 const float *new_coords, float *obj, uint8_t *flags,
                                 float *severity, uint32_t *counts, void *stream, float *best_ms);
 
-/* Current persistent launch shape of partial evaluation (blocks of 256
- * threads, items per queue pop).  Errors: MOREA_EINVAL. */
+/* Current launch shape of partial evaluation: persistent blocks of 256
+ * threads and items per queue pop, or *chunk = 0 (and *blocks = 0) for the
+ * grid form.  Errors: MOREA_EINVAL. */
 morea_status morea_partial_shape(const morea_problem *p, int32_t *blocks, int32_t *chunk);
+
+/* Set the launch shape of partial evaluation (as morea_tune_partial would):
+ * blocks >= 1 persistent blocks and 1 <= chunk <= 64 items per queue pop, or
+ * blocks = chunk = 0 for the grid form.  Errors: MOREA_EINVAL. */
+morea_status morea_set_partial_shape(morea_problem *p, int32_t blocks, int32_t chunk);
 
 /* Graph cache of morea_eval_partial: up to 8 captured graphs are kept, one
  * per argument set (pointers, sizes, launch shape); a call that matches one

@@ -29,7 +29,8 @@ EXPORTS = ["morea_problem_create", "morea_problem_destroy", "morea_cache_bytes",
            "morea_set_groups", "morea_reserve_partial", "morea_eval_partial", "morea_accept_partial", "morea_select_clusters",
            "morea_archive_clear", "morea_archive_update", "morea_mark_improvements", "morea_adapt_multipliers",
            "morea_mixing_bytes", "morea_estimate_distributions", "morea_sample_partial",
-           "morea_debug_distance_map", "morea_tune_partial", "morea_partial_shape", "morea_partial_graphs",
+           "morea_debug_distance_map", "morea_tune_partial", "morea_partial_shape", "morea_set_partial_shape",
+           "morea_partial_graphs",
            "morea_surrogate_num_params", "morea_surrogate_num_features", "morea_surrogate_create",
            "morea_surrogate_destroy", "morea_surrogate_features", "morea_surrogate_targets",
            "morea_surrogate_train_step",
@@ -118,6 +119,8 @@ def load_library():
     L.morea_tune_partial.restype = I32
     L.morea_partial_shape.argtypes = [P, P, P]
     L.morea_partial_shape.restype = I32
+    L.morea_set_partial_shape.argtypes = [P, I32, I32]
+    L.morea_set_partial_shape.restype = I32
     L.morea_partial_graphs.argtypes = [P, P, P]
     L.morea_partial_graphs.restype = I32
     L.morea_debug_distance_map.argtypes = [P, I32, I32, P, P]
@@ -347,6 +350,10 @@ def morea_partial_shape(handle):
     b, c = ctypes.c_int32(), ctypes.c_int32()
     _check(load_library().morea_partial_shape(handle, ctypes.byref(b), ctypes.byref(c)))
     return b.value, c.value
+
+
+def morea_set_partial_shape(handle, blocks, chunk):
+    _check(load_library().morea_set_partial_shape(handle, int(blocks), int(chunk)))
 
 
 def morea_partial_graphs(handle):
@@ -614,6 +621,14 @@ class Problem:
                                 eval_parent, eval_group, new_coords, out["obj"], out["flags"],
                                 out["severity"], out["counts"], stream)
         return ms, morea_partial_shape(self.handle)
+
+    def set_partial_shape(self, blocks, chunk):
+        """Launch shape of partial evaluation: persistent (blocks, chunk) or
+        (0, 0) for the grid form."""
+        morea_set_partial_shape(self.handle, blocks, chunk)
+
+    def partial_shape(self):
+        return morea_partial_shape(self.handle)
 
     def distance_map(self, image, set_index):
         return morea_debug_distance_map(self.handle, image, set_index, self.dims[::-1])

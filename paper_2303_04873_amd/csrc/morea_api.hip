@@ -83,7 +83,7 @@ namespace morea {
 void set_error(const char* msg) { g_error = msg; }
 
 void ensure_partial_shape(morea_problem* p) {
-  if (p->partial_blocks != 0) return;
+  if (p->partial_chunk >= 0) return;   // chosen already (a default or the tuner's)
   int cus = 0, per_cu = 0;
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
   per_cu = partial_blocks_per_cu(p->storage);
@@ -580,6 +580,10 @@ static hipError_t partial_launch(morea_problem* p, const float* parent_pts, int3
   const Record* prec = static_cast<const Record*>(parent_cache);
   const Totals* ptot = reinterpret_cast<const Totals*>(
       static_cast<const char*>(parent_cache) + static_cast<size_t>(n_parents) * p->view.n_tets * 2 * sizeof(Record));
+  if (chunk == 0) {   // grid form: one wave per item pair up to the bound n_evals x max_dep
+    const long long bound = static_cast<long long>(n_evals) * std::max(p->max_dep, 1);
+    blocks = static_cast<int>(std::min<long long>((bound + 7) / 8, 0x7fffffffLL));
+  }
   return launch_partial(p->view, p->storage, I, n_parents, p->n_groups, prec, ptot,
                         p->d_partial_records, p->d_queue, blocks, chunk, obj, flags, severity,
                         counts, s);
@@ -668,9 +672,10 @@ morea_status morea_tune_partial(morea_problem* p, const float* parent_pts, int32
   float best = 1e30f;
   int best_blocks = p->partial_blocks, best_chunk = p->partial_chunk;
   const int chunks[5] = {1, 2, 4, 8, 16};
-  for (int bpc = 1; bpc <= per_cu; bpc++)
-    for (int c = 0; c < 5; c++) {
-      const int blocks = bpc * cus, chunk = chunks[c];
+  // every persistent shape, then the grid form (chunk 0)
+  for (int bpc = 1; bpc <= per_cu + 1; bpc++)
+    for (int c = 0; c < (bpc <= per_cu ? 5 : 1); c++) {
+      const int blocks = bpc <= per_cu ? bpc * cus : 0, chunk = bpc <= per_cu ? chunks[c] : 0;
       float total = 0.f;
       hipError_t e = hipSuccess;
       for (int rep = 0; rep < 3 && e == hipSuccess; rep++) {
@@ -710,6 +715,16 @@ morea_status morea_partial_graphs(const morea_problem* p, int32_t* cached, int64
   for (const auto& g : p->graphs) n += g.exec ? 1 : 0;
   *cached = n;
   *captures = static_cast<int64_t>(p->graph_captures);
+  return MOREA_OK;
+}
+
+morea_status morea_set_partial_shape(morea_problem* p, int32_t blocks, int32_t chunk) {
+  if (!p) return fail(MOREA_EINVAL, "NULL argument");
+  const bool grid = blocks == 0 && chunk == 0;
+  if (!grid && (blocks < 1 || chunk < 1 || chunk > 64)) return fail(MOREA_EINVAL, "bad launch shape");
+  if (p->partial_blocks != blocks || p->partial_chunk != chunk) drop_graph(p);
+  p->partial_blocks = blocks;
+  p->partial_chunk = chunk;
   return MOREA_OK;
 }
 

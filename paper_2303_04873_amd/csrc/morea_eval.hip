@@ -1591,6 +1591,32 @@ __global__ __launch_bounds__(256) void k_partial_items(PartialItems I, int n_par
 // directions per item: each wave takes `chunk` consecutive items from a
 // device work queue until the list is exhausted.  Every wave leaves the loop
 // once the queue passes the end of the list.
+// Child coordinate of lane `lane` for the item pair (idx, idx + 1): lanes
+// 0..23 of each half hold the 24 coordinates of their item's tet (mesh 0
+// then 1, vertex-major), from the group's new coordinates or the parent.
+__device__ __forceinline__ float partial_coord(const ProblemView& P, const PartialItems& I, int4 it0, int4 it1,
+                                               bool has1, int lane) {
+  const int half = lane >> 5, hl = lane & 31;
+  const int4 it = half ? it1 : it0;
+  float coord = 0.f;
+  if (hl < 24 && (half == 0 || has1)) {
+    const int slot = it.x, tet = it.y, par = it.z, row = it.w;
+    const int i = (hl % 12) / 3, k = hl % 3;
+    const int mesh = hl < 12 ? 0 : 1;
+    const int loc = I.dep_local[4 * slot + i];
+    if (loc >= 0) {
+      coord = I.new_coords[((static_cast<size_t>(row) + loc) * 2 + mesh) * 3 + k];
+    } else {
+      const int4 tv = P.tets[tet];
+      const int v = i == 0 ? tv.x : (i == 1 ? tv.y : (i == 2 ? tv.z : tv.w));
+      coord = I.parent_pts[((static_cast<size_t>(par) * 2 + mesh) * 3 + k) * P.n_points + v];
+    }
+  }
+  return coord;
+}
+
+// Persistent form: every wave takes `chunk` items at a time from the queue
+// (items in processing order) until none is left.
 template <int ST>
 __global__ __launch_bounds__(256, 4) void k_eval_partial(ProblemView P, PartialItems I, Record* out,
                                                        int* queue, int chunk) {
@@ -1609,22 +1635,7 @@ __global__ __launch_bounds__(256, 4) void k_eval_partial(ProblemView P, PartialI
       const int4 it0 = I.item_info[idx];
       const int4 it1 = has1 ? I.item_info[idx + 1] : it0;
       const int tet0 = uniform_i(it0.y), tet1 = uniform_i(it1.y);
-      const int half = lane >> 5, hl = lane & 31;
-      const int4 it = half ? it1 : it0;
-      float coord = 0.f;
-      if (hl < 24 && (half == 0 || has1)) {
-        const int slot = it.x, tet = it.y, par = it.z, row = it.w;
-        const int i = (hl % 12) / 3, k = hl % 3;
-        const int mesh = hl < 12 ? 0 : 1;
-        const int loc = I.dep_local[4 * slot + i];
-        if (loc >= 0) {
-          coord = I.new_coords[((static_cast<size_t>(row) + loc) * 2 + mesh) * 3 + k];
-        } else {
-          const int4 tv = P.tets[tet];
-          const int v = i == 0 ? tv.x : (i == 1 ? tv.y : (i == 2 ? tv.z : tv.w));
-          coord = I.parent_pts[((static_cast<size_t>(par) * 2 + mesh) * 3 + k) * P.n_points + v];
-        }
-      }
+      const float coord = partial_coord(P, I, it0, it1, has1, lane);
       const int dest0 = uniform_i(I.item_dest[idx]);
       const int dest1 = has1 ? uniform_i(I.item_dest[idx + 1]) : dest0;
       eval_tet<ST>(P, tet0, tet1, has1, coord, &lds[wave], &out[static_cast<size_t>(dest0) * 2],
@@ -1633,9 +1644,36 @@ __global__ __launch_bounds__(256, 4) void k_eval_partial(ProblemView P, PartialI
   }
 }
 
+// Grid form: wave w evaluates items 2 w and 2 w + 1 (in processing order);
+// the grid covers a bound of the item count known on the host, and the
+// waves beyond the actual count return at once.  Without the persistent
+// loop the kernel fits five waves per SIMD.
+template <int ST>
+__global__ __launch_bounds__(256, 5) void k_eval_partial_grid(ProblemView P, PartialItems I, Record* out) {
+  __shared__ WaveLds lds[4];
+  const int wave = uniform_i(static_cast<int>(threadIdx.x >> 6));
+  const int lane = lane_id();
+  const int total = I.item_off[I.n_evals];
+  const long long idx_l = 2 * (static_cast<long long>(blockIdx.x) * 4 + wave);
+  if (idx_l >= total) return;
+  const int idx = static_cast<int>(idx_l);
+  const bool has1 = idx + 1 < total;
+  const int4 it0 = I.item_info[idx];
+  const int4 it1 = has1 ? I.item_info[idx + 1] : it0;
+  const int tet0 = uniform_i(it0.y), tet1 = uniform_i(it1.y);
+  const float coord = partial_coord(P, I, it0, it1, has1, lane);
+  const int dest0 = uniform_i(I.item_dest[idx]);
+  const int dest1 = has1 ? uniform_i(I.item_dest[idx + 1]) : dest0;
+  eval_tet<ST>(P, tet0, tet1, has1, coord, &lds[wave], &out[static_cast<size_t>(dest0) * 2],
+               &out[static_cast<size_t>(dest1) * 2]);
+}
+
 template __global__ void k_eval_partial<kF32>(ProblemView, PartialItems, Record*, int*, int);
 template __global__ void k_eval_partial<kBF16>(ProblemView, PartialItems, Record*, int*, int);
 template __global__ void k_eval_partial<kF16>(ProblemView, PartialItems, Record*, int*, int);
+template __global__ void k_eval_partial_grid<kF32>(ProblemView, PartialItems, Record*);
+template __global__ void k_eval_partial_grid<kBF16>(ProblemView, PartialItems, Record*);
+template __global__ void k_eval_partial_grid<kF16>(ProblemView, PartialItems, Record*);
 
 __device__ __forceinline__ void df_wave_sum(float& hi, float& lo) {
 #pragma unroll
@@ -1746,16 +1784,24 @@ hipError_t launch_partial(const ProblemView& P, int storage, const PartialItems&
   hipLaunchKernelGGL(k_prep_offsets, dim3(prep_blocks), dim3(kPrepBlock), 0, s, I, n_parents, n_groups);
   hipLaunchKernelGGL(k_prep_groups, dim3(1), dim3(1024), 0, s, I, n_groups);
   hipLaunchKernelGGL(k_partial_items, dim3((I.n_evals + 3) / 4), dim3(256), 0, s, I, n_parents, n_groups);
-  switch (storage) {
-    case kF32:
-      hipLaunchKernelGGL(k_eval_partial<kF32>, dim3(blocks), dim3(256), 0, s, P, I, new_rec, queue, chunk);
-      break;
-    case kBF16:
-      hipLaunchKernelGGL(k_eval_partial<kBF16>, dim3(blocks), dim3(256), 0, s, P, I, new_rec, queue, chunk);
-      break;
-    default:
-      hipLaunchKernelGGL(k_eval_partial<kF16>, dim3(blocks), dim3(256), 0, s, P, I, new_rec, queue, chunk);
-      break;
+  if (chunk == 0) {   // grid form: `blocks` covers the bound of the item count
+    switch (storage) {
+      case kF32: hipLaunchKernelGGL(k_eval_partial_grid<kF32>, dim3(blocks), dim3(256), 0, s, P, I, new_rec); break;
+      case kBF16: hipLaunchKernelGGL(k_eval_partial_grid<kBF16>, dim3(blocks), dim3(256), 0, s, P, I, new_rec); break;
+      default: hipLaunchKernelGGL(k_eval_partial_grid<kF16>, dim3(blocks), dim3(256), 0, s, P, I, new_rec); break;
+    }
+  } else {
+    switch (storage) {
+      case kF32:
+        hipLaunchKernelGGL(k_eval_partial<kF32>, dim3(blocks), dim3(256), 0, s, P, I, new_rec, queue, chunk);
+        break;
+      case kBF16:
+        hipLaunchKernelGGL(k_eval_partial<kBF16>, dim3(blocks), dim3(256), 0, s, P, I, new_rec, queue, chunk);
+        break;
+      default:
+        hipLaunchKernelGGL(k_eval_partial<kF16>, dim3(blocks), dim3(256), 0, s, P, I, new_rec, queue, chunk);
+        break;
+    }
   }
   hipLaunchKernelGGL(k_finalize_partial, dim3((I.n_evals + 3) / 4), dim3(256), 0, s, P, I,
                      parent_rec, parent_tot, n_parents, n_groups, new_rec, obj, flags, severity,

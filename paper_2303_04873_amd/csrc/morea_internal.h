@@ -157,8 +157,8 @@ struct morea_problem {
   int* d_queue = nullptr;
   hipStream_t capture_stream = nullptr;
   // autotuned persistent launch shape
-  int partial_blocks = 0;
-  int partial_chunk = 1;
+  int partial_blocks = 0;    // persistent blocks, or 0 with partial_chunk 0: the grid form
+  int partial_chunk = -1;    // items per queue pop; -1 until a shape is chosen
   // captured partial-evaluation graphs, each with the arguments it bakes in;
   // a call whose arguments match an entry replays it, otherwise the least
   // recently used entry is replaced (a generation alternates one argument set

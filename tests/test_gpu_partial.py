@@ -71,12 +71,25 @@ def test_partial_graph_replay_and_tuner():
         (junk * 2).sum().item()
         out["obj"].zero_()
     ms, shape = prob.tune_partial(dev["parents"], cache, dev["ep"], dev["eg"], dev["new"])
-    assert ms > 0 and shape[0] > 0 and shape[1] in (1, 2, 4)
+    assert ms > 0 and ((shape[0] > 0 and shape[1] in (1, 2, 4, 8, 16)) or shape == (0, 0))
     prob.eval_partial(dev["parents"], cache, dev["ep"], dev["eg"], dev["new"], out=out)
     torch.cuda.synchronize()
     g = to_host(out)
     for k in g:
         np.testing.assert_array_equal(g[k], ref[k])
+    # both launch forms, several shapes: the same outputs bit for bit
+    for shape in [(0, 0), (3, 1), (7, 16), (256, 8)]:
+        prob.set_partial_shape(*shape)
+        assert prob.partial_shape() == shape
+        out["obj"].zero_()
+        prob.eval_partial(dev["parents"], cache, dev["ep"], dev["eg"], dev["new"], out=out)
+        torch.cuda.synchronize()
+        g = to_host(out)
+        for k in g:
+            np.testing.assert_array_equal(g[k], ref[k], err_msg=f"shape {shape} {k}")
+    for bad in [(0, 4), (4, 0), (-1, 1), (4, 65)]:
+        with pytest.raises(morea.MoreaError):
+            prob.set_partial_shape(*bad)
 
 
 def test_partial_graph_cache_alternating_sets():
