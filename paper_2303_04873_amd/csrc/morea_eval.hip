@@ -292,15 +292,20 @@ __device__ __forceinline__ void row_span_fast(const DirConst& c, int yr, int zr,
   bool empty = false;
 #pragma unroll
   for (int i = 0; i < 4; i++) {
-    const int kind = c.kind[i];
+    // the face's orientation is the same for the whole wave (one item and
+    // direction): scalar branches, one rounding path per face
+    const int kind = uniform_i(c.kind[i]);
     const double t = fma(c.TA[i], y, fma(c.TB[i], z, c.TG[i]));
-    // face parallel to x (kind 0): t holds the plane value itself
-    empty = empty || (kind == 0 && !(t > 0.0));
+    if (kind == 0) {
+      // face parallel to x: t holds the plane value itself
+      empty = empty || !(t > 0.0);
+      continue;
+    }
     // a crossing beyond [-2, W + 1] leaves the row full or empty either way:
     // floor / ceil of the clamped value decide it without the exact test
     const double tc = fmin(fmax(t, -2.0), W + 1.0);
     const double r = rint(tc);
-    const bool near = kind != 0 && tc == t && fabs(tc - r) <= c.TE[i];
+    const bool near = tc == t && fabs(tc - r) <= c.TE[i];
     int j = kind > 0 ? static_cast<int>(floor(tc)) + 1 : static_cast<int>(ceil(tc)) - 1;
     if (__ballot(near)) {
       // rare: the exact plane value (+ tie-break bit) at x = r decides;
@@ -310,8 +315,10 @@ __device__ __forceinline__ void row_span_fast(const DirConst& c, int yr, int zr,
       const int jx = kind > 0 ? (e > 0.0 ? ri : ri + 1) : (e > 0.0 ? ri : ri - 1);
       j = near ? jx : j;
     }
-    js = kind > 0 ? max(js, j) : js;
-    je = kind < 0 ? min(je, j) : je;
+    if (kind > 0)
+      js = max(js, j);
+    else
+      je = min(je, j);
   }
   if (empty) je = -1;
 }
